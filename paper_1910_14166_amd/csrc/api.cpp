@@ -1,0 +1,702 @@
+// libihs C ABI: argument validation, workspace carving and the IHS loop.
+// Declarations and their contracts live in include/ihs.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <utility>
+#include <vector>
+
+#include "../../include/ihs.h"
+#include "kernels.hpp"
+
+using namespace ihs;
+
+namespace {
+
+constexpr int64_t kMaxSketchRows = 16384;  // per problem: 64 KiB LDS histogram
+constexpr int64_t kMaxDenseD = 1024;       // register-resident row slices
+constexpr int64_t kMaxCsrD = 1024;         // LDS-resident bucket rows (64 KiB)
+constexpr int32_t kSegRows = 256;          // rows per wavefront, natural-order passes
+constexpr int32_t kTilesPerChunk = 8;
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Bump allocator over the caller's workspace (or a size count when base is null).
+struct Carver {
+  char* base;
+  size_t used = 0;
+  explicit Carver(void* b) : base(static_cast<char*>(b)) {}
+  template <typename T>
+  T* take(size_t count) {
+    used = align_up(used, 256);
+    T* p = base ? reinterpret_cast<T*>(base + used) : nullptr;
+    used += count * sizeof(T);
+    return p;
+  }
+};
+
+int64_t dtype_size(int32_t dt) { return dt == IHS_F64 ? 8 : (dt == IHS_F32 ? 4 : 2); }
+
+bool valid_sketch(const ihs_sketch* sk) {
+  if (!sk) return false;
+  if (sk->kind != IHS_COUNTSKETCH && sk->kind != IHS_SJLT) return false;
+  if (sk->m < 1 || sk->s < 1) return false;
+  if (sk->kind == IHS_COUNTSKETCH && sk->s != 1) return false;
+  if (sk->m % sk->s != 0) return false;
+  return true;
+}
+
+ihs_status check_sketch(const ihs_sketch* sk) {
+  if (!valid_sketch(sk)) return IHS_ERR_INVALID_ARG;
+  if (sk->m > kMaxSketchRows) return IHS_ERR_UNSUPPORTED;
+  return IHS_OK;
+}
+
+// Problem table of a matrix (host copy).
+struct Layout {
+  std::vector<ProbInfo> probs;
+  int32_t batch = 1;
+  int64_t n = 0, d = 0;
+  int32_t tile_rows = 256;
+  int32_t total_tiles = 0, total_chunks = 0, total_seg = 0;
+};
+
+ihs_status check_matrix(const ihs_matrix* A) {
+  if (!A) return IHS_ERR_INVALID_ARG;
+  if (A->n < 0 || A->d < 1 || A->batch < 1) return IHS_ERR_INVALID_ARG;
+  if (A->n >= (int64_t(1) << 31)) return IHS_ERR_UNSUPPORTED;
+  if (A->format == IHS_DENSE) {
+    if (A->dtype != IHS_F64 && A->dtype != IHS_F32) return IHS_ERR_INVALID_ARG;
+    if (A->ld < A->d) return IHS_ERR_INVALID_ARG;
+    if (A->n > 0 && !A->values) return IHS_ERR_INVALID_ARG;
+    if (A->d > kMaxDenseD) return IHS_ERR_UNSUPPORTED;
+    // beyond 512 columns rows are read as aligned pairs
+    if (A->d > 512 && (A->d % 2 != 0 || A->ld % 2 != 0 ||
+                       reinterpret_cast<uintptr_t>(A->values) % (2 * (A->dtype == IHS_F64 ? 8 : 4)) != 0))
+      return IHS_ERR_UNSUPPORTED;
+  } else if (A->format == IHS_CSR) {
+    if (A->dtype != IHS_F64) return IHS_ERR_INVALID_ARG;
+    if (A->batch != 1) return IHS_ERR_UNSUPPORTED;
+    if (A->nnz < 0 || !A->row_ptr) return IHS_ERR_INVALID_ARG;
+    if (A->nnz > 0 && (!A->col_idx || !A->values)) return IHS_ERR_INVALID_ARG;
+    if (A->nnz >= (int64_t(1) << 31)) return IHS_ERR_UNSUPPORTED;
+    if (A->d > kMaxCsrD) return IHS_ERR_UNSUPPORTED;
+  } else {
+    return IHS_ERR_INVALID_ARG;
+  }
+  if (A->batch > 1) {
+    if (!A->row_offsets) return IHS_ERR_INVALID_ARG;
+    if (A->row_offsets[0] != 0 || A->row_offsets[A->batch] != A->n) return IHS_ERR_INVALID_ARG;
+    for (int32_t p = 0; p < A->batch; ++p)
+      if (A->row_offsets[p + 1] < A->row_offsets[p]) return IHS_ERR_INVALID_ARG;
+  }
+  return IHS_OK;
+}
+
+Layout make_layout(const ihs_matrix* A, int64_t m_local) {
+  Layout L;
+  L.batch = A->batch;
+  L.n = A->n;
+  L.d = A->d;
+  int64_t tr = std::max<int64_t>(m_local, (A->n + 1023) / 1024);
+  tr = std::max<int64_t>(256, align_up((size_t)tr, 256));
+  L.tile_rows = (int32_t)std::min<int64_t>(tr, int64_t(1) << 20);
+  L.probs.resize(A->batch);
+  int32_t tile = 0, chunk = 0, seg = 0;
+  for (int32_t p = 0; p < A->batch; ++p) {
+    ProbInfo& q = L.probs[p];
+    q.row0 = A->batch > 1 ? A->row_offsets[p] : 0;
+    q.rows = A->batch > 1 ? A->row_offsets[p + 1] - A->row_offsets[p] : A->n;
+    q.tile0 = tile;
+    q.ntiles = (int32_t)((q.rows + L.tile_rows - 1) / L.tile_rows);
+    q.chunk0 = chunk;
+    q.nchunks = (q.ntiles + kTilesPerChunk - 1) / kTilesPerChunk;
+    q.seg0 = seg;
+    q.nseg = (int32_t)((q.rows + kSegRows - 1) / kSegRows);
+    tile += q.ntiles;
+    chunk += q.nchunks;
+    seg += q.nseg;
+  }
+  L.total_tiles = tile;
+  L.total_chunks = chunk;
+  L.total_seg = seg;
+  return L;
+}
+
+// Device arrays of one sketch pass (sort + gather + gradient partials).
+struct PassBuffers {
+  ProbInfo* probs = nullptr;
+  DeviceStatus* status = nullptr;
+  uint32_t* keys = nullptr;
+  int32_t* tile_count = nullptr;
+  int32_t* chunk_part = nullptr;
+  int32_t* bucket_start = nullptr;
+  uint32_t* perm = nullptr;
+  double* gpart = nullptr;
+  double* fpart = nullptr;
+  double* g = nullptr;
+  double* f = nullptr;
+  double* bzero = nullptr;
+};
+
+void carve_pass(Carver& c, const Layout& L, const ihs_sketch* sk, PassBuffers& B) {
+  const int64_t m = sk ? sk->m : 1;
+  const int64_t s = sk ? sk->s : 1;
+  const int64_t m_blk = m / s;
+  const int64_t entries = L.n * s;
+  B.probs = c.take<ProbInfo>(L.batch);
+  B.status = c.take<DeviceStatus>(1);
+  B.keys = c.take<uint32_t>((size_t)std::max<int64_t>(entries, 1));
+  B.tile_count = c.take<int32_t>((size_t)std::max<int64_t>((int64_t)L.total_tiles * m, 1));
+  B.chunk_part = c.take<int32_t>((size_t)std::max<int64_t>((int64_t)L.total_chunks * m, 1));
+  B.bucket_start = c.take<int32_t>((size_t)(L.batch * m + 1));
+  B.perm = c.take<uint32_t>((size_t)std::max<int64_t>(entries, 1));
+  const int64_t parts = std::max<int64_t>((int64_t)L.batch * m_blk, L.total_seg);
+  B.gpart = c.take<double>((size_t)std::max<int64_t>(parts * L.d, 1));
+  B.fpart = c.take<double>((size_t)std::max<int64_t>(parts, 1));
+  B.g = c.take<double>((size_t)(L.batch * L.d));
+  B.f = c.take<double>((size_t)L.batch);
+  B.bzero = c.take<double>((size_t)std::max<int64_t>(L.n, 1));
+}
+
+SketchPlan make_plan(const Layout& L, const ihs_sketch* sk, const PassBuffers& B, uint64_t iter) {
+  SketchPlan P{};
+  P.probs = B.probs;
+  P.batch = L.batch;
+  P.s = sk->s;
+  P.m = sk->m;
+  P.m_blk = sk->m / sk->s;
+  P.seed = sk->seed;
+  P.iter = iter;
+  P.tile_rows = L.tile_rows;
+  P.tiles_per_chunk = kTilesPerChunk;
+  P.total_tiles = L.total_tiles;
+  P.total_chunks = L.total_chunks;
+  int32_t bits = 0;
+  while ((int64_t(1) << bits) < sk->m) ++bits;
+  P.bucket_bits = bits;
+  P.entries = L.n * sk->s;
+  P.keys = B.keys;
+  P.tile_count = B.tile_count;
+  P.chunk_part = B.chunk_part;
+  P.bucket_start = B.bucket_start;
+  P.perm = B.perm;
+  return P;
+}
+
+__global__ void k_zero_status(DeviceStatus* st) {
+  if (threadIdx.x == 0) {
+    st->code = 0;
+    st->failed_iter = -1;
+    st->failed_problem = -1;
+    st->done = 0;
+    st->iters = 0;
+    st->objective = 0.0;
+    st->last_step = 0.0;
+  }
+}
+
+__global__ void k_fill(double* p, int64_t n, double v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void k_add(const double* a, const double* b, double* out, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = a[i] + b[i];
+}
+
+hipError_t fill(double* p, int64_t n, double v, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+ihs_status upload_probs(const Layout& L, PassBuffers& B, hipStream_t st) {
+  if (launch_write_probs(L.probs.data(), L.batch, B.probs, st) != hipSuccess) return IHS_ERR_HIP;
+  hipLaunchKernelGGL(k_zero_status, dim3(1), dim3(64), 0, st, B.status);
+  return hipGetLastError() == hipSuccess ? IHS_OK : IHS_ERR_HIP;
+}
+
+// ---- profiling of the gather pass ----
+struct Profiler {
+  std::mutex mu;
+  bool on = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+} g_prof;
+
+void prof_begin(hipStream_t st, hipEvent_t* a) {
+  *a = nullptr;
+  if (!g_prof.on) return;
+  if (hipEventCreate(a) != hipSuccess) {
+    *a = nullptr;
+    return;
+  }
+  (void)hipEventRecord(*a, st);
+}
+
+void prof_end(hipStream_t st, hipEvent_t a) {
+  if (!a) return;
+  hipEvent_t b;
+  if (hipEventCreate(&b) != hipSuccess) return;
+  (void)hipEventRecord(b, st);
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  g_prof.ev.emplace_back(a, b);
+}
+
+// One sketch pass: sort by the hash of (seed, iter), then gather (with the
+// fused gradient when x != nullptr).
+ihs_status run_pass(const ihs_matrix* A, const Layout& L, const ihs_sketch* sk,
+                    const PassBuffers& B, uint64_t iter, void* SA, int32_t sa_dtype,
+                    int64_t ld_sa, const double* b, const double* x, double* r_out,
+                    hipStream_t st) {
+  SketchPlan P = make_plan(L, sk, B, iter);
+  if (launch_sort(P, st) != hipSuccess) return IHS_ERR_HIP;
+  const double scale = sk->s > 1 ? 1.0 / std::sqrt((double)sk->s) : 1.0;
+  hipEvent_t e0;
+  prof_begin(st, &e0);
+  hipError_t err;
+  if (A->format == IHS_DENSE) {
+    GatherArgs G{};
+    G.A = A->values;
+    G.a_dtype = A->dtype;
+    G.ld = A->ld;
+    G.d = A->d;
+    G.SA = SA;
+    G.sa_dtype = sa_dtype;
+    G.ld_sa = ld_sa;
+    G.scale = scale;
+    G.b = x ? (b ? b : B.bzero) : nullptr;
+    G.x = x;
+    G.gpart = B.gpart;
+    G.fpart = B.fpart;
+    G.r_out = r_out;
+    err = launch_sketch_gather(P, G, st);
+  } else {
+    CsrGatherArgs G{};
+    G.row_ptr = A->row_ptr;
+    G.col_idx = A->col_idx;
+    G.values = static_cast<const double*>(A->values);
+    G.d = A->d;
+    G.SA = SA;
+    G.sa_dtype = sa_dtype;
+    G.ld_sa = ld_sa;
+    G.scale = scale;
+    G.b = x ? (b ? b : B.bzero) : nullptr;
+    G.x = x;
+    G.gpart = B.gpart;
+    G.fpart = B.fpart;
+    G.r_out = r_out;
+    err = launch_sketch_gather_csr(P, G, st);
+  }
+  prof_end(st, e0);
+  return err == hipSuccess ? IHS_OK : IHS_ERR_HIP;
+}
+
+// Natural-order gradient pass + reduction into B.g / B.f.
+ihs_status run_gradient(const ihs_matrix* A, const Layout& L, const PassBuffers& B,
+                        const double* b, const double* x, double* g, double* f, double* r_out,
+                        DeviceStatus* status, int32_t iter, hipStream_t st) {
+  hipError_t err;
+  const double* bb = b ? b : B.bzero;
+  if (A->format == IHS_DENSE) {
+    err = launch_gradient_rows(B.probs, L.batch, L.total_seg, kSegRows, A->values, A->dtype,
+                               A->ld, A->d, bb, x, B.gpart, B.fpart, r_out, st);
+  } else {
+    err = launch_gradient_rows_csr(B.probs, L.batch, L.total_seg, kSegRows, A->row_ptr,
+                                   A->col_idx, static_cast<const double*>(A->values), A->d, bb,
+                                   x, B.gpart, B.fpart, r_out, st);
+  }
+  if (err != hipSuccess) return IHS_ERR_HIP;
+  if (L.total_seg == 0) {
+    if (fill(g, (int64_t)L.batch * L.d, 0.0, st) != hipSuccess) return IHS_ERR_HIP;
+    if (f && fill(f, L.batch, 0.0, st) != hipSuccess) return IHS_ERR_HIP;
+    return IHS_OK;
+  }
+  err = launch_reduce_partials(B.gpart, B.fpart, L.batch, 0, B.probs, L.d, g, f, status, iter,
+                               st);
+  return err == hipSuccess ? IHS_OK : IHS_ERR_HIP;
+}
+
+struct SolveBuffers {
+  PassBuffers pass;
+  void* SA = nullptr;
+  double* H = nullptr;
+  void* gram_part = nullptr;
+  double* Lf = nullptr;
+  double* work = nullptr;
+};
+
+int32_t gram_in_of(const ihs_options* o) { return o ? o->gram_in : IHS_F64; }
+int32_t gram_acc_of(const ihs_options* o) { return o ? o->gram_acc : IHS_F64; }
+
+size_t carve_solve(Carver& c, const Layout& L, const ihs_options* o, SolveBuffers& S) {
+  carve_pass(c, L, &o->sketch, S.pass);
+  const int64_t m = o->sketch.m;
+  S.SA = c.take<char>((size_t)(L.batch * m * L.d * dtype_size(gram_in_of(o))));
+  S.H = c.take<double>((size_t)(L.batch * L.d * L.d));
+  S.gram_part = c.take<char>(
+      gram_partials_bytes(m, L.d, L.batch, gram_in_of(o), gram_acc_of(o)));
+  S.Lf = c.take<double>((size_t)(L.batch * L.d * L.d));
+  S.work = c.take<double>((size_t)L.batch * qp_work_doubles(L.d, o->constraint));
+  return c.used;
+}
+
+bool valid_gram_types(int32_t in, int32_t acc) {
+  if (in == IHS_F64) return acc == IHS_F64;
+  if (in == IHS_F32) return acc == IHS_F64 || acc == IHS_F32;
+  if (in == IHS_BF16) return acc == IHS_F32;
+  return false;
+}
+
+ihs_status check_options(const ihs_options* o, bool need_loop) {
+  if (!o) return IHS_ERR_INVALID_ARG;
+  ihs_status s = check_sketch(&o->sketch);
+  if (s != IHS_OK) return s;
+  if (o->constraint < IHS_UNCONSTRAINED || o->constraint > IHS_L2_BALL) return IHS_ERR_INVALID_ARG;
+  if (o->constraint != IHS_UNCONSTRAINED && !(o->radius > 0.0)) return IHS_ERR_INVALID_ARG;
+  if (need_loop && o->max_iter < 1) return IHS_ERR_INVALID_ARG;
+  if (!valid_gram_types(o->gram_in, o->gram_acc)) return IHS_ERR_INVALID_ARG;
+  if (o->tol < 0.0 || o->qp_tol < 0.0 || o->qp_max_inner < 0) return IHS_ERR_INVALID_ARG;
+  return IHS_OK;
+}
+
+ihs_status read_status(DeviceStatus* dev, DeviceStatus* host, hipStream_t st) {
+  if (hipMemcpyAsync(host, dev, sizeof(DeviceStatus), hipMemcpyDeviceToHost, st) != hipSuccess)
+    return IHS_ERR_HIP;
+  if (hipStreamSynchronize(st) != hipSuccess) return IHS_ERR_HIP;
+  return IHS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ihs_status_string(int32_t status) {
+  switch (status) {
+    case IHS_OK: return "ok";
+    case IHS_ERR_INVALID_ARG: return "invalid argument";
+    case IHS_ERR_UNSUPPORTED: return "unsupported configuration";
+    case IHS_ERR_WORKSPACE: return "workspace too small";
+    case IHS_ERR_HIP: return "HIP runtime error";
+    case IHS_ERR_NOT_PD: return "Hessian sketch not positive definite";
+    case IHS_ERR_NOT_CONVERGED: return "inner QP iteration did not converge";
+    case IHS_ERR_NONFINITE: return "non-finite objective or iterate";
+    default: return "unknown status";
+  }
+}
+
+ihs_status ihs_sketch_hash(const ihs_sketch* sk, int64_t n, int32_t problem, int32_t* bucket,
+                           int8_t* sign, hipStream_t stream) {
+  if (!valid_sketch(sk) || n < 0 || problem < 0) return IHS_ERR_INVALID_ARG;
+  if (n > 0 && (!bucket || !sign)) return IHS_ERR_INVALID_ARG;
+  if (n * (int64_t)sk->s >= (int64_t(1) << 31)) return IHS_ERR_UNSUPPORTED;
+  SketchPlan P{};
+  P.s = sk->s;
+  P.m = sk->m;
+  P.m_blk = sk->m / sk->s;
+  P.seed = sk->seed;
+  P.iter = sk->iter;
+  return launch_sketch_hash(P, n, problem, bucket, sign, stream) == hipSuccess ? IHS_OK
+                                                                              : IHS_ERR_HIP;
+}
+
+size_t ihs_workspace_size(const ihs_matrix* A, const ihs_options* opt) {
+  if (check_matrix(A) != IHS_OK || !opt || check_sketch(&opt->sketch) != IHS_OK) return 0;
+  if (!valid_gram_types(opt->gram_in, opt->gram_acc)) return 0;
+  const Layout L = make_layout(A, opt->sketch.m);
+  Carver c(nullptr);
+  SolveBuffers S;
+  return carve_solve(c, L, opt, S) + 256;
+}
+
+ihs_status ihs_sketch_apply(const ihs_sketch* sk, const ihs_matrix* A, void* SA,
+                            int32_t sa_dtype, int64_t ld_sa, void* ws, size_t ws_bytes,
+                            hipStream_t stream) {
+  ihs_status s = check_matrix(A);
+  if (s != IHS_OK) return s;
+  if ((s = check_sketch(sk)) != IHS_OK) return s;
+  if (!SA || ld_sa < A->d) return IHS_ERR_INVALID_ARG;
+  if (sa_dtype != IHS_F64 && sa_dtype != IHS_F32 && sa_dtype != IHS_BF16) return IHS_ERR_INVALID_ARG;
+  if (A->n * (int64_t)sk->s >= (int64_t(1) << 31)) return IHS_ERR_UNSUPPORTED;
+  if (!ws) return IHS_ERR_INVALID_ARG;
+  const Layout L = make_layout(A, sk->m);
+  Carver need(nullptr);
+  PassBuffers tmp;
+  carve_pass(need, L, sk, tmp);
+  if (ws_bytes < need.used) return IHS_ERR_WORKSPACE;
+  Carver c(ws);
+  PassBuffers B;
+  carve_pass(c, L, sk, B);
+  if ((s = upload_probs(L, B, stream)) != IHS_OK) return s;
+  return run_pass(A, L, sk, B, sk->iter, SA, sa_dtype, ld_sa, nullptr, nullptr, nullptr, stream);
+}
+
+ihs_status ihs_sketch_adjoint(const ihs_sketch* sk, int64_t n, int64_t d, int32_t batch,
+                              const int64_t* row_offsets, const double* G, int64_t ld_g,
+                              double* out, int64_t ld_out, hipStream_t stream) {
+  ihs_status s = check_sketch(sk);
+  if (s != IHS_OK) return s;
+  if (n < 0 || d < 1 || batch < 1 || ld_g < d || ld_out < d) return IHS_ERR_INVALID_ARG;
+  if (n > 0 && (!G || !out)) return IHS_ERR_INVALID_ARG;
+  if (batch > 1) {
+    if (!row_offsets || row_offsets[0] != 0 || row_offsets[batch] != n) return IHS_ERR_INVALID_ARG;
+    for (int32_t p = 0; p < batch; ++p)
+      if (row_offsets[p + 1] < row_offsets[p]) return IHS_ERR_INVALID_ARG;
+  }
+  if (n >= (int64_t(1) << 31)) return IHS_ERR_UNSUPPORTED;
+  for (int32_t p = 0; p < batch; ++p) {
+    const int64_t r0 = batch > 1 ? row_offsets[p] : 0;
+    const int64_t r1 = batch > 1 ? row_offsets[p + 1] : n;
+    if (r1 == r0) continue;
+    SketchPlan P{};
+    P.s = sk->s;
+    P.m = sk->m;
+    P.m_blk = sk->m / sk->s;
+    P.seed = sk->seed;
+    P.iter = sk->iter;
+    if (launch_sketch_adjoint(P, G + (int64_t)p * sk->m * ld_g, ld_g, d, out + r0 * ld_out,
+                              ld_out, r1 - r0, p, stream) != hipSuccess)
+      return IHS_ERR_HIP;
+  }
+  return IHS_OK;
+}
+
+size_t ihs_gram_workspace_size(int64_t m, int64_t d, int32_t batch, int32_t in_dtype,
+                               int32_t acc_dtype) {
+  if (m < 1 || d < 1 || batch < 1 || !valid_gram_types(in_dtype, acc_dtype)) return 0;
+  return gram_partials_bytes(m, d, batch, in_dtype, acc_dtype) + 256;
+}
+
+ihs_status ihs_gram(const void* SA, int32_t in_dtype, int64_t m, int64_t d, int64_t ld,
+                    int32_t batch, int32_t acc_dtype, double* H, void* ws, size_t ws_bytes,
+                    hipStream_t stream) {
+  if (!SA || !H || !ws || m < 1 || d < 1 || batch < 1 || ld < d) return IHS_ERR_INVALID_ARG;
+  if (!valid_gram_types(in_dtype, acc_dtype)) return IHS_ERR_INVALID_ARG;
+  if (ws_bytes < gram_partials_bytes(m, d, batch, in_dtype, acc_dtype)) return IHS_ERR_WORKSPACE;
+  return launch_gram(SA, in_dtype, m, d, ld, batch, acc_dtype, H, ws, stream) == hipSuccess
+             ? IHS_OK
+             : IHS_ERR_HIP;
+}
+
+ihs_status ihs_gradient(const ihs_matrix* A, const double* b, const double* x, double* g,
+                        double* r, double* f, void* ws, size_t ws_bytes, hipStream_t stream) {
+  ihs_status s = check_matrix(A);
+  if (s != IHS_OK) return s;
+  if (!b || !x || !g || !ws) return IHS_ERR_INVALID_ARG;
+  const Layout L = make_layout(A, 1);
+  Carver need(nullptr);
+  PassBuffers tmp;
+  carve_pass(need, L, nullptr, tmp);
+  if (ws_bytes < need.used) return IHS_ERR_WORKSPACE;
+  Carver c(ws);
+  PassBuffers B;
+  carve_pass(c, L, nullptr, B);
+  if ((s = upload_probs(L, B, stream)) != IHS_OK) return s;
+  return run_gradient(A, L, B, b, x, g, f, r, nullptr, 0, stream);
+}
+
+size_t ihs_qp_workspace_size(int64_t d, int32_t batch, const ihs_options* opt) {
+  if (d < 1 || batch < 1 || !opt) return 0;
+  Carver c(nullptr);
+  c.take<DeviceStatus>(1);
+  c.take<double>((size_t)(batch * d * d));
+  c.take<double>((size_t)batch * qp_work_doubles(d, opt->constraint));
+  return c.used + 256;
+}
+
+ihs_status ihs_qp_step(int64_t d, int32_t batch, const double* H, const double* g,
+                       const double* x, double* x_out, const ihs_options* opt, void* ws,
+                       size_t ws_bytes, hipStream_t stream) {
+  if (d < 1 || batch < 1 || !H || !g || !x || !x_out || !opt || !ws) return IHS_ERR_INVALID_ARG;
+  if (opt->constraint < IHS_UNCONSTRAINED || opt->constraint > IHS_L2_BALL) return IHS_ERR_INVALID_ARG;
+  if (opt->constraint != IHS_UNCONSTRAINED && !(opt->radius > 0.0)) return IHS_ERR_INVALID_ARG;
+  if (ws_bytes < ihs_qp_workspace_size(d, batch, opt) - 256) return IHS_ERR_WORKSPACE;
+  Carver c(ws);
+  DeviceStatus* st = c.take<DeviceStatus>(1);
+  double* Lf = c.take<double>((size_t)(batch * d * d));
+  double* work = c.take<double>((size_t)batch * qp_work_doubles(d, opt->constraint));
+  hipLaunchKernelGGL(k_zero_status, dim3(1), dim3(64), 0, stream, st);
+  QpArgs a{};
+  a.d = d;
+  a.batch = batch;
+  a.constraint = opt->constraint;
+  a.radius = opt->radius;
+  a.max_inner = opt->qp_max_inner;
+  a.tol = opt->qp_tol;
+  a.H = H;
+  a.g = g;
+  a.x = x;
+  a.x_out = x_out;
+  a.L = Lf;
+  a.work = work;
+  a.status = st;
+  a.iter = 0;
+  const hipError_t e = launch_qp_step(a, stream);
+  if (e == hipErrorNotSupported) return IHS_ERR_UNSUPPORTED;
+  if (e != hipSuccess) return IHS_ERR_HIP;
+  DeviceStatus host;
+  if (read_status(st, &host, stream) != IHS_OK) return IHS_ERR_HIP;
+  return (ihs_status)host.code;
+}
+
+ihs_status ihs_solve(const ihs_matrix* A, const double* b, const ihs_options* opt, double* x,
+                     double* x_hist, double* factors, ihs_report* rep, void* ws,
+                     size_t ws_bytes, hipStream_t stream) {
+  ihs_status s = check_matrix(A);
+  if (s != IHS_OK) return s;
+  if ((s = check_options(opt, true)) != IHS_OK) return s;
+  if (!b || !x || !ws) return IHS_ERR_INVALID_ARG;
+  if (factors && (!opt->keep_factors || opt->constraint != IHS_UNCONSTRAINED))
+    return IHS_ERR_INVALID_ARG;
+  if (A->n * (int64_t)opt->sketch.s >= (int64_t(1) << 31)) return IHS_ERR_UNSUPPORTED;
+  if (A->format == IHS_CSR && opt->gram_in != IHS_F64 && opt->gram_in != IHS_F32 &&
+      opt->gram_in != IHS_BF16)
+    return IHS_ERR_INVALID_ARG;
+  const Layout L = make_layout(A, opt->sketch.m);
+  Carver need(nullptr);
+  SolveBuffers tmp;
+  carve_solve(need, L, opt, tmp);
+  if (ws_bytes < need.used) return IHS_ERR_WORKSPACE;
+  Carver c(ws);
+  SolveBuffers S;
+  carve_solve(c, L, opt, S);
+  PassBuffers& B = S.pass;
+  if ((s = upload_probs(L, B, stream)) != IHS_OK) return s;
+  const int64_t d = A->d, m = opt->sketch.m;
+  const int64_t m_blk = m / opt->sketch.s;
+  const int64_t bd = (int64_t)L.batch * d;
+  for (int32_t t = 0; t < opt->max_iter; ++t) {
+    const uint64_t iter = opt->sketch.iter + (uint64_t)t;
+    s = run_pass(A, L, &opt->sketch, B, iter, S.SA, opt->gram_in, d, b, x, nullptr, stream);
+    if (s != IHS_OK) return s;
+    if (launch_reduce_partials(B.gpart, B.fpart, L.batch, m_blk, B.probs, d, B.g, B.f, B.status,
+                               t, stream) != hipSuccess)
+      return IHS_ERR_HIP;
+    if (launch_gram(S.SA, opt->gram_in, m, d, d, L.batch, opt->gram_acc, S.H, S.gram_part,
+                    stream) != hipSuccess)
+      return IHS_ERR_HIP;
+    QpArgs a{};
+    a.d = d;
+    a.batch = L.batch;
+    a.constraint = opt->constraint;
+    a.radius = opt->radius;
+    a.max_inner = opt->qp_max_inner;
+    a.tol = opt->qp_tol;
+    a.H = S.H;
+    a.g = B.g;
+    a.x = x;
+    a.x_out = x;
+    a.L = factors ? factors + (int64_t)t * L.batch * d * d : S.Lf;
+    a.work = S.work;
+    a.status = B.status;
+    a.iter = t;
+    const hipError_t e = launch_qp_step(a, stream);
+    if (e == hipErrorNotSupported) return IHS_ERR_UNSUPPORTED;
+    if (e != hipSuccess) return IHS_ERR_HIP;
+    if (x_hist && hipMemcpyAsync(x_hist + (int64_t)t * bd, x, bd * sizeof(double),
+                                 hipMemcpyDeviceToDevice, stream) != hipSuccess)
+      return IHS_ERR_HIP;
+  }
+  DeviceStatus host;
+  if (read_status(B.status, &host, stream) != IHS_OK) return IHS_ERR_HIP;
+  if (rep) {
+    rep->status = host.code;
+    rep->failed_iter = host.code ? host.failed_iter : -1;
+    rep->failed_problem = host.code ? host.failed_problem : -1;
+    rep->iters = host.code ? std::max(0, host.failed_iter) : opt->max_iter;
+    rep->objective = host.objective;
+    rep->last_step = host.last_step;
+  }
+  return (ihs_status)host.code;
+}
+
+ihs_status ihs_adjoint_solve(const ihs_matrix* A, const double* xbar, const double* factors,
+                             int32_t n_factors, double* lambda, void* ws, size_t ws_bytes,
+                             hipStream_t stream) {
+  ihs_status s = check_matrix(A);
+  if (s != IHS_OK) return s;
+  if (!xbar || !factors || !lambda || !ws || n_factors < 1) return IHS_ERR_INVALID_ARG;
+  if (A->format != IHS_DENSE) return IHS_ERR_UNSUPPORTED;
+  const Layout L = make_layout(A, 1);
+  Carver need(nullptr);
+  PassBuffers tmp;
+  carve_pass(need, L, nullptr, tmp);
+  need.take<double>((size_t)(2 * L.batch * A->d));
+  if (ws_bytes < need.used) return IHS_ERR_WORKSPACE;
+  Carver c(ws);
+  PassBuffers B;
+  carve_pass(c, L, nullptr, B);
+  double* v = c.take<double>((size_t)(L.batch * A->d));
+  if ((s = upload_probs(L, B, stream)) != IHS_OK) return s;
+  const int64_t bd = (int64_t)L.batch * A->d;
+  if (fill(B.bzero, A->n, 0.0, stream) != hipSuccess) return IHS_ERR_HIP;
+  if (fill(lambda, bd, 0.0, stream) != hipSuccess) return IHS_ERR_HIP;
+  for (int32_t k = 0; k < n_factors; ++k) {
+    // v = xbar - A^T A lambda = xbar + A^T (0 - A lambda)
+    if ((s = run_gradient(A, L, B, B.bzero, lambda, B.g, nullptr, nullptr, B.status, k,
+                          stream)) != IHS_OK)
+      return s;
+    hipLaunchKernelGGL(k_add, dim3((unsigned)((bd + 255) / 256)), dim3(256), 0, stream, xbar,
+                       B.g, v, bd);
+    if (launch_chol_solve_update(factors + (int64_t)k * L.batch * A->d * A->d, A->d, L.batch, v,
+                                 lambda, lambda, B.status, stream) != hipSuccess)
+      return IHS_ERR_HIP;
+  }
+  return hipGetLastError() == hipSuccess ? IHS_OK : IHS_ERR_HIP;
+}
+
+ihs_status ihs_solution_grads(const ihs_matrix* A, const double* b, const double* x,
+                              const double* lambda, double* dl_db, double* dl_da,
+                              int64_t ld_da, hipStream_t stream) {
+  ihs_status s = check_matrix(A);
+  if (s != IHS_OK) return s;
+  if (A->format != IHS_DENSE || A->dtype != IHS_F64) return IHS_ERR_UNSUPPORTED;
+  if (!b || !x || !lambda) return IHS_ERR_INVALID_ARG;
+  if (dl_da && ld_da < A->d) return IHS_ERR_INVALID_ARG;
+  const Layout L = make_layout(A, 1);
+  // per-row problem index comes from the row offsets; pass them as a small
+  // device table through the per-problem launches
+  for (int32_t p = 0; p < L.batch; ++p) {
+    const ProbInfo& q = L.probs[p];
+    if (q.rows == 0) continue;
+    if (launch_solution_grads(nullptr, 1, q.rows, A->d,
+                              static_cast<const double*>(A->values) + q.row0 * A->ld, A->ld,
+                              b + q.row0, x + (int64_t)p * A->d, lambda + (int64_t)p * A->d,
+                              dl_db ? dl_db + q.row0 : nullptr,
+                              dl_da ? dl_da + q.row0 * ld_da : nullptr, ld_da,
+                              stream) != hipSuccess)
+      return IHS_ERR_HIP;
+  }
+  return IHS_OK;
+}
+
+void ihs_profile_enable(int32_t on) {
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  for (auto& e : g_prof.ev) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  g_prof.ev.clear();
+  g_prof.on = on != 0;
+}
+
+ihs_status ihs_profile_read(int64_t* launches, double* total_ms) {
+  if (!launches || !total_ms) return IHS_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  double tot = 0.0;
+  for (auto& e : g_prof.ev) {
+    if (hipEventSynchronize(e.second) != hipSuccess) return IHS_ERR_HIP;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, e.first, e.second) != hipSuccess) return IHS_ERR_HIP;
+    tot += ms;
+  }
+  *launches = (int64_t)g_prof.ev.size();
+  *total_ms = tot;
+  return IHS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,170 @@
+// Internal launch interface between the C-ABI host code and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "common.hpp"
+
+namespace ihs {
+
+// Row-range and sort-tile layout of one problem of a (possibly ragged) batch.
+struct ProbInfo {
+  int64_t row0;     // first global row
+  int64_t rows;     // number of rows
+  int32_t tile0;    // first sort tile
+  int32_t ntiles;
+  int32_t chunk0;   // first scan chunk
+  int32_t nchunks;
+  int32_t seg0;     // first row segment of the natural-order passes
+  int32_t nseg;
+};
+
+// Up to kProbChunk table entries travel by value in one kernel argument.
+constexpr int32_t kProbChunk = 48;
+struct ProbChunk {
+  int32_t first;
+  int32_t count;
+  ProbInfo p[kProbChunk];
+};
+hipError_t launch_write_probs(const ProbInfo* host, int32_t batch, ProbInfo* dst,
+                              hipStream_t st);
+
+// Everything the sort and gather kernels need about the sketch of one pass.
+struct SketchPlan {
+  const ProbInfo* probs;   // device, batch entries
+  int32_t batch;
+  int32_t s;               // blocks
+  int64_t m;               // sketch rows per problem
+  int64_t m_blk;           // m / s
+  uint64_t seed;
+  uint64_t iter;
+  int32_t tile_rows;       // rows per sort tile
+  int32_t tiles_per_chunk;
+  int32_t total_tiles;
+  int32_t total_chunks;
+  int32_t bucket_bits;     // ceil(log2(m))
+  int64_t entries;         // n * s
+  // workspace arrays
+  uint32_t* keys;          // entries: bucket | sign << 31, at row*s + k
+  int32_t* tile_count;     // total_tiles * m
+  int32_t* chunk_part;     // total_chunks * m
+  int32_t* bucket_start;   // batch*m + 1
+  uint32_t* perm;          // entries: global row | sign << 31, bucket-sorted
+};
+
+hipError_t launch_sketch_hash(const SketchPlan& p, int64_t n, int32_t problem,
+                              int32_t* bucket, int8_t* sign, hipStream_t st);
+hipError_t launch_sort(const SketchPlan& p, hipStream_t st);
+
+struct GatherArgs {
+  const void* A;           // dense rows
+  int32_t a_dtype;         // 0 f64, 1 f32
+  int64_t ld;
+  int64_t d;
+  void* SA;                // (batch*m) x d, ld_sa
+  int32_t sa_dtype;        // 0 f64, 1 f32, 2 bf16
+  int64_t ld_sa;
+  double scale;            // 1/sqrt(s) for s > 1, else 1
+  // fused gradient (nullable b => no gradient)
+  const double* b;
+  const double* x;         // batch x d
+  double* gpart;           // batch * m_blk * d
+  double* fpart;           // batch * m_blk
+  double* r_out;           // n, nullable
+};
+hipError_t launch_sketch_gather(const SketchPlan& p, const GatherArgs& g, hipStream_t st);
+
+// CSR counterpart of the gather (values f64).
+struct CsrGatherArgs {
+  const int32_t* row_ptr;
+  const int32_t* col_idx;
+  const double* values;
+  int64_t d;
+  void* SA;
+  int32_t sa_dtype;
+  int64_t ld_sa;
+  double scale;
+  const double* b;
+  const double* x;
+  double* gpart;           // batch * m_blk * d
+  double* fpart;
+  double* r_out;
+};
+hipError_t launch_sketch_gather_csr(const SketchPlan& p, const CsrGatherArgs& g,
+                                    hipStream_t st);
+
+// Natural-order gradient pass over dense rows: segments of seg_rows rows.
+hipError_t launch_gradient_rows(const ProbInfo* probs, int32_t batch, int32_t total_seg,
+                                int32_t seg_rows, const void* A, int32_t a_dtype,
+                                int64_t ld, int64_t d, const double* b, const double* x,
+                                double* gpart, double* fpart, double* r_out,
+                                hipStream_t st);
+hipError_t launch_gradient_rows_csr(const ProbInfo* probs, int32_t batch,
+                                    int32_t total_seg, int32_t seg_rows,
+                                    const int32_t* row_ptr, const int32_t* col_idx,
+                                    const double* values, int64_t d, const double* b,
+                                    const double* x, double* gpart, double* fpart,
+                                    double* r_out, hipStream_t st);
+
+// g[p][:] = sum over parts w (ascending, fixed tree) of gpart[p][w][:];
+// parts_of(p) = nparts_fixed if > 0, else probs[p].nseg (natural-order passes).
+hipError_t launch_reduce_partials(const double* gpart, const double* fpart,
+                                  int32_t batch, int64_t parts_fixed,
+                                  const ProbInfo* probs, int64_t d, double* g,
+                                  double* f, DeviceStatus* status, int32_t iter,
+                                  hipStream_t st);
+
+// Gram H = SA^T SA.
+size_t gram_partials_bytes(int64_t m, int64_t d, int32_t batch, int32_t in_dtype,
+                           int32_t acc_dtype);
+hipError_t launch_gram(const void* SA, int32_t in_dtype, int64_t m, int64_t d,
+                       int64_t ld, int32_t batch, int32_t acc_dtype, double* H,
+                       void* partials, hipStream_t st);
+
+// QP step kernels.
+struct QpArgs {
+  int64_t d;
+  int32_t batch;
+  int32_t constraint;
+  double radius;
+  int32_t max_inner;
+  double tol;
+  const double* H;         // batch x d x d
+  const double* g;         // batch x d
+  const double* x;         // batch x d
+  double* x_out;           // batch x d (may alias x)
+  double* L;               // batch x d x d factor workspace / output
+  double* work;            // batch x qp_work_doubles(d)
+  DeviceStatus* status;
+  int32_t iter;
+  double* x_hist;          // nullable: batch x d copy of x_out
+  int32_t respect_done;    // skip when status->done is set
+  double tol_stop;         // early-stop threshold on sqrt(dx^T H dx)/sqrt(x^T H x)
+};
+size_t qp_work_doubles(int64_t d, int32_t constraint);
+hipError_t launch_qp_step(const QpArgs& a, hipStream_t st);
+
+// Cholesky alone (lower factor of each H into L) and the two triangular
+// solves applied to a right-hand side: out = in + (L L^T)^{-1} v.
+// dside: batch * 64 * 64 doubles of scratch (blocked path only).
+hipError_t launch_cholesky(const double* H, double* L, int64_t d, int32_t batch,
+                           DeviceStatus* status, int32_t iter, double shift, double* dside,
+                           hipStream_t st);
+hipError_t launch_chol_solve_update(const double* L, int64_t d, int32_t batch,
+                                    const double* v, const double* base, double* out,
+                                    DeviceStatus* status, hipStream_t st);
+
+// Adjoint and solution-gradient passes.
+// S^T G for the nrows rows of one problem (G points at that problem's m rows).
+hipError_t launch_sketch_adjoint(const SketchPlan& p, const double* G, int64_t ld_g,
+                                 int64_t d, double* out, int64_t ld_out, int64_t nrows,
+                                 int32_t problem, hipStream_t st);
+hipError_t launch_solution_grads(const ProbInfo* probs, int32_t batch, int64_t n,
+                                 int64_t d, const double* A, int64_t ld,
+                                 const double* b, const double* x,
+                                 const double* lambda, double* dl_db, double* dl_da,
+                                 int64_t ld_da, hipStream_t st);
+
+}  // namespace ihs

@@ -1,0 +1,419 @@
+// The small d x d quadratic program of Eq.(2) (Sec. 1: T_solve = O(d^3);
+// App. A.1.1, "Solving the QP takes poly(d)") and the fixed-order reduction of
+// the gradient partials produced by the row passes.
+//
+// Unconstrained step: x^{t+1} = x^t + H^{-1} g with H = L L^T.
+//  * d <= 88: one workgroup per problem factors H in LDS.
+//  * d  > 88: right-looking blocked Cholesky, 64-column panels. A panel
+//    launch factors the 64 x 64 diagonal block in LDS (every workgroup of the
+//    launch redundantly, so no inter-workgroup wait is needed) and solves its
+//    share of the panel rows; an update launch subtracts P P^T from the
+//    trailing lower triangle with FP64 matrix-core tiles.
+//  * Triangular solves: one workgroup; each 64-block is solved by one
+//    wavefront with lane shuffles, the rest of the vector is updated by all.
+#include <algorithm>
+
+#include "kernels.hpp"
+
+namespace ihs {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kSmallChol = 88;  // d*d doubles within 64 KiB of LDS
+constexpr int kNb = 64;
+
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// ---------------------------------------------------------------------------
+// Gradient partial reduction: g[p][:] = sum_w gpart[p][w][:] in a fixed tree.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_reduce_partials(const double* __restrict__ gpart,
+                                                          const double* __restrict__ fpart,
+                                                          int32_t batch, int64_t parts_fixed,
+                                                          const ProbInfo* probs, int64_t d,
+                                                          double* g, double* f,
+                                                          DeviceStatus* st, int32_t iter) {
+  __shared__ double red[16][64];
+  __shared__ double fred[1024];
+  const int p = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, grp = tid >> 6;
+  const int64_t nparts = parts_fixed > 0 ? parts_fixed : (int64_t)probs[p].nseg;
+  const int64_t pbase = parts_fixed > 0 ? (int64_t)p * parts_fixed : (int64_t)probs[p].seg0;
+  const int64_t col = (int64_t)blockIdx.y * 64 + lane;
+  const int64_t per = (nparts + 15) / 16;
+  const int64_t w0 = min((int64_t)grp * per, nparts), w1 = min(w0 + per, nparts);
+  double s = 0.0;
+  if (col < d)
+    for (int64_t w = w0; w < w1; ++w) s += gpart[(pbase + w) * d + col];
+  red[grp][lane] = s;
+  if (blockIdx.y == 0) {
+    double fs = 0.0;
+    const int64_t fper = (nparts + 1023) / 1024;
+    const int64_t f0 = min((int64_t)tid * fper, nparts), f1 = min(f0 + fper, nparts);
+    for (int64_t w = f0; w < f1; ++w) fs += fpart[pbase + w];
+    fred[tid] = fs;
+  }
+  __syncthreads();
+  if (grp == 0 && col < d) {
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) t += red[q][lane];
+    g[(int64_t)p * d + col] = t;
+  }
+  if (blockIdx.y == 0) {
+    for (int stride = 512; stride > 0; stride >>= 1) {
+      __syncthreads();
+      if (tid < stride) fred[tid] = fred[tid] + fred[tid + stride];
+    }
+    if (tid == 0) {
+      const double fv = 0.5 * fred[0];
+      if (f != nullptr) f[p] = fv;
+      if (st != nullptr) {
+        if (p == 0) st->objective = fv;
+        if (!isfinite(fv)) status_fail(st, 7 /* IHS_ERR_NONFINITE */, iter, p);
+      }
+    }
+  }
+}
+
+hipError_t launch_reduce_partials(const double* gpart, const double* fpart, int32_t batch,
+                                  int64_t parts_fixed, const ProbInfo* probs, int64_t d,
+                                  double* g, double* f, DeviceStatus* status, int32_t iter,
+                                  hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce_partials, dim3(batch, (unsigned)((d + 63) / 64)), dim3(1024), 0,
+                     st, gpart, fpart, batch, parts_fixed, probs, d, g, f, status, iter);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Small Cholesky in LDS: one workgroup (256 threads) per problem.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_chol_small(const double* __restrict__ H, double* L,
+                                                    int64_t d, DeviceStatus* st, int32_t iter,
+                                                    double shift) {
+  extern __shared__ double a[];
+  __shared__ int fail;
+  const int p = blockIdx.x;
+  if (threadIdx.x == 0) fail = st->code;
+  __syncthreads();
+  if (fail != 0) return;  // one read per workgroup keeps the exit uniform
+  const double* Hp = H + (int64_t)p * d * d;
+  double* Lp = L + (int64_t)p * d * d;
+  const int tid = threadIdx.x;
+  for (int64_t e = tid; e < d * d; e += 256) {
+    const int64_t i = e / d, j = e - (e / d) * d;
+    a[e] = (j <= i) ? Hp[e] + (i == j ? shift : 0.0) : 0.0;
+  }
+  __syncthreads();
+  for (int64_t j = 0; j < d; ++j) {
+    const double piv = a[j * d + j];
+    const bool bad = !(piv > 0.0) || !isfinite(piv);
+    if (bad) {
+      if (tid == 0) {
+        fail = 1;
+        status_fail(st, 5 /* IHS_ERR_NOT_PD */, iter, p);
+      }
+      break;
+    }
+    const double ljj = sqrt(piv);
+    __syncthreads();
+    if (tid == 0) a[j * d + j] = ljj;
+    for (int64_t i = j + 1 + tid; i < d; i += 256) a[i * d + j] = a[i * d + j] / ljj;
+    __syncthreads();
+    const int64_t w = d - j - 1;
+    for (int64_t e = tid; e < w * w; e += 256) {
+      const int64_t i = j + 1 + e / w, k = j + 1 + (e - (e / w) * w);
+      if (k <= i) a[i * d + k] = fma(-a[i * d + j], a[k * d + j], a[i * d + k]);
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+  if (fail) return;
+  for (int64_t e = tid; e < d * d; e += 256) Lp[e] = a[e];
+}
+
+// ---------------------------------------------------------------------------
+// Blocked Cholesky for larger d, in place on L (lower triangle).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_chol_init(const double* __restrict__ H, double* L,
+                                                   int64_t d, int32_t batch, double shift) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= (int64_t)batch * d * d) return;
+  const int64_t e = idx % (d * d);
+  const int64_t i = e / d, j = e - (e / d) * d;
+  L[idx] = (j <= i) ? H[idx] + (i == j ? shift : 0.0) : 0.0;
+}
+
+// Every workgroup of a panel launch reads the unfactored diagonal block and
+// factors it in LDS; nobody writes that block during the launch (workgroup 0
+// leaves the factor in `dside`, and the update launch copies it back).
+__global__ __launch_bounds__(256) void k_chol_panel(double* L, int64_t d, int64_t kb,
+                                                    double* dside, DeviceStatus* st,
+                                                    int32_t iter) {
+  __shared__ double D[kNb][kNb + 1];
+  __shared__ int fail;
+  const int p = blockIdx.y;
+  if (threadIdx.x == 0) fail = st->code;
+  __syncthreads();
+  if (fail != 0) return;
+  double* W = L + (int64_t)p * d * d;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int nb = (int)min((int64_t)kNb, d - kb);
+  for (int e = tid; e < kNb * kNb; e += 256) {
+    const int i = e / kNb, j = e % kNb;
+    D[i][j] = (i < nb && j <= i) ? W[(kb + i) * d + kb + j] : 0.0;
+  }
+  __syncthreads();
+  if (wv == 0) {
+    for (int j = 0; j < nb; ++j) {
+      const double piv = D[j][j];
+      if (!(piv > 0.0) || !isfinite(piv)) {
+        if (lane == 0) {
+          fail = 1;
+          if (blockIdx.x == 0) status_fail(st, 5 /* IHS_ERR_NOT_PD */, iter, p);
+        }
+        break;
+      }
+      const double ljj = sqrt(piv);
+      wave_sync_lds();
+      if (lane == j) D[j][j] = ljj;
+      if (lane > j && lane < nb) D[lane][j] = D[lane][j] / ljj;
+      wave_sync_lds();
+      if (lane > j && lane < nb) {
+        const double lij = D[lane][j];
+        for (int k = j + 1; k <= lane; ++k) D[lane][k] = fma(-lij, D[k][j], D[lane][k]);
+      }
+      wave_sync_lds();
+    }
+  }
+  __syncthreads();
+  if (fail) return;
+  if (blockIdx.x == 0) {
+    double* ds = dside + (int64_t)p * kNb * kNb;
+    for (int e = tid; e < kNb * kNb; e += 256) ds[e] = D[e / kNb][e % kNb];
+  }
+  // panel rows below the diagonal block: x L_kk^T = a
+  const int64_t row = kb + nb + (int64_t)blockIdx.x * 256 + tid;
+  if (row >= d) return;
+  double x[kNb];
+  double* wr = W + row * d + kb;
+#pragma unroll
+  for (int c = 0; c < kNb; ++c) x[c] = (c < nb) ? wr[c] : 0.0;
+#pragma unroll
+  for (int c = 0; c < kNb; ++c) {
+    if (c < nb) {
+      double s = x[c];
+#pragma unroll
+      for (int k = 0; k < c; ++k) s = fma(-x[k], D[c][k], s);
+      x[c] = s / D[c][c];
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < kNb; ++c)
+    if (c < nb) wr[c] = x[c];
+}
+
+// Trailing update W[i][j] -= sum_k P[i][k] P[j][k], kb+64 <= j <= i < d, with
+// P = W[:, kb:kb+64]. One wavefront per 32 x 32 lower tile.
+__global__ __launch_bounds__(256) void k_chol_update(double* L, int64_t d, int64_t kb,
+                                                     int32_t batch, const double* dside,
+                                                     DeviceStatus* st) {
+  if (st->code != 0) return;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (blockIdx.x == 0) {  // the factored diagonal block of this panel
+    const int nb = (int)min((int64_t)kNb, d - kb);
+    for (int64_t e = threadIdx.x; e < (int64_t)batch * kNb * kNb; e += 256) {
+      const int q = (int)(e / (kNb * kNb));
+      const int i = (int)((e / kNb) % kNb), j = (int)(e % kNb);
+      if (i < nb && j <= i) L[(int64_t)q * d * d + (kb + i) * d + kb + j] = dside[e];
+    }
+  }
+  const int64_t t0 = kb + kNb;
+  const int64_t T = (d - t0 + 31) / 32;
+  const int64_t ntri = T * (T + 1) / 2;
+  const int64_t w = (int64_t)blockIdx.x * 4 + wv;
+  if (w >= ntri * batch) return;
+  const int p = (int)(w / ntri);
+  const int64_t t = w - (int64_t)p * ntri;
+  // t -> (ti, tj), tj <= ti, row-major lower triangle
+  int64_t ti = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+  while (ti * (ti + 1) / 2 > t) --ti;
+  while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+  const int64_t tj = t - ti * (ti + 1) / 2;
+  double* W = L + (int64_t)p * d * d;
+  const int64_t r0 = t0 + ti * 32, c0 = t0 + tj * 32;
+  const int r = lane & 15, kk = lane >> 4;
+  f64x4 c00 = {0, 0, 0, 0}, c01 = c00, c10 = c00, c11 = c00;
+  const bool ra0 = r0 + r < d, ra1 = r0 + 16 + r < d;
+  const bool rb0 = c0 + r < d, rb1 = c0 + 16 + r < d;
+#pragma unroll 4
+  for (int k = 0; k < kNb; k += 4) {
+    const int64_t col = kb + k + kk;
+    const double a0 = ra0 ? W[(r0 + r) * d + col] : 0.0;
+    const double a1 = ra1 ? W[(r0 + 16 + r) * d + col] : 0.0;
+    const double b0 = rb0 ? W[(c0 + r) * d + col] : 0.0;
+    const double b1 = rb1 ? W[(c0 + 16 + r) * d + col] : 0.0;
+    c00 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, c00, 0, 0, 0);
+    c01 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, c01, 0, 0, 0);
+    c10 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, c10, 0, 0, 0);
+    c11 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, c11, 0, 0, 0);
+  }
+  const int col = lane & 15, rq = lane >> 4;
+#pragma unroll
+  for (int reg = 0; reg < 4; ++reg) {
+    const int rr = 4 * reg + rq;
+    const double v[4] = {c00[reg], c01[reg], c10[reg], c11[reg]};
+    const int64_t ii[4] = {r0 + rr, r0 + rr, r0 + 16 + rr, r0 + 16 + rr};
+    const int64_t jj[4] = {c0 + col, c0 + 16 + col, c0 + col, c0 + 16 + col};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (ii[q] < d && jj[q] < d && jj[q] <= ii[q]) W[ii[q] * d + jj[q]] -= v[q];
+    }
+  }
+}
+
+hipError_t launch_cholesky(const double* H, double* L, int64_t d, int32_t batch,
+                           DeviceStatus* status, int32_t iter, double shift, double* dside,
+                           hipStream_t st) {
+  if (d <= kSmallChol) {
+    hipLaunchKernelGGL(k_chol_small, dim3(batch), dim3(256), (size_t)(d * d * sizeof(double)),
+                       st, H, L, d, status, iter, shift);
+    return hipGetLastError();
+  }
+  const int64_t tot = (int64_t)batch * d * d;
+  hipLaunchKernelGGL(k_chol_init, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, H, L, d,
+                     batch, shift);
+  for (int64_t kb = 0; kb < d; kb += kNb) {
+    const int64_t below = std::max<int64_t>(0, d - kb - kNb);
+    const unsigned gx = (unsigned)std::max<int64_t>(1, (below + 255) / 256);
+    hipLaunchKernelGGL(k_chol_panel, dim3(gx, batch), dim3(256), 0, st, L, d, kb, dside, status,
+                       iter);
+    const int64_t T = (below + 31) / 32;
+    const int64_t waves = T * (T + 1) / 2 * batch;
+    const unsigned gu = (unsigned)std::max<int64_t>(1, (waves + 3) / 4);
+    hipLaunchKernelGGL(k_chol_update, dim3(gu), dim3(256), 0, st, L, d, kb, batch, dside,
+                       status);
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// out = base + (L L^T)^{-1} v, one workgroup per problem.
+// Also records sqrt(dx^T v) (= sqrt(dx^T H dx) when H dx = v) for problem 0.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_chol_solve(const double* __restrict__ L, int64_t d,
+                                                    const double* __restrict__ v,
+                                                    const double* base, double* out,
+                                                    DeviceStatus* st) {
+  extern __shared__ double y[];
+  __shared__ double red[256];
+  __shared__ int code;
+  const int p = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const double* Lp = L + (int64_t)p * d * d;
+  const double* vp = v + (int64_t)p * d;
+  const double* bp = base + (int64_t)p * d;
+  double* op = out + (int64_t)p * d;
+  if (tid == 0) code = st->code;
+  __syncthreads();
+  if (code != 0) {
+    if (op != bp)
+      for (int64_t i = tid; i < d; i += 256) op[i] = bp[i];
+    return;
+  }
+  for (int64_t i = tid; i < d; i += 256) y[i] = vp[i];
+  __syncthreads();
+  // forward: L y = v
+  for (int64_t jb = 0; jb < d; jb += 64) {
+    const int nb = (int)min((int64_t)64, d - jb);
+    if (wv == 0) {
+      double yl = lane < nb ? y[jb + lane] : 0.0;
+      for (int c = 0; c < nb; ++c) {
+        if (lane == c) yl = yl / Lp[(jb + c) * d + jb + c];
+        const double yc = __shfl(yl, c, 64);
+        if (lane > c && lane < nb) yl = fma(-Lp[(jb + lane) * d + jb + c], yc, yl);
+      }
+      if (lane < nb) y[jb + lane] = yl;
+    }
+    __syncthreads();
+    for (int64_t i = jb + nb + tid; i < d; i += 256) {
+      const double* lr = Lp + i * d + jb;
+      double s = 0.0;
+      for (int c = 0; c < nb; ++c) s = fma(lr[c], y[jb + c], s);
+      y[i] -= s;
+    }
+    __syncthreads();
+  }
+  // backward: L^T z = y
+  const int64_t nblk = (d + 63) / 64;
+  for (int64_t bi = nblk - 1; bi >= 0; --bi) {
+    const int64_t jb = bi * 64;
+    const int nb = (int)min((int64_t)64, d - jb);
+    if (wv == 0) {
+      double yl = lane < nb ? y[jb + lane] : 0.0;
+      for (int c = nb - 1; c >= 0; --c) {
+        if (lane == c) yl = yl / Lp[(jb + c) * d + jb + c];
+        const double yc = __shfl(yl, c, 64);
+        if (lane < c) yl = fma(-Lp[(jb + c) * d + jb + lane], yc, yl);
+      }
+      if (lane < nb) y[jb + lane] = yl;
+    }
+    __syncthreads();
+    for (int64_t i = tid; i < jb; i += 256) {
+      double s = 0.0;
+      for (int c = 0; c < nb; ++c) s = fma(Lp[(jb + c) * d + i], y[jb + c], s);
+      y[i] -= s;
+    }
+    __syncthreads();
+  }
+  double part = 0.0;
+  bool finite = true;
+  for (int64_t i = tid; i < d; i += 256) {
+    const double xi = bp[i] + y[i];
+    part = fma(y[i], vp[i], part);
+    finite = finite && isfinite(xi);
+  }
+  red[tid] = part;
+  const int all_finite = __syncthreads_and(finite ? 1 : 0);
+  for (int stride = 128; stride > 0; stride >>= 1) {
+    if (tid < stride) red[tid] += red[tid + stride];
+    __syncthreads();
+  }
+  if (!all_finite) {
+    if (tid == 0) status_fail(st, 7 /* IHS_ERR_NONFINITE */, -1, p);
+    if (op != bp)
+      for (int64_t i = tid; i < d; i += 256) op[i] = bp[i];
+    return;
+  }
+  for (int64_t i = tid; i < d; i += 256) op[i] = bp[i] + y[i];
+  if (p == 0 && tid == 0) st->last_step = sqrt(fmax(red[0], 0.0));
+}
+
+hipError_t launch_chol_solve_update(const double* L, int64_t d, int32_t batch, const double* v,
+                                    const double* base, double* out, DeviceStatus* status,
+                                    hipStream_t st) {
+  hipLaunchKernelGGL(k_chol_solve, dim3(batch), dim3(256), (size_t)(d * sizeof(double)), st, L,
+                     d, v, base, out, status);
+  return hipGetLastError();
+}
+
+// Per-problem scratch of the QP kernels: the 64 x 64 diagonal-block side
+// buffer of the blocked Cholesky plus vectors.
+size_t qp_work_doubles(int64_t d, int32_t constraint) {
+  (void)constraint;
+  return (size_t)(kNb * kNb + 8 * d + 64);
+}
+
+hipError_t launch_qp_step(const QpArgs& a, hipStream_t st) {
+  if (a.constraint != 0) return hipErrorNotSupported;
+  hipError_t e = launch_cholesky(a.H, a.L, a.d, a.batch, a.status, a.iter, 0.0,
+                                 a.work, st);
+  if (e != hipSuccess) return e;
+  return launch_chol_solve_update(a.L, a.d, a.batch, a.g, a.x, a.x_out, a.status, st);
+}
+
+}  // namespace ihs

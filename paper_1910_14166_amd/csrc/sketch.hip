@@ -1,0 +1,807 @@
+// Sparse-embedding kernels: hash, bucket sort, and the bucket gather that
+// forms S A (Sec. 2, CountSketch / SJLT and their streaming application),
+// fused with the residual, objective and gradient pass of Eq.(2).
+//
+// Design (gfx950):
+//  * The hash is a pure function of (seed, iteration, row, block, problem)
+//    (Philox4x64-10), so no random state is stored.
+//  * Rows are sorted by sketch row with a stable counting sort: a per-tile
+//    LDS histogram, a three-level exclusive scan, and a scatter that ranks
+//    equal keys inside a wavefront with ballots. Integer atomics in LDS only.
+//  * Each sketch row (bucket) is owned by one wavefront, which streams its
+//    input rows in ascending order as contiguous 16-byte-per-lane loads and
+//    keeps the accumulators in registers. No floating-point atomics: every
+//    sum runs in the sequential order of the definition, so S A is bitwise
+//    reproducible and equal to a sequential evaluation.
+#include <algorithm>
+
+#include "kernels.hpp"
+
+namespace ihs {
+
+__device__ __forceinline__ int find_by_tile(const ProbInfo* probs, int batch, int tile) {
+  int lo = 0, hi = batch - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (probs[mid].tile0 <= tile) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ int find_by_chunk(const ProbInfo* probs, int batch, int c) {
+  int lo = 0, hi = batch - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (probs[mid].chunk0 <= c) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ int find_by_seg(const ProbInfo* probs, int batch, int sgi) {
+  int lo = 0, hi = batch - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (probs[mid].seg0 <= sgi) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// ---------------------------------------------------------------------------
+// Problem table upload through kernel arguments (no host buffer must outlive
+// the call, and the copy is safe under stream capture).
+// ---------------------------------------------------------------------------
+__global__ void k_write_probs(ProbChunk c, ProbInfo* dst) {
+  const int i = threadIdx.x;
+  if (i < c.count) dst[c.first + i] = c.p[i];
+}
+
+hipError_t launch_write_probs(const ProbInfo* host, int32_t batch, ProbInfo* dst,
+                              hipStream_t st) {
+  for (int32_t f = 0; f < batch; f += kProbChunk) {
+    ProbChunk c{};
+    c.first = f;
+    c.count = std::min<int32_t>(kProbChunk, batch - f);
+    for (int32_t i = 0; i < c.count; ++i) c.p[i] = host[f + i];
+    hipLaunchKernelGGL(k_write_probs, dim3(1), dim3(kProbChunk), 0, st, c, dst);
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Hash of one problem's rows, for inspection: bucket[i*s+k], sign[i*s+k].
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_sketch_hash(int64_t n, int32_t problem, int32_t s,
+                                                     int64_t m_blk, uint64_t seed,
+                                                     uint64_t iter, int32_t* bucket,
+                                                     int8_t* sign) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int q = 0; q < (s + 1) / 2; ++q) {
+    const U64x4 w = philox4x64_10((uint64_t)i, (uint64_t)q, (uint64_t)problem, 0ull, seed, iter);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int k = 2 * q + h;
+      if (k < s) {
+        const uint32_t lb = range_reduce(w.w[2 * h], (uint64_t)m_blk);
+        bucket[i * s + k] = (int32_t)(k * m_blk + lb);
+        sign[i * s + k] = (w.w[2 * h + 1] >> 63) ? (int8_t)-1 : (int8_t)1;
+      }
+    }
+  }
+}
+
+hipError_t launch_sketch_hash(const SketchPlan& p, int64_t n, int32_t problem,
+                              int32_t* bucket, int8_t* sign, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const int64_t blocks = (n + 255) / 256;
+  hipLaunchKernelGGL(k_sketch_hash, dim3((unsigned)blocks), dim3(256), 0, st, n, problem,
+                     p.s, p.m_blk, p.seed, p.iter, bucket, sign);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Sort step 1: hash every (row, block) of a tile, store its key, and count
+// keys per sketch row in LDS.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_hash_count(SketchPlan P) {
+  extern __shared__ int32_t cnt[];
+  const int tile = blockIdx.x;
+  const int p = find_by_tile(P.probs, P.batch, tile);
+  const ProbInfo pi = P.probs[p];
+  const int64_t lr0 = (int64_t)(tile - pi.tile0) * P.tile_rows;
+  const int64_t nr = min((int64_t)P.tile_rows, pi.rows - lr0);
+  for (int64_t b = threadIdx.x; b < P.m; b += blockDim.x) cnt[b] = 0;
+  __syncthreads();
+  const int npairs = (P.s + 1) / 2;
+  for (int64_t i = threadIdx.x; i < nr; i += blockDim.x) {
+    const int64_t lrow = lr0 + i;
+    const int64_t grow = pi.row0 + lrow;
+    for (int q = 0; q < npairs; ++q) {
+      const U64x4 w = philox4x64_10((uint64_t)lrow, (uint64_t)q, (uint64_t)p, 0ull, P.seed,
+                                    P.iter);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int k = 2 * q + h;
+        if (k < P.s) {
+          const uint32_t bkt = (uint32_t)(k * P.m_blk) + range_reduce(w.w[2 * h], (uint64_t)P.m_blk);
+          const uint32_t neg = (uint32_t)(w.w[2 * h + 1] >> 63);
+          P.keys[grow * P.s + k] = bkt | (neg << 31);
+          atomicAdd(&cnt[bkt], 1);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  int32_t* out = P.tile_count + (int64_t)tile * P.m;
+  for (int64_t b = threadIdx.x; b < P.m; b += blockDim.x) out[b] = cnt[b];
+}
+
+// Sort step 2a: per (chunk of tiles, sketch row) totals.
+__global__ __launch_bounds__(256) void k_scan_chunks(SketchPlan P) {
+  const int c = blockIdx.x;
+  const int64_t b = (int64_t)blockIdx.y * 256 + threadIdx.x;
+  if (b >= P.m) return;
+  const int p = find_by_chunk(P.probs, P.batch, c);
+  const ProbInfo pi = P.probs[p];
+  const int t0 = pi.tile0 + (c - pi.chunk0) * P.tiles_per_chunk;
+  const int t1 = min(t0 + P.tiles_per_chunk, pi.tile0 + pi.ntiles);
+  int32_t sum = 0;
+  for (int t = t0; t < t1; ++t) sum += P.tile_count[(int64_t)t * P.m + b];
+  P.chunk_part[(int64_t)c * P.m + b] = sum;
+}
+
+// Sort step 2b: one workgroup per problem. Exclusive scan over the problem's
+// chunks for every sketch row, then an exclusive scan over sketch rows that
+// gives each segment's start in the permutation.
+__global__ __launch_bounds__(1024) void k_scan_buckets(SketchPlan P) {
+  extern __shared__ int32_t tot[];  // m totals
+  __shared__ int32_t wsum[16];
+  const int p = blockIdx.x;
+  const ProbInfo pi = P.probs[p];
+  const int tid = threadIdx.x;
+  for (int64_t b = tid; b < P.m; b += 1024) {
+    int32_t run = 0;
+    for (int c = pi.chunk0; c < pi.chunk0 + pi.nchunks; ++c) {
+      int32_t* ptr = P.chunk_part + (int64_t)c * P.m + b;
+      const int32_t v = *ptr;
+      *ptr = run;
+      run += v;
+    }
+    tot[b] = run;
+  }
+  __syncthreads();
+  const int64_t per = (P.m + 1023) / 1024;
+  const int64_t lo = min((int64_t)tid * per, P.m), hi = min(lo + per, P.m);
+  int32_t s = 0;
+  for (int64_t b = lo; b < hi; ++b) s += tot[b];
+  // block exclusive scan of the thread sums
+  const int lane = tid & 63, wv = tid >> 6;
+  int32_t incl = s;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int32_t y = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += y;
+  }
+  if (lane == 63) wsum[wv] = incl;
+  __syncthreads();
+  if (tid == 0) {
+    int32_t run = 0;
+    for (int w = 0; w < 16; ++w) {
+      const int32_t v = wsum[w];
+      wsum[w] = run;
+      run += v;
+    }
+  }
+  __syncthreads();
+  int32_t base = wsum[wv] + incl - s;
+  for (int64_t b = lo; b < hi; ++b) {
+    const int32_t v = tot[b];
+    tot[b] = base;
+    base += v;
+  }
+  __syncthreads();
+  const int64_t start = pi.row0 * P.s;
+  for (int64_t b = tid; b < P.m; b += 1024)
+    P.bucket_start[(int64_t)p * P.m + b] = (int32_t)(start + tot[b]);
+  if (p == P.batch - 1 && tid == 0) P.bucket_start[(int64_t)P.batch * P.m] = (int32_t)P.entries;
+}
+
+// Sort step 2c: absolute start of every (tile, sketch row) block.
+__global__ __launch_bounds__(256) void k_scan_tiles(SketchPlan P) {
+  const int c = blockIdx.x;
+  const int64_t b = (int64_t)blockIdx.y * 256 + threadIdx.x;
+  if (b >= P.m) return;
+  const int p = find_by_chunk(P.probs, P.batch, c);
+  const ProbInfo pi = P.probs[p];
+  const int t0 = pi.tile0 + (c - pi.chunk0) * P.tiles_per_chunk;
+  const int t1 = min(t0 + P.tiles_per_chunk, pi.tile0 + pi.ntiles);
+  int32_t run = P.bucket_start[(int64_t)p * P.m + b] + P.chunk_part[(int64_t)c * P.m + b];
+  for (int t = t0; t < t1; ++t) {
+    int32_t* ptr = P.tile_count + (int64_t)t * P.m + b;
+    const int32_t v = *ptr;
+    *ptr = run;
+    run += v;
+  }
+}
+
+// Sort step 3: stable scatter. The tile's rows are taken 256 at a time in
+// ascending order; the four wavefronts take turns, each ranking its lanes
+// among equal keys with one ballot per key bit.
+__global__ __launch_bounds__(256) void k_scatter(SketchPlan P) {
+  extern __shared__ int32_t pos[];
+  const int tile = blockIdx.x;
+  const int p = find_by_tile(P.probs, P.batch, tile);
+  const ProbInfo pi = P.probs[p];
+  const int64_t lr0 = (int64_t)(tile - pi.tile0) * P.tile_rows;
+  const int64_t nr = min((int64_t)P.tile_rows, pi.rows - lr0);
+  const int32_t* start = P.tile_count + (int64_t)tile * P.m;
+  for (int64_t b = threadIdx.x; b < P.m; b += blockDim.x) pos[b] = start[b];
+  __syncthreads();
+  const int wv = threadIdx.x >> 6;
+  const uint64_t lt = lanemask_lt();
+  for (int64_t base = 0; base < nr; base += 256) {
+    const int64_t i = base + threadIdx.x;
+    const bool valid = i < nr;
+    const int64_t grow = pi.row0 + lr0 + (valid ? i : 0);
+    for (int w = 0; w < 4; ++w) {
+      if (wv == w) {
+        for (int k = 0; k < P.s; ++k) {
+          const uint32_t kv = valid ? P.keys[grow * P.s + k] : 0u;
+          const uint32_t bkt = kv & 0x7FFFFFFFu;
+          uint64_t peers = __ballot(valid);
+          for (int bit = 0; bit < P.bucket_bits; ++bit) {
+            const bool on = (bkt >> bit) & 1u;
+            const uint64_t bb = __ballot(on);
+            peers &= on ? bb : ~bb;
+          }
+          if (valid) {
+            const int rank = __popcll(peers & lt);
+            const int32_t p0 = pos[bkt];
+            P.perm[p0 + rank] = (uint32_t)grow | (kv & 0x80000000u);
+            if (rank == 0) pos[bkt] = p0 + __popcll(peers);
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+hipError_t launch_sort(const SketchPlan& P, hipStream_t st) {
+  if (P.total_tiles == 0) {
+    // every problem is empty: bucket starts are all zero
+    hipLaunchKernelGGL(k_scan_buckets, dim3(P.batch), dim3(1024),
+                       (size_t)P.m * sizeof(int32_t), st, P);
+    return hipGetLastError();
+  }
+  const size_t lds_m = (size_t)P.m * sizeof(int32_t);
+  hipLaunchKernelGGL(k_hash_count, dim3(P.total_tiles), dim3(256), lds_m, st, P);
+  const unsigned gy = (unsigned)((P.m + 255) / 256);
+  hipLaunchKernelGGL(k_scan_chunks, dim3(P.total_chunks, gy), dim3(256), 0, st, P);
+  hipLaunchKernelGGL(k_scan_buckets, dim3(P.batch), dim3(1024), lds_m, st, P);
+  hipLaunchKernelGGL(k_scan_tiles, dim3(P.total_chunks, gy), dim3(256), 0, st, P);
+  hipLaunchKernelGGL(k_scatter, dim3(P.total_tiles), dim3(256), lds_m, st, P);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Dense bucket gather, optionally fused with r = b - A x, g = A^T r, f.
+// Lane l owns columns c*64*VEC + l*VEC + v (c < NCH, v < VEC).
+// ---------------------------------------------------------------------------
+template <typename TA, int VEC>
+struct VecLoad;
+template <>
+struct VecLoad<double, 1> {
+  static __device__ __forceinline__ void ld(const double* p, double* o) { o[0] = *p; }
+};
+template <>
+struct VecLoad<double, 2> {
+  static __device__ __forceinline__ void ld(const double* p, double* o) {
+    const double2 v = *reinterpret_cast<const double2*>(p);
+    o[0] = v.x;
+    o[1] = v.y;
+  }
+};
+template <>
+struct VecLoad<float, 1> {
+  static __device__ __forceinline__ void ld(const float* p, double* o) { o[0] = (double)*p; }
+};
+template <>
+struct VecLoad<float, 2> {
+  static __device__ __forceinline__ void ld(const float* p, double* o) {
+    const float2 v = *reinterpret_cast<const float2*>(p);
+    o[0] = (double)v.x;
+    o[1] = (double)v.y;
+  }
+};
+
+__device__ __forceinline__ void store_sa(void* SA, int32_t dt, int64_t idx, double v) {
+  if (dt == 0) {
+    static_cast<double*>(SA)[idx] = v;
+  } else if (dt == 1) {
+    static_cast<float*>(SA)[idx] = (float)v;
+  } else {
+    static_cast<uint16_t*>(SA)[idx] = f64_to_bf16_bits(v);
+  }
+}
+
+// IDENT: natural row order (no sketch): wavefront w takes rows
+// [row0 + seg*seg_rows, ...) of its problem, and only the gradient is formed.
+template <typename TA, int VEC, int NCH, int U, bool GRAD, bool IDENT>
+__global__ __launch_bounds__(256) void k_gather(SketchPlan P, GatherArgs G, int32_t total_seg,
+                                                int32_t seg_rows) {
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t nbk = IDENT ? (int64_t)total_seg : (int64_t)P.batch * P.m;
+  const int64_t bg = (int64_t)blockIdx.x * 4 + wv;
+  if (bg >= nbk) return;
+  int p;
+  int64_t bl, beg, end, gslot;
+  if (IDENT) {
+    p = find_by_seg(P.probs, P.batch, (int)bg);
+    const ProbInfo pi = P.probs[p];
+    beg = pi.row0 + (bg - pi.seg0) * (int64_t)seg_rows;
+    end = min(beg + seg_rows, pi.row0 + pi.rows);
+    bl = 0;
+    gslot = bg;
+  } else {
+    p = (int)(bg / P.m);
+    bl = bg - (int64_t)p * P.m;
+    beg = P.bucket_start[bg];
+    end = P.bucket_start[bg + 1];
+    gslot = (int64_t)p * P.m_blk + bl;
+  }
+  const bool grad = GRAD && (bl < P.m_blk);  // block 0 visits every row once
+  const TA* __restrict__ A = static_cast<const TA*>(G.A);
+  const int64_t d = G.d;
+  constexpr int SPAN = 64 * VEC;
+
+  double acc[NCH][VEC];
+  double xr[NCH][VEC];
+  double ga[NCH][VEC];
+  double fa = 0.0;
+#pragma unroll
+  for (int c = 0; c < NCH; ++c)
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+      acc[c][v] = 0.0;
+      ga[c][v] = 0.0;
+      xr[c][v] = 0.0;
+    }
+  if (grad) {
+#pragma unroll
+    for (int c = 0; c < NCH; ++c)
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) {
+        const int64_t col = (int64_t)c * SPAN + lane * VEC + v;
+        if (col < d) xr[c][v] = G.x[(int64_t)p * d + col];
+      }
+  }
+
+  for (int64_t base = beg; base < end; base += 64) {
+    const int cnt = (int)min((int64_t)64, end - base);
+    uint32_t pe = 0u;
+    if (lane < cnt) pe = IDENT ? (uint32_t)(base + lane) : P.perm[base + lane];
+    for (int j = 0; j < cnt; j += U) {
+      double val[U][NCH][VEC];
+      uint32_t ent[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int jj = min(j + u, cnt - 1);
+        ent[u] = readlane_u32(pe, jj);
+        const uint32_t row = ent[u] & 0x7FFFFFFFu;
+        const TA* rp = A + (int64_t)row * G.ld;
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+          const int64_t col = (int64_t)c * SPAN + lane * VEC;
+          if (col < d) {
+            VecLoad<TA, VEC>::ld(rp + col, val[u][c]);
+          } else {
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) val[u][c][v] = 0.0;
+          }
+        }
+      }
+      if (grad) {
+        double dot[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          double s = 0.0;
+#pragma unroll
+          for (int c = 0; c < NCH; ++c)
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) s = fma(val[u][c][v], xr[c][v], s);
+          dot[u] = s;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) dot[u] = wave_sum(dot[u]);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          if (j + u < cnt) {
+            const uint32_t row = ent[u] & 0x7FFFFFFFu;
+            const double ri = G.b[row] - dot[u];
+            fa = fma(ri, ri, fa);
+#pragma unroll
+            for (int c = 0; c < NCH; ++c)
+#pragma unroll
+              for (int v = 0; v < VEC; ++v) ga[c][v] = fma(ri, val[u][c][v], ga[c][v]);
+            if (G.r_out != nullptr && lane == 0) G.r_out[row] = ri;
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (j + u < cnt) {
+          const bool neg = (ent[u] >> 31) != 0;
+#pragma unroll
+          for (int c = 0; c < NCH; ++c)
+#pragma unroll
+            for (int v = 0; v < VEC; ++v)
+              acc[c][v] = neg ? (acc[c][v] - val[u][c][v]) : (acc[c][v] + val[u][c][v]);
+        }
+      }
+    }
+  }
+
+  if (!IDENT) {
+    const int64_t orow = bg * G.ld_sa;
+#pragma unroll
+    for (int c = 0; c < NCH; ++c)
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) {
+        const int64_t col = (int64_t)c * SPAN + lane * VEC + v;
+        if (col < d) store_sa(G.SA, G.sa_dtype, orow + col, acc[c][v] * G.scale);
+      }
+  }
+  if (grad) {
+    double* gp = G.gpart + gslot * d;
+#pragma unroll
+    for (int c = 0; c < NCH; ++c)
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) {
+        const int64_t col = (int64_t)c * SPAN + lane * VEC + v;
+        if (col < d) gp[col] = ga[c][v];
+      }
+    if (lane == 0) G.fpart[gslot] = fa;
+  }
+}
+
+template <typename TA, int VEC, int NCH, bool GRAD, bool IDENT>
+static hipError_t gather_inst(const SketchPlan& P, const GatherArgs& G, int32_t total_seg,
+                              int32_t seg_rows, hipStream_t st) {
+  constexpr int U = NCH <= 2 ? 8 : (NCH <= 4 ? 4 : 2);
+  const int64_t nbk = IDENT ? (int64_t)total_seg : (int64_t)P.batch * P.m;
+  const unsigned blocks = (unsigned)((nbk + 3) / 4);
+  if (blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_gather<TA, VEC, NCH, U, GRAD, IDENT>), dim3(blocks), dim3(256), 0, st,
+                     P, G, total_seg, seg_rows);
+  return hipGetLastError();
+}
+
+template <typename TA, int VEC, bool GRAD, bool IDENT>
+static hipError_t gather_nch(const SketchPlan& P, const GatherArgs& G, int32_t ts, int32_t sr,
+                             hipStream_t st) {
+  const int64_t span = 64 * VEC;
+  const int64_t nch = (G.d + span - 1) / span;
+  switch (nch) {
+    case 1: return gather_inst<TA, VEC, 1, GRAD, IDENT>(P, G, ts, sr, st);
+    case 2: return gather_inst<TA, VEC, 2, GRAD, IDENT>(P, G, ts, sr, st);
+    case 3: return gather_inst<TA, VEC, 3, GRAD, IDENT>(P, G, ts, sr, st);
+    case 4: return gather_inst<TA, VEC, 4, GRAD, IDENT>(P, G, ts, sr, st);
+    case 5: return gather_inst<TA, VEC, 5, GRAD, IDENT>(P, G, ts, sr, st);
+    case 6: return gather_inst<TA, VEC, 6, GRAD, IDENT>(P, G, ts, sr, st);
+    case 7: return gather_inst<TA, VEC, 7, GRAD, IDENT>(P, G, ts, sr, st);
+    case 8: return gather_inst<TA, VEC, 8, GRAD, IDENT>(P, G, ts, sr, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// Two doubles (or floats) per lane per load when rows allow aligned pairs.
+template <typename TA, bool GRAD, bool IDENT>
+static hipError_t gather_vec(const SketchPlan& P, const GatherArgs& G, int32_t ts, int32_t sr,
+                             hipStream_t st) {
+  const bool v2 = (G.d % 2 == 0) && (G.ld % 2 == 0) &&
+                  ((reinterpret_cast<uintptr_t>(G.A) % (2 * sizeof(TA))) == 0) && G.d > 64;
+  if (v2) return gather_nch<TA, 2, GRAD, IDENT>(P, G, ts, sr, st);
+  if (G.d > 512) return hipErrorInvalidValue;
+  return gather_nch<TA, 1, GRAD, IDENT>(P, G, ts, sr, st);
+}
+
+hipError_t launch_sketch_gather(const SketchPlan& P, const GatherArgs& G, hipStream_t st) {
+  const bool grad = G.b != nullptr;
+  if (G.a_dtype == 0)
+    return grad ? gather_vec<double, true, false>(P, G, 0, 0, st)
+                : gather_vec<double, false, false>(P, G, 0, 0, st);
+  return grad ? gather_vec<float, true, false>(P, G, 0, 0, st)
+              : gather_vec<float, false, false>(P, G, 0, 0, st);
+}
+
+hipError_t launch_gradient_rows(const ProbInfo* probs, int32_t batch, int32_t total_seg,
+                                int32_t seg_rows, const void* A, int32_t a_dtype, int64_t ld,
+                                int64_t d, const double* b, const double* x, double* gpart,
+                                double* fpart, double* r_out, hipStream_t st) {
+  SketchPlan P{};
+  P.probs = probs;
+  P.batch = batch;
+  P.s = 1;
+  P.m = 1;
+  P.m_blk = 1;
+  GatherArgs G{};
+  G.A = A;
+  G.a_dtype = a_dtype;
+  G.ld = ld;
+  G.d = d;
+  G.scale = 1.0;
+  G.b = b;
+  G.x = x;
+  G.gpart = gpart;
+  G.fpart = fpart;
+  G.r_out = r_out;
+  if (a_dtype == 0) return gather_vec<double, true, true>(P, G, total_seg, seg_rows, st);
+  return gather_vec<float, true, true>(P, G, total_seg, seg_rows, st);
+}
+
+// ---------------------------------------------------------------------------
+// CSR bucket gather. One wavefront per sketch row keeps a dense row of S A
+// (and of the gradient partial) in LDS. Nonzeros are staged 64 at a time in
+// (row, column) order; lanes holding the same column are ranked with ballots
+// and applied round by round, so each (sketch row, column) still sums in
+// ascending row order.
+// ---------------------------------------------------------------------------
+template <bool GRAD, bool IDENT>
+__global__ __launch_bounds__(256) void k_gather_csr(SketchPlan P, CsrGatherArgs G,
+                                                    int32_t col_bits, int32_t total_seg,
+                                                    int32_t seg_rows) {
+  extern __shared__ double smem[];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t d = G.d;
+  double* acc = smem + (int64_t)wv * (GRAD ? 2 : 1) * d;
+  double* gac = acc + d;
+  __shared__ int32_t st_col[4][64];
+  __shared__ double st_val[4][64];
+  __shared__ double st_rv[4][64];
+  const int64_t nbk = IDENT ? (int64_t)total_seg : (int64_t)P.batch * P.m;
+  const int64_t bg = (int64_t)blockIdx.x * 4 + wv;
+  if (bg >= nbk) return;  // no workgroup barriers below: waves are independent
+  int p;
+  int64_t bl, beg, end, gslot;
+  if (IDENT) {
+    p = find_by_seg(P.probs, P.batch, (int)bg);
+    const ProbInfo pi = P.probs[p];
+    beg = pi.row0 + (bg - pi.seg0) * (int64_t)seg_rows;
+    end = min(beg + seg_rows, pi.row0 + pi.rows);
+    bl = 0;
+    gslot = bg;
+  } else {
+    p = (int)(bg / P.m);
+    bl = bg - (int64_t)p * P.m;
+    beg = P.bucket_start[bg];
+    end = P.bucket_start[bg + 1];
+    gslot = (int64_t)p * P.m_blk + bl;
+  }
+  const bool grad = GRAD && (bl < P.m_blk);
+  for (int64_t c = lane; c < d; c += 64) {
+    if (!IDENT) acc[c] = 0.0;
+    if (GRAD) gac[c] = 0.0;
+  }
+  const uint64_t lt = lanemask_lt();
+  double fa = 0.0;
+  for (int64_t base = beg; base < end; base += 64) {
+    const int cnt = (int)min((int64_t)64, end - base);
+    const bool rv_ok = lane < cnt;
+    uint32_t pe = 0u;
+    if (rv_ok) pe = IDENT ? (uint32_t)(base + lane) : P.perm[base + lane];
+    const uint32_t row = pe & 0x7FFFFFFFu;
+    const double sg = (pe >> 31) ? -1.0 : 1.0;
+    int32_t rs = 0, re = 0;
+    if (rv_ok) {
+      rs = G.row_ptr[row];
+      re = G.row_ptr[row + 1];
+    }
+    double ri = 0.0;
+    if (grad && rv_ok) {
+      double dot = 0.0;
+      for (int32_t q = rs; q < re; ++q) dot = fma(G.values[q], G.x[(int64_t)p * d + G.col_idx[q]], dot);
+      ri = G.b[row] - dot;
+      fa = fma(ri, ri, fa);
+      if (G.r_out != nullptr) G.r_out[row] = ri;
+    }
+    // flattened positions of this batch's nonzeros
+    const int len = re - rs;
+    int incl = len;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int y = __shfl_up(incl, off, 64);
+      if (lane >= off) incl += y;
+    }
+    const int excl = incl - len;
+    const int total = __shfl(incl, 63, 64);
+    for (int w0 = 0; w0 < total; w0 += 64) {
+      // stage the nonzeros whose flattened index falls in [w0, w0 + 64)
+      for (int q = max(excl, w0); q < min(excl + len, w0 + 64); ++q) {
+        const int32_t src = rs + (q - excl);
+        st_col[wv][q - w0] = G.col_idx[src];
+        const double v = G.values[src];
+        st_val[wv][q - w0] = sg * v;
+        st_rv[wv][q - w0] = ri * v;
+      }
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      const bool ok = (w0 + lane) < total;
+      const int32_t col = ok ? st_col[wv][lane] : 0;
+      const double v = ok ? st_val[wv][lane] : 0.0;
+      const double rvv = ok ? st_rv[wv][lane] : 0.0;
+      uint64_t peers = __ballot(ok);
+      for (int bit = 0; bit < col_bits; ++bit) {
+        const bool on = (col >> bit) & 1;
+        const uint64_t bb = __ballot(on);
+        peers &= on ? bb : ~bb;
+      }
+      const int rank = __popcll(peers & lt);
+      for (int r = 0; __ballot(ok && rank >= r) != 0ull; ++r) {
+        if (ok && rank == r) {
+          if (!IDENT) acc[col] = acc[col] + v;
+          if (grad) gac[col] = gac[col] + rvv;
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      }
+    }
+  }
+  if (!IDENT) {
+    const int64_t orow = bg * G.ld_sa;
+    for (int64_t c = lane; c < d; c += 64) store_sa(G.SA, G.sa_dtype, orow + c, acc[c] * G.scale);
+  }
+  if (grad) {
+    double* gp = G.gpart + gslot * d;
+    for (int64_t c = lane; c < d; c += 64) gp[c] = gac[c];
+    const double fs = wave_sum(fa);
+    if (lane == 0) G.fpart[gslot] = fs;
+  }
+}
+
+static int32_t bits_for(int64_t d) {
+  int32_t bits = 0;
+  while ((1ll << bits) < d) ++bits;
+  return bits;
+}
+
+hipError_t launch_sketch_gather_csr(const SketchPlan& P, const CsrGatherArgs& G,
+                                    hipStream_t st) {
+  const int64_t nbk = (int64_t)P.batch * P.m;
+  const unsigned blocks = (unsigned)((nbk + 3) / 4);
+  const bool grad = G.b != nullptr;
+  const size_t lds = (size_t)4 * (grad ? 2 : 1) * G.d * sizeof(double);
+  if (grad)
+    hipLaunchKernelGGL((k_gather_csr<true, false>), dim3(blocks), dim3(256), lds, st, P, G,
+                       bits_for(G.d), 0, 0);
+  else
+    hipLaunchKernelGGL((k_gather_csr<false, false>), dim3(blocks), dim3(256), lds, st, P, G,
+                       bits_for(G.d), 0, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_gradient_rows_csr(const ProbInfo* probs, int32_t batch, int32_t total_seg,
+                                    int32_t seg_rows, const int32_t* row_ptr,
+                                    const int32_t* col_idx, const double* values, int64_t d,
+                                    const double* b, const double* x, double* gpart,
+                                    double* fpart, double* r_out, hipStream_t st) {
+  if (total_seg == 0) return hipSuccess;
+  SketchPlan P{};
+  P.probs = probs;
+  P.batch = batch;
+  P.s = 1;
+  P.m = 1;
+  P.m_blk = 1;
+  CsrGatherArgs G{};
+  G.row_ptr = row_ptr;
+  G.col_idx = col_idx;
+  G.values = values;
+  G.d = d;
+  G.scale = 1.0;
+  G.b = b;
+  G.x = x;
+  G.gpart = gpart;
+  G.fpart = fpart;
+  G.r_out = r_out;
+  // the IDENT variant keeps only the gradient row in LDS; acc aliases it
+  const size_t lds = (size_t)4 * 2 * d * sizeof(double);
+  hipLaunchKernelGGL((k_gather_csr<true, true>), dim3((unsigned)((total_seg + 3) / 4)),
+                     dim3(256), lds, st, P, G, bits_for(d), total_seg, seg_rows);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint S^T G for the rows of one problem: row i re-derives its s (bucket,
+// sign) pairs from the hash and sums c_s * sign * G[bucket][:] over blocks in
+// ascending order. One wavefront per row, lanes over columns.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_adjoint(int32_t s, int64_t m_blk, uint64_t seed,
+                                                 uint64_t iter, int32_t problem,
+                                                 const double* __restrict__ Gm, int64_t ld_g,
+                                                 int64_t d, double* out, int64_t ld_out,
+                                                 double scale, int64_t nrows) {
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t waves = (int64_t)gridDim.x * 4;
+  for (int64_t row = (int64_t)blockIdx.x * 4 + wv; row < nrows; row += waves) {
+    uint32_t keys[16];
+    const int sk = s < 16 ? s : 16;
+    for (int q = 0; q < (sk + 1) / 2; ++q) {
+      const U64x4 w = philox4x64_10((uint64_t)row, (uint64_t)q, (uint64_t)problem, 0ull, seed,
+                                    iter);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int k = 2 * q + h;
+        if (k < sk) {
+          const uint32_t bkt = (uint32_t)(k * m_blk) + range_reduce(w.w[2 * h], (uint64_t)m_blk);
+          keys[k] = bkt | ((uint32_t)(w.w[2 * h + 1] >> 63) << 31);
+        }
+      }
+    }
+    for (int64_t c = lane; c < d; c += 64) {
+      double acc = 0.0;
+      for (int k = 0; k < sk; ++k) {
+        double t = Gm[(int64_t)(keys[k] & 0x7FFFFFFFu) * ld_g + c];
+        if (s > 1) t = t * scale;
+        acc = (keys[k] >> 31) ? (acc - t) : (acc + t);
+      }
+      out[row * ld_out + c] = acc;
+    }
+  }
+}
+
+hipError_t launch_sketch_adjoint(const SketchPlan& P, const double* G, int64_t ld_g, int64_t d,
+                                 double* out, int64_t ld_out, int64_t nrows, int32_t problem,
+                                 hipStream_t st) {
+  if (nrows == 0) return hipSuccess;
+  if (P.s > 16) return hipErrorInvalidValue;
+  const double scale = 1.0 / sqrt((double)P.s);
+  const unsigned blocks = (unsigned)std::min<int64_t>((nrows + 3) / 4, 65536);
+  hipLaunchKernelGGL(k_adjoint, dim3(blocks), dim3(256), 0, st, P.s, P.m_blk, P.seed, P.iter,
+                     problem, G, ld_g, d, out, ld_out, scale, nrows);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// dL/db = A lambda and dL/dA = r lambda^T - (A lambda) x^T, r = b - A x,
+// for the rows of one problem. One wavefront per row.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_solution_grads(int64_t nrows, int64_t d,
+                                                        const double* __restrict__ A, int64_t ld,
+                                                        const double* __restrict__ b,
+                                                        const double* __restrict__ x,
+                                                        const double* __restrict__ lam,
+                                                        double* dl_db, double* dl_da,
+                                                        int64_t ld_da) {
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t waves = (int64_t)gridDim.x * 4;
+  for (int64_t row = (int64_t)blockIdx.x * 4 + wv; row < nrows; row += waves) {
+    const double* ar = A + row * ld;
+    double sl = 0.0, sx = 0.0;
+    for (int64_t c = lane; c < d; c += 64) {
+      const double a = ar[c];
+      sl = fma(a, lam[c], sl);
+      sx = fma(a, x[c], sx);
+    }
+    sl = wave_sum(sl);
+    sx = wave_sum(sx);
+    const double r = b[row] - sx;
+    if (dl_db != nullptr && lane == 0) dl_db[row] = sl;
+    if (dl_da != nullptr)
+      for (int64_t c = lane; c < d; c += 64) dl_da[row * ld_da + c] = r * lam[c] - sl * x[c];
+  }
+}
+
+hipError_t launch_solution_grads(const ProbInfo*, int32_t, int64_t n, int64_t d, const double* A,
+                                 int64_t ld, const double* b, const double* x,
+                                 const double* lambda, double* dl_db, double* dl_da,
+                                 int64_t ld_da, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const unsigned blocks = (unsigned)std::min<int64_t>((n + 3) / 4, 65536);
+  hipLaunchKernelGGL(k_solution_grads, dim3(blocks), dim3(256), 0, st, n, d, A, ld, b, x, lambda,
+                     dl_db, dl_da, ld_da);
+  return hipGetLastError();
+}
+
+}  // namespace ihs

@@ -1,0 +1,228 @@
+"""GPU parity of the gradient pass, the Gram, the QP step and the IHS loop
+against the oracle.
+
+Tolerances follow the arithmetic: a length-k float64 dot product differs
+from any other summation order by at most 2 k u sum|terms| (u = 2^-53), so
+gradients, Gram entries and objectives are compared componentwise against
+those bounds; QP solutions and IHS iterates against a small multiple of the
+problem's conditioning times u; the IHS result against x_OPT in the paper's
+prediction norm (Def. A.1)."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import ihs as O
+from oracle import sketch as OS
+
+pytestmark = pytest.mark.gpu
+U = 2.0 ** -53
+
+
+def dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def host(t):
+    return t.double().cpu().numpy()
+
+
+# ------------------------------------------------------------- gradient ----
+@pytest.mark.parametrize("n,d", [(5000, 50), (10000, 256), (777, 1024), (1, 3), (300, 511)])
+def test_gradient_dense(gpu_lib, n, d):
+    P = gpu_lib
+    g = np.random.default_rng(n + d)
+    A = g.standard_normal((n, d))
+    b = g.standard_normal(n)
+    x = g.standard_normal(d)
+    gg, r, f = P.gradient(P.Matrix(dense=dev(A)), dev(b), dev(x[None, :]), want_r=True)
+    r_ref, g_ref, f_ref = O.gradient(A, b, x)
+    rb = 2 * d * U * (np.abs(A) @ np.abs(x) + np.abs(b))
+    assert np.all(np.abs(host(r) - r_ref) <= rb + 1e-300)
+    gb = 4 * (n + d) * U * (np.abs(A).T @ (np.abs(b) + np.abs(A) @ np.abs(x)))
+    assert np.all(np.abs(host(gg)[0] - g_ref) <= gb)
+    fb = 4 * (n + d) * U * np.sum((np.abs(b) + np.abs(A) @ np.abs(x)) ** 2)
+    assert abs(host(f)[0] - f_ref) <= fb
+
+
+def test_gradient_csr(gpu_lib):
+    P = gpu_lib
+    wl = W.ridge_csr(rows=30000, d=300, density=0.01)
+    A = O.csr_matrix(wl.indptr, wl.indices, wl.data, wl.n, wl.d)
+    x = np.random.default_rng(1).standard_normal(wl.d)
+    M = P.Matrix(row_ptr=dev(wl.indptr), col_idx=dev(wl.indices), values=dev(wl.data),
+                 n=wl.n, d=wl.d)
+    gg, r, f = P.gradient(M, dev(wl.b), dev(x[None, :]), want_r=True)
+    r_ref, g_ref, f_ref = O.gradient(A, wl.b, x)
+    absA = abs(A)
+    scale = absA.T @ (np.abs(wl.b) + absA @ np.abs(x))
+    assert np.all(np.abs(host(gg)[0] - g_ref) <= 4 * (wl.n + wl.d) * U * scale)
+    assert np.allclose(host(r), r_ref, rtol=0, atol=1e-12)
+    assert abs(host(f)[0] - f_ref) <= 1e-12 * f_ref
+
+
+def test_gradient_ragged_batch(gpu_lib):
+    P = gpu_lib
+    g = np.random.default_rng(2)
+    sizes = [1000, 1, 257, 4096]
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    A = g.standard_normal((offs[-1], 64))
+    b = g.standard_normal(offs[-1])
+    X = g.standard_normal((len(sizes), 64))
+    gg, _, f = P.gradient(P.Matrix(dense=dev(A), row_offsets=offs), dev(b), dev(X))
+    for p in range(len(sizes)):
+        Ap, bp = A[offs[p]:offs[p + 1]], b[offs[p]:offs[p + 1]]
+        _, g_ref, f_ref = O.gradient(Ap, bp, X[p])
+        assert np.allclose(host(gg)[p], g_ref, rtol=1e-11, atol=1e-10)
+        assert np.isclose(host(f)[p], f_ref, rtol=1e-12)
+
+
+# ----------------------------------------------------------------- Gram ----
+@pytest.mark.parametrize("m,d,batch", [(500, 50, 1), (4096, 256, 1), (640, 64, 3),
+                                       (100, 33, 1), (8192, 1024, 1), (3, 5, 2)])
+def test_gram_f64(gpu_lib, m, d, batch):
+    P = gpu_lib
+    g = np.random.default_rng(m + d)
+    SA = g.standard_normal((batch * m, d))
+    H = host(P.gram(dev(SA), m, batch=batch))
+    for p in range(batch):
+        S = SA[p * m:(p + 1) * m]
+        ref = O.gram(S)
+        bound = 2 * m * U * (np.abs(S).T @ np.abs(S))
+        assert np.all(np.abs(H[p] - ref) <= bound), p
+        assert np.array_equal(H[p], H[p].T)
+
+
+@pytest.mark.parametrize("in_dt,acc", [("float32", "float64"), ("float32", "float32"),
+                                       ("bfloat16", "float32")])
+def test_gram_mixed(gpu_lib, in_dt, acc):
+    import torch
+    P = gpu_lib
+    g = np.random.default_rng(3)
+    m, d = 2048, 160
+    SA64 = g.standard_normal((m, d))
+    SA_in = OS.round_output(SA64, in_dt)
+    t = dev(SA64).to(torch.float32 if in_dt == "float32" else torch.bfloat16)
+    assert np.array_equal(host(t), np.asarray(SA_in, dtype=np.float64))
+    H = host(P.gram(t, m, in_dtype=in_dt, acc_dtype=acc))[0]
+    S = np.asarray(SA_in, dtype=np.float64)
+    ref = S.T @ S
+    u_acc = 2.0 ** -24 if acc == "float32" else U
+    bound = 2 * m * u_acc * (np.abs(S).T @ np.abs(S))
+    assert np.all(np.abs(H - ref) <= bound)
+
+
+# ------------------------------------------------------------------- QP ----
+def spd(d, g, cond):
+    Q, _ = np.linalg.qr(g.standard_normal((d, d)))
+    return Q @ np.diag(np.geomspace(1.0, cond, d)) @ Q.T
+
+
+@pytest.mark.parametrize("d,batch", [(50, 1), (64, 4), (256, 1), (512, 1), (130, 2), (1, 1),
+                                     (1024, 1)])
+def test_qp_unconstrained(gpu_lib, d, batch):
+    P = gpu_lib
+    g = np.random.default_rng(d)
+    Hs = np.stack([spd(d, g, 1e3) for _ in range(batch)])
+    gs = g.standard_normal((batch, d))
+    xs = g.standard_normal((batch, d))
+    out = host(P.qp_step(dev(Hs), dev(gs), dev(xs)))
+    for p in range(batch):
+        ref = O.qp_step(Hs[p], gs[p], xs[p])
+        dx, dref = out[p] - xs[p], ref - xs[p]
+        assert np.linalg.norm(dx - dref) <= 1e-12 * 1e3 * np.linalg.norm(dref) * max(1, d / 64)
+
+
+def test_qp_not_positive_definite(gpu_lib):
+    P = gpu_lib
+    d = 200
+    H = np.eye(d)
+    H[150, 150] = -1.0
+    with pytest.raises(P.IHSError) as e:
+        P.qp_step(dev(H[None]), dev(np.ones((1, d))), dev(np.zeros((1, d))))
+    assert e.value.code == P.ERR_NOT_PD
+
+
+# ------------------------------------------------------------------ IHS ----
+def test_ihs_unconstrained_iterates_match_oracle(gpu_lib):
+    P = gpu_lib
+    wl = W.ols_dense(rows=20000, d=50, m=500, iters=10)
+    opts = P.options(wl.m, seed=wl.sketch_seed, max_iter=wl.iters)
+    res = P.solve(P.Matrix(dense=dev(wl.A)), dev(wl.b), opts, history=True)
+    assert res.report.status == 0 and res.report.iters == wl.iters
+    xs = O.ihs(wl.A, wl.b, wl.m, seed=wl.sketch_seed, iters=wl.iters)
+    hist = host(res.history)[:, 0, :]
+    for t in range(wl.iters):
+        assert np.linalg.norm(hist[t] - xs[t + 1]) <= 1e-11 * np.linalg.norm(xs[t + 1]), t
+    xo = O.x_opt(wl.A, wl.b)
+    errs = [O.error_A(wl.A, hist[t], xo) for t in range(wl.iters)]
+    assert errs[-1] < errs[0] * 0.6 ** 9
+    r_ref, _, f_ref = O.gradient(wl.A, wl.b, xs[wl.iters - 1])
+    assert abs(res.report.objective - f_ref) <= 1e-11 * f_ref
+
+
+def test_ihs_f32_data_and_mixed_gram(gpu_lib):
+    P = gpu_lib
+    wl = W.ols_dense(rows=8000, d=40, m=400, iters=8)
+    A32 = wl.A.astype(np.float32)
+    for gin, gacc in (("float64", "float64"), ("float32", "float64"), ("float32", "float32"),
+                      ("bfloat16", "float32")):
+        opts = P.options(wl.m, seed=wl.sketch_seed, max_iter=wl.iters, gram_in=gin, gram_acc=gacc)
+        res = P.solve(P.Matrix(dense=dev(A32)), dev(wl.b), opts)
+        xs = O.ihs(A32, wl.b, wl.m, seed=wl.sketch_seed, iters=wl.iters, sketch_dtype=gin)
+        xo = O.x_opt(A32.astype(np.float64), wl.b)
+        e_gpu = O.error_A(A32.astype(np.float64), host(res.x)[0], xo)
+        e_ref = O.error_A(A32.astype(np.float64), xs[-1], xo)
+        assert e_gpu < 1e-4 and abs(np.log10(e_gpu) - np.log10(e_ref)) < 0.5, (gin, gacc)
+
+
+def test_ihs_ragged_batch(gpu_lib):
+    P = gpu_lib
+    wl = W.batch_ragged(num=6, n_lo=2000, n_hi=9000, d=64, iters=12)
+    opts = P.options(wl.m, seed=wl.sketch_seed, max_iter=wl.iters)
+    res = P.solve(P.Matrix(dense=dev(wl.A), row_offsets=wl.row_offsets), dev(wl.b), opts)
+    X = host(res.x)
+    for p in range(wl.batch):
+        r0, r1 = wl.row_offsets[p], wl.row_offsets[p + 1]
+        Ap = wl.A[r0:r1]
+        # the oracle draws problem p's sketch with problem index p
+        x = np.zeros(64)
+        for t in range(wl.iters):
+            SA = OS.sketch_apply_dense(Ap, wl.sketch_seed, t, wl.m, 1, problem=p)
+            _, gr, _ = O.gradient(Ap, wl.b[r0:r1], x)
+            x = O.qp_step(SA.T @ SA, gr, x)
+        assert np.linalg.norm(X[p] - x) <= 1e-11 * np.linalg.norm(x), p
+        assert O.error_A(Ap, X[p], O.x_opt(Ap, wl.b[r0:r1])) < 1e-8
+
+
+def test_ihs_rank_deficient_reports_not_pd(gpu_lib):
+    P = gpu_lib
+    g = np.random.default_rng(9)
+    A = g.standard_normal((2000, 20))
+    A[:, 7] = 0.0                           # empty column: H exactly singular
+    b = g.standard_normal(2000)
+    opts = P.options(200, seed=1, max_iter=3)
+    res = P.solve(P.Matrix(dense=dev(A)), dev(b), opts, raise_on_error=False)
+    assert res.report.status == P.ERR_NOT_PD
+    assert res.report.failed_iter == 0
+
+
+def test_ihs_nonfinite_objective_detected(gpu_lib):
+    P = gpu_lib
+    g = np.random.default_rng(10)
+    A = g.standard_normal((3000, 16))
+    b = g.standard_normal(3000)
+    b[123] = np.nan
+    res = P.solve(P.Matrix(dense=dev(A)), dev(b), P.options(160, max_iter=2),
+                  raise_on_error=False)
+    assert res.report.status == P.ERR_NONFINITE
+
+
+def test_ihs_deterministic(gpu_lib):
+    P = gpu_lib
+    wl = W.lasso_dense(rows=30000, d=128, m=1024)
+    opts = P.options(1024, seed=3, max_iter=4)
+    M = P.Matrix(dense=dev(wl.A))
+    a = P.solve(M, dev(wl.b), opts).x
+    b = P.solve(M, dev(wl.b), opts).x
+    assert bool((a == b).all())
