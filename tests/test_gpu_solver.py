@@ -102,7 +102,9 @@ def test_gram_mixed(gpu_lib, in_dt, acc):
     m, d = 2048, 160
     SA64 = g.standard_normal((m, d))
     SA_in = OS.round_output(SA64, in_dt)
-    t = dev(SA64).to(torch.float32 if in_dt == "float32" else torch.bfloat16)
+    # SA_in holds values exactly representable in the input type, so the cast is exact
+    t = dev(np.asarray(SA_in, dtype=np.float64)).to(
+        torch.float32 if in_dt == "float32" else torch.bfloat16)
     assert np.array_equal(host(t), np.asarray(SA_in, dtype=np.float64))
     H = host(P.gram(t, m, in_dtype=in_dt, acc_dtype=acc))[0]
     S = np.asarray(SA_in, dtype=np.float64)
@@ -173,7 +175,8 @@ def test_ihs_f32_data_and_mixed_gram(gpu_lib):
         xo = O.x_opt(A32.astype(np.float64), wl.b)
         e_gpu = O.error_A(A32.astype(np.float64), host(res.x)[0], xo)
         e_ref = O.error_A(A32.astype(np.float64), xs[-1], xo)
-        assert e_gpu < 1e-4 and abs(np.log10(e_gpu) - np.log10(e_ref)) < 0.5, (gin, gacc)
+        # about 0.37 per step at m = 10 d: 8 steps reach a few 1e-4
+        assert e_gpu < 3e-3 and abs(np.log10(e_gpu) - np.log10(e_ref)) < 0.3, (gin, gacc)
 
 
 def test_ihs_ragged_batch(gpu_lib):
@@ -192,7 +195,7 @@ def test_ihs_ragged_batch(gpu_lib):
             _, gr, _ = O.gradient(Ap, wl.b[r0:r1], x)
             x = O.qp_step(SA.T @ SA, gr, x)
         assert np.linalg.norm(X[p] - x) <= 1e-11 * np.linalg.norm(x), p
-        assert O.error_A(Ap, X[p], O.x_opt(Ap, wl.b[r0:r1])) < 1e-8
+        assert O.error_A(Ap, X[p], O.x_opt(Ap, wl.b[r0:r1])) < 1e-4
 
 
 def test_ihs_rank_deficient_reports_not_pd(gpu_lib):
