@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--no-tol", action="store_true", help="skip time-to-tolerance runs")
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--max-iter", type=int, default=60)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 2 GiB device copy (counter calibration)")
     return ap.parse_args()
 
 
@@ -106,6 +108,14 @@ def main():
 
     P.load()
     dev = "cuda"
+    if args.calibrate_copy:
+        # a plain copy of known size: 2 GiB read + 2 GiB written per launch
+        src = torch.ones(1 << 28, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     t_gen = time.time()
     if args.workload == "precision":
         wl = W.precision(rows=args.rows, backend="torch", device=dev, keep_factors=True)

@@ -140,6 +140,8 @@ struct PassBuffers {
   double* g = nullptr;
   double* f = nullptr;
   double* bzero = nullptr;
+  double* red = nullptr;   // two-level reduction scratch
+  double* rdiag = nullptr; // batch x d reciprocal pivots (adjoint path)
 };
 
 void carve_pass(Carver& c, const Layout& L, const ihs_sketch* sk, PassBuffers& B) {
@@ -160,6 +162,15 @@ void carve_pass(Carver& c, const Layout& L, const ihs_sketch* sk, PassBuffers& B
   B.g = c.take<double>((size_t)(L.batch * L.d));
   B.f = c.take<double>((size_t)L.batch);
   B.bzero = c.take<double>((size_t)std::max<int64_t>(L.n, 1));
+  B.red = c.take<double>(reduce_scratch_doubles(L.batch, L.d));
+  B.rdiag = c.take<double>((size_t)(L.batch * L.d));
+}
+
+// Gradient partials written by one sketch pass: one per workgroup of four
+// sketch rows for dense data, one per sketch row for CSR data.
+int64_t pass_parts(const ihs_matrix* A, const ihs_sketch* sk) {
+  const int64_t m_blk = sk->m / sk->s;
+  return A->format == IHS_DENSE ? (m_blk + 3) / 4 : m_blk;
 }
 
 SketchPlan make_plan(const Layout& L, const ihs_sketch* sk, const PassBuffers& B, uint64_t iter) {
@@ -317,7 +328,7 @@ ihs_status run_gradient(const ihs_matrix* A, const Layout& L, const PassBuffers&
     return IHS_OK;
   }
   err = launch_reduce_partials(B.gpart, B.fpart, L.batch, 0, B.probs, L.d, g, f, status, iter,
-                               st);
+                               B.red, st);
   return err == hipSuccess ? IHS_OK : IHS_ERR_HIP;
 }
 
@@ -567,14 +578,13 @@ ihs_status ihs_solve(const ihs_matrix* A, const double* b, const ihs_options* op
   PassBuffers& B = S.pass;
   if ((s = upload_probs(L, B, stream)) != IHS_OK) return s;
   const int64_t d = A->d, m = opt->sketch.m;
-  const int64_t m_blk = m / opt->sketch.s;
   const int64_t bd = (int64_t)L.batch * d;
   for (int32_t t = 0; t < opt->max_iter; ++t) {
     const uint64_t iter = opt->sketch.iter + (uint64_t)t;
     s = run_pass(A, L, &opt->sketch, B, iter, S.SA, opt->gram_in, d, b, x, nullptr, stream);
     if (s != IHS_OK) return s;
-    if (launch_reduce_partials(B.gpart, B.fpart, L.batch, m_blk, B.probs, d, B.g, B.f, B.status,
-                               t, stream) != hipSuccess)
+    if (launch_reduce_partials(B.gpart, B.fpart, L.batch, pass_parts(A, &opt->sketch), B.probs,
+                               d, B.g, B.f, B.status, t, B.red, stream) != hipSuccess)
       return IHS_ERR_HIP;
     if (launch_gram(S.SA, opt->gram_in, m, d, d, L.batch, opt->gram_acc, S.H, S.gram_part,
                     stream) != hipSuccess)
@@ -642,8 +652,10 @@ ihs_status ihs_adjoint_solve(const ihs_matrix* A, const double* xbar, const doub
       return s;
     hipLaunchKernelGGL(k_add, dim3((unsigned)((bd + 255) / 256)), dim3(256), 0, stream, xbar,
                        B.g, v, bd);
-    if (launch_chol_solve_update(factors + (int64_t)k * L.batch * A->d * A->d, A->d, L.batch, v,
-                                 lambda, lambda, B.status, stream) != hipSuccess)
+    const double* Lk = factors + (int64_t)k * L.batch * A->d * A->d;
+    if (launch_recip_diag(Lk, A->d, L.batch, B.rdiag, stream) != hipSuccess) return IHS_ERR_HIP;
+    if (launch_chol_solve_update(Lk, B.rdiag, A->d, L.batch, v, lambda, lambda, B.status,
+                                 stream) != hipSuccess)
       return IHS_ERR_HIP;
   }
   return hipGetLastError() == hipSuccess ? IHS_OK : IHS_ERR_HIP;

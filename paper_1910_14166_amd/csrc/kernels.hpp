@@ -110,11 +110,15 @@ hipError_t launch_gradient_rows_csr(const ProbInfo* probs, int32_t batch,
 
 // g[p][:] = sum over parts w (ascending, fixed tree) of gpart[p][w][:];
 // parts_of(p) = nparts_fixed if > 0, else probs[p].nseg (natural-order passes).
+// scratch: reduce_scratch_doubles(batch, d) doubles.
+size_t reduce_scratch_doubles(int32_t batch, int64_t d);
 hipError_t launch_reduce_partials(const double* gpart, const double* fpart,
                                   int32_t batch, int64_t parts_fixed,
                                   const ProbInfo* probs, int64_t d, double* g,
                                   double* f, DeviceStatus* status, int32_t iter,
-                                  hipStream_t st);
+                                  double* scratch, hipStream_t st);
+hipError_t launch_recip_diag(const double* L, int64_t d, int32_t batch, double* rdiag,
+                             hipStream_t st);
 
 // Gram H = SA^T SA.
 size_t gram_partials_bytes(int64_t m, int64_t d, int32_t batch, int32_t in_dtype,
@@ -148,13 +152,15 @@ hipError_t launch_qp_step(const QpArgs& a, hipStream_t st);
 
 // Cholesky alone (lower factor of each H into L) and the two triangular
 // solves applied to a right-hand side: out = in + (L L^T)^{-1} v.
-// dside: batch * 64 * 64 doubles of scratch (blocked path only).
+// scratch: batch * (64*64 + d) doubles: the diagonal-block side buffers of
+// the blocked path, then the reciprocal pivots 1/L_jj (chol_rdiag).
 hipError_t launch_cholesky(const double* H, double* L, int64_t d, int32_t batch,
-                           DeviceStatus* status, int32_t iter, double shift, double* dside,
+                           DeviceStatus* status, int32_t iter, double shift, double* scratch,
                            hipStream_t st);
-hipError_t launch_chol_solve_update(const double* L, int64_t d, int32_t batch,
-                                    const double* v, const double* base, double* out,
-                                    DeviceStatus* status, hipStream_t st);
+double* chol_rdiag(double* scratch, int32_t batch);
+hipError_t launch_chol_solve_update(const double* L, const double* rdiag, int64_t d,
+                                    int32_t batch, const double* v, const double* base,
+                                    double* out, DeviceStatus* status, hipStream_t st);
 
 // Adjoint and solution-gradient passes.
 // S^T G for the nrows rows of one problem (G points at that problem's m rows).

@@ -29,63 +29,89 @@ __device__ __forceinline__ void wave_sync_lds() {
 }
 
 // ---------------------------------------------------------------------------
-// Gradient partial reduction: g[p][:] = sum_w gpart[p][w][:] in a fixed tree.
+// Gradient partial reduction, g[p][:] = sum_w gpart[p][w][:], in a fixed
+// two-level order: kRedSplit x 4 contiguous groups of parts are summed in
+// ascending order (first kernel), then the group sums in ascending order
+// (second kernel). The objective f[p] follows the same pattern.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_reduce_partials(const double* __restrict__ gpart,
-                                                          const double* __restrict__ fpart,
-                                                          int32_t batch, int64_t parts_fixed,
-                                                          const ProbInfo* probs, int64_t d,
-                                                          double* g, double* f,
-                                                          DeviceStatus* st, int32_t iter) {
-  __shared__ double red[16][64];
-  __shared__ double fred[1024];
-  const int p = blockIdx.x;
-  const int tid = threadIdx.x, lane = tid & 63, grp = tid >> 6;
+constexpr int kRedSplit = 16;
+
+__global__ __launch_bounds__(256) void k_reduce_a(const double* __restrict__ gpart,
+                                                  const double* __restrict__ fpart,
+                                                  int64_t parts_fixed, const ProbInfo* probs,
+                                                  int64_t d, double* red, double* fred) {
+  const int p = blockIdx.z;
+  const int split = blockIdx.y;
+  const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
   const int64_t nparts = parts_fixed > 0 ? parts_fixed : (int64_t)probs[p].nseg;
   const int64_t pbase = parts_fixed > 0 ? (int64_t)p * parts_fixed : (int64_t)probs[p].seg0;
-  const int64_t col = (int64_t)blockIdx.y * 64 + lane;
-  const int64_t per = (nparts + 15) / 16;
+  const int grp = split * 4 + q;  // 0 .. 4*kRedSplit-1
+  const int64_t per = (nparts + 4 * kRedSplit - 1) / (4 * kRedSplit);
   const int64_t w0 = min((int64_t)grp * per, nparts), w1 = min(w0 + per, nparts);
-  double s = 0.0;
-  if (col < d)
-    for (int64_t w = w0; w < w1; ++w) s += gpart[(pbase + w) * d + col];
-  red[grp][lane] = s;
-  if (blockIdx.y == 0) {
-    double fs = 0.0;
-    const int64_t fper = (nparts + 1023) / 1024;
-    const int64_t f0 = min((int64_t)tid * fper, nparts), f1 = min(f0 + fper, nparts);
-    for (int64_t w = f0; w < f1; ++w) fs += fpart[pbase + w];
-    fred[tid] = fs;
-  }
-  __syncthreads();
-  if (grp == 0 && col < d) {
-    double t = 0.0;
-#pragma unroll
-    for (int q = 0; q < 16; ++q) t += red[q][lane];
-    g[(int64_t)p * d + col] = t;
-  }
-  if (blockIdx.y == 0) {
-    for (int stride = 512; stride > 0; stride >>= 1) {
-      __syncthreads();
-      if (tid < stride) fred[tid] = fred[tid] + fred[tid + stride];
-    }
-    if (tid == 0) {
-      const double fv = 0.5 * fred[0];
-      if (f != nullptr) f[p] = fv;
-      if (st != nullptr) {
-        if (p == 0) st->objective = fv;
-        if (!isfinite(fv)) status_fail(st, 7 /* IHS_ERR_NONFINITE */, iter, p);
+  {
+    const int64_t col = (int64_t)blockIdx.x * 64 + lane;
+    double s = 0.0;
+    if (col < d) {
+      int64_t w = w0;
+      for (; w + 4 <= w1; w += 4) {
+        const double a0 = gpart[(pbase + w) * d + col];
+        const double a1 = gpart[(pbase + w + 1) * d + col];
+        const double a2 = gpart[(pbase + w + 2) * d + col];
+        const double a3 = gpart[(pbase + w + 3) * d + col];
+        s += a0;
+        s += a1;
+        s += a2;
+        s += a3;
       }
+      for (; w < w1; ++w) s += gpart[(pbase + w) * d + col];
+      red[((int64_t)p * 4 * kRedSplit + grp) * d + col] = s;
     }
   }
+  if (blockIdx.x == 0 && lane == 0) {
+    double fs = 0.0;
+    for (int64_t w = w0; w < w1; ++w) fs += fpart[pbase + w];
+    fred[(int64_t)p * 4 * kRedSplit + grp] = fs;
+  }
+}
+
+__global__ __launch_bounds__(64) void k_reduce_b(const double* __restrict__ red,
+                                                 const double* __restrict__ fred, int64_t d,
+                                                 double* g, double* f, DeviceStatus* st,
+                                                 int32_t iter) {
+  const int p = blockIdx.y;
+  const int64_t col = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  if (col < d) {
+    double s = 0.0;
+    for (int q = 0; q < 4 * kRedSplit; ++q) s += red[((int64_t)p * 4 * kRedSplit + q) * d + col];
+    g[(int64_t)p * d + col] = s;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    double fs = 0.0;
+    for (int q = 0; q < 4 * kRedSplit; ++q) fs += fred[(int64_t)p * 4 * kRedSplit + q];
+    const double fv = 0.5 * fs;
+    if (f != nullptr) f[p] = fv;
+    if (st != nullptr) {
+      if (p == 0) st->objective = fv;
+      if (!isfinite(fv)) status_fail(st, 7 /* IHS_ERR_NONFINITE */, iter, p);
+    }
+  }
+}
+
+size_t reduce_scratch_doubles(int32_t batch, int64_t d) {
+  return (size_t)batch * 4 * kRedSplit * (d + 1);
 }
 
 hipError_t launch_reduce_partials(const double* gpart, const double* fpart, int32_t batch,
                                   int64_t parts_fixed, const ProbInfo* probs, int64_t d,
                                   double* g, double* f, DeviceStatus* status, int32_t iter,
-                                  hipStream_t st) {
-  hipLaunchKernelGGL(k_reduce_partials, dim3(batch, (unsigned)((d + 63) / 64)), dim3(1024), 0,
-                     st, gpart, fpart, batch, parts_fixed, probs, d, g, f, status, iter);
+                                  double* scratch, hipStream_t st) {
+  double* red = scratch;
+  double* fred = scratch + (int64_t)batch * 4 * kRedSplit * d;
+  hipLaunchKernelGGL(k_reduce_a, dim3((unsigned)((d + 63) / 64), kRedSplit, batch), dim3(256), 0,
+                     st, gpart, fpart,
+                     parts_fixed, probs, d, red, fred);
+  hipLaunchKernelGGL(k_reduce_b, dim3((unsigned)((d + 63) / 64), batch), dim3(64), 0, st, red,
+                     fred, d, g, f, status, iter);
   return hipGetLastError();
 }
 
@@ -94,7 +120,7 @@ hipError_t launch_reduce_partials(const double* gpart, const double* fpart, int3
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_chol_small(const double* __restrict__ H, double* L,
                                                     int64_t d, DeviceStatus* st, int32_t iter,
-                                                    double shift) {
+                                                    double shift, double* rdiag) {
   extern __shared__ double a[];
   __shared__ int fail;
   const int p = blockIdx.x;
@@ -121,7 +147,10 @@ __global__ __launch_bounds__(256) void k_chol_small(const double* __restrict__ H
     }
     const double ljj = sqrt(piv);
     __syncthreads();
-    if (tid == 0) a[j * d + j] = ljj;
+    if (tid == 0) {
+      a[j * d + j] = ljj;
+      rdiag[(int64_t)p * d + j] = 1.0 / ljj;
+    }
     for (int64_t i = j + 1 + tid; i < d; i += 256) a[i * d + j] = a[i * d + j] / ljj;
     __syncthreads();
     const int64_t w = d - j - 1;
@@ -151,52 +180,59 @@ __global__ __launch_bounds__(256) void k_chol_init(const double* __restrict__ H,
 // Every workgroup of a panel launch reads the unfactored diagonal block and
 // factors it in LDS; nobody writes that block during the launch (workgroup 0
 // leaves the factor in `dside`, and the update launch copies it back).
+// The block is factored by all 256 threads (right-looking, one barrier per
+// column); each thread then solves one panel row x L_kk^T = a in registers,
+// column by column so the updates of different entries are independent.
+// Workgroup 0 also stores the reciprocal pivots 1/L_jj in `rdiag`.
 __global__ __launch_bounds__(256) void k_chol_panel(double* L, int64_t d, int64_t kb,
-                                                    double* dside, DeviceStatus* st,
-                                                    int32_t iter) {
+                                                    double* dside, double* rdiag,
+                                                    DeviceStatus* st, int32_t iter) {
   __shared__ double D[kNb][kNb + 1];
-  __shared__ int fail;
+  __shared__ double rd[kNb];
+  __shared__ int flag;
   const int p = blockIdx.y;
-  if (threadIdx.x == 0) fail = st->code;
+  const int tid = threadIdx.x;
+  if (tid == 0) flag = st->code;
   __syncthreads();
-  if (fail != 0) return;
+  if (flag != 0) return;
   double* W = L + (int64_t)p * d * d;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nb = (int)min((int64_t)kNb, d - kb);
   for (int e = tid; e < kNb * kNb; e += 256) {
     const int i = e / kNb, j = e % kNb;
     D[i][j] = (i < nb && j <= i) ? W[(kb + i) * d + kb + j] : 0.0;
   }
   __syncthreads();
-  if (wv == 0) {
-    for (int j = 0; j < nb; ++j) {
-      const double piv = D[j][j];
-      if (!(piv > 0.0) || !isfinite(piv)) {
-        if (lane == 0) {
-          fail = 1;
-          if (blockIdx.x == 0) status_fail(st, 5 /* IHS_ERR_NOT_PD */, iter, p);
-        }
-        break;
-      }
-      const double ljj = sqrt(piv);
-      wave_sync_lds();
-      if (lane == j) D[j][j] = ljj;
-      if (lane > j && lane < nb) D[lane][j] = D[lane][j] / ljj;
-      wave_sync_lds();
-      if (lane > j && lane < nb) {
-        const double lij = D[lane][j];
-        for (int k = j + 1; k <= lane; ++k) D[lane][k] = fma(-lij, D[k][j], D[lane][k]);
-      }
-      wave_sync_lds();
+  int bad = 0;
+  for (int j = 0; j < nb; ++j) {
+    const double piv = D[j][j];
+    if (!(piv > 0.0) || !isfinite(piv)) {  // every thread sees the same pivot
+      bad = 1;
+      break;
     }
+    const double ljj = sqrt(piv);
+    const double r = 1.0 / ljj;
+    const int w = nb - j - 1;
+    for (int e = tid; e < w * w; e += 256) {
+      const int i = j + 1 + e / w, k = j + 1 + e % w;
+      if (k <= i) D[i][k] = fma(-(D[i][j] * r), D[k][j] * r, D[i][k]);
+    }
+    __syncthreads();  // column j is no longer read: scale it
+    if (tid == 0) {
+      D[j][j] = ljj;
+      rd[j] = r;
+    }
+    for (int i = j + 1 + tid; i < nb; i += 256) D[i][j] = D[i][j] * r;
   }
   __syncthreads();
-  if (fail) return;
+  if (bad) {
+    if (tid == 0 && blockIdx.x == 0) status_fail(st, 5 /* IHS_ERR_NOT_PD */, iter, p);
+    return;
+  }
   if (blockIdx.x == 0) {
     double* ds = dside + (int64_t)p * kNb * kNb;
     for (int e = tid; e < kNb * kNb; e += 256) ds[e] = D[e / kNb][e % kNb];
+    for (int j = tid; j < nb; j += 256) rdiag[(int64_t)p * d + kb + j] = rd[j];
   }
-  // panel rows below the diagonal block: x L_kk^T = a
   const int64_t row = kb + nb + (int64_t)blockIdx.x * 256 + tid;
   if (row >= d) return;
   double x[kNb];
@@ -206,10 +242,9 @@ __global__ __launch_bounds__(256) void k_chol_panel(double* L, int64_t d, int64_
 #pragma unroll
   for (int c = 0; c < kNb; ++c) {
     if (c < nb) {
-      double s = x[c];
+      x[c] = x[c] * rd[c];
 #pragma unroll
-      for (int k = 0; k < c; ++k) s = fma(-x[k], D[c][k], s);
-      x[c] = s / D[c][c];
+      for (int k = c + 1; k < kNb; ++k) x[k] = fma(-x[c], D[k][c], x[k]);
     }
   }
 #pragma unroll
@@ -277,11 +312,13 @@ __global__ __launch_bounds__(256) void k_chol_update(double* L, int64_t d, int64
 }
 
 hipError_t launch_cholesky(const double* H, double* L, int64_t d, int32_t batch,
-                           DeviceStatus* status, int32_t iter, double shift, double* dside,
+                           DeviceStatus* status, int32_t iter, double shift, double* scratch,
                            hipStream_t st) {
+  double* dside = scratch;
+  double* rdiag = scratch + (int64_t)batch * kNb * kNb;
   if (d <= kSmallChol) {
     hipLaunchKernelGGL(k_chol_small, dim3(batch), dim3(256), (size_t)(d * d * sizeof(double)),
-                       st, H, L, d, status, iter, shift);
+                       st, H, L, d, status, iter, shift, rdiag);
     return hipGetLastError();
   }
   const int64_t tot = (int64_t)batch * d * d;
@@ -290,8 +327,8 @@ hipError_t launch_cholesky(const double* H, double* L, int64_t d, int32_t batch,
   for (int64_t kb = 0; kb < d; kb += kNb) {
     const int64_t below = std::max<int64_t>(0, d - kb - kNb);
     const unsigned gx = (unsigned)std::max<int64_t>(1, (below + 255) / 256);
-    hipLaunchKernelGGL(k_chol_panel, dim3(gx, batch), dim3(256), 0, st, L, d, kb, dside, status,
-                       iter);
+    hipLaunchKernelGGL(k_chol_panel, dim3(gx, batch), dim3(256), 0, st, L, d, kb, dside, rdiag,
+                       status, iter);
     const int64_t T = (below + 31) / 32;
     const int64_t waves = T * (T + 1) / 2 * batch;
     const unsigned gu = (unsigned)std::max<int64_t>(1, (waves + 3) / 4);
@@ -302,19 +339,24 @@ hipError_t launch_cholesky(const double* H, double* L, int64_t d, int32_t batch,
 }
 
 // ---------------------------------------------------------------------------
-// out = base + (L L^T)^{-1} v, one workgroup per problem.
-// Also records sqrt(dx^T v) (= sqrt(dx^T H dx) when H dx = v) for problem 0.
+// out = base + (L L^T)^{-1} v, one workgroup (256 threads) per problem.
+// Each 64 x 64 diagonal block is solved by wavefront 0 with the block held in
+// registers (lane i keeps row i, or column i for the transposed sweep) and
+// the reciprocal pivots from the factorisation; the rest of the vector is
+// then updated by all threads. Also records sqrt(dx^T v) for problem 0.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_chol_solve(const double* __restrict__ L, int64_t d,
-                                                    const double* __restrict__ v,
-                                                    const double* base, double* out,
-                                                    DeviceStatus* st) {
+                                                     const double* __restrict__ rdiag,
+                                                     const double* __restrict__ v,
+                                                     const double* base, double* out,
+                                                     DeviceStatus* st) {
   extern __shared__ double y[];
   __shared__ double red[256];
   __shared__ int code;
   const int p = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const double* Lp = L + (int64_t)p * d * d;
+  const double* rp = rdiag + (int64_t)p * d;
   const double* vp = v + (int64_t)p * d;
   const double* bp = base + (int64_t)p * d;
   double* op = out + (int64_t)p * d;
@@ -331,19 +373,28 @@ __global__ __launch_bounds__(256) void k_chol_solve(const double* __restrict__ L
   for (int64_t jb = 0; jb < d; jb += 64) {
     const int nb = (int)min((int64_t)64, d - jb);
     if (wv == 0) {
+      double lr[64];
+      const double* row = Lp + (jb + lane) * d + jb;
+#pragma unroll
+      for (int k = 0; k < 64; ++k) lr[k] = (lane < nb && k < lane) ? row[k] : 0.0;
       double yl = lane < nb ? y[jb + lane] : 0.0;
-      for (int c = 0; c < nb; ++c) {
-        if (lane == c) yl = yl / Lp[(jb + c) * d + jb + c];
-        const double yc = __shfl(yl, c, 64);
-        if (lane > c && lane < nb) yl = fma(-Lp[(jb + lane) * d + jb + c], yc, yl);
+      const double rl = lane < nb ? rp[jb + lane] : 0.0;
+#pragma unroll
+      for (int c = 0; c < 64; ++c) {
+        if (c < nb) {
+          if (lane == c) yl = yl * rl;
+          const double yc = __shfl(yl, c, 64);
+          if (lane > c) yl = fma(-lr[c], yc, yl);
+        }
       }
       if (lane < nb) y[jb + lane] = yl;
     }
     __syncthreads();
     for (int64_t i = jb + nb + tid; i < d; i += 256) {
-      const double* lr = Lp + i * d + jb;
+      const double* lrow = Lp + i * d + jb;
       double s = 0.0;
-      for (int c = 0; c < nb; ++c) s = fma(lr[c], y[jb + c], s);
+#pragma unroll 16
+      for (int c = 0; c < nb; ++c) s = fma(lrow[c], y[jb + c], s);
       y[i] -= s;
     }
     __syncthreads();
@@ -354,17 +405,26 @@ __global__ __launch_bounds__(256) void k_chol_solve(const double* __restrict__ L
     const int64_t jb = bi * 64;
     const int nb = (int)min((int64_t)64, d - jb);
     if (wv == 0) {
+      double lc[64];
+#pragma unroll
+      for (int k = 0; k < 64; ++k)
+        lc[k] = (lane < nb && k > lane && k < nb) ? Lp[(jb + k) * d + jb + lane] : 0.0;
       double yl = lane < nb ? y[jb + lane] : 0.0;
-      for (int c = nb - 1; c >= 0; --c) {
-        if (lane == c) yl = yl / Lp[(jb + c) * d + jb + c];
-        const double yc = __shfl(yl, c, 64);
-        if (lane < c) yl = fma(-Lp[(jb + c) * d + jb + lane], yc, yl);
+      const double rl = lane < nb ? rp[jb + lane] : 0.0;
+#pragma unroll
+      for (int c = 63; c >= 0; --c) {
+        if (c < nb) {
+          if (lane == c) yl = yl * rl;
+          const double yc = __shfl(yl, c, 64);
+          if (lane < c) yl = fma(-lc[c], yc, yl);
+        }
       }
       if (lane < nb) y[jb + lane] = yl;
     }
     __syncthreads();
     for (int64_t i = tid; i < jb; i += 256) {
       double s = 0.0;
+#pragma unroll 16
       for (int c = 0; c < nb; ++c) s = fma(Lp[(jb + c) * d + i], y[jb + c], s);
       y[i] -= s;
     }
@@ -393,19 +453,37 @@ __global__ __launch_bounds__(256) void k_chol_solve(const double* __restrict__ L
   if (p == 0 && tid == 0) st->last_step = sqrt(fmax(red[0], 0.0));
 }
 
-hipError_t launch_chol_solve_update(const double* L, int64_t d, int32_t batch, const double* v,
-                                    const double* base, double* out, DeviceStatus* status,
-                                    hipStream_t st) {
+hipError_t launch_chol_solve_update(const double* L, const double* rdiag, int64_t d,
+                                    int32_t batch, const double* v, const double* base,
+                                    double* out, DeviceStatus* status, hipStream_t st) {
   hipLaunchKernelGGL(k_chol_solve, dim3(batch), dim3(256), (size_t)(d * sizeof(double)), st, L,
-                     d, v, base, out, status);
+                     d, rdiag, v, base, out, status);
   return hipGetLastError();
 }
+
+__global__ void k_recip_diag(const double* L, int64_t d, int32_t batch, double* rdiag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)batch * d) return;
+  const int64_t p = i / d, j = i - p * d;
+  rdiag[i] = 1.0 / L[p * d * d + j * d + j];
+}
+
+hipError_t launch_recip_diag(const double* L, int64_t d, int32_t batch, double* rdiag,
+                             hipStream_t st) {
+  const int64_t n = (int64_t)batch * d;
+  hipLaunchKernelGGL(k_recip_diag, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, L, d,
+                     batch, rdiag);
+  return hipGetLastError();
+}
+
+// Reciprocal pivots inside the Cholesky scratch (after the side buffers).
+double* chol_rdiag(double* scratch, int32_t batch) { return scratch + (int64_t)batch * kNb * kNb; }
 
 // Per-problem scratch of the QP kernels: the 64 x 64 diagonal-block side
 // buffer of the blocked Cholesky plus vectors.
 size_t qp_work_doubles(int64_t d, int32_t constraint) {
   (void)constraint;
-  return (size_t)(kNb * kNb + 8 * d + 64);
+  return (size_t)(kNb * kNb + 9 * d + 64);
 }
 
 hipError_t launch_qp_step(const QpArgs& a, hipStream_t st) {
@@ -413,7 +491,8 @@ hipError_t launch_qp_step(const QpArgs& a, hipStream_t st) {
   hipError_t e = launch_cholesky(a.H, a.L, a.d, a.batch, a.status, a.iter, 0.0,
                                  a.work, st);
   if (e != hipSuccess) return e;
-  return launch_chol_solve_update(a.L, a.d, a.batch, a.g, a.x, a.x_out, a.status, st);
+  return launch_chol_solve_update(a.L, chol_rdiag(a.work, a.batch), a.d, a.batch, a.g, a.x,
+                                  a.x_out, a.status, st);
 }
 
 }  // namespace ihs

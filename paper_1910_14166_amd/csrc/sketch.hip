@@ -150,31 +150,47 @@ __global__ __launch_bounds__(256) void k_scan_chunks(SketchPlan P) {
   P.chunk_part[(int64_t)c * P.m + b] = sum;
 }
 
-// Sort step 2b: one workgroup per problem. Exclusive scan over the problem's
-// chunks for every sketch row, then an exclusive scan over sketch rows that
-// gives each segment's start in the permutation.
-__global__ __launch_bounds__(1024) void k_scan_buckets(SketchPlan P) {
-  extern __shared__ int32_t tot[];  // m totals
+// Sort step 2b: per sketch row, exclusive scan over the problem's chunks (in
+// place); the row's total goes to bucket_start, which step 2b' turns into the
+// exclusive scan over sketch rows.
+__global__ __launch_bounds__(256) void k_scan_rows(SketchPlan P) {
+  const int p = blockIdx.y;
+  const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (b >= P.m) return;
+  const ProbInfo pi = P.probs[p];
+  int32_t run = 0;
+  int c = pi.chunk0;
+  const int c1 = pi.chunk0 + pi.nchunks;
+  for (; c + 4 <= c1; c += 4) {
+    int32_t* q0 = P.chunk_part + (int64_t)c * P.m + b;
+    const int32_t v0 = q0[0], v1 = q0[P.m], v2 = q0[2 * P.m], v3 = q0[3 * P.m];
+    q0[0] = run;
+    q0[P.m] = run + v0;
+    q0[2 * P.m] = run + v0 + v1;
+    q0[3 * P.m] = run + v0 + v1 + v2;
+    run += v0 + v1 + v2 + v3;
+  }
+  for (; c < c1; ++c) {
+    int32_t* ptr = P.chunk_part + (int64_t)c * P.m + b;
+    const int32_t v = *ptr;
+    *ptr = run;
+    run += v;
+  }
+  P.bucket_start[(int64_t)p * P.m + b] = run;
+}
+
+// Sort step 2b': one workgroup per problem turns the sketch-row totals into
+// segment starts (exclusive scan, offset by the problem's first entry).
+__global__ __launch_bounds__(1024) void k_scan_totals(SketchPlan P) {
   __shared__ int32_t wsum[16];
   const int p = blockIdx.x;
   const ProbInfo pi = P.probs[p];
   const int tid = threadIdx.x;
-  for (int64_t b = tid; b < P.m; b += 1024) {
-    int32_t run = 0;
-    for (int c = pi.chunk0; c < pi.chunk0 + pi.nchunks; ++c) {
-      int32_t* ptr = P.chunk_part + (int64_t)c * P.m + b;
-      const int32_t v = *ptr;
-      *ptr = run;
-      run += v;
-    }
-    tot[b] = run;
-  }
-  __syncthreads();
+  int32_t* tot = P.bucket_start + (int64_t)p * P.m;
   const int64_t per = (P.m + 1023) / 1024;
   const int64_t lo = min((int64_t)tid * per, P.m), hi = min(lo + per, P.m);
   int32_t s = 0;
   for (int64_t b = lo; b < hi; ++b) s += tot[b];
-  // block exclusive scan of the thread sums
   const int lane = tid & 63, wv = tid >> 6;
   int32_t incl = s;
 #pragma unroll
@@ -193,16 +209,12 @@ __global__ __launch_bounds__(1024) void k_scan_buckets(SketchPlan P) {
     }
   }
   __syncthreads();
-  int32_t base = wsum[wv] + incl - s;
+  int32_t base = (int32_t)(pi.row0 * P.s) + wsum[wv] + incl - s;
   for (int64_t b = lo; b < hi; ++b) {
     const int32_t v = tot[b];
     tot[b] = base;
     base += v;
   }
-  __syncthreads();
-  const int64_t start = pi.row0 * P.s;
-  for (int64_t b = tid; b < P.m; b += 1024)
-    P.bucket_start[(int64_t)p * P.m + b] = (int32_t)(start + tot[b]);
   if (p == P.batch - 1 && tid == 0) P.bucket_start[(int64_t)P.batch * P.m] = (int32_t)P.entries;
 }
 
@@ -267,18 +279,25 @@ __global__ __launch_bounds__(256) void k_scatter(SketchPlan P) {
   }
 }
 
+__global__ void k_zero_i32(int32_t* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
 hipError_t launch_sort(const SketchPlan& P, hipStream_t st) {
+  const unsigned gy = (unsigned)((P.m + 255) / 256);
   if (P.total_tiles == 0) {
-    // every problem is empty: bucket starts are all zero
-    hipLaunchKernelGGL(k_scan_buckets, dim3(P.batch), dim3(1024),
-                       (size_t)P.m * sizeof(int32_t), st, P);
+    // every problem is empty: all segments start (and end) at 0
+    const int64_t nb = (int64_t)P.batch * P.m + 1;
+    hipLaunchKernelGGL(k_zero_i32, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, st,
+                       P.bucket_start, nb);
     return hipGetLastError();
   }
   const size_t lds_m = (size_t)P.m * sizeof(int32_t);
   hipLaunchKernelGGL(k_hash_count, dim3(P.total_tiles), dim3(256), lds_m, st, P);
-  const unsigned gy = (unsigned)((P.m + 255) / 256);
   hipLaunchKernelGGL(k_scan_chunks, dim3(P.total_chunks, gy), dim3(256), 0, st, P);
-  hipLaunchKernelGGL(k_scan_buckets, dim3(P.batch), dim3(1024), lds_m, st, P);
+  hipLaunchKernelGGL(k_scan_rows, dim3(gy, P.batch), dim3(256), 0, st, P);
+  hipLaunchKernelGGL(k_scan_totals, dim3(P.batch), dim3(1024), 0, st, P);
   hipLaunchKernelGGL(k_scan_tiles, dim3(P.total_chunks, gy), dim3(256), 0, st, P);
   hipLaunchKernelGGL(k_scatter, dim3(P.total_tiles), dim3(256), lds_m, st, P);
   return hipGetLastError();
@@ -325,35 +344,91 @@ __device__ __forceinline__ void store_sa(void* SA, int32_t dt, int64_t idx, doub
   }
 }
 
+// Sum of U per-lane partial vectors across the wavefront with a transposing
+// butterfly: each exchange step halves the number of live values, so U row
+// sums cost log2(U) + (6 - log2(U)) exchanges of decreasing width instead of
+// 6 U. Afterwards lanes with bits (32, 16, ...) equal to the row index bits
+// hold that row's total; row_lane<U>(u) names one such lane. Fixed order.
+template <int U>
+__device__ __forceinline__ double multi_row_sum(const double (&v)[U], int lane) {
+  double cur[U];
+#pragma unroll
+  for (int i = 0; i < U; ++i) cur[i] = v[i];
+  int off = 32;
+#pragma unroll
+  for (int n = U; n > 1; n >>= 1) {
+    const bool hi = (lane & off) != 0;
+    const int h = n / 2;
+#pragma unroll
+    for (int i = 0; i < h; ++i) {
+      const double send = hi ? cur[i] : cur[h + i];
+      const double keep = hi ? cur[h + i] : cur[i];
+      cur[i] = keep + __shfl_xor(send, off, 64);
+    }
+    off >>= 1;
+  }
+  double s = cur[0];
+#pragma unroll
+  for (; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  return s;
+}
+
+template <int U>
+__device__ __forceinline__ int row_lane(int u) {
+  // row u's bits, most significant first, select lanes 32, 16, ...
+  int lane = 0, off = 32;
+#pragma unroll
+  for (int bit = U / 2; bit > 0; bit >>= 1, off >>= 1)
+    if (u & bit) lane += off;
+  return lane;
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+
 // IDENT: natural row order (no sketch): wavefront w takes rows
 // [row0 + seg*seg_rows, ...) of its problem, and only the gradient is formed.
+// Otherwise the grid is (ceil(m/4), batch): wavefront wv of workgroup x owns
+// sketch row 4x + wv of problem blockIdx.y, and the four wavefronts add their
+// gradient partials in LDS (fixed order) into one partial per workgroup.
 template <typename TA, int VEC, int NCH, int U, bool GRAD, bool IDENT>
-__global__ __launch_bounds__(256) void k_gather(SketchPlan P, GatherArgs G, int32_t total_seg,
-                                                int32_t seg_rows) {
+__global__ __launch_bounds__(256, (NCH <= 4 ? 4 : 2)) void k_gather(SketchPlan P, GatherArgs G,
+                                                                    int32_t total_seg,
+                                                                    int32_t seg_rows) {
+  extern __shared__ double gsh[];  // 4 x d (fused gradient, non-IDENT)
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t nbk = IDENT ? (int64_t)total_seg : (int64_t)P.batch * P.m;
-  const int64_t bg = (int64_t)blockIdx.x * 4 + wv;
-  if (bg >= nbk) return;
+  const int64_t d = G.d;
+  constexpr int SPAN = 64 * VEC;
   int p;
-  int64_t bl, beg, end, gslot;
+  int64_t bl, beg = 0, end = 0, gslot, bg;
+  bool active;
   if (IDENT) {
-    p = find_by_seg(P.probs, P.batch, (int)bg);
-    const ProbInfo pi = P.probs[p];
-    beg = pi.row0 + (bg - pi.seg0) * (int64_t)seg_rows;
-    end = min(beg + seg_rows, pi.row0 + pi.rows);
+    bg = (int64_t)blockIdx.x * 4 + wv;
+    active = bg < total_seg;
+    p = active ? find_by_seg(P.probs, P.batch, (int)bg) : 0;
+    if (active) {
+      const ProbInfo pi = P.probs[p];
+      beg = pi.row0 + (bg - pi.seg0) * (int64_t)seg_rows;
+      end = min(beg + seg_rows, pi.row0 + pi.rows);
+    }
     bl = 0;
     gslot = bg;
   } else {
-    p = (int)(bg / P.m);
-    bl = bg - (int64_t)p * P.m;
-    beg = P.bucket_start[bg];
-    end = P.bucket_start[bg + 1];
-    gslot = (int64_t)p * P.m_blk + bl;
+    p = blockIdx.y;
+    bl = (int64_t)blockIdx.x * 4 + wv;
+    active = bl < P.m;
+    bg = (int64_t)p * P.m + bl;
+    if (active) {
+      beg = P.bucket_start[bg];
+      end = P.bucket_start[bg + 1];
+    }
+    gslot = (int64_t)p * ((P.m_blk + 3) / 4) + blockIdx.x;
   }
-  const bool grad = GRAD && (bl < P.m_blk);  // block 0 visits every row once
+  const bool grad = GRAD && active && (bl < P.m_blk);  // block 0 visits every row once
   const TA* __restrict__ A = static_cast<const TA*>(G.A);
-  const int64_t d = G.d;
-  constexpr int SPAN = 64 * VEC;
 
   double acc[NCH][VEC];
   double xr[NCH][VEC];
@@ -377,10 +452,15 @@ __global__ __launch_bounds__(256) void k_gather(SketchPlan P, GatherArgs G, int3
       }
   }
 
+  uint32_t pe_next = 0u;
+  if (beg + lane < end) pe_next = IDENT ? (uint32_t)(beg + lane) : P.perm[beg + lane];
   for (int64_t base = beg; base < end; base += 64) {
     const int cnt = (int)min((int64_t)64, end - base);
-    uint32_t pe = 0u;
-    if (lane < cnt) pe = IDENT ? (uint32_t)(base + lane) : P.perm[base + lane];
+    const uint32_t pe = pe_next;
+    if (base + 64 + lane < end)  // next batch's row ids, one batch ahead
+      pe_next = IDENT ? (uint32_t)(base + 64 + lane) : P.perm[base + 64 + lane];
+    double bv = 0.0;
+    if (grad && lane < cnt) bv = G.b ? G.b[pe & 0x7FFFFFFFu] : 0.0;
     for (int j = 0; j < cnt; j += U) {
       double val[U][NCH][VEC];
       uint32_t ent[U];
@@ -412,37 +492,37 @@ __global__ __launch_bounds__(256) void k_gather(SketchPlan P, GatherArgs G, int3
             for (int v = 0; v < VEC; ++v) s = fma(val[u][c][v], xr[c][v], s);
           dot[u] = s;
         }
-#pragma unroll
-        for (int u = 0; u < U; ++u) dot[u] = wave_sum(dot[u]);
+        const double red = multi_row_sum<U>(dot, lane);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           if (j + u < cnt) {
-            const uint32_t row = ent[u] & 0x7FFFFFFFu;
-            const double ri = G.b[row] - dot[u];
+            const double ri = readlane_f64(bv, j + u) - readlane_f64(red, row_lane<U>(u));
             fa = fma(ri, ri, fa);
 #pragma unroll
             for (int c = 0; c < NCH; ++c)
 #pragma unroll
               for (int v = 0; v < VEC; ++v) ga[c][v] = fma(ri, val[u][c][v], ga[c][v]);
-            if (G.r_out != nullptr && lane == 0) G.r_out[row] = ri;
+            if (G.r_out != nullptr && lane == 0) G.r_out[ent[u] & 0x7FFFFFFFu] = ri;
           }
         }
       }
+      if (!IDENT) {
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        if (j + u < cnt) {
-          const bool neg = (ent[u] >> 31) != 0;
+        for (int u = 0; u < U; ++u) {
+          if (j + u < cnt) {
+            const bool neg = (ent[u] >> 31) != 0;
 #pragma unroll
-          for (int c = 0; c < NCH; ++c)
+            for (int c = 0; c < NCH; ++c)
 #pragma unroll
-            for (int v = 0; v < VEC; ++v)
-              acc[c][v] = neg ? (acc[c][v] - val[u][c][v]) : (acc[c][v] + val[u][c][v]);
+              for (int v = 0; v < VEC; ++v)
+                acc[c][v] = neg ? (acc[c][v] - val[u][c][v]) : (acc[c][v] + val[u][c][v]);
+          }
         }
       }
     }
   }
 
-  if (!IDENT) {
+  if (!IDENT && active) {
     const int64_t orow = bg * G.ld_sa;
 #pragma unroll
     for (int c = 0; c < NCH; ++c)
@@ -452,28 +532,56 @@ __global__ __launch_bounds__(256) void k_gather(SketchPlan P, GatherArgs G, int3
         if (col < d) store_sa(G.SA, G.sa_dtype, orow + col, acc[c][v] * G.scale);
       }
   }
-  if (grad) {
-    double* gp = G.gpart + gslot * d;
+  if (GRAD && IDENT) {
+    if (grad) {
+      double* gp = G.gpart + gslot * d;
 #pragma unroll
-    for (int c = 0; c < NCH; ++c)
+      for (int c = 0; c < NCH; ++c)
 #pragma unroll
-      for (int v = 0; v < VEC; ++v) {
-        const int64_t col = (int64_t)c * SPAN + lane * VEC + v;
-        if (col < d) gp[col] = ga[c][v];
-      }
-    if (lane == 0) G.fpart[gslot] = fa;
+        for (int v = 0; v < VEC; ++v) {
+          const int64_t col = (int64_t)c * SPAN + lane * VEC + v;
+          if (col < d) gp[col] = ga[c][v];
+        }
+      if (lane == 0) G.fpart[gslot] = fa;
+    }
+  } else if (GRAD) {
+    // one partial per workgroup: wavefronts 0..3 added in order
+    if ((int64_t)blockIdx.x * 4 < P.m_blk) {
+      __shared__ double fsh[4];
+#pragma unroll
+      for (int c = 0; c < NCH; ++c)
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) {
+          const int64_t col = (int64_t)c * SPAN + lane * VEC + v;
+          if (col < d) gsh[wv * d + col] = grad ? ga[c][v] : 0.0;
+        }
+      if (lane == 0) fsh[wv] = grad ? fa : 0.0;
+      __syncthreads();
+      double* gp = G.gpart + gslot * d;
+      for (int64_t col = threadIdx.x; col < d; col += 256)
+        gp[col] = ((gsh[col] + gsh[d + col]) + gsh[2 * d + col]) + gsh[3 * d + col];
+      if (threadIdx.x == 0) G.fpart[gslot] = ((fsh[0] + fsh[1]) + fsh[2]) + fsh[3];
+    }
   }
 }
 
 template <typename TA, int VEC, int NCH, bool GRAD, bool IDENT>
 static hipError_t gather_inst(const SketchPlan& P, const GatherArgs& G, int32_t total_seg,
                               int32_t seg_rows, hipStream_t st) {
-  constexpr int U = NCH <= 2 ? 8 : (NCH <= 4 ? 4 : 2);
-  const int64_t nbk = IDENT ? (int64_t)total_seg : (int64_t)P.batch * P.m;
-  const unsigned blocks = (unsigned)((nbk + 3) / 4);
-  if (blocks == 0) return hipSuccess;
-  hipLaunchKernelGGL((k_gather<TA, VEC, NCH, U, GRAD, IDENT>), dim3(blocks), dim3(256), 0, st,
-                     P, G, total_seg, seg_rows);
+  // rows in flight per wavefront: enough with 16 wavefronts per CU, while the
+  // register budget keeps 4 wavefronts per SIMD
+  constexpr int U = NCH == 1 ? 8 : (NCH == 2 ? 4 : 2);
+  if (IDENT) {
+    const unsigned blocks = (unsigned)((total_seg + 3) / 4);
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_gather<TA, VEC, NCH, U, GRAD, IDENT>), dim3(blocks), dim3(256), 0, st,
+                       P, G, total_seg, seg_rows);
+  } else {
+    const size_t lds = GRAD ? (size_t)4 * G.d * sizeof(double) : 0;
+    hipLaunchKernelGGL((k_gather<TA, VEC, NCH, U, GRAD, IDENT>),
+                       dim3((unsigned)((P.m + 3) / 4), P.batch), dim3(256), lds, st, P, G,
+                       total_seg, seg_rows);
+  }
   return hipGetLastError();
 }
 
