@@ -106,6 +106,17 @@ typedef struct {
   double qp_tol;               /* relative inner stopping tolerance; 0 = default */
   double tol;                  /* stop early once sqrt(dx^T H dx) <= tol * sqrt(x^T H x);
                                   0 = run all max_iter steps                   */
+  int32_t schedule;            /* 0: overlap the next step's sort, Gram and
+                                  factorisation with the current pass over A
+                                  on a second stream (unconstrained problems;
+                                  one extra sketch-only pass per solve);
+                                  1: strictly sequential steps. Both form
+                                  bitwise identical sketches and factors; the
+                                  iterates agree to rounding, since the fused
+                                  pass adds up A^T r in the row order of the
+                                  sketch it forms (S_{t+1} when overlapping,
+                                  S_t otherwise).                             */
+  int32_t reserved;
 } ihs_options;
 
 /* Filled by ihs_solve (host memory). */

@@ -60,7 +60,8 @@ class Options_t(ctypes.Structure):
                 ("radius", ctypes.c_double), ("sketch", Sketch_t),
                 ("gram_in", ctypes.c_int32), ("gram_acc", ctypes.c_int32),
                 ("qp_max_inner", ctypes.c_int32), ("keep_factors", ctypes.c_int32),
-                ("qp_tol", ctypes.c_double), ("tol", ctypes.c_double)]
+                ("qp_tol", ctypes.c_double), ("tol", ctypes.c_double),
+                ("schedule", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Report_t(ctypes.Structure):
@@ -217,7 +218,7 @@ class Matrix:
 
 def options(m, s=1, kind="countsketch", seed=0, iter0=0, max_iter=10, constraint="none",
             radius=0.0, gram_in="float64", gram_acc="float64", keep_factors=False,
-            qp_max_inner=0, qp_tol=0.0, tol=0.0):
+            qp_max_inner=0, qp_tol=0.0, tol=0.0, schedule="overlap"):
     o = Options_t()
     o.constraint = _CONSTRAINTS[constraint] if isinstance(constraint, str) else constraint
     o.max_iter = int(max_iter)
@@ -226,6 +227,8 @@ def options(m, s=1, kind="countsketch", seed=0, iter0=0, max_iter=10, constraint
     o.gram_in, o.gram_acc = _dt(gram_in), _dt(gram_acc)
     o.qp_max_inner, o.keep_factors = int(qp_max_inner), int(bool(keep_factors))
     o.qp_tol, o.tol = float(qp_tol), float(tol)
+    o.schedule = {"overlap": 0, "sequential": 1}[schedule] if isinstance(schedule, str) \
+        else int(schedule)
     return o
 
 

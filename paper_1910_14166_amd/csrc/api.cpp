@@ -205,6 +205,7 @@ __global__ void k_zero_status(DeviceStatus* st) {
     st->failed_problem = -1;
     st->done = 0;
     st->iters = 0;
+    st->claim = 0;
     st->objective = 0.0;
     st->last_step = 0.0;
   }
@@ -260,12 +261,23 @@ void prof_end(hipStream_t st, hipEvent_t a) {
 
 // One sketch pass: sort by the hash of (seed, iter), then gather (with the
 // fused gradient when x != nullptr).
+ihs_status run_gather(const ihs_matrix* A, const ihs_sketch* sk, const PassBuffers& B,
+                      const SketchPlan& P, void* SA, int32_t sa_dtype, int64_t ld_sa,
+                      const double* b, const double* x, double* r_out, hipStream_t st);
+
 ihs_status run_pass(const ihs_matrix* A, const Layout& L, const ihs_sketch* sk,
                     const PassBuffers& B, uint64_t iter, void* SA, int32_t sa_dtype,
                     int64_t ld_sa, const double* b, const double* x, double* r_out,
                     hipStream_t st) {
   SketchPlan P = make_plan(L, sk, B, iter);
   if (launch_sort(P, st) != hipSuccess) return IHS_ERR_HIP;
+  return run_gather(A, sk, B, P, SA, sa_dtype, ld_sa, b, x, r_out, st);
+}
+
+// The gather over A for an already sorted sketch.
+ihs_status run_gather(const ihs_matrix* A, const ihs_sketch* sk, const PassBuffers& B,
+                      const SketchPlan& P, void* SA, int32_t sa_dtype, int64_t ld_sa,
+                      const double* b, const double* x, double* r_out, hipStream_t st) {
   const double scale = sk->s > 1 ? 1.0 / std::sqrt((double)sk->s) : 1.0;
   hipEvent_t e0;
   prof_begin(st, &e0);
@@ -339,6 +351,13 @@ struct SolveBuffers {
   void* gram_part = nullptr;
   double* Lf = nullptr;
   double* work = nullptr;
+  // second set of the double-buffered arrays of the overlapped schedule
+  uint32_t* perm1 = nullptr;
+  int32_t* bstart1 = nullptr;
+  void* SA1 = nullptr;
+  double* Lf1 = nullptr;
+  double* work1 = nullptr;
+  DeviceStatus* side_status = nullptr;
 };
 
 int32_t gram_in_of(const ihs_options* o) { return o ? o->gram_in : IHS_F64; }
@@ -353,8 +372,47 @@ size_t carve_solve(Carver& c, const Layout& L, const ihs_options* o, SolveBuffer
       gram_partials_bytes(m, L.d, L.batch, gram_in_of(o), gram_acc_of(o)));
   S.Lf = c.take<double>((size_t)(L.batch * L.d * L.d));
   S.work = c.take<double>((size_t)L.batch * qp_work_doubles(L.d, o->constraint));
+  const int64_t entries = L.n * o->sketch.s;
+  S.perm1 = c.take<uint32_t>((size_t)std::max<int64_t>(entries, 1));
+  S.bstart1 = c.take<int32_t>((size_t)(L.batch * m + 1));
+  S.SA1 = c.take<char>((size_t)(L.batch * m * L.d * dtype_size(gram_in_of(o))));
+  S.Lf1 = c.take<double>((size_t)(L.batch * L.d * L.d));
+  S.work1 = c.take<double>((size_t)L.batch * qp_work_doubles(L.d, o->constraint));
+  S.side_status = c.take<DeviceStatus>(1);
   return c.used;
 }
+
+// ---- the second stream of the overlapped schedule (one per device) ----
+hipStream_t side_stream() {
+  static std::mutex mu;
+  static std::vector<hipStream_t> streams;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> lk(mu);
+  if ((int)streams.size() <= dev) streams.resize(dev + 1, nullptr);
+  if (!streams[dev]) {
+    hipStream_t s = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return nullptr;
+    streams[dev] = s;
+  }
+  return streams[dev];
+}
+
+// A ring of timing-free events; a slot is re-recorded only after every wait
+// on its previous record has been enqueued.
+struct EventRing {
+  std::vector<hipEvent_t> ev;
+  bool ok = true;
+  explicit EventRing(int n) : ev(n, nullptr) {
+    for (auto& e : ev)
+      if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) ok = false;
+  }
+  ~EventRing() {
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+  hipEvent_t at(int64_t i) { return ev[(size_t)(((i % (int64_t)ev.size()) + ev.size()) % ev.size())]; }
+};
 
 bool valid_gram_types(int32_t in, int32_t acc) {
   if (in == IHS_F64) return acc == IHS_F64;
@@ -372,6 +430,7 @@ ihs_status check_options(const ihs_options* o, bool need_loop) {
   if (need_loop && o->max_iter < 1) return IHS_ERR_INVALID_ARG;
   if (!valid_gram_types(o->gram_in, o->gram_acc)) return IHS_ERR_INVALID_ARG;
   if (o->tol < 0.0 || o->qp_tol < 0.0 || o->qp_max_inner < 0) return IHS_ERR_INVALID_ARG;
+  if (o->schedule != 0 && o->schedule != 1) return IHS_ERR_INVALID_ARG;
   return IHS_OK;
 }
 
@@ -380,6 +439,116 @@ ihs_status read_status(DeviceStatus* dev, DeviceStatus* host, hipStream_t st) {
     return IHS_ERR_HIP;
   if (hipStreamSynchronize(st) != hipSuccess) return IHS_ERR_HIP;
   return IHS_OK;
+}
+
+// The overlapped schedule of the IHS loop (unconstrained problems). Step t
+// needs the factor of H_t = (S_t A)^T (S_t A) and g(x^t); since S_t does not
+// depend on x, the pass that forms g(x^t) also forms S_{t+1} A, and a second
+// stream sorts rows for S_{t+2}, forms H_{t+1} and factors it while the main
+// stream runs the next pass over A. A sketch-only pass first forms S_0 A.
+// Sketches and factors are bitwise those of the sequential loop; g(x^t) is
+// summed in the row order of S_{t+1} instead of S_t, so iterates agree with
+// the sequential loop to rounding.
+ihs_status solve_overlap(const ihs_matrix* A, const Layout& L, const ihs_options* opt,
+                         SolveBuffers& S, const double* b, double* x, double* x_hist,
+                         double* factors, ihs_report* rep, hipStream_t stream) {
+  hipStream_t side = side_stream();
+  if (!side) return IHS_ERR_HIP;
+  PassBuffers& B = S.pass;
+  const int32_t N = opt->max_iter;
+  const int64_t d = A->d, m = opt->sketch.m;
+  const int64_t bd = (int64_t)L.batch * d;
+  EventRing evSort(4), evPass(4), evChol(4), evMisc(2);
+  if (!evSort.ok || !evPass.ok || !evChol.ok || !evMisc.ok) return IHS_ERR_HIP;
+  auto ck = [](hipError_t e) { return e == hipSuccess; };
+  // the side stream starts after everything already queued on the caller's stream
+  if (!ck(hipEventRecord(evMisc.at(0), stream)) || !ck(hipStreamWaitEvent(side, evMisc.at(0), 0)))
+    return IHS_ERR_HIP;
+  hipLaunchKernelGGL(k_zero_status, dim3(1), dim3(64), 0, side, S.side_status);
+
+  auto plan_for = [&](int64_t k) {  // sketch S_k, sorted into buffer set k % 2
+    SketchPlan P = make_plan(L, &opt->sketch, B, opt->sketch.iter + (uint64_t)k);
+    if (k % 2) {
+      P.perm = S.perm1;
+      P.bucket_start = S.bstart1;
+    }
+    return P;
+  };
+  auto sa_buf = [&](int64_t k) { return (k % 2) ? S.SA1 : S.SA; };
+  auto l_buf = [&](int64_t k) {
+    return factors ? factors + k * L.batch * d * d : ((k % 2) ? S.Lf1 : S.Lf);
+  };
+  auto w_buf = [&](int64_t k) { return (k % 2) ? S.work1 : S.work; };
+  auto factor = [&](int64_t k) -> bool {  // side stream: H_k and its Cholesky factor
+    if (!ck(launch_gram(sa_buf(k), opt->gram_in, m, d, d, L.batch, opt->gram_acc, S.H,
+                        S.gram_part, side)))
+      return false;
+    return ck(launch_cholesky(S.H, l_buf(k), d, L.batch, S.side_status, (int32_t)k, 0.0,
+                              w_buf(k), side));
+  };
+
+  // prologue: sort S_0 and S_1, sketch-only pass for S_0 A, factor H_0
+  if (!ck(launch_sort(plan_for(0), side)) || !ck(hipEventRecord(evSort.at(0), side)))
+    return IHS_ERR_HIP;
+  if (!ck(launch_sort(plan_for(1), side)) || !ck(hipEventRecord(evSort.at(1), side)))
+    return IHS_ERR_HIP;
+  if (!ck(hipStreamWaitEvent(stream, evSort.at(0), 0))) return IHS_ERR_HIP;
+  ihs_status s = run_gather(A, &opt->sketch, B, plan_for(0), sa_buf(0), opt->gram_in, d,
+                            nullptr, nullptr, nullptr, stream);
+  if (s != IHS_OK) return s;
+  if (!ck(hipEventRecord(evPass.at(-1), stream)) || !ck(hipStreamWaitEvent(side, evPass.at(-1), 0)))
+    return IHS_ERR_HIP;
+  if (!factor(0) || !ck(hipEventRecord(evChol.at(0), side))) return IHS_ERR_HIP;
+
+  for (int32_t t = 0; t < N; ++t) {
+    // main: pass P_t forms g(x^t) and S_{t+1} A
+    if (!ck(hipStreamWaitEvent(stream, evSort.at(t + 1), 0))) return IHS_ERR_HIP;
+    s = run_gather(A, &opt->sketch, B, plan_for(t + 1), sa_buf(t + 1), opt->gram_in, d, b, x,
+                   nullptr, stream);
+    if (s != IHS_OK) return s;
+    if (!ck(hipEventRecord(evPass.at(t), stream))) return IHS_ERR_HIP;
+    if (!ck(launch_reduce_partials(B.gpart, B.fpart, L.batch, pass_parts(A, &opt->sketch),
+                                   B.probs, d, B.g, B.f, B.status, t, B.red, stream)))
+      return IHS_ERR_HIP;
+    // side: sort for P_{t+1}, then H_{t+1} and its factor
+    if (!ck(hipStreamWaitEvent(side, evPass.at(t), 0))) return IHS_ERR_HIP;
+    if (t + 2 <= N) {
+      if (!ck(launch_sort(plan_for(t + 2), side)) || !ck(hipEventRecord(evSort.at(t + 2), side)))
+        return IHS_ERR_HIP;
+    }
+    if (t + 1 < N) {
+      if (!factor(t + 1) || !ck(hipEventRecord(evChol.at(t + 1), side))) return IHS_ERR_HIP;
+    }
+    // main: x^{t+1} = x^t + H_t^{-1} g(x^t)
+    if (!ck(hipStreamWaitEvent(stream, evChol.at(t), 0))) return IHS_ERR_HIP;
+    if (!ck(launch_chol_solve_update(l_buf(t), chol_rdiag(w_buf(t), L.batch), d, L.batch, B.g,
+                                     x, x, B.status, stream, S.side_status, t)))
+      return IHS_ERR_HIP;
+    if (x_hist && !ck(hipMemcpyAsync(x_hist + (int64_t)t * bd, x, bd * sizeof(double),
+                                     hipMemcpyDeviceToDevice, stream)))
+      return IHS_ERR_HIP;
+  }
+  if (!ck(hipEventRecord(evMisc.at(1), side)) || !ck(hipStreamWaitEvent(stream, evMisc.at(1), 0)))
+    return IHS_ERR_HIP;
+  DeviceStatus hm, hs;
+  if (read_status(B.status, &hm, stream) != IHS_OK) return IHS_ERR_HIP;
+  if (read_status(S.side_status, &hs, stream) != IHS_OK) return IHS_ERR_HIP;
+  // the earlier of the two failures (the side stream only fails with NOT_PD)
+  DeviceStatus f = hm;
+  if (hs.code && (!hm.code || hs.failed_iter < hm.failed_iter || hm.failed_iter < 0)) {
+    f.code = hs.code;
+    f.failed_iter = hs.failed_iter;
+    f.failed_problem = hs.failed_problem;
+  }
+  if (rep) {
+    rep->status = f.code;
+    rep->failed_iter = f.code ? f.failed_iter : -1;
+    rep->failed_problem = f.code ? f.failed_problem : -1;
+    rep->iters = f.code ? std::max(0, f.failed_iter) : N;
+    rep->objective = hm.objective;
+    rep->last_step = hm.last_step;
+  }
+  return (ihs_status)f.code;
 }
 
 }  // namespace
@@ -577,6 +746,8 @@ ihs_status ihs_solve(const ihs_matrix* A, const double* b, const ihs_options* op
   carve_solve(c, L, opt, S);
   PassBuffers& B = S.pass;
   if ((s = upload_probs(L, B, stream)) != IHS_OK) return s;
+  if (opt->schedule == 0 && opt->constraint == IHS_UNCONSTRAINED && opt->max_iter >= 2)
+    return solve_overlap(A, L, opt, S, b, x, x_hist, factors, rep, stream);
   const int64_t d = A->d, m = opt->sketch.m;
   const int64_t bd = (int64_t)L.batch * d;
   for (int32_t t = 0; t < opt->max_iter; ++t) {

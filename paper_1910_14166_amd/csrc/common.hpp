@@ -102,17 +102,32 @@ struct DeviceStatus {
   int32_t failed_problem;
   int32_t done;          // early-stop flag of the outer loop
   int32_t iters;         // steps whose update was applied
-  int32_t pad[3];
+  int32_t claim;         // first failure wins the claim, then publishes
+  int32_t pad[2];
   double objective;      // 1/2 ||A x - b||^2 of problem 0 at the last pass
   double last_step;      // sqrt(dx^T H dx) of problem 0 at the last step
 };
 
+// The first failing thread claims the record, writes where it failed, and
+// only then publishes the code, so a reader that sees a non-zero code (from
+// any stream) also sees the step and problem it belongs to.
 __device__ __forceinline__ void status_fail(DeviceStatus* st, int code, int iter,
                                             int problem) {
-  if (atomicCAS(&st->code, 0, code) == 0) {
+  if (atomicCAS(&st->claim, 0, 1) == 0) {
     st->failed_iter = iter;
     st->failed_problem = problem;
+    __threadfence();
+    atomicExch(&st->code, code);
   }
+}
+
+// True when `st` records a failure at or before step `iter` (iter < 0: any).
+__device__ __forceinline__ bool status_failed_by(const DeviceStatus* st, int iter) {
+  const int code = __atomic_load_n(&st->code, __ATOMIC_ACQUIRE);
+  if (code == 0) return false;
+  if (iter < 0) return true;
+  const int fi = __atomic_load_n(&st->failed_iter, __ATOMIC_RELAXED);
+  return fi <= iter;
 }
 
 }  // namespace ihs

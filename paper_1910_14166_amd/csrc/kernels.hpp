@@ -158,9 +158,13 @@ hipError_t launch_cholesky(const double* H, double* L, int64_t d, int32_t batch,
                            DeviceStatus* status, int32_t iter, double shift, double* scratch,
                            hipStream_t st);
 double* chol_rdiag(double* scratch, int32_t batch);
+// Skips the update (out = base) when `status` records any failure or `gate`
+// (nullable, another stream's record) a failure at or before step gate_iter.
 hipError_t launch_chol_solve_update(const double* L, const double* rdiag, int64_t d,
                                     int32_t batch, const double* v, const double* base,
-                                    double* out, DeviceStatus* status, hipStream_t st);
+                                    double* out, DeviceStatus* status, hipStream_t st,
+                                    const DeviceStatus* gate = nullptr,
+                                    int32_t gate_iter = -1);
 
 // Adjoint and solution-gradient passes.
 // S^T G for the nrows rows of one problem (G points at that problem's m rows).

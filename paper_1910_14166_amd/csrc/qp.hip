@@ -349,7 +349,8 @@ __global__ __launch_bounds__(256) void k_chol_solve(const double* __restrict__ L
                                                      const double* __restrict__ rdiag,
                                                      const double* __restrict__ v,
                                                      const double* base, double* out,
-                                                     DeviceStatus* st) {
+                                                     DeviceStatus* st, const DeviceStatus* gate,
+                                                     int32_t gate_iter) {
   extern __shared__ double y[];
   __shared__ double red[256];
   __shared__ int code;
@@ -360,7 +361,10 @@ __global__ __launch_bounds__(256) void k_chol_solve(const double* __restrict__ L
   const double* vp = v + (int64_t)p * d;
   const double* bp = base + (int64_t)p * d;
   double* op = out + (int64_t)p * d;
-  if (tid == 0) code = st->code;
+  if (tid == 0) {
+    code = status_failed_by(st, -1) ? 1 : 0;
+    if (gate != nullptr && status_failed_by(gate, gate_iter)) code = 1;
+  }
   __syncthreads();
   if (code != 0) {
     if (op != bp)
@@ -455,9 +459,10 @@ __global__ __launch_bounds__(256) void k_chol_solve(const double* __restrict__ L
 
 hipError_t launch_chol_solve_update(const double* L, const double* rdiag, int64_t d,
                                     int32_t batch, const double* v, const double* base,
-                                    double* out, DeviceStatus* status, hipStream_t st) {
+                                    double* out, DeviceStatus* status, hipStream_t st,
+                                    const DeviceStatus* gate, int32_t gate_iter) {
   hipLaunchKernelGGL(k_chol_solve, dim3(batch), dim3(256), (size_t)(d * sizeof(double)), st, L,
-                     d, rdiag, v, base, out, status);
+                     d, rdiag, v, base, out, status, gate, gate_iter);
   return hipGetLastError();
 }
 

@@ -229,3 +229,38 @@ def test_ihs_deterministic(gpu_lib):
     a = P.solve(M, dev(wl.b), opts).x
     b = P.solve(M, dev(wl.b), opts).x
     assert bool((a == b).all())
+
+
+@pytest.mark.parametrize("shape", [(30000, 64, 640, 1), (20000, 256, 2048, 1), (9000, 40, 400, 3)])
+def test_overlap_schedule_matches_sequential(gpu_lib, shape):
+    P = gpu_lib
+    n, d, m, batch = shape
+    g = np.random.default_rng(n + d)
+    A = g.standard_normal((n, d))
+    b = g.standard_normal(n)
+    offs = None if batch == 1 else np.linspace(0, n, batch + 1).astype(np.int64)
+    M = P.Matrix(dense=dev(A), row_offsets=offs)
+    out = {}
+    for sched in ("overlap", "sequential"):
+        opts = P.options(m, seed=17, iter0=5, max_iter=7, schedule=sched)
+        r = P.solve(M, dev(b), opts, history=True, factors=True)
+        out[sched] = (host(r.x), host(r.history), host(r.factors), r.report)
+    a, s = out["overlap"], out["sequential"]
+    # same sketches, so the same factors bit for bit; the gradient is summed in
+    # another row order, so iterates agree to rounding
+    assert np.array_equal(a[2], s[2])
+    for t in range(7):
+        assert np.allclose(a[1][t], s[1][t], rtol=1e-12, atol=1e-14 * np.abs(s[1][t]).max())
+    assert a[3].status == s[3].status == 0
+    assert abs(a[3].objective - s[3].objective) <= 1e-12 * s[3].objective
+
+
+def test_overlap_reports_not_pd_step(gpu_lib):
+    P = gpu_lib
+    g = np.random.default_rng(21)
+    A = g.standard_normal((4000, 32))
+    A[:, 5] = 0.0
+    res = P.solve(P.Matrix(dense=dev(A)), dev(g.standard_normal(4000)),
+                  P.options(320, max_iter=4), raise_on_error=False, history=True)
+    assert res.report.status == P.ERR_NOT_PD and res.report.failed_iter == 0
+    assert bool((res.x == 0).all())
