@@ -166,11 +166,13 @@ void carve_pass(Carver& c, const Layout& L, const ihs_sketch* sk, PassBuffers& B
   B.rdiag = c.take<double>((size_t)(L.batch * L.d));
 }
 
-// Gradient partials written by one sketch pass: one per workgroup of four
-// sketch rows for dense data, one per sketch row for CSR data.
-int64_t pass_parts(const ihs_matrix* A, const ihs_sketch* sk) {
+// Gradient partials written by one sketch pass: one per wavefront that owns
+// sketch rows of block 0 (dense), one per sketch row of block 0 (CSR).
+int64_t pass_parts(const ihs_matrix* A, const ihs_sketch* sk, int32_t batch) {
   const int64_t m_blk = sk->m / sk->s;
-  return A->format == IHS_DENSE ? (m_blk + 3) / 4 : m_blk;
+  if (A->format != IHS_DENSE) return m_blk;
+  const int64_t bpw = gather_rows_per_wave(sk->m, batch, A->d);
+  return (m_blk + bpw - 1) / bpw;
 }
 
 SketchPlan make_plan(const Layout& L, const ihs_sketch* sk, const PassBuffers& B, uint64_t iter) {
@@ -358,7 +360,15 @@ struct SolveBuffers {
   double* Lf1 = nullptr;
   double* work1 = nullptr;
   DeviceStatus* side_status = nullptr;
+  double* Hinv0 = nullptr;   // explicit inverses of the overlapped schedule
+  double* Hinv1 = nullptr;
+  double* dx = nullptr;
 };
+
+// Above this width the overlapped schedule forms H^{-1} on the second stream
+// and the critical path only applies it; below, the triangular solves run on
+// the main stream directly.
+constexpr int64_t kInverseMinD = 89;
 
 int32_t gram_in_of(const ihs_options* o) { return o ? o->gram_in : IHS_F64; }
 int32_t gram_acc_of(const ihs_options* o) { return o ? o->gram_acc : IHS_F64; }
@@ -379,23 +389,30 @@ size_t carve_solve(Carver& c, const Layout& L, const ihs_options* o, SolveBuffer
   S.Lf1 = c.take<double>((size_t)(L.batch * L.d * L.d));
   S.work1 = c.take<double>((size_t)L.batch * qp_work_doubles(L.d, o->constraint));
   S.side_status = c.take<DeviceStatus>(1);
+  if (L.d >= kInverseMinD && o->constraint == IHS_UNCONSTRAINED) {
+    S.Hinv0 = c.take<double>((size_t)(L.batch * L.d * L.d));
+    S.Hinv1 = c.take<double>((size_t)(L.batch * L.d * L.d));
+  }
+  S.dx = c.take<double>((size_t)(L.batch * L.d));
   return c.used;
 }
 
-// ---- the second stream of the overlapped schedule (one per device) ----
-hipStream_t side_stream() {
+// ---- the extra streams of the overlapped schedule (kept per device) ----
+// which = 0: Gram / factorisation / inverse; which = 1: bucket sorts.
+hipStream_t side_stream(int which) {
   static std::mutex mu;
   static std::vector<hipStream_t> streams;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return nullptr;
   std::lock_guard<std::mutex> lk(mu);
-  if ((int)streams.size() <= dev) streams.resize(dev + 1, nullptr);
-  if (!streams[dev]) {
+  const size_t slot = (size_t)dev * 2 + (size_t)which;
+  if (streams.size() <= slot) streams.resize(slot + 1, nullptr);
+  if (!streams[slot]) {
     hipStream_t s = nullptr;
     if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return nullptr;
-    streams[dev] = s;
+    streams[slot] = s;
   }
-  return streams[dev];
+  return streams[slot];
 }
 
 // A ring of timing-free events; a slot is re-recorded only after every wait
@@ -444,25 +461,30 @@ ihs_status read_status(DeviceStatus* dev, DeviceStatus* host, hipStream_t st) {
 // The overlapped schedule of the IHS loop (unconstrained problems). Step t
 // needs the factor of H_t = (S_t A)^T (S_t A) and g(x^t); since S_t does not
 // depend on x, the pass that forms g(x^t) also forms S_{t+1} A, and a second
-// stream sorts rows for S_{t+2}, forms H_{t+1} and factors it while the main
-// stream runs the next pass over A. A sketch-only pass first forms S_0 A.
+// stream sorts rows for S_{t+2}, forms H_{t+1}, factors it and (for wider
+// problems) inverts it while the main stream runs the next pass over A, so
+// the step itself only applies H_t^{-1} to g. A sketch-only pass first forms
+// S_0 A.
 // Sketches and factors are bitwise those of the sequential loop; g(x^t) is
-// summed in the row order of S_{t+1} instead of S_t, so iterates agree with
-// the sequential loop to rounding.
+// summed in the row order of S_{t+1} instead of S_t, and H_t^{-1} g is a
+// product with the explicit inverse, so iterates agree with the sequential
+// loop to rounding.
 ihs_status solve_overlap(const ihs_matrix* A, const Layout& L, const ihs_options* opt,
                          SolveBuffers& S, const double* b, double* x, double* x_hist,
                          double* factors, ihs_report* rep, hipStream_t stream) {
-  hipStream_t side = side_stream();
-  if (!side) return IHS_ERR_HIP;
+  hipStream_t side = side_stream(0);
+  hipStream_t sorter = side_stream(1);
+  if (!side || !sorter) return IHS_ERR_HIP;
   PassBuffers& B = S.pass;
   const int32_t N = opt->max_iter;
   const int64_t d = A->d, m = opt->sketch.m;
   const int64_t bd = (int64_t)L.batch * d;
-  EventRing evSort(4), evPass(4), evChol(4), evMisc(2);
+  EventRing evSort(4), evPass(4), evChol(4), evMisc(3);
   if (!evSort.ok || !evPass.ok || !evChol.ok || !evMisc.ok) return IHS_ERR_HIP;
   auto ck = [](hipError_t e) { return e == hipSuccess; };
-  // the side stream starts after everything already queued on the caller's stream
-  if (!ck(hipEventRecord(evMisc.at(0), stream)) || !ck(hipStreamWaitEvent(side, evMisc.at(0), 0)))
+  // the extra streams start after everything already queued on the caller's stream
+  if (!ck(hipEventRecord(evMisc.at(0), stream)) || !ck(hipStreamWaitEvent(side, evMisc.at(0), 0)) ||
+      !ck(hipStreamWaitEvent(sorter, evMisc.at(0), 0)))
     return IHS_ERR_HIP;
   hipLaunchKernelGGL(k_zero_status, dim3(1), dim3(64), 0, side, S.side_status);
 
@@ -479,18 +501,24 @@ ihs_status solve_overlap(const ihs_matrix* A, const Layout& L, const ihs_options
     return factors ? factors + k * L.batch * d * d : ((k % 2) ? S.Lf1 : S.Lf);
   };
   auto w_buf = [&](int64_t k) { return (k % 2) ? S.work1 : S.work; };
-  auto factor = [&](int64_t k) -> bool {  // side stream: H_k and its Cholesky factor
+  const bool use_inv = d >= kInverseMinD;
+  auto hinv_buf = [&](int64_t k) { return (k % 2) ? S.Hinv1 : S.Hinv0; };
+  auto factor = [&](int64_t k) -> bool {  // side stream: H_k, its factor (and inverse)
     if (!ck(launch_gram(sa_buf(k), opt->gram_in, m, d, d, L.batch, opt->gram_acc, S.H,
                         S.gram_part, side)))
       return false;
-    return ck(launch_cholesky(S.H, l_buf(k), d, L.batch, S.side_status, (int32_t)k, 0.0,
-                              w_buf(k), side));
+    if (!ck(launch_cholesky(S.H, l_buf(k), d, L.batch, S.side_status, (int32_t)k, 0.0,
+                            w_buf(k), side)))
+      return false;
+    if (!use_inv) return true;
+    return ck(launch_chol_inverse(l_buf(k), chol_rdiag(w_buf(k), L.batch), d, L.batch,
+                                  hinv_buf(k), S.side_status, side));
   };
 
   // prologue: sort S_0 and S_1, sketch-only pass for S_0 A, factor H_0
-  if (!ck(launch_sort(plan_for(0), side)) || !ck(hipEventRecord(evSort.at(0), side)))
+  if (!ck(launch_sort(plan_for(0), sorter)) || !ck(hipEventRecord(evSort.at(0), sorter)))
     return IHS_ERR_HIP;
-  if (!ck(launch_sort(plan_for(1), side)) || !ck(hipEventRecord(evSort.at(1), side)))
+  if (!ck(launch_sort(plan_for(1), sorter)) || !ck(hipEventRecord(evSort.at(1), sorter)))
     return IHS_ERR_HIP;
   if (!ck(hipStreamWaitEvent(stream, evSort.at(0), 0))) return IHS_ERR_HIP;
   ihs_status s = run_gather(A, &opt->sketch, B, plan_for(0), sa_buf(0), opt->gram_in, d,
@@ -507,28 +535,39 @@ ihs_status solve_overlap(const ihs_matrix* A, const Layout& L, const ihs_options
                    nullptr, stream);
     if (s != IHS_OK) return s;
     if (!ck(hipEventRecord(evPass.at(t), stream))) return IHS_ERR_HIP;
-    if (!ck(launch_reduce_partials(B.gpart, B.fpart, L.batch, pass_parts(A, &opt->sketch),
+    if (!ck(launch_reduce_partials(B.gpart, B.fpart, L.batch, pass_parts(A, &opt->sketch, L.batch),
                                    B.probs, d, B.g, B.f, B.status, t, B.red, stream)))
       return IHS_ERR_HIP;
-    // side: sort for P_{t+1}, then H_{t+1} and its factor
-    if (!ck(hipStreamWaitEvent(side, evPass.at(t), 0))) return IHS_ERR_HIP;
+    // sorter: rows for S_{t+2}, once P_t is done (its scattered writes would
+    // slow the pass if they ran beside it); it shares the gap between passes
+    // with the tail of the side stream and the update of x
     if (t + 2 <= N) {
-      if (!ck(launch_sort(plan_for(t + 2), side)) || !ck(hipEventRecord(evSort.at(t + 2), side)))
+      if (!ck(hipStreamWaitEvent(sorter, evPass.at(t), 0)) ||
+          !ck(launch_sort(plan_for(t + 2), sorter)) ||
+          !ck(hipEventRecord(evSort.at(t + 2), sorter)))
         return IHS_ERR_HIP;
     }
+    // side: H_{t+1} and its factor, during P_{t+1}
+    if (!ck(hipStreamWaitEvent(side, evPass.at(t), 0))) return IHS_ERR_HIP;
     if (t + 1 < N) {
       if (!factor(t + 1) || !ck(hipEventRecord(evChol.at(t + 1), side))) return IHS_ERR_HIP;
     }
     // main: x^{t+1} = x^t + H_t^{-1} g(x^t)
     if (!ck(hipStreamWaitEvent(stream, evChol.at(t), 0))) return IHS_ERR_HIP;
-    if (!ck(launch_chol_solve_update(l_buf(t), chol_rdiag(w_buf(t), L.batch), d, L.batch, B.g,
-                                     x, x, B.status, stream, S.side_status, t)))
+    if (use_inv) {
+      if (!ck(launch_inv_apply(hinv_buf(t), d, L.batch, B.g, x, x, S.dx, B.status, stream,
+                               S.side_status, t)))
+        return IHS_ERR_HIP;
+    } else if (!ck(launch_chol_solve_update(l_buf(t), chol_rdiag(w_buf(t), L.batch), d, L.batch,
+                                            B.g, x, x, B.status, stream, S.side_status, t))) {
       return IHS_ERR_HIP;
+    }
     if (x_hist && !ck(hipMemcpyAsync(x_hist + (int64_t)t * bd, x, bd * sizeof(double),
                                      hipMemcpyDeviceToDevice, stream)))
       return IHS_ERR_HIP;
   }
-  if (!ck(hipEventRecord(evMisc.at(1), side)) || !ck(hipStreamWaitEvent(stream, evMisc.at(1), 0)))
+  if (!ck(hipEventRecord(evMisc.at(1), side)) || !ck(hipStreamWaitEvent(stream, evMisc.at(1), 0)) ||
+      !ck(hipEventRecord(evMisc.at(2), sorter)) || !ck(hipStreamWaitEvent(stream, evMisc.at(2), 0)))
     return IHS_ERR_HIP;
   DeviceStatus hm, hs;
   if (read_status(B.status, &hm, stream) != IHS_OK) return IHS_ERR_HIP;
@@ -754,7 +793,7 @@ ihs_status ihs_solve(const ihs_matrix* A, const double* b, const ihs_options* op
     const uint64_t iter = opt->sketch.iter + (uint64_t)t;
     s = run_pass(A, L, &opt->sketch, B, iter, S.SA, opt->gram_in, d, b, x, nullptr, stream);
     if (s != IHS_OK) return s;
-    if (launch_reduce_partials(B.gpart, B.fpart, L.batch, pass_parts(A, &opt->sketch), B.probs,
+    if (launch_reduce_partials(B.gpart, B.fpart, L.batch, pass_parts(A, &opt->sketch, L.batch), B.probs,
                                d, B.g, B.f, B.status, t, B.red, stream) != hipSuccess)
       return IHS_ERR_HIP;
     if (launch_gram(S.SA, opt->gram_in, m, d, d, L.batch, opt->gram_acc, S.H, S.gram_part,

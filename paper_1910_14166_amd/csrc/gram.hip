@@ -1,8 +1,8 @@
 // The sketched Hessian H = (SA)^T (SA) (Sec. 1, the T_QP term; App. A.1.1,
 // "O(m d^2) to compute the approximate Hessian") on gfx950 matrix cores.
 //
-// Each wavefront owns one 32 x 32 tile of the upper triangle of H and a
-// contiguous slice of the m rows of SA (split-K). Operands come straight from
+// Two wavefronts share each 32 x 32 tile of the upper triangle of H (16 rows
+// each), for a contiguous slice of the m rows of SA (split-K). Operands come straight from
 // L2: for a 16 x 16 x 4 product a lane supplies SA[k0 + lane/16][col0 + lane%16],
 // so every operand load is four 128-byte row segments. Partial tiles are
 // summed over the slices in a fixed order and mirrored into both triangles,
@@ -60,140 +60,159 @@ __device__ __forceinline__ void tri_index(int t, int& ti, int& tj) {
   ti = t - j * (j + 1) / 2;
 }
 
-// Operand fetch converting to the MFMA input type.
-__device__ __forceinline__ double ld_f64(const void* SA, int32_t dt, int64_t idx) {
-  if (dt == 0) return static_cast<const double*>(SA)[idx];
-  if (dt == 1) return (double)static_cast<const float*>(SA)[idx];
-  return bf16_bits_to_f64(static_cast<const uint16_t*>(SA)[idx]);
+template <typename TI>
+__device__ __forceinline__ double to_f64(TI v);
+template <>
+__device__ __forceinline__ double to_f64<double>(double v) { return v; }
+template <>
+__device__ __forceinline__ double to_f64<float>(float v) { return (double)v; }
+
+// Wavefront w = ((p * ntri + t) * splits + split) * 2 + half computes rows
+// [16 half, 16 half + 16) of 32 x 32 tile t over its slice of the m rows.
+// Two accumulators and a few k-steps of operands keep the register footprint
+// small enough to run beside the memory-bound pass.
+__device__ __forceinline__ void gram_wave_coords(const GramPlan& G, int64_t w, int& p, int& t,
+                                                 int& split, int& half) {
+  half = (int)(w & 1);
+  const int64_t q = w >> 1;
+  split = (int)(q % G.splits);
+  t = (int)((q / G.splits) % G.ntri);
+  p = (int)(q / ((int64_t)G.splits * G.ntri));
 }
 
-// FP64 (or F32 inputs widened to FP64) on the FP64 matrix cores.
-__global__ __launch_bounds__(256) void k_gram_f64(const void* __restrict__ SA, int32_t in_dt,
-                                                  GramPlan G, double* __restrict__ part) {
+// FP64 matrix cores; F64 inputs, or F32 inputs widened exactly to F64.
+template <typename TI>
+__global__ __launch_bounds__(256, 8) void k_gram_f64(const TI* __restrict__ SA, GramPlan G,
+                                                     double* __restrict__ part) {
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t w = (int64_t)blockIdx.x * 4 + wv;
-  const int64_t total = (int64_t)G.batch * G.ntri * G.splits;
+  const int64_t total = (int64_t)G.batch * G.ntri * G.splits * 2;
   if (w >= total) return;
-  const int split = (int)(w % G.splits);
-  const int t = (int)((w / G.splits) % G.ntri);
-  const int p = (int)(w / ((int64_t)G.splits * G.ntri));
+  int p, t, split, half;
+  gram_wave_coords(G, w, p, t, split, half);
   int ti, tj;
   tri_index(t, ti, tj);
-  const int64_t i0 = (int64_t)ti * kTile, j0 = (int64_t)tj * kTile;
+  const int64_t i0 = (int64_t)ti * kTile + 16 * half, j0 = (int64_t)tj * kTile;
   const int64_t kb = (int64_t)split * G.kchunk;
   const int64_t ke = min(G.m, kb + G.kchunk);
   const int r = lane & 15, kk = lane >> 4;
-  const int64_t base = (int64_t)p * G.m * G.ld;
-  const bool ci0 = i0 + r < G.d, ci1 = i0 + 16 + r < G.d;
-  const bool cj0 = j0 + r < G.d, cj1 = j0 + 16 + r < G.d;
-  f64x4 c00 = {0, 0, 0, 0}, c01 = c00, c10 = c00, c11 = c00;
-  for (int64_t k = kb; k < ke; k += 16) {
-    double a0[4], a1[4], b0[4], b1[4];
+  const TI* base = SA + (int64_t)p * G.m * G.ld;
+  const bool ci = i0 + r < G.d, cj0 = j0 + r < G.d, cj1 = j0 + 16 + r < G.d;
+  f64x4 c0 = {0, 0, 0, 0}, c1 = c0;
+  for (int64_t k = kb; k < ke; k += 8) {
+    double a[2], b0[2], b1[2];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < 2; ++q) {
       const int64_t row = k + 4 * q + kk;
       const bool okr = row < ke;
-      const int64_t off = base + row * G.ld;
-      a0[q] = (okr && ci0) ? ld_f64(SA, in_dt, off + i0 + r) : 0.0;
-      a1[q] = (okr && ci1) ? ld_f64(SA, in_dt, off + i0 + 16 + r) : 0.0;
-      b0[q] = (okr && cj0) ? ld_f64(SA, in_dt, off + j0 + r) : 0.0;
-      b1[q] = (okr && cj1) ? ld_f64(SA, in_dt, off + j0 + 16 + r) : 0.0;
+      const TI* rp = base + row * G.ld;
+      a[q] = (okr && ci) ? to_f64(rp[i0 + r]) : 0.0;
+      b0[q] = (okr && cj0) ? to_f64(rp[j0 + r]) : 0.0;
+      b1[q] = (okr && cj1) ? to_f64(rp[j0 + 16 + r]) : 0.0;
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      c00 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[q], b0[q], c00, 0, 0, 0);
-      c01 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[q], b1[q], c01, 0, 0, 0);
-      c10 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[q], b0[q], c10, 0, 0, 0);
-      c11 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[q], b1[q], c11, 0, 0, 0);
+    for (int q = 0; q < 2; ++q) {
+      c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], b0[q], c0, 0, 0, 0);
+      c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], b1[q], c1, 0, 0, 0);
     }
   }
-  // D(i, j) of a 16 x 16 block sits in lane 16*(i%4)... : row 4*reg + lane/16, col lane%16
-  double* out = part + w * (kTile * kTile);
+  // 16 x 16 f64 output: row 4*reg + lane/16, column lane%16
+  double* out = part + (w >> 1) * (kTile * kTile) + 16 * half * kTile;
   const int col = lane & 15, rq = lane >> 4;
 #pragma unroll
   for (int reg = 0; reg < 4; ++reg) {
     const int row = 4 * reg + rq;
-    out[row * kTile + col] = c00[reg];
-    out[row * kTile + 16 + col] = c01[reg];
-    out[(16 + row) * kTile + col] = c10[reg];
-    out[(16 + row) * kTile + 16 + col] = c11[reg];
+    out[row * kTile + col] = c0[reg];
+    out[row * kTile + 16 + col] = c1[reg];
   }
 }
 
-// FP32 accumulation on the FP32 matrix cores: F32 inputs (16x16x4) or BF16
+// FP32 accumulation on the matrix cores: F32 inputs (16x16x4) or BF16
 // inputs (16x16x32, eight consecutive k per lane).
-__global__ __launch_bounds__(256) void k_gram_f32acc(const void* __restrict__ SA, int32_t in_dt,
-                                                     GramPlan G, double* __restrict__ part) {
+__global__ __launch_bounds__(256, 8) void k_gram_f32_f32(const float* __restrict__ SA, GramPlan G,
+                                                         double* __restrict__ part) {
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t w = (int64_t)blockIdx.x * 4 + wv;
-  const int64_t total = (int64_t)G.batch * G.ntri * G.splits;
+  const int64_t total = (int64_t)G.batch * G.ntri * G.splits * 2;
   if (w >= total) return;
-  const int split = (int)(w % G.splits);
-  const int t = (int)((w / G.splits) % G.ntri);
-  const int p = (int)(w / ((int64_t)G.splits * G.ntri));
+  int p, t, split, half;
+  gram_wave_coords(G, w, p, t, split, half);
   int ti, tj;
   tri_index(t, ti, tj);
-  const int64_t i0 = (int64_t)ti * kTile, j0 = (int64_t)tj * kTile;
+  const int64_t i0 = (int64_t)ti * kTile + 16 * half, j0 = (int64_t)tj * kTile;
   const int64_t kb = (int64_t)split * G.kchunk;
   const int64_t ke = min(G.m, kb + G.kchunk);
   const int r = lane & 15, kk = lane >> 4;
-  const int64_t base = (int64_t)p * G.m * G.ld;
-  const bool ci0 = i0 + r < G.d, ci1 = i0 + 16 + r < G.d;
-  const bool cj0 = j0 + r < G.d, cj1 = j0 + 16 + r < G.d;
-  f32x4 c00 = {0, 0, 0, 0}, c01 = c00, c10 = c00, c11 = c00;
-  if (in_dt == 1) {
-    const float* S = static_cast<const float*>(SA);
-    for (int64_t k = kb; k < ke; k += 16) {
-      float a0[4], a1[4], b0[4], b1[4];
+  const float* base = SA + (int64_t)p * G.m * G.ld;
+  const bool ci = i0 + r < G.d, cj0 = j0 + r < G.d, cj1 = j0 + 16 + r < G.d;
+  f32x4 c0 = {0, 0, 0, 0}, c1 = c0;
+  for (int64_t k = kb; k < ke; k += 16) {
+    float a[4], b0[4], b1[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int64_t row = k + 4 * q + kk;
-        const bool okr = row < ke;
-        const int64_t off = base + row * G.ld;
-        a0[q] = (okr && ci0) ? S[off + i0 + r] : 0.f;
-        a1[q] = (okr && ci1) ? S[off + i0 + 16 + r] : 0.f;
-        b0[q] = (okr && cj0) ? S[off + j0 + r] : 0.f;
-        b1[q] = (okr && cj1) ? S[off + j0 + 16 + r] : 0.f;
-      }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        c00 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[q], b0[q], c00, 0, 0, 0);
-        c01 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[q], b1[q], c01, 0, 0, 0);
-        c10 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[q], b0[q], c10, 0, 0, 0);
-        c11 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[q], b1[q], c11, 0, 0, 0);
-      }
+    for (int q = 0; q < 4; ++q) {
+      const int64_t row = k + 4 * q + kk;
+      const bool okr = row < ke;
+      const float* rp = base + row * G.ld;
+      a[q] = (okr && ci) ? rp[i0 + r] : 0.f;
+      b0[q] = (okr && cj0) ? rp[j0 + r] : 0.f;
+      b1[q] = (okr && cj1) ? rp[j0 + 16 + r] : 0.f;
     }
-  } else {
-    const uint16_t* S = static_cast<const uint16_t*>(SA);
-    // 16x16x32: lane supplies A[i = lane%16][k = 8*(lane/16) + e], e < 8
-    for (int64_t k = kb; k < ke; k += 32) {
-      bf16x8 a0, a1, b0, b1;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int64_t row = k + 8 * kk + e;
-        const bool okr = row < ke;
-        const int64_t off = base + row * G.ld;
-        a0[e] = (short)((okr && ci0) ? S[off + i0 + r] : 0);
-        a1[e] = (short)((okr && ci1) ? S[off + i0 + 16 + r] : 0);
-        b0[e] = (short)((okr && cj0) ? S[off + j0 + r] : 0);
-        b1[e] = (short)((okr && cj1) ? S[off + j0 + 16 + r] : 0);
-      }
-      c00 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0, c00, 0, 0, 0);
-      c01 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b1, c01, 0, 0, 0);
-      c10 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b0, c10, 0, 0, 0);
-      c11 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, c11, 0, 0, 0);
+    for (int q = 0; q < 4; ++q) {
+      c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[q], b0[q], c0, 0, 0, 0);
+      c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[q], b1[q], c1, 0, 0, 0);
     }
   }
-  // 16x16 f32 output: row 4*(lane/16) + reg, col lane%16
-  double* out = part + w * (kTile * kTile);
+  // 16 x 16 f32 output: row 4*(lane/16) + reg, column lane%16
+  double* out = part + (w >> 1) * (kTile * kTile) + 16 * half * kTile;
   const int col = lane & 15, rq = lane >> 4;
 #pragma unroll
   for (int reg = 0; reg < 4; ++reg) {
     const int row = 4 * rq + reg;
-    out[row * kTile + col] = (double)c00[reg];
-    out[row * kTile + 16 + col] = (double)c01[reg];
-    out[(16 + row) * kTile + col] = (double)c10[reg];
-    out[(16 + row) * kTile + 16 + col] = (double)c11[reg];
+    out[row * kTile + col] = (double)c0[reg];
+    out[row * kTile + 16 + col] = (double)c1[reg];
+  }
+}
+
+__global__ __launch_bounds__(256, 6) void k_gram_bf16_f32(const uint16_t* __restrict__ SA,
+                                                          GramPlan G, double* __restrict__ part) {
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t w = (int64_t)blockIdx.x * 4 + wv;
+  const int64_t total = (int64_t)G.batch * G.ntri * G.splits * 2;
+  if (w >= total) return;
+  int p, t, split, half;
+  gram_wave_coords(G, w, p, t, split, half);
+  int ti, tj;
+  tri_index(t, ti, tj);
+  const int64_t i0 = (int64_t)ti * kTile + 16 * half, j0 = (int64_t)tj * kTile;
+  const int64_t kb = (int64_t)split * G.kchunk;
+  const int64_t ke = min(G.m, kb + G.kchunk);
+  const int r = lane & 15, kk = lane >> 4;
+  const uint16_t* base = SA + (int64_t)p * G.m * G.ld;
+  const bool ci = i0 + r < G.d, cj0 = j0 + r < G.d, cj1 = j0 + 16 + r < G.d;
+  f32x4 c0 = {0, 0, 0, 0}, c1 = c0;
+  // lane supplies A[i = lane%16][k = 8*(lane/16) + e]; A and B use the same k map
+  for (int64_t k = kb; k < ke; k += 32) {
+    bf16x8 a, b0, b1;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int64_t row = k + 8 * kk + e;
+      const bool okr = row < ke;
+      const uint16_t* rp = base + row * G.ld;
+      a[e] = (short)((okr && ci) ? rp[i0 + r] : 0);
+      b0[e] = (short)((okr && cj0) ? rp[j0 + r] : 0);
+      b1[e] = (short)((okr && cj1) ? rp[j0 + 16 + r] : 0);
+    }
+    c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b0, c0, 0, 0, 0);
+    c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b1, c1, 0, 0, 0);
+  }
+  double* out = part + (w >> 1) * (kTile * kTile) + 16 * half * kTile;
+  const int col = lane & 15, rq = lane >> 4;
+#pragma unroll
+  for (int reg = 0; reg < 4; ++reg) {
+    const int row = 4 * rq + reg;
+    out[row * kTile + col] = (double)c0[reg];
+    out[row * kTile + 16 + col] = (double)c1[reg];
   }
 }
 
@@ -218,13 +237,31 @@ __global__ __launch_bounds__(256) void k_gram_reduce(GramPlan G, const double* _
   const double* src = part + (((int64_t)p * G.ntri + t) * G.splits) * (kTile * kTile);
   // inside a diagonal tile the lower half mirrors the upper half
   int64_t off = (ti == tj && li > lj) ? (lj * kTile + li) : (li * kTile + lj);
+  // loads of eight slices are issued together, then added in ascending order
+  const int64_t stride = (int64_t)kTile * kTile;
   if (acc32) {
     float s = 0.f;
-    for (int q = 0; q < G.splits; ++q) s += (float)src[(int64_t)q * kTile * kTile + off];
+    int q = 0;
+    for (; q + 8 <= G.splits; q += 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = src[(int64_t)(q + u) * stride + off];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += (float)v[u];
+    }
+    for (; q < G.splits; ++q) s += (float)src[(int64_t)q * stride + off];
     H[idx] = (double)s;
   } else {
     double s = 0.0;
-    for (int q = 0; q < G.splits; ++q) s += src[(int64_t)q * kTile * kTile + off];
+    int q = 0;
+    for (; q + 8 <= G.splits; q += 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = src[(int64_t)(q + u) * stride + off];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; q < G.splits; ++q) s += src[(int64_t)q * stride + off];
     H[idx] = s;
   }
 }
@@ -233,13 +270,27 @@ hipError_t launch_gram(const void* SA, int32_t in_dtype, int64_t m, int64_t d, i
                        int32_t batch, int32_t acc_dtype, double* H, void* partials,
                        hipStream_t st) {
   const GramPlan G = make_gram_plan(m, d, ld, batch);
-  const int64_t waves = (int64_t)batch * G.ntri * G.splits;
+  const int64_t waves = (int64_t)batch * G.ntri * G.splits * 2;
   const unsigned blocks = (unsigned)((waves + 3) / 4);
   double* part = static_cast<double*>(partials);
   if (acc_dtype == 0) {
-    hipLaunchKernelGGL(k_gram_f64, dim3(blocks), dim3(256), 0, st, SA, in_dtype, G, part);
+    if (in_dtype == 0)
+      hipLaunchKernelGGL(k_gram_f64<double>, dim3(blocks), dim3(256), 0, st,
+                         static_cast<const double*>(SA), G, part);
+    else if (in_dtype == 1)
+      hipLaunchKernelGGL(k_gram_f64<float>, dim3(blocks), dim3(256), 0, st,
+                         static_cast<const float*>(SA), G, part);
+    else
+      return hipErrorInvalidValue;
   } else {
-    hipLaunchKernelGGL(k_gram_f32acc, dim3(blocks), dim3(256), 0, st, SA, in_dtype, G, part);
+    if (in_dtype == 1)
+      hipLaunchKernelGGL(k_gram_f32_f32, dim3(blocks), dim3(256), 0, st,
+                         static_cast<const float*>(SA), G, part);
+    else if (in_dtype == 2)
+      hipLaunchKernelGGL(k_gram_bf16_f32, dim3(blocks), dim3(256), 0, st,
+                         static_cast<const uint16_t*>(SA), G, part);
+    else
+      return hipErrorInvalidValue;
   }
   const int64_t n_out = (int64_t)batch * d * d;
   hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((n_out + 255) / 256)), dim3(256), 0, st, G,

@@ -75,6 +75,8 @@ struct GatherArgs {
   double* r_out;           // n, nullable
 };
 hipError_t launch_sketch_gather(const SketchPlan& p, const GatherArgs& g, hipStream_t st);
+// Sketch rows owned by one wavefront of the dense gather (1 or 2).
+int32_t gather_rows_per_wave(int64_t m, int32_t batch, int64_t d);
 
 // CSR counterpart of the gather (values f64).
 struct CsrGatherArgs {
@@ -158,6 +160,13 @@ hipError_t launch_cholesky(const double* H, double* L, int64_t d, int32_t batch,
                            DeviceStatus* status, int32_t iter, double shift, double* scratch,
                            hipStream_t st);
 double* chol_rdiag(double* scratch, int32_t batch);
+// H^{-1} = (L L^T)^{-1}, one workgroup per (problem, identity column).
+hipError_t launch_chol_inverse(const double* L, const double* rdiag, int64_t d, int32_t batch,
+                               double* Hinv, DeviceStatus* status, hipStream_t st);
+// x_out = x + Hinv g (dx receives Hinv g); records sqrt(dx^T g) of problem 0.
+hipError_t launch_inv_apply(const double* Hinv, int64_t d, int32_t batch, const double* g,
+                            const double* x, double* x_out, double* dx, DeviceStatus* status,
+                            hipStream_t st, const DeviceStatus* gate, int32_t gate_iter);
 // Skips the update (out = base) when `status` records any failure or `gate`
 // (nullable, another stream's record) a failure at or before step gate_iter.
 hipError_t launch_chol_solve_update(const double* L, const double* rdiag, int64_t d,

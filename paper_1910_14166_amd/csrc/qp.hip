@@ -19,7 +19,21 @@ namespace ihs {
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kSmallChol = 88;  // d*d doubles within 64 KiB of LDS
+constexpr int kSmallChol = 88;
+
+// Sum four per-lane partial values across the wavefront (transposing
+// butterfly, fixed order): afterwards lane row_lane4(u) holds row u's total.
+__device__ __forceinline__ double multi_row_sum4(const double (&v)[4], int lane) {
+  const bool h32 = (lane & 32) != 0;
+  double a0 = (h32 ? v[2] : v[0]) + __shfl_xor(h32 ? v[0] : v[2], 32, 64);
+  double a1 = (h32 ? v[3] : v[1]) + __shfl_xor(h32 ? v[1] : v[3], 32, 64);
+  const bool h16 = (lane & 16) != 0;
+  double s = (h16 ? a1 : a0) + __shfl_xor(h16 ? a0 : a1, 16, 64);
+#pragma unroll
+  for (int off = 8; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  return s;
+}
+__device__ __forceinline__ int row_lane4(int u) { return ((u >> 1) & 1) * 32 + (u & 1) * 16; }  // d*d doubles within 64 KiB of LDS
 constexpr int kNb = 64;
 
 __device__ __forceinline__ void wave_sync_lds() {
@@ -177,20 +191,16 @@ __global__ __launch_bounds__(256) void k_chol_init(const double* __restrict__ H,
   L[idx] = (j <= i) ? H[idx] + (i == j ? shift : 0.0) : 0.0;
 }
 
-// Every workgroup of a panel launch reads the unfactored diagonal block and
-// factors it in LDS; nobody writes that block during the launch (workgroup 0
-// leaves the factor in `dside`, and the update launch copies it back).
-// The block is factored by all 256 threads (right-looking, one barrier per
-// column); each thread then solves one panel row x L_kk^T = a in registers,
-// column by column so the updates of different entries are independent.
-// Workgroup 0 also stores the reciprocal pivots 1/L_jj in `rdiag`.
-__global__ __launch_bounds__(256) void k_chol_panel(double* L, int64_t d, int64_t kb,
-                                                    double* dside, double* rdiag,
-                                                    DeviceStatus* st, int32_t iter) {
+// Diagonal block of panel kb: one workgroup per problem factors the 64 x 64
+// block in LDS (right-looking, one barrier per column; thread t owns row t/4,
+// columns 16*(t%4) .. +15) and writes L_kk and 1/L_jj back.
+__global__ __launch_bounds__(256) void k_chol_diag(double* L, int64_t d, int64_t kb,
+                                                   double* rdiag, DeviceStatus* st,
+                                                   int32_t iter) {
   __shared__ double D[kNb][kNb + 1];
   __shared__ double rd[kNb];
   __shared__ int flag;
-  const int p = blockIdx.y;
+  const int p = blockIdx.x;
   const int tid = threadIdx.x;
   if (tid == 0) flag = st->code;
   __syncthreads();
@@ -198,124 +208,134 @@ __global__ __launch_bounds__(256) void k_chol_panel(double* L, int64_t d, int64_
   double* W = L + (int64_t)p * d * d;
   const int nb = (int)min((int64_t)kNb, d - kb);
   for (int e = tid; e < kNb * kNb; e += 256) {
-    const int i = e / kNb, j = e % kNb;
+    const int i = e >> 6, j = e & 63;
     D[i][j] = (i < nb && j <= i) ? W[(kb + i) * d + kb + j] : 0.0;
   }
   __syncthreads();
+  const int my_i = tid >> 2, k0 = (tid & 3) * 16;
   int bad = 0;
   for (int j = 0; j < nb; ++j) {
     const double piv = D[j][j];
-    if (!(piv > 0.0) || !isfinite(piv)) {  // every thread sees the same pivot
+    if (!(piv > 0.0) || !isfinite(piv)) {  // the same pivot for every thread
       bad = 1;
       break;
     }
-    const double ljj = sqrt(piv);
-    const double r = 1.0 / ljj;
-    const int w = nb - j - 1;
-    for (int e = tid; e < w * w; e += 256) {
-      const int i = j + 1 + e / w, k = j + 1 + e % w;
-      if (k <= i) D[i][k] = fma(-(D[i][j] * r), D[k][j] * r, D[i][k]);
+    const double r = 1.0 / sqrt(piv);
+    if (my_i > j && my_i < nb) {
+      const double lij = D[my_i][j] * r;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int k = k0 + q;
+        if (k > j && k <= my_i) D[my_i][k] = fma(-lij, D[k][j] * r, D[my_i][k]);
+      }
     }
     __syncthreads();  // column j is no longer read: scale it
     if (tid == 0) {
-      D[j][j] = ljj;
+      D[j][j] = sqrt(piv);
       rd[j] = r;
     }
-    for (int i = j + 1 + tid; i < nb; i += 256) D[i][j] = D[i][j] * r;
+    if (tid > j && tid < nb) D[tid][j] = D[tid][j] * r;
   }
   __syncthreads();
   if (bad) {
-    if (tid == 0 && blockIdx.x == 0) status_fail(st, 5 /* IHS_ERR_NOT_PD */, iter, p);
+    if (tid == 0) status_fail(st, 5 /* IHS_ERR_NOT_PD */, iter, p);
     return;
   }
-  if (blockIdx.x == 0) {
-    double* ds = dside + (int64_t)p * kNb * kNb;
-    for (int e = tid; e < kNb * kNb; e += 256) ds[e] = D[e / kNb][e % kNb];
-    for (int j = tid; j < nb; j += 256) rdiag[(int64_t)p * d + kb + j] = rd[j];
+  for (int e = tid; e < kNb * kNb; e += 256) {
+    const int i = e >> 6, j = e & 63;
+    if (i < nb && j <= i) W[(kb + i) * d + kb + j] = D[i][j];
   }
-  const int64_t row = kb + nb + (int64_t)blockIdx.x * 256 + tid;
-  if (row >= d) return;
-  double x[kNb];
-  double* wr = W + row * d + kb;
+  if (tid < nb) rdiag[(int64_t)p * d + kb + tid] = rd[tid];
+}
+
+// Panel rows below the diagonal block: x L_kk^T = a for each row, one row per
+// wavefront pass with lanes over the 64 columns; the factored block is staged
+// in LDS and x_c is broadcast from lane c (column-oriented substitution).
+// Four rows are interleaved per wavefront for independent dependency chains.
+__global__ __launch_bounds__(256) void k_chol_trsm(double* L, int64_t d, int64_t kb,
+                                                   const double* __restrict__ rdiag,
+                                                   DeviceStatus* st) {
+  __shared__ double D[kNb][kNb + 1];
+  __shared__ double rd[kNb];
+  __shared__ int flag;
+  const int p = blockIdx.y;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  if (tid == 0) flag = st->code;
+  __syncthreads();
+  if (flag != 0) return;
+  double* W = L + (int64_t)p * d * d;
+  for (int e = tid; e < kNb * kNb; e += 256) {
+    const int i = e >> 6, j = e & 63;
+    D[i][j] = (j <= i) ? W[(kb + i) * d + kb + j] : 0.0;
+  }
+  if (tid < kNb) rd[tid] = rdiag[(int64_t)p * d + kb + tid];
+  __syncthreads();
+  const int64_t rows0 = kb + kNb;
+  const int64_t r_first = rows0 + ((int64_t)blockIdx.x * 4 + wv) * 4;
+  double a[4];
+  bool ok[4];
 #pragma unroll
-  for (int c = 0; c < kNb; ++c) x[c] = (c < nb) ? wr[c] : 0.0;
-#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    ok[u] = r_first + u < d;
+    a[u] = ok[u] ? W[(r_first + u) * d + kb + lane] : 0.0;
+  }
   for (int c = 0; c < kNb; ++c) {
-    if (c < nb) {
-      x[c] = x[c] * rd[c];
+    const double lkc = D[lane][c];
+    const double rc = rd[c];
 #pragma unroll
-      for (int k = c + 1; k < kNb; ++k) x[k] = fma(-x[c], D[k][c], x[k]);
+    for (int u = 0; u < 4; ++u) {
+      const double xc = __shfl(a[u], c, 64) * rc;
+      if (lane == c) a[u] = xc;
+      else if (lane > c) a[u] = fma(-xc, lkc, a[u]);
     }
   }
 #pragma unroll
-  for (int c = 0; c < kNb; ++c)
-    if (c < nb) wr[c] = x[c];
+  for (int u = 0; u < 4; ++u)
+    if (ok[u]) W[(r_first + u) * d + kb + lane] = a[u];
 }
 
 // Trailing update W[i][j] -= sum_k P[i][k] P[j][k], kb+64 <= j <= i < d, with
-// P = W[:, kb:kb+64]. One wavefront per 32 x 32 lower tile.
+// P = W[:, kb:kb+64]. One wavefront per 16 x 16 lower tile (small register
+// footprint, so these tiles also run beside a memory-bound pass).
 __global__ __launch_bounds__(256) void k_chol_update(double* L, int64_t d, int64_t kb,
-                                                     int32_t batch, const double* dside,
-                                                     DeviceStatus* st) {
+                                                     int32_t batch, DeviceStatus* st) {
   if (st->code != 0) return;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  if (blockIdx.x == 0) {  // the factored diagonal block of this panel
-    const int nb = (int)min((int64_t)kNb, d - kb);
-    for (int64_t e = threadIdx.x; e < (int64_t)batch * kNb * kNb; e += 256) {
-      const int q = (int)(e / (kNb * kNb));
-      const int i = (int)((e / kNb) % kNb), j = (int)(e % kNb);
-      if (i < nb && j <= i) L[(int64_t)q * d * d + (kb + i) * d + kb + j] = dside[e];
-    }
-  }
   const int64_t t0 = kb + kNb;
-  const int64_t T = (d - t0 + 31) / 32;
+  const int64_t T = (d - t0 + 15) / 16;
   const int64_t ntri = T * (T + 1) / 2;
   const int64_t w = (int64_t)blockIdx.x * 4 + wv;
   if (w >= ntri * batch) return;
   const int p = (int)(w / ntri);
   const int64_t t = w - (int64_t)p * ntri;
-  // t -> (ti, tj), tj <= ti, row-major lower triangle
   int64_t ti = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
   while (ti * (ti + 1) / 2 > t) --ti;
   while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
   const int64_t tj = t - ti * (ti + 1) / 2;
   double* W = L + (int64_t)p * d * d;
-  const int64_t r0 = t0 + ti * 32, c0 = t0 + tj * 32;
+  const int64_t r0 = t0 + ti * 16, c0 = t0 + tj * 16;
   const int r = lane & 15, kk = lane >> 4;
-  f64x4 c00 = {0, 0, 0, 0}, c01 = c00, c10 = c00, c11 = c00;
-  const bool ra0 = r0 + r < d, ra1 = r0 + 16 + r < d;
-  const bool rb0 = c0 + r < d, rb1 = c0 + 16 + r < d;
+  f64x4 acc = {0, 0, 0, 0};
+  const bool ra = r0 + r < d, rb = c0 + r < d;
 #pragma unroll 4
   for (int k = 0; k < kNb; k += 4) {
     const int64_t col = kb + k + kk;
-    const double a0 = ra0 ? W[(r0 + r) * d + col] : 0.0;
-    const double a1 = ra1 ? W[(r0 + 16 + r) * d + col] : 0.0;
-    const double b0 = rb0 ? W[(c0 + r) * d + col] : 0.0;
-    const double b1 = rb1 ? W[(c0 + 16 + r) * d + col] : 0.0;
-    c00 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, c00, 0, 0, 0);
-    c01 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, c01, 0, 0, 0);
-    c10 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, c10, 0, 0, 0);
-    c11 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, c11, 0, 0, 0);
+    const double av = ra ? W[(r0 + r) * d + col] : 0.0;
+    const double bv = rb ? W[(c0 + r) * d + col] : 0.0;
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
   }
   const int col = lane & 15, rq = lane >> 4;
 #pragma unroll
   for (int reg = 0; reg < 4; ++reg) {
-    const int rr = 4 * reg + rq;
-    const double v[4] = {c00[reg], c01[reg], c10[reg], c11[reg]};
-    const int64_t ii[4] = {r0 + rr, r0 + rr, r0 + 16 + rr, r0 + 16 + rr};
-    const int64_t jj[4] = {c0 + col, c0 + 16 + col, c0 + col, c0 + 16 + col};
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      if (ii[q] < d && jj[q] < d && jj[q] <= ii[q]) W[ii[q] * d + jj[q]] -= v[q];
-    }
+    const int64_t ii = r0 + 4 * reg + rq, jj = c0 + col;
+    if (ii < d && jj < d && jj <= ii) W[ii * d + jj] -= acc[reg];
   }
 }
 
 hipError_t launch_cholesky(const double* H, double* L, int64_t d, int32_t batch,
                            DeviceStatus* status, int32_t iter, double shift, double* scratch,
                            hipStream_t st) {
-  double* dside = scratch;
-  double* rdiag = scratch + (int64_t)batch * kNb * kNb;
+  double* rdiag = chol_rdiag(scratch, batch);
   if (d <= kSmallChol) {
     hipLaunchKernelGGL(k_chol_small, dim3(batch), dim3(256), (size_t)(d * d * sizeof(double)),
                        st, H, L, d, status, iter, shift, rdiag);
@@ -325,114 +345,125 @@ hipError_t launch_cholesky(const double* H, double* L, int64_t d, int32_t batch,
   hipLaunchKernelGGL(k_chol_init, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, H, L, d,
                      batch, shift);
   for (int64_t kb = 0; kb < d; kb += kNb) {
+    hipLaunchKernelGGL(k_chol_diag, dim3(batch), dim3(256), 0, st, L, d, kb, rdiag, status, iter);
     const int64_t below = std::max<int64_t>(0, d - kb - kNb);
-    const unsigned gx = (unsigned)std::max<int64_t>(1, (below + 255) / 256);
-    hipLaunchKernelGGL(k_chol_panel, dim3(gx, batch), dim3(256), 0, st, L, d, kb, dside, rdiag,
-                       status, iter);
-    const int64_t T = (below + 31) / 32;
+    if (below == 0) break;
+    const unsigned gx = (unsigned)((below + 15) / 16);  // 16 rows per workgroup
+    hipLaunchKernelGGL(k_chol_trsm, dim3(gx, batch), dim3(256), 0, st, L, d, kb, rdiag, status);
+    const int64_t T = (below + 15) / 16;
     const int64_t waves = T * (T + 1) / 2 * batch;
-    const unsigned gu = (unsigned)std::max<int64_t>(1, (waves + 3) / 4);
-    hipLaunchKernelGGL(k_chol_update, dim3(gu), dim3(256), 0, st, L, d, kb, batch, dside,
-                       status);
+    hipLaunchKernelGGL(k_chol_update, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st, L, d,
+                       kb, batch, status);
   }
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
 // out = base + (L L^T)^{-1} v, one workgroup (256 threads) per problem.
-// Each 64 x 64 diagonal block is solved by wavefront 0 with the block held in
-// registers (lane i keeps row i, or column i for the transposed sweep) and
-// the reciprocal pivots from the factorisation; the rest of the vector is
-// then updated by all threads. Also records sqrt(dx^T v) for problem 0.
+// Per 64-row block: the diagonal block is staged in LDS and solved by
+// wavefront 0 (lane c holds y_c; x_c is broadcast from lane c, reciprocal
+// pivots from the factorisation); the remaining rows are updated by all four
+// wavefronts, four rows at a time with one transposing butterfly.
+// Also records sqrt(dx^T v) for problem 0.
 // ---------------------------------------------------------------------------
+// INV: right-hand side e_j for j = blockIdx.y; the solution (column j of H^{-1})
+// is stored in row j of `out` (batch x d x d); base, v and the step record
+// are unused.
+template <bool INV>
 __global__ __launch_bounds__(256) void k_chol_solve(const double* __restrict__ L, int64_t d,
-                                                     const double* __restrict__ rdiag,
-                                                     const double* __restrict__ v,
-                                                     const double* base, double* out,
-                                                     DeviceStatus* st, const DeviceStatus* gate,
-                                                     int32_t gate_iter) {
+                                                    const double* __restrict__ rdiag,
+                                                    const double* __restrict__ v,
+                                                    const double* base, double* out,
+                                                    DeviceStatus* st, const DeviceStatus* gate,
+                                                    int32_t gate_iter) {
   extern __shared__ double y[];
+  __shared__ double D[64][65];
   __shared__ double red[256];
   __shared__ int code;
   const int p = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const double* Lp = L + (int64_t)p * d * d;
   const double* rp = rdiag + (int64_t)p * d;
-  const double* vp = v + (int64_t)p * d;
-  const double* bp = base + (int64_t)p * d;
-  double* op = out + (int64_t)p * d;
+  const double* vp = INV ? nullptr : v + (int64_t)p * d;
+  const double* bp = INV ? nullptr : base + (int64_t)p * d;
+  double* op = INV ? out + ((int64_t)p * d + blockIdx.y) * d : out + (int64_t)p * d;
   if (tid == 0) {
     code = status_failed_by(st, -1) ? 1 : 0;
     if (gate != nullptr && status_failed_by(gate, gate_iter)) code = 1;
   }
   __syncthreads();
   if (code != 0) {
-    if (op != bp)
+    if (!INV && op != bp)
       for (int64_t i = tid; i < d; i += 256) op[i] = bp[i];
     return;
   }
-  for (int64_t i = tid; i < d; i += 256) y[i] = vp[i];
-  __syncthreads();
+  for (int64_t i = tid; i < d; i += 256) y[i] = INV ? (i == (int64_t)blockIdx.y ? 1.0 : 0.0) : vp[i];
+  const int64_t nblk = (d + 63) / 64;
   // forward: L y = v
-  for (int64_t jb = 0; jb < d; jb += 64) {
+  for (int64_t bi = 0; bi < nblk; ++bi) {
+    const int64_t jb = bi * 64;
     const int nb = (int)min((int64_t)64, d - jb);
+    for (int e = tid; e < 64 * 64; e += 256) {
+      const int i = e >> 6, j = e & 63;
+      D[i][j] = (i < nb && j < nb && j <= i) ? Lp[(jb + i) * d + jb + j] : 0.0;
+    }
+    __syncthreads();
     if (wv == 0) {
-      double lr[64];
-      const double* row = Lp + (jb + lane) * d + jb;
-#pragma unroll
-      for (int k = 0; k < 64; ++k) lr[k] = (lane < nb && k < lane) ? row[k] : 0.0;
       double yl = lane < nb ? y[jb + lane] : 0.0;
-      const double rl = lane < nb ? rp[jb + lane] : 0.0;
-#pragma unroll
-      for (int c = 0; c < 64; ++c) {
-        if (c < nb) {
-          if (lane == c) yl = yl * rl;
-          const double yc = __shfl(yl, c, 64);
-          if (lane > c) yl = fma(-lr[c], yc, yl);
-        }
+      for (int c = 0; c < nb; ++c) {
+        const double lkc = D[lane][c];
+        const double xc = __shfl(yl, c, 64) * rp[jb + c];
+        if (lane == c) yl = xc;
+        else if (lane > c) yl = fma(-xc, lkc, yl);
       }
       if (lane < nb) y[jb + lane] = yl;
     }
     __syncthreads();
-    for (int64_t i = jb + nb + tid; i < d; i += 256) {
-      const double* lrow = Lp + i * d + jb;
-      double s = 0.0;
-#pragma unroll 16
-      for (int c = 0; c < nb; ++c) s = fma(lrow[c], y[jb + c], s);
-      y[i] -= s;
+    for (int64_t i0 = jb + nb + (int64_t)wv * 4; i0 < d; i0 += 16) {
+      double t[4];
+      const double yb = lane < nb ? y[jb + lane] : 0.0;
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        t[u] = (i0 + u < d && lane < nb) ? Lp[(i0 + u) * d + jb + lane] * yb : 0.0;
+      const double s = multi_row_sum4(t, lane);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (lane == row_lane4(u) && i0 + u < d) y[i0 + u] -= s;
+      }
     }
     __syncthreads();
   }
   // backward: L^T z = y
-  const int64_t nblk = (d + 63) / 64;
   for (int64_t bi = nblk - 1; bi >= 0; --bi) {
     const int64_t jb = bi * 64;
     const int nb = (int)min((int64_t)64, d - jb);
+    for (int e = tid; e < 64 * 64; e += 256) {
+      const int i = e >> 6, j = e & 63;
+      D[i][j] = (i < nb && j < nb && j <= i) ? Lp[(jb + i) * d + jb + j] : 0.0;
+    }
+    __syncthreads();
     if (wv == 0) {
-      double lc[64];
-#pragma unroll
-      for (int k = 0; k < 64; ++k)
-        lc[k] = (lane < nb && k > lane && k < nb) ? Lp[(jb + k) * d + jb + lane] : 0.0;
       double yl = lane < nb ? y[jb + lane] : 0.0;
-      const double rl = lane < nb ? rp[jb + lane] : 0.0;
-#pragma unroll
-      for (int c = 63; c >= 0; --c) {
-        if (c < nb) {
-          if (lane == c) yl = yl * rl;
-          const double yc = __shfl(yl, c, 64);
-          if (lane < c) yl = fma(-lc[c], yc, yl);
-        }
+      for (int c = nb - 1; c >= 0; --c) {
+        const double lck = D[c][lane];
+        const double xc = __shfl(yl, c, 64) * rp[jb + c];
+        if (lane == c) yl = xc;
+        else if (lane < c) yl = fma(-xc, lck, yl);
       }
       if (lane < nb) y[jb + lane] = yl;
     }
     __syncthreads();
     for (int64_t i = tid; i < jb; i += 256) {
       double s = 0.0;
-#pragma unroll 16
+#pragma unroll 8
       for (int c = 0; c < nb; ++c) s = fma(Lp[(jb + c) * d + i], y[jb + c], s);
       y[i] -= s;
     }
     __syncthreads();
+  }
+  if (INV) {
+    for (int64_t i = tid; i < d; i += 256) op[i] = y[i];
+    return;
   }
   double part = 0.0;
   bool finite = true;
@@ -461,8 +492,75 @@ hipError_t launch_chol_solve_update(const double* L, const double* rdiag, int64_
                                     int32_t batch, const double* v, const double* base,
                                     double* out, DeviceStatus* status, hipStream_t st,
                                     const DeviceStatus* gate, int32_t gate_iter) {
-  hipLaunchKernelGGL(k_chol_solve, dim3(batch), dim3(256), (size_t)(d * sizeof(double)), st, L,
-                     d, rdiag, v, base, out, status, gate, gate_iter);
+  hipLaunchKernelGGL(k_chol_solve<false>, dim3(batch), dim3(256), (size_t)(d * sizeof(double)),
+                     st, L, d, rdiag, v, base, out, status, gate, gate_iter);
+  return hipGetLastError();
+}
+
+hipError_t launch_chol_inverse(const double* L, const double* rdiag, int64_t d, int32_t batch,
+                               double* Hinv, DeviceStatus* status, hipStream_t st) {
+  hipLaunchKernelGGL(k_chol_solve<true>, dim3(batch, (unsigned)d), dim3(256),
+                     (size_t)(d * sizeof(double)), st, L, d, rdiag, nullptr, nullptr, Hinv,
+                     status, nullptr, -1);
+  return hipGetLastError();
+}
+
+// x_out = x + Hinv g per problem, one wavefront per row of Hinv (a symmetric
+// matrix, so row i is column i). A second kernel records sqrt(dx^T g) and
+// checks finiteness. Skips (x_out = x) on a recorded failure.
+__global__ __launch_bounds__(256) void k_inv_apply(const double* __restrict__ Hinv, int64_t d,
+                                                   const double* __restrict__ g,
+                                                   const double* x, double* x_out, double* dx,
+                                                   const DeviceStatus* st,
+                                                   const DeviceStatus* gate, int32_t gate_iter) {
+  const int p = blockIdx.y;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * 4 + wv;
+  if (i >= d) return;
+  const bool skip = status_failed_by(st, -1) || (gate && status_failed_by(gate, gate_iter));
+  const double* hr = Hinv + ((int64_t)p * d + i) * d;
+  const double* gp = g + (int64_t)p * d;
+  double s = 0.0;
+  for (int64_t c = lane; c < d; c += 64) s = fma(hr[c], gp[c], s);
+  s = wave_sum(s);
+  if (lane == 0) {
+    const int64_t k = (int64_t)p * d + i;
+    dx[k] = skip ? 0.0 : s;
+    x_out[k] = skip ? x[k] : x[k] + s;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_inv_finish(int64_t d, int32_t batch, const double* g,
+                                                    const double* dx, const double* x_out,
+                                                    DeviceStatus* st) {
+  __shared__ double red[256];
+  __shared__ int bad;
+  const int tid = threadIdx.x;
+  if (tid == 0) bad = 0;
+  __syncthreads();
+  double part = 0.0;
+  for (int64_t k = tid; k < (int64_t)batch * d; k += 256) {
+    if (k < d) part = fma(dx[k], g[k], part);
+    if (!isfinite(x_out[k])) bad = 1;
+  }
+  red[tid] = part;
+  __syncthreads();
+  for (int stride = 128; stride > 0; stride >>= 1) {
+    if (tid < stride) red[tid] += red[tid + stride];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    if (bad) status_fail(st, 7 /* IHS_ERR_NONFINITE */, -1, 0);
+    st->last_step = sqrt(fmax(red[0], 0.0));
+  }
+}
+
+hipError_t launch_inv_apply(const double* Hinv, int64_t d, int32_t batch, const double* g,
+                            const double* x, double* x_out, double* dx, DeviceStatus* status,
+                            hipStream_t st, const DeviceStatus* gate, int32_t gate_iter) {
+  hipLaunchKernelGGL(k_inv_apply, dim3((unsigned)((d + 3) / 4), batch), dim3(256), 0, st, Hinv, d,
+                     g, x, x_out, dx, status, gate, gate_iter);
+  hipLaunchKernelGGL(k_inv_finish, dim3(1), dim3(256), 0, st, d, batch, g, dx, x_out, status);
   return hipGetLastError();
 }
 

@@ -103,9 +103,11 @@ hipError_t launch_sketch_hash(const SketchPlan& p, int64_t n, int32_t problem,
 // Sort step 1: hash every (row, block) of a tile, store its key, and count
 // keys per sketch row in LDS.
 // ---------------------------------------------------------------------------
+// Tiles are visited grid-stride by a capped grid, so the sort never takes
+// more than a small share of the CUs beside a running pass over A.
 __global__ __launch_bounds__(256) void k_hash_count(SketchPlan P) {
   extern __shared__ int32_t cnt[];
-  const int tile = blockIdx.x;
+  for (int tile = blockIdx.x; tile < P.total_tiles; tile += gridDim.x) {
   const int p = find_by_tile(P.probs, P.batch, tile);
   const ProbInfo pi = P.probs[p];
   const int64_t lr0 = (int64_t)(tile - pi.tile0) * P.tile_rows;
@@ -134,6 +136,8 @@ __global__ __launch_bounds__(256) void k_hash_count(SketchPlan P) {
   __syncthreads();
   int32_t* out = P.tile_count + (int64_t)tile * P.m;
   for (int64_t b = threadIdx.x; b < P.m; b += blockDim.x) out[b] = cnt[b];
+  __syncthreads();  // the LDS histogram is reused by the next tile
+  }
 }
 
 // Sort step 2a: per (chunk of tiles, sketch row) totals.
@@ -241,7 +245,7 @@ __global__ __launch_bounds__(256) void k_scan_tiles(SketchPlan P) {
 // among equal keys with one ballot per key bit.
 __global__ __launch_bounds__(256) void k_scatter(SketchPlan P) {
   extern __shared__ int32_t pos[];
-  const int tile = blockIdx.x;
+  for (int tile = blockIdx.x; tile < P.total_tiles; tile += gridDim.x) {
   const int p = find_by_tile(P.probs, P.batch, tile);
   const ProbInfo pi = P.probs[p];
   const int64_t lr0 = (int64_t)(tile - pi.tile0) * P.tile_rows;
@@ -277,7 +281,11 @@ __global__ __launch_bounds__(256) void k_scatter(SketchPlan P) {
       __syncthreads();
     }
   }
+  __syncthreads();  // pos is reloaded for the next tile
+  }
 }
+
+constexpr int32_t kSortGrid = 2048;  // workgroup cap of the tile-parallel sort kernels
 
 __global__ void k_zero_i32(int32_t* p, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -294,12 +302,13 @@ hipError_t launch_sort(const SketchPlan& P, hipStream_t st) {
     return hipGetLastError();
   }
   const size_t lds_m = (size_t)P.m * sizeof(int32_t);
-  hipLaunchKernelGGL(k_hash_count, dim3(P.total_tiles), dim3(256), lds_m, st, P);
+  const unsigned tiles_grid = (unsigned)std::min<int32_t>(P.total_tiles, kSortGrid);
+  hipLaunchKernelGGL(k_hash_count, dim3(tiles_grid), dim3(256), lds_m, st, P);
   hipLaunchKernelGGL(k_scan_chunks, dim3(P.total_chunks, gy), dim3(256), 0, st, P);
   hipLaunchKernelGGL(k_scan_rows, dim3(gy, P.batch), dim3(256), 0, st, P);
   hipLaunchKernelGGL(k_scan_totals, dim3(P.batch), dim3(1024), 0, st, P);
   hipLaunchKernelGGL(k_scan_tiles, dim3(P.total_chunks, gy), dim3(256), 0, st, P);
-  hipLaunchKernelGGL(k_scatter, dim3(P.total_tiles), dim3(256), lds_m, st, P);
+  hipLaunchKernelGGL(k_scatter, dim3(tiles_grid), dim3(256), lds_m, st, P);
   return hipGetLastError();
 }
 
@@ -391,46 +400,38 @@ __device__ __forceinline__ double readlane_f64(double v, int l) {
 
 // IDENT: natural row order (no sketch): wavefront w takes rows
 // [row0 + seg*seg_rows, ...) of its problem, and only the gradient is formed.
-// Otherwise the grid is (ceil(m/4), batch): wavefront wv of workgroup x owns
-// sketch row 4x + wv of problem blockIdx.y, and the four wavefronts add their
-// gradient partials in LDS (fixed order) into one partial per workgroup.
-template <typename TA, int VEC, int NCH, int U, bool GRAD, bool IDENT>
-__global__ __launch_bounds__(256, (NCH <= 4 ? 4 : 2)) void k_gather(SketchPlan P, GatherArgs G,
-                                                                    int32_t total_seg,
-                                                                    int32_t seg_rows) {
-  extern __shared__ double gsh[];  // 4 x d (fused gradient, non-IDENT)
+// Otherwise the grid is (ceil(ceil(m/BPW)/4), batch): wavefront w of problem
+// blockIdx.y owns sketch rows [w*BPW, w*BPW + BPW) and streams them one after
+// the other, so each sketch row is still summed in ascending input-row order
+// by one lane per column. Owning two sketch rows halves the number of
+// resident wavefronts, which leaves room on every CU for the overlapped work
+// of the next step. Each wavefront of block 0 writes one gradient partial.
+template <typename TA, int VEC, int NCH, int U, int BPW, bool GRAD, bool IDENT>
+__global__ __launch_bounds__(256, (BPW > 1 ? 3 : (NCH <= 4 ? 4 : 2))) void k_gather(
+    SketchPlan P, GatherArgs G, int32_t total_seg, int32_t seg_rows) {
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t d = G.d;
   constexpr int SPAN = 64 * VEC;
   int p;
-  int64_t bl, beg = 0, end = 0, gslot, bg;
+  int64_t wid, gslot, nown;
   bool active;
   if (IDENT) {
-    bg = (int64_t)blockIdx.x * 4 + wv;
-    active = bg < total_seg;
-    p = active ? find_by_seg(P.probs, P.batch, (int)bg) : 0;
-    if (active) {
-      const ProbInfo pi = P.probs[p];
-      beg = pi.row0 + (bg - pi.seg0) * (int64_t)seg_rows;
-      end = min(beg + seg_rows, pi.row0 + pi.rows);
-    }
-    bl = 0;
-    gslot = bg;
+    wid = (int64_t)blockIdx.x * 4 + wv;
+    active = wid < total_seg;
+    p = active ? find_by_seg(P.probs, P.batch, (int)wid) : 0;
+    gslot = wid;
+    nown = 1;
   } else {
     p = blockIdx.y;
-    bl = (int64_t)blockIdx.x * 4 + wv;
-    active = bl < P.m;
-    bg = (int64_t)p * P.m + bl;
-    if (active) {
-      beg = P.bucket_start[bg];
-      end = P.bucket_start[bg + 1];
-    }
-    gslot = (int64_t)p * ((P.m_blk + 3) / 4) + blockIdx.x;
+    wid = (int64_t)blockIdx.x * 4 + wv;
+    const int64_t b0 = wid * BPW;
+    active = b0 < P.m;
+    nown = active ? min((int64_t)BPW, P.m - b0) : 0;
+    gslot = (int64_t)p * ((P.m_blk + BPW - 1) / BPW) + wid;
   }
-  const bool grad = GRAD && active && (bl < P.m_blk);  // block 0 visits every row once
+  const bool any_grad = GRAD && active && (IDENT || wid * BPW < P.m_blk);
   const TA* __restrict__ A = static_cast<const TA*>(G.A);
 
-  double acc[NCH][VEC];
   double xr[NCH][VEC];
   double ga[NCH][VEC];
   double fa = 0.0;
@@ -438,11 +439,10 @@ __global__ __launch_bounds__(256, (NCH <= 4 ? 4 : 2)) void k_gather(SketchPlan P
   for (int c = 0; c < NCH; ++c)
 #pragma unroll
     for (int v = 0; v < VEC; ++v) {
-      acc[c][v] = 0.0;
       ga[c][v] = 0.0;
       xr[c][v] = 0.0;
     }
-  if (grad) {
+  if (any_grad) {
 #pragma unroll
     for (int c = 0; c < NCH; ++c)
 #pragma unroll
@@ -452,134 +452,147 @@ __global__ __launch_bounds__(256, (NCH <= 4 ? 4 : 2)) void k_gather(SketchPlan P
       }
   }
 
-  uint32_t pe_next = 0u;
-  if (beg + lane < end) pe_next = IDENT ? (uint32_t)(beg + lane) : P.perm[beg + lane];
-  for (int64_t base = beg; base < end; base += 64) {
-    const int cnt = (int)min((int64_t)64, end - base);
-    const uint32_t pe = pe_next;
-    if (base + 64 + lane < end)  // next batch's row ids, one batch ahead
-      pe_next = IDENT ? (uint32_t)(base + 64 + lane) : P.perm[base + 64 + lane];
-    double bv = 0.0;
-    if (grad && lane < cnt) bv = G.b ? G.b[pe & 0x7FFFFFFFu] : 0.0;
-    for (int j = 0; j < cnt; j += U) {
-      double val[U][NCH][VEC];
-      uint32_t ent[U];
+  for (int64_t own = 0; own < nown; ++own) {
+    int64_t bl, bg, beg, end;
+    if (IDENT) {
+      const ProbInfo pi = P.probs[p];
+      bl = 0;
+      bg = wid;
+      beg = pi.row0 + (wid - pi.seg0) * (int64_t)seg_rows;
+      end = min(beg + seg_rows, pi.row0 + pi.rows);
+    } else {
+      bl = wid * BPW + own;
+      bg = (int64_t)p * P.m + bl;
+      beg = P.bucket_start[bg];
+      end = P.bucket_start[bg + 1];
+    }
+    const bool grad = GRAD && (IDENT || bl < P.m_blk);  // block 0 visits every row once
+    double acc[NCH][VEC];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int jj = min(j + u, cnt - 1);
-        ent[u] = readlane_u32(pe, jj);
-        const uint32_t row = ent[u] & 0x7FFFFFFFu;
-        const TA* rp = A + (int64_t)row * G.ld;
+    for (int c = 0; c < NCH; ++c)
 #pragma unroll
-        for (int c = 0; c < NCH; ++c) {
-          const int64_t col = (int64_t)c * SPAN + lane * VEC;
-          if (col < d) {
-            VecLoad<TA, VEC>::ld(rp + col, val[u][c]);
-          } else {
+      for (int v = 0; v < VEC; ++v) acc[c][v] = 0.0;
+
+    uint32_t pe_next = 0u;
+    if (beg + lane < end) pe_next = IDENT ? (uint32_t)(beg + lane) : P.perm[beg + lane];
+    for (int64_t base = beg; base < end; base += 64) {
+      const int cnt = (int)min((int64_t)64, end - base);
+      const uint32_t pe = pe_next;
+      if (base + 64 + lane < end)  // next batch's row ids, one batch ahead
+        pe_next = IDENT ? (uint32_t)(base + 64 + lane) : P.perm[base + 64 + lane];
+      double bv = 0.0;
+      if (grad && lane < cnt) bv = G.b ? G.b[pe & 0x7FFFFFFFu] : 0.0;
+      for (int j = 0; j < cnt; j += U) {
+        double val[U][NCH][VEC];
+        uint32_t ent[U];
 #pragma unroll
-            for (int v = 0; v < VEC; ++v) val[u][c][v] = 0.0;
+        for (int u = 0; u < U; ++u) {
+          const int jj = min(j + u, cnt - 1);
+          ent[u] = readlane_u32(pe, jj);
+          const uint32_t row = ent[u] & 0x7FFFFFFFu;
+          const TA* rp = A + (int64_t)row * G.ld;
+#pragma unroll
+          for (int c = 0; c < NCH; ++c) {
+            const int64_t col = (int64_t)c * SPAN + lane * VEC;
+            if (col < d) {
+              VecLoad<TA, VEC>::ld(rp + col, val[u][c]);
+            } else {
+#pragma unroll
+              for (int v = 0; v < VEC; ++v) val[u][c][v] = 0.0;
+            }
           }
         }
-      }
-      if (grad) {
-        double dot[U];
+        if (grad) {
+          double dot[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          double s = 0.0;
-#pragma unroll
-          for (int c = 0; c < NCH; ++c)
-#pragma unroll
-            for (int v = 0; v < VEC; ++v) s = fma(val[u][c][v], xr[c][v], s);
-          dot[u] = s;
-        }
-        const double red = multi_row_sum<U>(dot, lane);
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          if (j + u < cnt) {
-            const double ri = readlane_f64(bv, j + u) - readlane_f64(red, row_lane<U>(u));
-            fa = fma(ri, ri, fa);
+          for (int u = 0; u < U; ++u) {
+            double s = 0.0;
 #pragma unroll
             for (int c = 0; c < NCH; ++c)
 #pragma unroll
-              for (int v = 0; v < VEC; ++v) ga[c][v] = fma(ri, val[u][c][v], ga[c][v]);
-            if (G.r_out != nullptr && lane == 0) G.r_out[ent[u] & 0x7FFFFFFFu] = ri;
+              for (int v = 0; v < VEC; ++v) s = fma(val[u][c][v], xr[c][v], s);
+            dot[u] = s;
+          }
+          const double red = multi_row_sum<U>(dot, lane);
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            if (j + u < cnt) {
+              const double ri = readlane_f64(bv, j + u) - readlane_f64(red, row_lane<U>(u));
+              fa = fma(ri, ri, fa);
+#pragma unroll
+              for (int c = 0; c < NCH; ++c)
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) ga[c][v] = fma(ri, val[u][c][v], ga[c][v]);
+              if (G.r_out != nullptr && lane == 0) G.r_out[ent[u] & 0x7FFFFFFFu] = ri;
+            }
           }
         }
-      }
-      if (!IDENT) {
+        if (!IDENT) {
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          if (j + u < cnt) {
-            const bool neg = (ent[u] >> 31) != 0;
+          for (int u = 0; u < U; ++u) {
+            if (j + u < cnt) {
+              const bool neg = (ent[u] >> 31) != 0;
 #pragma unroll
-            for (int c = 0; c < NCH; ++c)
+              for (int c = 0; c < NCH; ++c)
 #pragma unroll
-              for (int v = 0; v < VEC; ++v)
-                acc[c][v] = neg ? (acc[c][v] - val[u][c][v]) : (acc[c][v] + val[u][c][v]);
+                for (int v = 0; v < VEC; ++v)
+                  acc[c][v] = neg ? (acc[c][v] - val[u][c][v]) : (acc[c][v] + val[u][c][v]);
+            }
           }
         }
       }
     }
+    if (!IDENT) {
+      const int64_t orow = bg * G.ld_sa;
+#pragma unroll
+      for (int c = 0; c < NCH; ++c)
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) {
+          const int64_t col = (int64_t)c * SPAN + lane * VEC + v;
+          if (col < d) store_sa(G.SA, G.sa_dtype, orow + col, acc[c][v] * G.scale);
+        }
+    }
   }
-
-  if (!IDENT && active) {
-    const int64_t orow = bg * G.ld_sa;
+  if (any_grad) {  // one partial per wavefront
+    double* gp = G.gpart + gslot * d;
 #pragma unroll
     for (int c = 0; c < NCH; ++c)
 #pragma unroll
       for (int v = 0; v < VEC; ++v) {
         const int64_t col = (int64_t)c * SPAN + lane * VEC + v;
-        if (col < d) store_sa(G.SA, G.sa_dtype, orow + col, acc[c][v] * G.scale);
+        if (col < d) gp[col] = ga[c][v];
       }
+    if (lane == 0) G.fpart[gslot] = fa;
   }
-  if (GRAD && IDENT) {
-    if (grad) {
-      double* gp = G.gpart + gslot * d;
-#pragma unroll
-      for (int c = 0; c < NCH; ++c)
-#pragma unroll
-        for (int v = 0; v < VEC; ++v) {
-          const int64_t col = (int64_t)c * SPAN + lane * VEC + v;
-          if (col < d) gp[col] = ga[c][v];
-        }
-      if (lane == 0) G.fpart[gslot] = fa;
-    }
-  } else if (GRAD) {
-    // one partial per workgroup: wavefronts 0..3 added in order
-    if ((int64_t)blockIdx.x * 4 < P.m_blk) {
-      __shared__ double fsh[4];
-#pragma unroll
-      for (int c = 0; c < NCH; ++c)
-#pragma unroll
-        for (int v = 0; v < VEC; ++v) {
-          const int64_t col = (int64_t)c * SPAN + lane * VEC + v;
-          if (col < d) gsh[wv * d + col] = grad ? ga[c][v] : 0.0;
-        }
-      if (lane == 0) fsh[wv] = grad ? fa : 0.0;
-      __syncthreads();
-      double* gp = G.gpart + gslot * d;
-      for (int64_t col = threadIdx.x; col < d; col += 256)
-        gp[col] = ((gsh[col] + gsh[d + col]) + gsh[2 * d + col]) + gsh[3 * d + col];
-      if (threadIdx.x == 0) G.fpart[gslot] = ((fsh[0] + fsh[1]) + fsh[2]) + fsh[3];
-    }
-  }
+}
+
+// Sketch rows per wavefront of the dense gather.
+int32_t gather_rows_per_wave(int64_t m, int32_t batch, int64_t d) {
+  return ((int64_t)batch * m >= 2048 && d > 64 && d <= 768) ? 2 : 1;
 }
 
 template <typename TA, int VEC, int NCH, bool GRAD, bool IDENT>
 static hipError_t gather_inst(const SketchPlan& P, const GatherArgs& G, int32_t total_seg,
                               int32_t seg_rows, hipStream_t st) {
-  // rows in flight per wavefront: enough with 16 wavefronts per CU, while the
-  // register budget keeps 4 wavefronts per SIMD
-  constexpr int U = NCH == 1 ? 8 : (NCH == 2 ? 4 : 2);
   if (IDENT) {
+    // rows in flight per wavefront: enough with 16 wavefronts per CU, while the
+    // register budget keeps 4 wavefronts per SIMD
+    constexpr int U = NCH == 1 ? 8 : (NCH == 2 ? 4 : 2);
     const unsigned blocks = (unsigned)((total_seg + 3) / 4);
     if (blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_gather<TA, VEC, NCH, U, GRAD, IDENT>), dim3(blocks), dim3(256), 0, st,
-                       P, G, total_seg, seg_rows);
+    hipLaunchKernelGGL((k_gather<TA, VEC, NCH, U, 1, GRAD, IDENT>), dim3(blocks), dim3(256), 0,
+                       st, P, G, total_seg, seg_rows);
+  } else if (gather_rows_per_wave(P.m, P.batch, G.d) == 2) {
+    // half the wavefronts, twice the rows in flight each
+    constexpr int U = NCH == 1 ? 8 : (NCH <= 4 ? 4 : 2);
+    const int64_t waves = (P.m + 1) / 2;
+    hipLaunchKernelGGL((k_gather<TA, VEC, NCH, U, 2, GRAD, IDENT>),
+                       dim3((unsigned)((waves + 3) / 4), P.batch), dim3(256), 0, st, P, G,
+                       total_seg, seg_rows);
   } else {
-    const size_t lds = GRAD ? (size_t)4 * G.d * sizeof(double) : 0;
-    hipLaunchKernelGGL((k_gather<TA, VEC, NCH, U, GRAD, IDENT>),
-                       dim3((unsigned)((P.m + 3) / 4), P.batch), dim3(256), lds, st, P, G,
+    constexpr int U = NCH == 1 ? 8 : (NCH == 2 ? 4 : 2);
+    hipLaunchKernelGGL((k_gather<TA, VEC, NCH, U, 1, GRAD, IDENT>),
+                       dim3((unsigned)((P.m + 3) / 4), P.batch), dim3(256), 0, st, P, G,
                        total_seg, seg_rows);
   }
   return hipGetLastError();

@@ -247,7 +247,8 @@ def test_overlap_schedule_matches_sequential(gpu_lib, shape):
         out[sched] = (host(r.x), host(r.history), host(r.factors), r.report)
     a, s = out["overlap"], out["sequential"]
     # same sketches, so the same factors bit for bit; the gradient is summed in
-    # another row order, so iterates agree to rounding
+    # another row order (and wide problems apply an explicit inverse), so
+    # iterates agree to rounding
     assert np.array_equal(a[2], s[2])
     for t in range(7):
         assert np.allclose(a[1][t], s[1][t], rtol=1e-12, atol=1e-14 * np.abs(s[1][t]).max())
