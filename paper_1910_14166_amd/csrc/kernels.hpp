@@ -151,14 +151,19 @@ struct QpArgs {
 };
 size_t qp_work_doubles(int64_t d, int32_t constraint);
 hipError_t launch_qp_step(const QpArgs& a, hipStream_t st);
+// The l1- and l2-ball steps (constraint 1 and 2); a.work holds
+// qp_work_doubles(d, constraint) doubles per problem.
+hipError_t launch_qp_constrained(const QpArgs& a, hipStream_t st);
 
 // Cholesky alone (lower factor of each H into L) and the two triangular
 // solves applied to a right-hand side: out = in + (L L^T)^{-1} v.
 // scratch: batch * (64*64 + d) doubles: the diagonal-block side buffers of
 // the blocked path, then the reciprocal pivots 1/L_jj (chol_rdiag).
+// trs (nullable): per-problem shift and skip state of the l2-ball iteration
+// (trs[4p] replaces `shift`; problems with trs[4p+1] >= 2 are left untouched).
 hipError_t launch_cholesky(const double* H, double* L, int64_t d, int32_t batch,
                            DeviceStatus* status, int32_t iter, double shift, double* scratch,
-                           hipStream_t st);
+                           hipStream_t st, const double* trs = nullptr);
 double* chol_rdiag(double* scratch, int32_t batch);
 // H^{-1} = (L L^T)^{-1}, one workgroup per (problem, identity column).
 hipError_t launch_chol_inverse(const double* L, const double* rdiag, int64_t d, int32_t batch,

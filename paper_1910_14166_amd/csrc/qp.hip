@@ -36,6 +36,12 @@ __device__ __forceinline__ double multi_row_sum4(const double (&v)[4], int lane)
 __device__ __forceinline__ int row_lane4(int u) { return ((u >> 1) & 1) * 32 + (u & 1) * 16; }  // d*d doubles within 64 KiB of LDS
 constexpr int kNb = 64;
 
+// Per-problem state of the l2-ball shift iteration: trs[4p] is the shift mu
+// added to the diagonal, trs[4p+1] >= 2 marks a problem that needs no factor.
+__device__ __forceinline__ bool trs_skip(const double* trs, int p) {
+  return trs != nullptr && trs[4 * p + 1] >= 2.0;
+}
+
 __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -134,13 +140,15 @@ hipError_t launch_reduce_partials(const double* gpart, const double* fpart, int3
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_chol_small(const double* __restrict__ H, double* L,
                                                     int64_t d, DeviceStatus* st, int32_t iter,
-                                                    double shift, double* rdiag) {
+                                                    double shift, double* rdiag,
+                                                    const double* __restrict__ trs) {
   extern __shared__ double a[];
   __shared__ int fail;
   const int p = blockIdx.x;
-  if (threadIdx.x == 0) fail = st->code;
+  if (threadIdx.x == 0) fail = (st->code != 0 || trs_skip(trs, p)) ? 1 : 0;
   __syncthreads();
   if (fail != 0) return;  // one read per workgroup keeps the exit uniform
+  if (trs) shift = trs[4 * p];
   const double* Hp = H + (int64_t)p * d * d;
   double* Lp = L + (int64_t)p * d * d;
   const int tid = threadIdx.x;
@@ -183,9 +191,13 @@ __global__ __launch_bounds__(256) void k_chol_small(const double* __restrict__ H
 // Blocked Cholesky for larger d, in place on L (lower triangle).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_chol_init(const double* __restrict__ H, double* L,
-                                                   int64_t d, int32_t batch, double shift) {
+                                                   int64_t d, int32_t batch, double shift,
+                                                   const double* __restrict__ trs) {
   const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (idx >= (int64_t)batch * d * d) return;
+  const int p = (int)(idx / (d * d));
+  if (trs_skip(trs, p)) return;
+  if (trs) shift = trs[4 * p];
   const int64_t e = idx % (d * d);
   const int64_t i = e / d, j = e - (e / d) * d;
   L[idx] = (j <= i) ? H[idx] + (i == j ? shift : 0.0) : 0.0;
@@ -196,13 +208,13 @@ __global__ __launch_bounds__(256) void k_chol_init(const double* __restrict__ H,
 // columns 16*(t%4) .. +15) and writes L_kk and 1/L_jj back.
 __global__ __launch_bounds__(256) void k_chol_diag(double* L, int64_t d, int64_t kb,
                                                    double* rdiag, DeviceStatus* st,
-                                                   int32_t iter) {
+                                                   int32_t iter, const double* __restrict__ trs) {
   __shared__ double D[kNb][kNb + 1];
   __shared__ double rd[kNb];
   __shared__ int flag;
   const int p = blockIdx.x;
   const int tid = threadIdx.x;
-  if (tid == 0) flag = st->code;
+  if (tid == 0) flag = (st->code != 0 || trs_skip(trs, p)) ? 1 : 0;
   __syncthreads();
   if (flag != 0) return;
   double* W = L + (int64_t)p * d * d;
@@ -254,13 +266,13 @@ __global__ __launch_bounds__(256) void k_chol_diag(double* L, int64_t d, int64_t
 // Four rows are interleaved per wavefront for independent dependency chains.
 __global__ __launch_bounds__(256) void k_chol_trsm(double* L, int64_t d, int64_t kb,
                                                    const double* __restrict__ rdiag,
-                                                   DeviceStatus* st) {
+                                                   DeviceStatus* st, const double* __restrict__ trs) {
   __shared__ double D[kNb][kNb + 1];
   __shared__ double rd[kNb];
   __shared__ int flag;
   const int p = blockIdx.y;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  if (tid == 0) flag = st->code;
+  if (tid == 0) flag = (st->code != 0 || trs_skip(trs, p)) ? 1 : 0;
   __syncthreads();
   if (flag != 0) return;
   double* W = L + (int64_t)p * d * d;
@@ -298,7 +310,8 @@ __global__ __launch_bounds__(256) void k_chol_trsm(double* L, int64_t d, int64_t
 // P = W[:, kb:kb+64]. One wavefront per 16 x 16 lower tile (small register
 // footprint, so these tiles also run beside a memory-bound pass).
 __global__ __launch_bounds__(256) void k_chol_update(double* L, int64_t d, int64_t kb,
-                                                     int32_t batch, DeviceStatus* st) {
+                                                     int32_t batch, DeviceStatus* st,
+                                                     const double* __restrict__ trs) {
   if (st->code != 0) return;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t t0 = kb + kNb;
@@ -307,6 +320,7 @@ __global__ __launch_bounds__(256) void k_chol_update(double* L, int64_t d, int64
   const int64_t w = (int64_t)blockIdx.x * 4 + wv;
   if (w >= ntri * batch) return;
   const int p = (int)(w / ntri);
+  if (trs_skip(trs, p)) return;
   const int64_t t = w - (int64_t)p * ntri;
   int64_t ti = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
   while (ti * (ti + 1) / 2 > t) --ti;
@@ -334,26 +348,28 @@ __global__ __launch_bounds__(256) void k_chol_update(double* L, int64_t d, int64
 
 hipError_t launch_cholesky(const double* H, double* L, int64_t d, int32_t batch,
                            DeviceStatus* status, int32_t iter, double shift, double* scratch,
-                           hipStream_t st) {
+                           hipStream_t st, const double* trs) {
   double* rdiag = chol_rdiag(scratch, batch);
   if (d <= kSmallChol) {
     hipLaunchKernelGGL(k_chol_small, dim3(batch), dim3(256), (size_t)(d * d * sizeof(double)),
-                       st, H, L, d, status, iter, shift, rdiag);
+                       st, H, L, d, status, iter, shift, rdiag, trs);
     return hipGetLastError();
   }
   const int64_t tot = (int64_t)batch * d * d;
   hipLaunchKernelGGL(k_chol_init, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, H, L, d,
-                     batch, shift);
+                     batch, shift, trs);
   for (int64_t kb = 0; kb < d; kb += kNb) {
-    hipLaunchKernelGGL(k_chol_diag, dim3(batch), dim3(256), 0, st, L, d, kb, rdiag, status, iter);
+    hipLaunchKernelGGL(k_chol_diag, dim3(batch), dim3(256), 0, st, L, d, kb, rdiag, status, iter,
+                       trs);
     const int64_t below = std::max<int64_t>(0, d - kb - kNb);
     if (below == 0) break;
     const unsigned gx = (unsigned)((below + 15) / 16);  // 16 rows per workgroup
-    hipLaunchKernelGGL(k_chol_trsm, dim3(gx, batch), dim3(256), 0, st, L, d, kb, rdiag, status);
+    hipLaunchKernelGGL(k_chol_trsm, dim3(gx, batch), dim3(256), 0, st, L, d, kb, rdiag, status,
+                       trs);
     const int64_t T = (below + 15) / 16;
     const int64_t waves = T * (T + 1) / 2 * batch;
     hipLaunchKernelGGL(k_chol_update, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st, L, d,
-                       kb, batch, status);
+                       kb, batch, status, trs);
   }
   return hipGetLastError();
 }
@@ -585,12 +601,13 @@ double* chol_rdiag(double* scratch, int32_t batch) { return scratch + (int64_t)b
 // Per-problem scratch of the QP kernels: the 64 x 64 diagonal-block side
 // buffer of the blocked Cholesky plus vectors.
 size_t qp_work_doubles(int64_t d, int32_t constraint) {
-  (void)constraint;
-  return (size_t)(kNb * kNb + 9 * d + 64);
+  // constrained steps add c, the unconstrained minimiser and two Newton
+  // vectors, plus four state words
+  return (size_t)(kNb * kNb + 9 * d + 64) + (constraint != 0 ? (size_t)(5 * d + 8) : 0);
 }
 
 hipError_t launch_qp_step(const QpArgs& a, hipStream_t st) {
-  if (a.constraint != 0) return hipErrorNotSupported;
+  if (a.constraint != 0) return launch_qp_constrained(a, st);
   hipError_t e = launch_cholesky(a.H, a.L, a.d, a.batch, a.status, a.iter, 0.0,
                                  a.work, st);
   if (e != hipSuccess) return e;

@@ -1,0 +1,510 @@
+// The step of Eq.(2) over the l1 and l2 balls of Eq.(1):
+//     minimise 1/2 x^T H x - c^T x  over C,   c = H x^t + g,
+// solved to optimality at every outer step (the experiments of Sec. 3 solve
+// each sketched subproblem exactly).
+//
+// Both start from the unconstrained minimiser x^t + H^{-1} g (the regular
+// Cholesky kernels) and return it when it already lies in the ball.
+//
+// l1 ball ||x||_1 <= tau (one 1024-thread workgroup per problem, d <= 1024):
+//   accelerated projected gradient (FISTA) with step 1/B, B the Gershgorin
+//   bound of lambda_max(H), momentum restart by the gradient-mapping test of
+//   O'Donoghue and Candes (2015), and the exact finite projection of
+//   Michelot (1986). Once the support and signs stop changing (and at the
+//   end), a KKT polish solves the face exactly,
+//       H_SS x_S + mu sigma = c_S,   sigma^T x_S = tau,
+//   and is accepted when it keeps the signs, has mu >= 0 and leaves every
+//   off-support |c_j - (H x)_j| <= mu (to 1e-9 max(1, |c|_inf)). An accepted
+//   KKT point is the minimiser, which ends the iteration.
+// l2 ball ||x||_2 <= r:
+//   Newton's method on phi(mu) = 1/||x(mu)|| - 1/r, x(mu) = (H + mu I)^{-1} c
+//   (More and Sorensen, 1983). 1/||x(mu)|| is concave and increasing, so from
+//   mu = 0 the iterates rise monotonically to the root when H is positive
+//   definite; phi'(mu) needs x^T (H + mu I)^{-1} x, one more solve with the
+//   same factor. The shifts live on the device and each Newton step
+//   re-factors H + mu I with per-problem shifts.
+#include <algorithm>
+
+#include "kernels.hpp"
+
+namespace ihs {
+
+constexpr int kQpThreads = 1024;
+constexpr int kQpWaves = kQpThreads / 64;
+constexpr int kPolishMax = 256;   // largest support the KKT polish takes on
+constexpr int kPolishEvery = 16;  // unchanged iterations before a polish attempt
+constexpr size_t kQpLdsBytes = 61440;
+
+constexpr int kRed = 8;  // values one fused block reduction carries
+
+struct BlockShared {
+  double red[kQpWaves];
+  double redv[kQpWaves][kRed];
+  int flag[4];
+  int wave_count[kQpWaves];
+};
+
+// Block-wide sum (resp. max) of one double per thread; every thread gets it.
+__device__ __forceinline__ double block_sum(double v, BlockShared& sh) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  v = wave_sum(v);
+  __syncthreads();
+  if (lane == 0) sh.red[wv] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int w = 0; w < kQpWaves; ++w) s += sh.red[w];
+  return s;
+}
+
+__device__ __forceinline__ double block_max(double v, BlockShared& sh) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  __syncthreads();
+  if (lane == 0) sh.red[wv] = v;
+  __syncthreads();
+  double s = sh.red[0];
+#pragma unroll
+  for (int w = 1; w < kQpWaves; ++w) s = fmax(s, sh.red[w]);
+  return s;
+}
+
+// Fused block reduction: the first NS entries of v are summed, the next NM
+// maximised; one barrier pair for all of them. Results replace v.
+template <int NS, int NM>
+__device__ __forceinline__ void block_reduce(double (&v)[NS + NM], BlockShared& sh) {
+  static_assert(NS + NM <= kRed, "too many values");
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < NS + NM; ++q)
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double o = __shfl_xor(v[q], off, 64);
+      v[q] = q < NS ? v[q] + o : fmax(v[q], o);
+    }
+  __syncthreads();
+  if (lane == 0)
+#pragma unroll
+    for (int q = 0; q < NS + NM; ++q) sh.redv[wv][q] = v[q];
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NS + NM; ++q) {
+    double s = sh.redv[0][q];
+    for (int w = 1; w < kQpWaves; ++w) s = q < NS ? s + sh.redv[w][q] : fmax(s, sh.redv[w][q]);
+    v[q] = s;
+  }
+}
+
+// out[i] = sum_k |H[i][k]| (ABS) or (H v)[i], one wavefront per row so each
+// row is read coalesced; v and out in LDS. Ends with a barrier.
+template <bool ABS>
+__device__ __forceinline__ void block_rows(const double* __restrict__ H, int64_t d,
+                                           const double* v, double* out) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int64_t i = wv; i < d; i += kQpWaves) {
+    const double* hr = H + i * d;
+    double s = 0.0;
+    for (int64_t k = lane; k < d; k += 64) {
+      if constexpr (ABS) s += fabs(hr[k]);
+      else s = fma(hr[k], v[k], s);
+    }
+    s = wave_sum(s);
+    if (lane == 0) out[i] = s;
+  }
+  __syncthreads();
+}
+
+// Euclidean projection onto {||x||_1 <= tau}, thread i < d holding v_i: when
+// ||v||_1 > tau, x_i = sign(v_i) max(|v_i| - theta, 0) with theta from
+// Michelot's finite iteration theta = (sum of |v_i| over the active set - tau)
+// / |active set|, the active set shrinking to {|v_i| > theta}; it only
+// shrinks, so an unchanged count means it is stable.
+__device__ double project_l1(double vi, int64_t d, double tau, BlockShared& sh) {
+  const int tid = threadIdx.x;
+  const double a = tid < d ? fabs(vi) : 0.0;
+  bool act = tid < d;
+  double r[2] = {act ? 1.0 : 0.0, a};
+  block_reduce<2, 0>(r, sh);
+  if (r[1] <= tau) return vi;
+  double theta = (r[1] - tau) / r[0];
+  for (int64_t it = 0; it <= d; ++it) {
+    const bool nact = act && a > theta;
+    double q[2] = {nact ? 1.0 : 0.0, nact ? a : 0.0};
+    block_reduce<2, 0>(q, sh);
+    act = nact;
+    if (q[0] == r[0]) break;
+    r[0] = q[0];
+    r[1] = q[1];
+    theta = (r[1] - tau) / r[0];
+  }
+  return (tid < d && a > theta) ? copysign(a - theta, vi) : 0.0;
+}
+
+// KKT polish on the support of x (thread i holds x_i in *xi). M: ns*ns
+// doubles (LDS or global), u, w: kPolishMax doubles, idx: kPolishMax ints,
+// cand, hc: d doubles of LDS. On success returns true with the polished x_i.
+__device__ __attribute__((noinline)) bool l1_polish(const double* __restrict__ H, int64_t d, double ci, double tau,
+                          double* xi, double* M, double* u, double* w, int* idx, double* cand,
+                          double* hc, double cscale, BlockShared& sh) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const bool on = tid < d && *xi != 0.0;
+  // ascending support indices by wave ballots
+  const uint64_t bal = __ballot(on);
+  if (lane == 0) sh.wave_count[wv] = __popcll(bal);
+  __syncthreads();
+  int base = 0, ns = 0;
+  for (int k = 0; k < kQpWaves; ++k) {
+    if (k < wv) base += sh.wave_count[k];
+    ns += sh.wave_count[k];
+  }
+  if (ns == 0 || ns > kPolishMax) return false;
+  const int slot = on ? base + __popcll(bal & lanemask_lt()) : -1;
+  if (on) idx[slot] = tid;
+  __syncthreads();
+  for (int e = tid; e < ns * ns; e += kQpThreads) {
+    const int a = e / ns, b = e - (e / ns) * ns;
+    M[e] = H[(int64_t)idx[a] * d + idx[b]];
+  }
+  if (tid == 0) sh.flag[2] = 1;
+  __syncthreads();
+  // Cholesky of H_SS (lower, in place, one column per round)
+  for (int j = 0; j < ns; ++j) {
+    const double piv = M[j * ns + j];
+    if (!(piv > 0.0) || !isfinite(piv)) {  // the same value in every thread
+      if (tid == 0) sh.flag[2] = 0;
+      break;
+    }
+    const double ljj = sqrt(piv);
+    for (int i = j + 1 + tid; i < ns; i += kQpThreads) M[i * ns + j] /= ljj;
+    __syncthreads();
+    if (tid == 0) M[j * ns + j] = ljj;
+    const int rem = ns - j - 1;
+    for (int e = tid; e < rem * rem; e += kQpThreads) {
+      const int i = j + 1 + e / rem, k = j + 1 + (e - (e / rem) * rem);
+      if (k <= i) M[i * ns + k] = fma(-M[i * ns + j], M[k * ns + j], M[i * ns + k]);
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+  if (!sh.flag[2]) return false;
+  // u = H_SS^{-1} c_S and w = H_SS^{-1} sigma: forward then backward sweep
+  for (int a = tid; a < ns; a += kQpThreads) u[a] = w[a] = 0.0;
+  __syncthreads();
+  const double sg = on ? copysign(1.0, *xi) : 0.0;
+  if (on) {
+    u[slot] = ci;
+    w[slot] = sg;
+  }
+  __syncthreads();
+  for (int j = 0; j < ns; ++j) {
+    const double r = 1.0 / M[j * ns + j];
+    const double uj = u[j] * r, wj = w[j] * r;
+    for (int i = j + 1 + tid; i < ns; i += kQpThreads) {
+      const double lij = M[i * ns + j];
+      u[i] = fma(-lij, uj, u[i]);
+      w[i] = fma(-lij, wj, w[i]);
+    }
+    __syncthreads();
+    if (tid == 0) {
+      u[j] = uj;
+      w[j] = wj;
+    }
+  }
+  __syncthreads();
+  for (int j = ns - 1; j >= 0; --j) {
+    const double r = 1.0 / M[j * ns + j];
+    const double uj = u[j] * r, wj = w[j] * r;
+    for (int i = tid; i < j; i += kQpThreads) {
+      const double lji = M[j * ns + i];
+      u[i] = fma(-lji, uj, u[i]);
+      w[i] = fma(-lji, wj, w[i]);
+    }
+    __syncthreads();
+    if (tid == 0) {
+      u[j] = uj;
+      w[j] = wj;
+    }
+  }
+  __syncthreads();
+  const double SU = block_sum(on ? sg * u[slot] : 0.0, sh);
+  const double SW = block_sum(on ? sg * w[slot] : 0.0, sh);
+  const double mu = (SU - tau) / SW;
+  double xs = 0.0;
+  bool bad = false;
+  if (on) {
+    xs = u[slot] - mu * w[slot];
+    bad = !(copysign(1.0, xs) == sg) || xs == 0.0;
+  }
+  const double anybad = block_max(bad ? 1.0 : 0.0, sh);
+  if (anybad != 0.0 || !(mu >= 0.0) || !isfinite(mu)) return false;
+  if (tid < d) cand[tid] = xs;
+  __syncthreads();
+  block_rows<false>(H, d, cand, hc);
+  const double viol = (tid < d && !on) ? fabs(ci - hc[tid]) - mu : -1.0;
+  if (block_max(viol, sh) > 1e-9 * cscale) return false;
+  *xi = xs;
+  return true;
+}
+
+// One workgroup per problem. xunc: the unconstrained minimiser; Lscratch:
+// d*d doubles per problem for a polish matrix too large for LDS.
+//
+// The Lipschitz constant L of the gradient starts at 1.05 x the Rayleigh
+// quotient of 24 power steps and is raised by backtracking (Beck and
+// Teboulle, 2009): for this quadratic the sufficient-decrease test reads
+// (x+ - y)^T H (x+ - y) <= L ||x+ - y||^2. The kernel forms H x+ once per
+// iteration and gets H y by linearity, y = x+ + beta (x+ - x).
+__global__ __launch_bounds__(kQpThreads) void k_qp_l1(
+    const double* __restrict__ Hall, const double* __restrict__ call,
+    const double* __restrict__ xunc_all, const double* x0_all, double* xout_all,
+    double* Lscratch, int64_t d, double tau, int32_t max_iter, double tol, int32_t lds_mcap,
+    DeviceStatus* st, int32_t iter) {
+  extern __shared__ double lds[];
+  double* vec = lds;            // d: the vector being multiplied
+  double* cand = vec + d;       // d: polish candidate
+  double* hv = cand + d;        // d: products
+  double* u = hv + d;           // kPolishMax
+  double* w = u + kPolishMax;   // kPolishMax
+  double* Mlds = w + kPolishMax;
+  __shared__ int idx[kPolishMax];
+  __shared__ BlockShared sh;
+  const int p = blockIdx.x;
+  const int tid = threadIdx.x;
+  if (tid == 0) sh.flag[0] = st->code;
+  __syncthreads();
+  const double* H = Hall + (int64_t)p * d * d;
+  double* xout = xout_all + (int64_t)p * d;
+  const double x0 = tid < d ? x0_all[(int64_t)p * d + tid] : 0.0;
+  if (sh.flag[0] != 0) {  // an earlier failure: keep x^t
+    if (tid < d) xout[tid] = x0;
+    return;
+  }
+  const double ci = tid < d ? call[(int64_t)p * d + tid] : 0.0;
+  const double xu = tid < d ? xunc_all[(int64_t)p * d + tid] : 0.0;
+  double r0[2] = {fabs(xu), 0.0};
+  r0[1] = fabs(ci);
+  block_reduce<1, 1>(r0, sh);
+  if (r0[0] <= tau) {  // the ball is inactive
+    if (tid < d) xout[tid] = xu;
+    return;
+  }
+  const double cscale = fmax(1.0, r0[1]);
+  // power steps for the initial Lipschitz estimate
+  double pv = tid < d ? 1.0 + 0.25 * (double)((tid * 7) % 5) : 0.0;
+  double rq = 0.0;
+  for (int k = 0; k < 24; ++k) {
+    if (tid < d) vec[tid] = pv;
+    __syncthreads();
+    block_rows<false>(H, d, vec, hv);
+    const double hp = tid < d ? hv[tid] : 0.0;
+    double q[3] = {pv * hp, hp * hp, pv * pv};
+    block_reduce<3, 0>(q, sh);
+    rq = q[0] / q[2];
+    pv = hp / sqrt(fmax(q[1], 1e-300));
+  }
+  double Lip = 1.05 * rq;
+  // FISTA from the projection of x^t; thread i keeps x_i, (Hx)_i, y_i, (Hy)_i
+  double xi = project_l1(x0, d, tau, sh);
+  if (tid < d) vec[tid] = xi;
+  __syncthreads();
+  block_rows<false>(H, d, vec, hv);
+  double hxi = tid < d ? hv[tid] : 0.0;
+  double yi = xi, hyi = hxi;
+  double tk = 1.0;
+  double sig_prev = -1.0;
+  int stable = 0;
+  bool done = false;
+  for (int it = 0; it < max_iter && !done; ++it) {
+    const double vi = tid < d ? yi - (hyi - ci) / Lip : 0.0;
+    const double xn = project_l1(vi, d, tau, sh);
+    if (tid < d) vec[tid] = xn;
+    __syncthreads();
+    block_rows<false>(H, d, vec, hv);
+    const double hxn = tid < d ? hv[tid] : 0.0;
+    const double e = xn - yi;
+    // sums: curvature, |e|^2, restart test, support signature, support size;
+    // maxima: step, |x|
+    double red[7] = {e * (hxn - hyi), e * e, (yi - xn) * (xn - xi),
+                     xn != 0.0 ? (xn > 0.0 ? 1.0 : -1.0) * (double)(tid + 1) : 0.0,
+                     xn != 0.0 ? 1.0 : 0.0, fabs(xn - xi), fabs(xn)};
+    block_reduce<5, 2>(red, sh);
+    if (red[0] > Lip * red[1] * (1.0 + 1e-12)) {  // L too small: back off
+      Lip = 1.25 * fmax(Lip, red[0] / red[1]);
+      continue;
+    }
+    double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * tk * tk));
+    double beta = (tk - 1.0) / tn;
+    if (red[2] > 0.0) {  // the momentum points uphill: restart it
+      tn = 1.0;
+      beta = 0.0;
+    }
+    yi = xn + beta * (xn - xi);
+    hyi = hxn + beta * (hxn - hxi);
+    xi = xn;
+    hxi = hxn;
+    tk = tn;
+    const bool conv = red[5] <= tol * fmax(1.0, red[6]);
+    const double sig = red[3] + 4096.0 * red[4];
+    stable = (sig == sig_prev) ? stable + 1 : 0;
+    sig_prev = sig;
+    if (conv || stable == kPolishEvery) {
+      stable = 0;
+      const int64_t nsz = (int64_t)red[4];
+      double* M = (nsz * nsz <= lds_mcap) ? Mlds : Lscratch + (int64_t)p * d * d;
+      double xp = xi;
+      if (l1_polish(H, d, ci, tau, &xp, M, u, w, idx, cand, hv, cscale, sh)) {
+        xi = xp;
+        done = true;
+      } else if (conv) {
+        done = true;  // converged iterate; the polish did not apply
+      }
+    }
+  }
+  if (!done) {  // uniform: `done` follows block-wide values only
+    if (tid < d) xout[tid] = x0;  // keep x^t
+    if (tid == 0) status_fail(st, 6 /* IHS_ERR_NOT_CONVERGED */, iter, p);
+    return;
+  }
+  if (tid < d) xout[tid] = xi;
+}
+
+// c = H x + g per problem (one wavefront per row).
+__global__ __launch_bounds__(256) void k_form_c(const double* __restrict__ H, int64_t d,
+                                                const double* __restrict__ x,
+                                                const double* __restrict__ g, double* c) {
+  const int p = blockIdx.y;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * 4 + wv;
+  if (i >= d) return;
+  const double* hr = H + ((int64_t)p * d + i) * d;
+  const double* xp = x + (int64_t)p * d;
+  double s = 0.0;
+  for (int64_t k = lane; k < d; k += 64) s = fma(hr[k], xp[k], s);
+  s = wave_sum(s);
+  if (lane == 0) c[(int64_t)p * d + i] = s + g[(int64_t)p * d + i];
+}
+
+__global__ void k_fill_f64(double* v, int64_t n, double val) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) v[i] = val;
+}
+
+// ---------------------------------------------------------------------------
+// l2 ball. State per problem: trs[4p] = mu, trs[4p+1] = phase
+// (0 iterating, 1 one last Newton step, 2 done).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double block256_sum(double v, double* red) {
+  const int tid = threadIdx.x;
+  v = wave_sum(v);
+  __syncthreads();
+  if ((tid & 63) == 0) red[tid >> 6] = v;
+  __syncthreads();
+  return red[0] + red[1] + red[2] + red[3];
+}
+
+// Given x = x(mu) and z = (H + mu I)^{-1} x, applies the Newton step
+// mu += (||x||^2 / x^T z) (||x|| - r) / r. When | ||x|| - r | <= tol r the
+// problem takes that one more step (phase 1) and accepts the next x, which
+// the quadratic rate puts at rounding level. `first`: x is the unconstrained
+// minimiser (mu = 0), accepted when it lies in the ball.
+__global__ __launch_bounds__(256) void k_trs_update(const double* __restrict__ xk,
+                                                    const double* __restrict__ zk, int64_t d,
+                                                    double r, double tol, double* trs,
+                                                    double* xout, const DeviceStatus* st,
+                                                    int32_t first) {
+  __shared__ double red[4];
+  __shared__ int skip;
+  const int p = blockIdx.x, tid = threadIdx.x;
+  if (tid == 0) skip = (status_failed_by(st, -1) || trs[4 * p + 1] >= 2.0) ? 1 : 0;
+  __syncthreads();
+  if (skip) return;
+  const double* xp = xk + (int64_t)p * d;
+  const double* zp = zk + (int64_t)p * d;
+  double sx = 0.0, sq = 0.0;
+  for (int64_t i = tid; i < d; i += 256) {
+    sx = fma(xp[i], xp[i], sx);
+    sq = fma(xp[i], zp[i], sq);
+  }
+  const double nx2 = block256_sum(sx, red);
+  const double q = block256_sum(sq, red);
+  const double nx = sqrt(nx2);
+  const double phase = trs[4 * p + 1];
+  if ((first && nx <= r) || (!first && phase == 1.0)) {
+    for (int64_t i = tid; i < d; i += 256) xout[(int64_t)p * d + i] = xp[i];
+    if (tid == 0) trs[4 * p + 1] = 2.0;
+    return;
+  }
+  if (tid == 0) {
+    const double mu = trs[4 * p];
+    trs[4 * p] = fmax(mu + (nx2 / q) * ((nx - r) / r), mu);
+    if (fabs(nx - r) <= tol * r) trs[4 * p + 1] = 1.0;
+  }
+}
+
+// Problems still iterating after the last Newton step keep x^t and report.
+__global__ void k_trs_finish(const double* trs, int64_t d, const double* x, double* xout,
+                             DeviceStatus* st, int32_t iter) {
+  const int p = blockIdx.x;
+  if (status_failed_by(st, -1) || trs[4 * p + 1] >= 2.0) return;
+  for (int64_t i = threadIdx.x; i < d; i += 256) xout[(int64_t)p * d + i] = x[(int64_t)p * d + i];
+  if (threadIdx.x == 0) status_fail(st, 6 /* IHS_ERR_NOT_CONVERGED */, iter, p);
+}
+
+hipError_t launch_qp_constrained(const QpArgs& a, hipStream_t st) {
+  const int64_t d = a.d;
+  const int32_t B = a.batch;
+  if (d > kQpThreads) return hipErrorNotSupported;
+  double* scratch = a.work;
+  double* rdiag = chol_rdiag(scratch, B);
+  // past the unconstrained step's scratch: c, x_unc, x(mu), z, zeros, state
+  double* cbuf = a.work + (int64_t)B * (64 * 64 + 9 * d + 64);
+  double* xunc = cbuf + (int64_t)B * d;
+  double* xk = xunc + (int64_t)B * d;
+  double* zk = xk + (int64_t)B * d;
+  double* zero = zk + (int64_t)B * d;
+  double* trs = zero + (int64_t)B * d;
+  hipLaunchKernelGGL(k_form_c, dim3((unsigned)((d + 3) / 4), B), dim3(256), 0, st, a.H, d, a.x,
+                     a.g, cbuf);
+  hipError_t e = launch_cholesky(a.H, a.L, d, B, a.status, a.iter, 0.0, scratch, st);
+  if (e != hipSuccess) return e;
+  e = launch_chol_solve_update(a.L, rdiag, d, B, a.g, a.x, xunc, a.status, st);
+  if (e != hipSuccess) return e;
+  if (a.constraint == 1) {
+    const int32_t max_iter = a.max_inner > 0 ? a.max_inner : 5000;
+    const double tol = a.tol > 0 ? a.tol : 1e-15;
+    const size_t fixed = (size_t)(3 * d + 2 * kPolishMax) * sizeof(double);
+    const int32_t lds_mcap = (int32_t)((kQpLdsBytes - fixed) / sizeof(double));
+    hipLaunchKernelGGL(k_qp_l1, dim3(B), dim3(kQpThreads), kQpLdsBytes, st, a.H, cbuf, xunc,
+                       a.x, a.x_out, a.L, d, a.radius, max_iter, tol, lds_mcap, a.status,
+                       a.iter);
+    return hipGetLastError();
+  }
+  const int32_t newton = a.max_inner > 0 ? a.max_inner : 20;
+  const double tol = a.tol > 0 ? a.tol : 1e-10;
+  const int64_t bd = (int64_t)B * d;
+  hipLaunchKernelGGL(k_fill_f64, dim3((unsigned)((bd + 255) / 256)), dim3(256), 0, st, zero, bd,
+                     0.0);
+  hipLaunchKernelGGL(k_fill_f64, dim3((unsigned)((4 * B + 255) / 256)), dim3(256), 0, st, trs,
+                     (int64_t)4 * B, 0.0);
+  // mu = 0: x(0) is the unconstrained minimiser and a.L already its factor
+  e = launch_chol_solve_update(a.L, rdiag, d, B, xunc, zero, zk, a.status, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_trs_update, dim3(B), dim3(256), 0, st, xunc, zk, d, a.radius, tol, trs,
+                     a.x_out, a.status, 1);
+  for (int32_t k = 0; k < newton; ++k) {
+    e = launch_cholesky(a.H, a.L, d, B, a.status, a.iter, 0.0, scratch, st, trs);
+    if (e != hipSuccess) return e;
+    e = launch_chol_solve_update(a.L, rdiag, d, B, cbuf, zero, xk, a.status, st);
+    if (e != hipSuccess) return e;
+    e = launch_chol_solve_update(a.L, rdiag, d, B, xk, zero, zk, a.status, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_trs_update, dim3(B), dim3(256), 0, st, xk, zk, d, a.radius, tol, trs,
+                       a.x_out, a.status, 0);
+  }
+  hipLaunchKernelGGL(k_trs_finish, dim3(B), dim3(256), 0, st, trs, d, a.x, a.x_out, a.status,
+                     a.iter);
+  return hipGetLastError();
+}
+
+}  // namespace ihs

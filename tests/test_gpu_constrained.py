@@ -1,0 +1,213 @@
+"""GPU parity of the constrained steps of Eq.(2) (l1 and l2 balls of Eq.(1))
+and of IHS on the constrained problems, against the oracle.
+
+The QP solution is unique for a positive definite H, so the GPU's inner
+iterates (a different step size, restart rule and projection order than the
+oracle's) are not compared; only the solution is. Tolerance: both sides end
+on the exact KKT solution of the identified face (l1) or the root of the
+secular equation (l2), so they agree to a small multiple of cond(H) u."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import ihs as O
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def host(t):
+    return t.double().cpu().numpy()
+
+
+def spd(d, g, cond):
+    Q, _ = np.linalg.qr(g.standard_normal((d, d)))
+    return Q @ np.diag(np.geomspace(1.0, cond, d)) @ Q.T
+
+
+def unconstrained_min(H, g, x):
+    return x + np.linalg.solve(H, g)
+
+
+def kkt_l1_residual(H, c, x, tau):
+    """Max violation of the l1-ball KKT conditions at x (scaled)."""
+    grad = c - H @ x
+    S = x != 0
+    if not S.any():
+        return np.inf
+    mu = float(np.mean(grad[S] * np.sign(x[S])))
+    scale = max(1.0, np.abs(c).max())
+    on = np.abs(grad[S] - mu * np.sign(x[S])).max() / scale
+    off = max(0.0, (np.abs(grad[~S]).max() - mu) / scale) if (~S).any() else 0.0
+    feas = max(0.0, np.abs(x).sum() - tau) / tau
+    return max(on, off, feas, max(0.0, -mu / scale))
+
+
+# ------------------------------------------------------------ l1 ball ----
+@pytest.mark.parametrize("d,batch,frac,cond", [
+    (8, 1, 0.5, 10.0), (50, 2, 0.3, 1e2), (64, 3, 0.6, 1e2), (130, 1, 0.5, 1e2),
+    (256, 1, 0.5, 1e2), (256, 1, 0.97, 10.0), (1000, 1, 0.5, 10.0), (1, 1, 0.5, 1.0),
+    (97, 2, 0.05, 1e3)])
+def test_qp_l1_matches_oracle(gpu_lib, d, batch, frac, cond):
+    P = gpu_lib
+    g = np.random.default_rng(1000 + d)
+    Hs = np.stack([spd(d, g, cond) for _ in range(batch)])
+    gs = g.standard_normal((batch, d))
+    xs = 0.1 * g.standard_normal((batch, d))
+    # one radius for the batch, active for every problem
+    tau = frac * min(np.abs(unconstrained_min(Hs[p], gs[p], xs[p])).sum() for p in range(batch))
+    out = host(P.qp_step(dev(Hs), dev(gs), dev(xs), constraint="l1", radius=tau))
+    for p in range(batch):
+        ref = O.qp_step(Hs[p], gs[p], xs[p], "l1", tau)
+        assert np.abs(out[p]).sum() <= tau * (1 + 1e-12)
+        assert np.linalg.norm(out[p] - ref) <= 1e-9 * cond * np.linalg.norm(ref), p
+        c = Hs[p] @ xs[p] + gs[p]
+        assert kkt_l1_residual(Hs[p], c, out[p], tau) < 1e-8 * cond
+
+
+def test_qp_l1_inactive_ball_is_the_unconstrained_step(gpu_lib):
+    P = gpu_lib
+    g = np.random.default_rng(7)
+    d = 77
+    H, gv, x = spd(d, g, 1e2)[None], g.standard_normal((1, d)), g.standard_normal((1, d))
+    free = host(P.qp_step(dev(H), dev(gv), dev(x)))
+    tau = 10 * np.abs(free).sum()
+    for cons in ("l1", "l2"):
+        out = host(P.qp_step(dev(H), dev(gv), dev(x), constraint=cons, radius=tau))
+        assert np.array_equal(out, free), cons
+
+
+def test_qp_l1_not_converged_keeps_iterate(gpu_lib):
+    P = gpu_lib
+    g = np.random.default_rng(8)
+    d = 300
+    H, gv = spd(d, g, 1e3)[None], g.standard_normal((1, d))
+    x = 0.01 * g.standard_normal((1, d))
+    tau = 0.5 * np.abs(unconstrained_min(H[0], gv[0], x[0])).sum()
+    with pytest.raises(P.IHSError) as e:
+        P.qp_step(dev(H), dev(gv), dev(x), constraint="l1", radius=tau, qp_max_inner=2)
+    assert e.value.code == P.ERR_NOT_CONVERGED
+
+
+def test_qp_l1_projection_special_case(gpu_lib):
+    """H = I: the minimiser of 1/2||x||^2 - c^T x over the ball is the
+    Euclidean projection of c, fixed here by a hand-checkable case."""
+    P = gpu_lib
+    H = np.eye(4)[None]
+    c = np.array([[3.0, -1.0, 0.5, 0.0]])
+    out = host(P.qp_step(dev(H), dev(c), dev(np.zeros((1, 4))), constraint="l1", radius=2.0))
+    # threshold theta = 1: the largest magnitude alone exceeds it, 3 - 1 = 2
+    np.testing.assert_allclose(out[0], [2.0, 0.0, 0.0, 0.0], atol=1e-14)
+
+
+# ------------------------------------------------------------ l2 ball ----
+@pytest.mark.parametrize("d,batch,frac,cond", [
+    (8, 1, 0.5, 10.0), (50, 3, 0.3, 1e2), (100, 1, 0.9, 1e3), (513, 1, 0.5, 1e2),
+    (1024, 1, 0.2, 1e2), (1, 1, 0.5, 1.0), (200, 2, 0.999, 1e2)])
+def test_qp_l2_matches_oracle(gpu_lib, d, batch, frac, cond):
+    P = gpu_lib
+    g = np.random.default_rng(2000 + d)
+    Hs = np.stack([spd(d, g, cond) for _ in range(batch)])
+    gs = g.standard_normal((batch, d))
+    xs = 0.1 * g.standard_normal((batch, d))
+    r = frac * min(np.linalg.norm(unconstrained_min(Hs[p], gs[p], xs[p])) for p in range(batch))
+    out = host(P.qp_step(dev(Hs), dev(gs), dev(xs), constraint="l2", radius=r))
+    for p in range(batch):
+        ref = O.qp_step(Hs[p], gs[p], xs[p], "l2", r)
+        assert np.linalg.norm(out[p]) <= r * (1 + 1e-9)
+        assert np.linalg.norm(out[p] - ref) <= 1e-9 * cond * np.linalg.norm(ref), p
+
+
+def test_qp_l2_mixed_batch_and_identity(gpu_lib):
+    """H = I gives x = c min(1, r/||c||) (closed form); a batch where one
+    problem's ball is inactive and the other's active."""
+    P = gpu_lib
+    d = 40
+    g = np.random.default_rng(11)
+    c = np.stack([0.1 * g.standard_normal(d), 10.0 * g.standard_normal(d)])
+    H = np.stack([np.eye(d), np.eye(d)])
+    out = host(P.qp_step(dev(H), dev(c), dev(np.zeros((2, d))), constraint="l2", radius=1.0))
+    for p in range(2):
+        want = c[p] * min(1.0, 1.0 / np.linalg.norm(c[p]))
+        np.testing.assert_allclose(out[p], want, rtol=1e-12, atol=1e-15)
+
+
+# --------------------------------------------------- constrained IHS ----
+@pytest.mark.parametrize("kind,s", [("countsketch", 1), ("sjlt", 4)])
+def test_ihs_l1_lasso_iterates_match_oracle(gpu_lib, kind, s):
+    P = gpu_lib
+    wl = W.lasso_dense(rows=40000, d=64, m=1024, sketch=kind, iters=6)
+    opts = P.options(wl.m, s=s, kind=kind, seed=wl.sketch_seed, max_iter=wl.iters,
+                     constraint="l1", radius=wl.radius)
+    res = P.solve(P.Matrix(dense=dev(wl.A)), dev(wl.b), opts, history=True)
+    assert res.report.status == 0
+    xs = O.ihs(wl.A, wl.b, wl.m, s=s, seed=wl.sketch_seed, iters=wl.iters,
+               constraint="l1", radius=wl.radius)
+    hist = host(res.history)[:, 0, :]
+    for t in range(wl.iters):
+        assert np.abs(hist[t]).sum() <= wl.radius * (1 + 1e-12)
+        assert np.linalg.norm(hist[t] - xs[t + 1]) <= 1e-8 * np.linalg.norm(xs[t + 1]), t
+    xo = O.x_opt(wl.A, wl.b, "l1", wl.radius)
+    assert O.error_A(wl.A, hist[-1], xo) < 0.05 * O.error_A(wl.A, hist[0], xo)
+
+
+def test_ihs_l1_lasso_full_width(gpu_lib):
+    """The lasso shape at d = 256, m = 4096 on a row-scaled sample: the
+    iterates match the oracle and the error in the prediction norm falls."""
+    P = gpu_lib
+    wl = W.lasso_dense(rows=1 << 16, d=256, m=4096, iters=4)
+    opts = P.options(wl.m, seed=wl.sketch_seed, max_iter=wl.iters, constraint="l1",
+                     radius=wl.radius)
+    res = P.solve(P.Matrix(dense=dev(wl.A)), dev(wl.b), opts, history=True)
+    assert res.report.status == 0
+    xs = O.ihs(wl.A, wl.b, wl.m, seed=wl.sketch_seed, iters=wl.iters, constraint="l1",
+               radius=wl.radius)
+    hist = host(res.history)[:, 0, :]
+    for t in range(wl.iters):
+        assert np.linalg.norm(hist[t] - xs[t + 1]) <= 1e-8 * np.linalg.norm(xs[t + 1]), t
+
+
+def test_ihs_l2_csr_iterates_match_oracle(gpu_lib):
+    P = gpu_lib
+    wl = W.ridge_csr(rows=1 << 15, d=128, density=8e-3, m=1024, iters=6, radius_factor=0.5)
+    A = P.Matrix(row_ptr=dev(wl.indptr), col_idx=dev(wl.indices), values=dev(wl.data),
+                 n=wl.n, d=wl.d)
+    opts = P.options(wl.m, seed=wl.sketch_seed, max_iter=wl.iters, constraint="l2",
+                     radius=wl.radius)
+    res = P.solve(A, dev(wl.b), opts, history=True)
+    assert res.report.status == 0
+    csr = (wl.indptr, wl.indices, wl.data, wl.n, wl.d)
+    xs = O.ihs(None, wl.b, wl.m, seed=wl.sketch_seed, iters=wl.iters, constraint="l2",
+               radius=wl.radius, csr=csr)
+    hist = host(res.history)[:, 0, :]
+    for t in range(wl.iters):
+        assert np.linalg.norm(hist[t]) <= wl.radius * (1 + 1e-9)
+        assert np.linalg.norm(hist[t] - xs[t + 1]) <= 1e-8 * np.linalg.norm(xs[t + 1]), t
+    Asp = O.csr_matrix(*csr)
+    xo = O.x_opt(Asp, wl.b, "l2", wl.radius)
+    assert O.error_A(Asp, hist[-1], xo) < 0.1 * O.error_A(Asp, hist[0], xo)
+
+
+def test_ihs_l2_csr_bf16_gram_converges(gpu_lib):
+    """CSR with the BF16 Gram (FP32 accumulation): the outer loop still
+    drives the error down on a well-conditioned Zipf problem."""
+    P = gpu_lib
+    wl = W.ridge_csr(rows=1 << 15, d=128, density=8e-3, m=1024, iters=10, radius_factor=0.5)
+    A = P.Matrix(row_ptr=dev(wl.indptr), col_idx=dev(wl.indices), values=dev(wl.data),
+                 n=wl.n, d=wl.d)
+    csr = (wl.indptr, wl.indices, wl.data, wl.n, wl.d)
+    Asp = O.csr_matrix(*csr)
+    xo = O.x_opt(Asp, wl.b, "l2", wl.radius)
+    errs = {}
+    for gin, gacc in (("float64", "float64"), ("bfloat16", "float32")):
+        opts = P.options(wl.m, seed=wl.sketch_seed, max_iter=wl.iters, constraint="l2",
+                         radius=wl.radius, gram_in=gin, gram_acc=gacc)
+        res = P.solve(A, dev(wl.b), opts)
+        assert res.report.status == 0
+        errs[gin] = O.error_A(Asp, host(res.x)[0], xo)
+    assert errs["float64"] < 1e-2
+    assert errs["bfloat16"] < 3 * errs["float64"] + 1e-6
