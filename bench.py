@@ -90,6 +90,34 @@ def reference_solution(wl):
     return x
 
 
+def kernel_source_hash():
+    """sha256 over the gather kernel's sources (sketch.hip, common.hpp,
+    kernels.hpp, in that order): the key of the recorded counter summary."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("sketch.hip", "common.hpp", "kernels.hpp"):
+        with open(os.path.join(ROOT, "paper_1910_14166_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(bytes_per_launch):
+    """HBM bytes per launch of the gather kernel from the committed
+    FETCH_SIZE/WRITE_SIZE summary (profiles/gather_traffic.json, calibrated
+    against a plain copy), or None when the kernel source or the workload has
+    changed since the counters were taken."""
+    try:
+        with open(os.path.join(ROOT, "profiles", "gather_traffic.json")) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    if int(rec.get("algorithmic_bytes", -1)) != int(bytes_per_launch):
+        return None
+    return float(rec["traffic_bytes"])
+
+
 def rel_err_A(A, x, xo, Axo_norm):
     return float(chunked_matvec(A, x - xo).norm() / Axo_norm)
 
@@ -154,6 +182,7 @@ def main():
     fused_bytes = n * d * 8 + n * 8 + m * d * 8
     gather_avg_ms = gather_ms / max(launches, 1)
     achieved = fused_bytes / (gather_avg_ms * 1e-3) / 1e9
+    traffic = recorded_traffic(fused_bytes)
 
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "GB/s", "n_gpus": 1,
@@ -164,7 +193,12 @@ def main():
                    "s": 1, "step": "hash+sort, fused sketch+gradient pass, Gram, QP"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None, "kernel": "k_gather (fused sketch + gradient)",
+                     "traffic": round(traffic) if traffic else None,
+                     "traffic_unit": "HBM bytes per launch (FETCH_SIZE x 2 + WRITE_SIZE, "
+                                     "calibrated on a plain copy)",
+                     "traffic_vs_algorithmic": round(traffic / fused_bytes, 4)
+                     if traffic else None,
+                     "kernel": "k_gather (fused sketch + gradient)",
                      "bytes_per_launch": fused_bytes, "avg_ms": round(gather_avg_ms, 4),
                      "launches": launches},
     }

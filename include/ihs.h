@@ -101,11 +101,19 @@ typedef struct {
   ihs_sketch sketch;
   int32_t gram_in;             /* dtype SA is stored in for the Gram          */
   int32_t gram_acc;            /* dtype the Gram accumulates in (F64 or F32)  */
-  int32_t qp_max_inner;        /* cap on inner QP iterations (l1, l2); 0 = default */
+  int32_t qp_max_inner;        /* cap on inner QP iterations; 0 = default:
+                                  l1 ball: accelerated projected-gradient
+                                  iterations (5000); l2 ball: Newton steps on
+                                  the shift (20)                               */
   int32_t keep_factors;        /* store each step's Cholesky factor           */
-  double qp_tol;               /* relative inner stopping tolerance; 0 = default */
-  double tol;                  /* stop early once sqrt(dx^T H dx) <= tol * sqrt(x^T H x);
-                                  0 = run all max_iter steps                   */
+  double qp_tol;               /* inner stopping tolerance; 0 = default:
+                                  l1 ball: max |x_{k+1} - x_k| <= qp_tol
+                                  max(1, |x|_inf) (1e-15; a KKT-certified
+                                  polish usually ends the iteration first);
+                                  l2 ball: | ||x|| - r | <= qp_tol r, then one
+                                  more Newton step (1e-10)                     */
+  double tol;                  /* reserved, must be 0: a solve always runs
+                                  max_iter steps (stopping rules read x_hist) */
   int32_t schedule;            /* 0: overlap the next step's sort, Gram and
                                   factorisation with the current pass over A
                                   on a second stream (unconstrained problems;
@@ -195,9 +203,12 @@ size_t ihs_qp_workspace_size(int64_t d, int32_t batch, const ihs_options* opt);
 /* One QP of Eq.(2) per problem: given H (device, batch x d x d symmetric
  * positive definite, float64), g (device, batch x d) and x^t (device,
  * batch x d), writes x^{t+1} (device, batch x d) = argmin over C of
- * 1/2 (x - x^t)^T H (x - x^t) - g^T (x - x^t). Only opt->constraint, radius,
- * qp_max_inner and qp_tol are read. Synchronises; returns IHS_ERR_NOT_PD when
- * a factorisation meets a non-positive pivot (x_out then holds x^t). */
+ * 1/2 (x - x^t)^T H (x - x^t) - g^T (x - x^t), with C from Eq.(1): R^d, the
+ * l1 ball or the l2 ball of radius opt->radius centred at 0 (d <= 1024 for
+ * the balls). Only opt->constraint, radius, qp_max_inner and qp_tol are read.
+ * x_out may alias x. Synchronises; returns IHS_ERR_NOT_PD when a
+ * factorisation meets a non-positive pivot and IHS_ERR_NOT_CONVERGED when a
+ * ball QP ends its iteration budget unsolved (x_out then holds x^t). */
 ihs_status ihs_qp_step(int64_t d, int32_t batch, const double* H,
                        const double* g, const double* x, double* x_out,
                        const ihs_options* opt, void* ws, size_t ws_bytes,
@@ -230,8 +241,9 @@ ihs_status ihs_adjoint_solve(const ihs_matrix* A, const double* xbar,
 
 /* Gradients of a loss L(x) through x = x_OPT(A, b), given lambda from
  * ihs_adjoint_solve: dL/db = A lambda (device, n) and
- * dL/dA = r lambda^T - (A lambda) x^T with r = b - A x (device, n x d,
- * leading dimension ld_da; dense F64 A only). Either output may be NULL.
+ * dL/dA = r lambda^T - (A lambda) x^T with r = b - A x (device, float64,
+ * n x d, leading dimension ld_da; dense A, F64 or F32). Either output may be
+ * NULL.
  * Asynchronous. */
 ihs_status ihs_solution_grads(const ihs_matrix* A, const double* b,
                               const double* x, const double* lambda,

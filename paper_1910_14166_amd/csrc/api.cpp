@@ -446,7 +446,7 @@ ihs_status check_options(const ihs_options* o, bool need_loop) {
   if (o->constraint != IHS_UNCONSTRAINED && !(o->radius > 0.0)) return IHS_ERR_INVALID_ARG;
   if (need_loop && o->max_iter < 1) return IHS_ERR_INVALID_ARG;
   if (!valid_gram_types(o->gram_in, o->gram_acc)) return IHS_ERR_INVALID_ARG;
-  if (o->tol < 0.0 || o->qp_tol < 0.0 || o->qp_max_inner < 0) return IHS_ERR_INVALID_ARG;
+  if (o->tol != 0.0 || o->qp_tol < 0.0 || o->qp_max_inner < 0) return IHS_ERR_INVALID_ARG;
   if (o->schedule != 0 && o->schedule != 1) return IHS_ERR_INVALID_ARG;
   return IHS_OK;
 }
@@ -876,8 +876,10 @@ ihs_status ihs_solution_grads(const ihs_matrix* A, const double* b, const double
                               int64_t ld_da, hipStream_t stream) {
   ihs_status s = check_matrix(A);
   if (s != IHS_OK) return s;
-  if (A->format != IHS_DENSE || A->dtype != IHS_F64) return IHS_ERR_UNSUPPORTED;
+  if (A->format != IHS_DENSE) return IHS_ERR_UNSUPPORTED;
   if (!b || !x || !lambda) return IHS_ERR_INVALID_ARG;
+  const bool f32 = A->dtype == IHS_F32;
+  const size_t esz = f32 ? sizeof(float) : sizeof(double);
   if (dl_da && ld_da < A->d) return IHS_ERR_INVALID_ARG;
   const Layout L = make_layout(A, 1);
   // per-row problem index comes from the row offsets; pass them as a small
@@ -886,7 +888,8 @@ ihs_status ihs_solution_grads(const ihs_matrix* A, const double* b, const double
     const ProbInfo& q = L.probs[p];
     if (q.rows == 0) continue;
     if (launch_solution_grads(nullptr, 1, q.rows, A->d,
-                              static_cast<const double*>(A->values) + q.row0 * A->ld, A->ld,
+                              static_cast<const char*>(A->values) + q.row0 * A->ld * esz, f32,
+                              A->ld,
                               b + q.row0, x + (int64_t)p * A->d, lambda + (int64_t)p * A->d,
                               dl_db ? dl_db + q.row0 : nullptr,
                               dl_da ? dl_da + q.row0 * ld_da : nullptr, ld_da,

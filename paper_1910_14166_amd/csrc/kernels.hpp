@@ -186,7 +186,7 @@ hipError_t launch_sketch_adjoint(const SketchPlan& p, const double* G, int64_t l
                                  int64_t d, double* out, int64_t ld_out, int64_t nrows,
                                  int32_t problem, hipStream_t st);
 hipError_t launch_solution_grads(const ProbInfo* probs, int32_t batch, int64_t n,
-                                 int64_t d, const double* A, int64_t ld,
+                                 int64_t d, const void* A, bool a_f32, int64_t ld,
                                  const double* b, const double* x,
                                  const double* lambda, double* dl_db, double* dl_da,
                                  int64_t ld_da, hipStream_t st);

@@ -888,8 +888,9 @@ hipError_t launch_sketch_adjoint(const SketchPlan& P, const double* G, int64_t l
 // dL/db = A lambda and dL/dA = r lambda^T - (A lambda) x^T, r = b - A x,
 // for the rows of one problem. One wavefront per row.
 // ---------------------------------------------------------------------------
+template <typename TA>
 __global__ __launch_bounds__(256) void k_solution_grads(int64_t nrows, int64_t d,
-                                                        const double* __restrict__ A, int64_t ld,
+                                                        const TA* __restrict__ A, int64_t ld,
                                                         const double* __restrict__ b,
                                                         const double* __restrict__ x,
                                                         const double* __restrict__ lam,
@@ -898,10 +899,10 @@ __global__ __launch_bounds__(256) void k_solution_grads(int64_t nrows, int64_t d
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t waves = (int64_t)gridDim.x * 4;
   for (int64_t row = (int64_t)blockIdx.x * 4 + wv; row < nrows; row += waves) {
-    const double* ar = A + row * ld;
+    const TA* ar = A + row * ld;
     double sl = 0.0, sx = 0.0;
     for (int64_t c = lane; c < d; c += 64) {
-      const double a = ar[c];
+      const double a = (double)ar[c];
       sl = fma(a, lam[c], sl);
       sx = fma(a, x[c], sx);
     }
@@ -914,14 +915,18 @@ __global__ __launch_bounds__(256) void k_solution_grads(int64_t nrows, int64_t d
   }
 }
 
-hipError_t launch_solution_grads(const ProbInfo*, int32_t, int64_t n, int64_t d, const double* A,
-                                 int64_t ld, const double* b, const double* x,
+hipError_t launch_solution_grads(const ProbInfo*, int32_t, int64_t n, int64_t d, const void* A,
+                                 bool a_f32, int64_t ld, const double* b, const double* x,
                                  const double* lambda, double* dl_db, double* dl_da,
                                  int64_t ld_da, hipStream_t st) {
   if (n == 0) return hipSuccess;
   const unsigned blocks = (unsigned)std::min<int64_t>((n + 3) / 4, 65536);
-  hipLaunchKernelGGL(k_solution_grads, dim3(blocks), dim3(256), 0, st, n, d, A, ld, b, x, lambda,
-                     dl_db, dl_da, ld_da);
+  if (a_f32)
+    hipLaunchKernelGGL(k_solution_grads<float>, dim3(blocks), dim3(256), 0, st, n, d,
+                       static_cast<const float*>(A), ld, b, x, lambda, dl_db, dl_da, ld_da);
+  else
+    hipLaunchKernelGGL(k_solution_grads<double>, dim3(blocks), dim3(256), 0, st, n, d,
+                       static_cast<const double*>(A), ld, b, x, lambda, dl_db, dl_da, ld_da);
   return hipGetLastError();
 }
 
