@@ -362,6 +362,7 @@ struct SolveBuffers {
   DeviceStatus* side_status = nullptr;
   double* Hinv0 = nullptr;   // explicit inverses of the overlapped schedule
   double* Hinv1 = nullptr;
+  double* Linv = nullptr;    // triangular-inverse scratch of the second stream
   double* dx = nullptr;
 };
 
@@ -392,6 +393,7 @@ size_t carve_solve(Carver& c, const Layout& L, const ihs_options* o, SolveBuffer
   if (L.d >= kInverseMinD && o->constraint == IHS_UNCONSTRAINED) {
     S.Hinv0 = c.take<double>((size_t)(L.batch * L.d * L.d));
     S.Hinv1 = c.take<double>((size_t)(L.batch * L.d * L.d));
+    S.Linv = c.take<double>((size_t)(L.batch * L.d * L.d));
   }
   S.dx = c.take<double>((size_t)(L.batch * L.d));
   return c.used;
@@ -512,7 +514,7 @@ ihs_status solve_overlap(const ihs_matrix* A, const Layout& L, const ihs_options
       return false;
     if (!use_inv) return true;
     return ck(launch_chol_inverse(l_buf(k), chol_rdiag(w_buf(k), L.batch), d, L.batch,
-                                  hinv_buf(k), S.side_status, side));
+                                  hinv_buf(k), S.Linv, S.side_status, side));
   };
 
   // prologue: sort S_0 and S_1, sketch-only pass for S_0 A, factor H_0
@@ -814,6 +816,7 @@ ihs_status ihs_solve(const ihs_matrix* A, const double* b, const ihs_options* op
     a.work = S.work;
     a.status = B.status;
     a.iter = t;
+    a.warm = t > 0 ? 1 : 0;
     const hipError_t e = launch_qp_step(a, stream);
     if (e == hipErrorNotSupported) return IHS_ERR_UNSUPPORTED;
     if (e != hipSuccess) return IHS_ERR_HIP;

@@ -145,9 +145,7 @@ struct QpArgs {
   double* work;            // batch x qp_work_doubles(d)
   DeviceStatus* status;
   int32_t iter;
-  double* x_hist;          // nullable: batch x d copy of x_out
-  int32_t respect_done;    // skip when status->done is set
-  double tol_stop;         // early-stop threshold on sqrt(dx^T H dx)/sqrt(x^T H x)
+  int32_t warm;            // l2 ball: start the shift from the previous step's root
 };
 size_t qp_work_doubles(int64_t d, int32_t constraint);
 hipError_t launch_qp_step(const QpArgs& a, hipStream_t st);
@@ -165,9 +163,11 @@ hipError_t launch_cholesky(const double* H, double* L, int64_t d, int32_t batch,
                            DeviceStatus* status, int32_t iter, double shift, double* scratch,
                            hipStream_t st, const double* trs = nullptr);
 double* chol_rdiag(double* scratch, int32_t batch);
-// H^{-1} = (L L^T)^{-1}, one workgroup per (problem, identity column).
+// H^{-1} = L^{-T} L^{-1} (blocked triangular inverse, then the product).
+// Linv: batch x d x d scratch. trs as for launch_cholesky (nullable).
 hipError_t launch_chol_inverse(const double* L, const double* rdiag, int64_t d, int32_t batch,
-                               double* Hinv, DeviceStatus* status, hipStream_t st);
+                               double* Hinv, double* Linv, DeviceStatus* status, hipStream_t st,
+                               const double* trs = nullptr);
 // x_out = x + Hinv g (dx receives Hinv g); records sqrt(dx^T g) of problem 0.
 hipError_t launch_inv_apply(const double* Hinv, int64_t d, int32_t batch, const double* g,
                             const double* x, double* x_out, double* dx, DeviceStatus* status,

@@ -382,10 +382,6 @@ hipError_t launch_cholesky(const double* H, double* L, int64_t d, int32_t batch,
 // wavefronts, four rows at a time with one transposing butterfly.
 // Also records sqrt(dx^T v) for problem 0.
 // ---------------------------------------------------------------------------
-// INV: right-hand side e_j for j = blockIdx.y; the solution (column j of H^{-1})
-// is stored in row j of `out` (batch x d x d); base, v and the step record
-// are unused.
-template <bool INV>
 __global__ __launch_bounds__(256) void k_chol_solve(const double* __restrict__ L, int64_t d,
                                                     const double* __restrict__ rdiag,
                                                     const double* __restrict__ v,
@@ -400,20 +396,20 @@ __global__ __launch_bounds__(256) void k_chol_solve(const double* __restrict__ L
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const double* Lp = L + (int64_t)p * d * d;
   const double* rp = rdiag + (int64_t)p * d;
-  const double* vp = INV ? nullptr : v + (int64_t)p * d;
-  const double* bp = INV ? nullptr : base + (int64_t)p * d;
-  double* op = INV ? out + ((int64_t)p * d + blockIdx.y) * d : out + (int64_t)p * d;
+  const double* vp = v + (int64_t)p * d;
+  const double* bp = base + (int64_t)p * d;
+  double* op = out + (int64_t)p * d;
   if (tid == 0) {
     code = status_failed_by(st, -1) ? 1 : 0;
     if (gate != nullptr && status_failed_by(gate, gate_iter)) code = 1;
   }
   __syncthreads();
   if (code != 0) {
-    if (!INV && op != bp)
+    if (op != bp)
       for (int64_t i = tid; i < d; i += 256) op[i] = bp[i];
     return;
   }
-  for (int64_t i = tid; i < d; i += 256) y[i] = INV ? (i == (int64_t)blockIdx.y ? 1.0 : 0.0) : vp[i];
+  for (int64_t i = tid; i < d; i += 256) y[i] = vp[i];
   const int64_t nblk = (d + 63) / 64;
   // forward: L y = v
   for (int64_t bi = 0; bi < nblk; ++bi) {
@@ -477,10 +473,6 @@ __global__ __launch_bounds__(256) void k_chol_solve(const double* __restrict__ L
     }
     __syncthreads();
   }
-  if (INV) {
-    for (int64_t i = tid; i < d; i += 256) op[i] = y[i];
-    return;
-  }
   double part = 0.0;
   bool finite = true;
   for (int64_t i = tid; i < d; i += 256) {
@@ -508,16 +500,190 @@ hipError_t launch_chol_solve_update(const double* L, const double* rdiag, int64_
                                     int32_t batch, const double* v, const double* base,
                                     double* out, DeviceStatus* status, hipStream_t st,
                                     const DeviceStatus* gate, int32_t gate_iter) {
-  hipLaunchKernelGGL(k_chol_solve<false>, dim3(batch), dim3(256), (size_t)(d * sizeof(double)),
+  hipLaunchKernelGGL(k_chol_solve, dim3(batch), dim3(256), (size_t)(d * sizeof(double)),
                      st, L, d, rdiag, v, base, out, status, gate, gate_iter);
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Explicit inverse H^{-1} = L^{-T} L^{-1} from the Cholesky factor, in three
+// stages over 64 x 64 blocks (the blocked triangular inverse followed by the
+// product L^{-T} L^{-1}), the last two on f64 MFMA:
+//   1. diagonal blocks Linv_ii = L_ii^{-1}, one wavefront per block;
+//   2. block diagonals s = 1 .. nblk-1 in turn, every block of a diagonal in
+//      parallel: Linv_{j+s,j} = -Linv_{j+s,j+s} sum_{k=j}^{j+s-1} L_{j+s,k} Linv_{kj};
+//   3. H^{-1}_{IJ} = sum_{k >= I} Linv_{kI}^T Linv_{kJ} for I >= J, mirrored.
+// Entries at or beyond d read as zero, so a ragged last block needs no
+// padding. Problems with trs[4p+1] >= 2 (nullable) are skipped.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool inv_skip(const DeviceStatus* st, const double* trs, int p) {
+  return status_failed_by(st, -1) || trs_skip(trs, p);
+}
+
+// Column j of L_ii^{-1} by lane j (forward substitution on e_j).
+__global__ __launch_bounds__(64) void k_trtri_diag(const double* __restrict__ L,
+                                                   const double* __restrict__ rdiag, int64_t d,
+                                                   double* Linv, const DeviceStatus* st,
+                                                   const double* __restrict__ trs) {
+  __shared__ double Ls[kNb][kNb + 1];
+  __shared__ double X[kNb][kNb + 1];
+  const int p = blockIdx.y, lane = threadIdx.x;
+  const int skip = __shfl(inv_skip(st, trs, p) ? 1 : 0, 0, 64);
+  if (skip) return;
+  const int64_t jb = (int64_t)blockIdx.x * kNb;
+  const int nb = (int)min((int64_t)kNb, d - jb);
+  const double* Lp = L + (int64_t)p * d * d;
+  const double* rp = rdiag + (int64_t)p * d + jb;
+  for (int r = 0; r < kNb; ++r) {
+    Ls[r][lane] = (r < nb && lane <= r) ? Lp[(jb + r) * d + jb + lane] : 0.0;
+    X[r][lane] = 0.0;
+  }
+  __syncthreads();
+  const int j = lane;
+  if (j < nb) {
+    X[j][j] = rp[j];
+    for (int i = j + 1; i < nb; ++i) {
+      double sacc = 0.0;
+      for (int k = j; k < i; ++k) sacc = fma(Ls[i][k], X[k][j], sacc);
+      X[i][j] = -sacc * rp[i];
+    }
+  }
+  __syncthreads();
+  double* Op = Linv + (int64_t)p * d * d;
+  for (int r = 0; r < nb; ++r)
+    if (lane < nb) Op[(jb + r) * d + jb + lane] = X[r][lane];
+}
+
+// One 64 x 64 block product on a 256-thread workgroup: wave w owns the
+// 32 x 32 quadrant (w / 2, w % 2) as 2 x 2 tiles of 16 x 16 (f64 MFMA
+// 16x16x4). A(r, k) and B(k, c) are read through the functors.
+template <typename FA, typename FB>
+__device__ __forceinline__ void block_mma64(f64x4 (&acc)[2][2], FA a_at, FB b_at) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int r = lane & 15, kk = lane >> 4;
+  const int r0 = 32 * (wv >> 1), c0 = 32 * (wv & 1);
+#pragma unroll 4
+  for (int k0 = 0; k0 < kNb; k0 += 4) {
+    double av[2], bv[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      av[t] = a_at(r0 + 16 * t + r, k0 + kk);
+      bv[t] = b_at(k0 + kk, c0 + 16 * t + r);
+    }
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 2; ++tj)
+        acc[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ti], bv[tj], acc[ti][tj], 0, 0, 0);
+  }
+}
+
+// Calls f(row, col, value) for every element a wave holds in acc.
+template <typename F>
+__device__ __forceinline__ void block_store64(const f64x4 (&acc)[2][2], F f) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int r0 = 32 * (wv >> 1), c0 = 32 * (wv & 1);
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int reg = 0; reg < 4; ++reg)
+        f(r0 + 16 * ti + 4 * reg + (lane >> 4), c0 + 16 * tj + (lane & 15), acc[ti][tj][reg]);
+}
+
+__global__ __launch_bounds__(256) void k_trtri_level(const double* __restrict__ L, double* Linv,
+                                                     int64_t d, int32_t s,
+                                                     const DeviceStatus* st,
+                                                     const double* __restrict__ trs) {
+  __shared__ double Ts[kNb][kNb + 1];
+  __shared__ int skip;
+  const int p = blockIdx.y;
+  if (threadIdx.x == 0) skip = inv_skip(st, trs, p) ? 1 : 0;
+  __syncthreads();
+  if (skip) return;
+  const int64_t jb = (int64_t)blockIdx.x * kNb, ib = jb + (int64_t)s * kNb;
+  const double* Lp = L + (int64_t)p * d * d;
+  double* Xp = Linv + (int64_t)p * d * d;
+  f64x4 acc[2][2] = {};
+  for (int64_t kb = jb; kb < ib; kb += kNb) {  // T = sum_k L_ik Linv_kj
+    block_mma64(
+        acc,
+        [&](int rr, int cc) {
+          const int64_t row = ib + rr, col = kb + cc;
+          return (row < d && col < d) ? Lp[row * d + col] : 0.0;
+        },
+        [&](int rr, int cc) {
+          const int64_t row = kb + rr, col = jb + cc;
+          return (row < d && col < d) ? Xp[row * d + col] : 0.0;
+        });
+  }
+  block_store64(acc, [&](int rr, int cc, double v) { Ts[rr][cc] = v; });
+  __syncthreads();
+  f64x4 out[2][2] = {};
+  block_mma64(
+      out,
+      [&](int rr, int cc) {
+        const int64_t row = ib + rr, col = ib + cc;
+        return (row < d && col < d) ? Xp[row * d + col] : 0.0;
+      },
+      [&](int rr, int cc) { return Ts[rr][cc]; });
+  block_store64(out, [&](int rr, int cc, double v) {
+    const int64_t row = ib + rr, col = jb + cc;
+    if (row < d && col < d) Xp[row * d + col] = -v;
+  });
+}
+
+__global__ __launch_bounds__(256) void k_lauum(const double* __restrict__ Linv, double* Hinv,
+                                               int64_t d, int32_t nblk, const DeviceStatus* st,
+                                               const double* __restrict__ trs) {
+  __shared__ int skip;
+  const int p = blockIdx.y;
+  if (threadIdx.x == 0) skip = inv_skip(st, trs, p) ? 1 : 0;
+  __syncthreads();
+  if (skip) return;
+  const int64_t t = blockIdx.x;
+  int64_t I = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+  while (I * (I + 1) / 2 > t) --I;
+  while ((I + 1) * (I + 2) / 2 <= t) ++I;
+  const int64_t J = t - I * (I + 1) / 2;
+  const int64_t Ib = I * kNb, Jb = J * kNb;
+  const double* Xp = Linv + (int64_t)p * d * d;
+  double* Hp = Hinv + (int64_t)p * d * d;
+  f64x4 acc[2][2] = {};
+  for (int64_t kb = Ib; kb < (int64_t)nblk * kNb; kb += kNb) {
+    block_mma64(
+        acc,
+        [&](int rr, int cc) {  // (Linv_kI)^T
+          const int64_t row = kb + cc, col = Ib + rr;
+          return (row < d && col < d) ? Xp[row * d + col] : 0.0;
+        },
+        [&](int rr, int cc) {
+          const int64_t row = kb + rr, col = Jb + cc;
+          return (row < d && col < d) ? Xp[row * d + col] : 0.0;
+        });
+  }
+  block_store64(acc, [&](int rr, int cc, double v) {
+    const int64_t row = Ib + rr, col = Jb + cc;
+    if (row < d && col < d) {
+      Hp[row * d + col] = v;
+      if (I != J) Hp[col * d + row] = v;
+    }
+  });
+}
+
 hipError_t launch_chol_inverse(const double* L, const double* rdiag, int64_t d, int32_t batch,
-                               double* Hinv, DeviceStatus* status, hipStream_t st) {
-  hipLaunchKernelGGL(k_chol_solve<true>, dim3(batch, (unsigned)d), dim3(256),
-                     (size_t)(d * sizeof(double)), st, L, d, rdiag, nullptr, nullptr, Hinv,
-                     status, nullptr, -1);
+                               double* Hinv, double* Linv, DeviceStatus* status, hipStream_t st,
+                               const double* trs) {
+  const int32_t nblk = (int32_t)((d + kNb - 1) / kNb);
+  hipLaunchKernelGGL(k_trtri_diag, dim3(nblk, batch), dim3(64), 0, st, L, rdiag, d, Linv, status,
+                     trs);
+  for (int32_t s = 1; s < nblk; ++s)
+    hipLaunchKernelGGL(k_trtri_level, dim3(nblk - s, batch), dim3(256), 0, st, L, Linv, d, s,
+                       status, trs);
+  const unsigned ntri = (unsigned)(nblk * (nblk + 1) / 2);
+  hipLaunchKernelGGL(k_lauum, dim3(ntri, batch), dim3(256), 0, st, Linv, Hinv, d, nblk, status,
+                     trs);
   return hipGetLastError();
 }
 
@@ -601,9 +767,12 @@ double* chol_rdiag(double* scratch, int32_t batch) { return scratch + (int64_t)b
 // Per-problem scratch of the QP kernels: the 64 x 64 diagonal-block side
 // buffer of the blocked Cholesky plus vectors.
 size_t qp_work_doubles(int64_t d, int32_t constraint) {
-  // constrained steps add c, the unconstrained minimiser and two Newton
-  // vectors, plus four state words
-  return (size_t)(kNb * kNb + 9 * d + 64) + (constraint != 0 ? (size_t)(5 * d + 8) : 0);
+  // ball steps add c, the unconstrained minimiser, two Newton vectors, a
+  // spare vector and the shift state; the l2 step also H^{-1} and L^{-1}
+  size_t n = (size_t)(kNb * kNb + 9 * d + 64);
+  if (constraint != 0) n += (size_t)(5 * d + 8);
+  if (constraint == 2) n += (size_t)(2 * d * d);
+  return n;
 }
 
 hipError_t launch_qp_step(const QpArgs& a, hipStream_t st) {

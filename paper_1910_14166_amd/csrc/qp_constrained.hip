@@ -24,6 +24,7 @@
 //   same factor. The shifts live on the device and each Newton step
 //   re-factors H + mu I with per-problem shifts.
 #include <algorithm>
+#include <vector>
 
 #include "kernels.hpp"
 
@@ -385,11 +386,6 @@ __global__ __launch_bounds__(256) void k_form_c(const double* __restrict__ H, in
   if (lane == 0) c[(int64_t)p * d + i] = s + g[(int64_t)p * d + i];
 }
 
-__global__ void k_fill_f64(double* v, int64_t n, double val) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i < n) v[i] = val;
-}
-
 // ---------------------------------------------------------------------------
 // l2 ball. State per problem: trs[4p] = mu, trs[4p+1] = phase
 // (0 iterating, 1 one last Newton step, 2 done).
@@ -403,16 +399,62 @@ __device__ __forceinline__ double block256_sum(double v, double* red) {
   return red[0] + red[1] + red[2] + red[3];
 }
 
+// Start of a step: phase 0; the shift starts from the previous step's root
+// when `warm` (the same problems, with nearby H and c), else from 0.
+__global__ void k_trs_init(double* trs, int32_t batch, int32_t warm) {
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p >= batch) return;
+  trs[4 * p] = warm ? fmax(trs[4 * p], 0.0) : 0.0;
+  trs[4 * p + 1] = 0.0;
+}
+
+// The unconstrained minimiser inside the ball is the answer.
+__global__ __launch_bounds__(256) void k_trs_inside(const double* __restrict__ xunc, int64_t d,
+                                                    double r, double* trs, double* xout,
+                                                    const DeviceStatus* st) {
+  __shared__ double red[4];
+  __shared__ int skip;
+  const int p = blockIdx.x, tid = threadIdx.x;
+  if (tid == 0) skip = status_failed_by(st, -1) ? 1 : 0;
+  __syncthreads();
+  if (skip) return;
+  const double* xp = xunc + (int64_t)p * d;
+  double sx = 0.0;
+  for (int64_t i = tid; i < d; i += 256) sx = fma(xp[i], xp[i], sx);
+  if (sqrt(block256_sum(sx, red)) > r) return;
+  for (int64_t i = tid; i < d; i += 256) xout[(int64_t)p * d + i] = xp[i];
+  if (tid == 0) trs[4 * p + 1] = 2.0;
+}
+
+// out = M v per problem (M symmetric, one wavefront per row), for problems
+// still iterating.
+__global__ __launch_bounds__(256) void k_trs_symv(const double* __restrict__ M, int64_t d,
+                                                  const double* __restrict__ v, double* out,
+                                                  const double* __restrict__ trs,
+                                                  const DeviceStatus* st) {
+  const int p = blockIdx.y;
+  if (trs[4 * p + 1] >= 2.0 || status_failed_by(st, -1)) return;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * 4 + wv;
+  if (i >= d) return;
+  const double* mr = M + ((int64_t)p * d + i) * d;
+  const double* vp = v + (int64_t)p * d;
+  double s = 0.0;
+  for (int64_t k = lane; k < d; k += 64) s = fma(mr[k], vp[k], s);
+  s = wave_sum(s);
+  if (lane == 0) out[(int64_t)p * d + i] = s;
+}
+
 // Given x = x(mu) and z = (H + mu I)^{-1} x, applies the Newton step
-// mu += (||x||^2 / x^T z) (||x|| - r) / r. When | ||x|| - r | <= tol r the
-// problem takes that one more step (phase 1) and accepts the next x, which
-// the quadratic rate puts at rounding level. `first`: x is the unconstrained
-// minimiser (mu = 0), accepted when it lies in the ball.
+// mu <- max(mu + (||x||^2 / x^T z) (||x|| - r) / r, 0). When
+// | ||x|| - r | <= tol r the problem takes that one more step (phase 1) and
+// accepts the next x, which the quadratic rate puts at rounding level. From
+// a warm start above the root, the first step lands below it (the tangent of
+// a concave function lies above it) and the rest rise monotonically.
 __global__ __launch_bounds__(256) void k_trs_update(const double* __restrict__ xk,
                                                     const double* __restrict__ zk, int64_t d,
                                                     double r, double tol, double* trs,
-                                                    double* xout, const DeviceStatus* st,
-                                                    int32_t first) {
+                                                    double* xout, const DeviceStatus* st) {
   __shared__ double red[4];
   __shared__ int skip;
   const int p = blockIdx.x, tid = threadIdx.x;
@@ -429,15 +471,13 @@ __global__ __launch_bounds__(256) void k_trs_update(const double* __restrict__ x
   const double nx2 = block256_sum(sx, red);
   const double q = block256_sum(sq, red);
   const double nx = sqrt(nx2);
-  const double phase = trs[4 * p + 1];
-  if ((first && nx <= r) || (!first && phase == 1.0)) {
+  if (trs[4 * p + 1] == 1.0) {
     for (int64_t i = tid; i < d; i += 256) xout[(int64_t)p * d + i] = xp[i];
     if (tid == 0) trs[4 * p + 1] = 2.0;
     return;
   }
   if (tid == 0) {
-    const double mu = trs[4 * p];
-    trs[4 * p] = fmax(mu + (nx2 / q) * ((nx - r) / r), mu);
+    trs[4 * p] = fmax(trs[4 * p] + (nx2 / q) * ((nx - r) / r), 0.0);
     if (fabs(nx - r) <= tol * r) trs[4 * p + 1] = 1.0;
   }
 }
@@ -451,19 +491,39 @@ __global__ void k_trs_finish(const double* trs, int64_t d, const double* x, doub
   if (threadIdx.x == 0) status_fail(st, 6 /* IHS_ERR_NOT_CONVERGED */, iter, p);
 }
 
+// True when every problem has finished its Newton iteration or a failure is
+// recorded. Synchronises the stream.
+static bool trs_all_done(const double* trs, const DeviceStatus* status, int32_t batch,
+                         hipStream_t st) {
+  std::vector<double> h((size_t)4 * batch);
+  int32_t code = 0;
+  if (hipMemcpyAsync(h.data(), trs, h.size() * sizeof(double), hipMemcpyDeviceToHost, st) !=
+          hipSuccess ||
+      hipMemcpyAsync(&code, &status->code, sizeof(code), hipMemcpyDeviceToHost, st) !=
+          hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return false;
+  if (code != 0) return true;
+  for (int32_t p = 0; p < batch; ++p)
+    if (h[(size_t)4 * p + 1] < 2.0) return false;
+  return true;
+}
+
 hipError_t launch_qp_constrained(const QpArgs& a, hipStream_t st) {
   const int64_t d = a.d;
   const int32_t B = a.batch;
   if (d > kQpThreads) return hipErrorNotSupported;
   double* scratch = a.work;
   double* rdiag = chol_rdiag(scratch, B);
-  // past the unconstrained step's scratch: c, x_unc, x(mu), z, zeros, state
+  // past the unconstrained step's scratch: c, x_unc, x(mu), z, a spare
+  // vector, the shift state, then (l2) H^{-1} and the triangular inverse
   double* cbuf = a.work + (int64_t)B * (64 * 64 + 9 * d + 64);
   double* xunc = cbuf + (int64_t)B * d;
   double* xk = xunc + (int64_t)B * d;
   double* zk = xk + (int64_t)B * d;
-  double* zero = zk + (int64_t)B * d;
-  double* trs = zero + (int64_t)B * d;
+  double* trs = zk + (int64_t)B * 2 * d;
+  double* hinv = trs + (int64_t)B * 8;
+  double* linv = hinv + (int64_t)B * d * d;
   hipLaunchKernelGGL(k_form_c, dim3((unsigned)((d + 3) / 4), B), dim3(256), 0, st, a.H, d, a.x,
                      a.g, cbuf);
   hipError_t e = launch_cholesky(a.H, a.L, d, B, a.status, a.iter, 0.0, scratch, st);
@@ -480,27 +540,25 @@ hipError_t launch_qp_constrained(const QpArgs& a, hipStream_t st) {
                        a.iter);
     return hipGetLastError();
   }
-  const int32_t newton = a.max_inner > 0 ? a.max_inner : 20;
+  const int32_t newton = a.max_inner > 0 ? a.max_inner : 30;
   const double tol = a.tol > 0 ? a.tol : 1e-10;
-  const int64_t bd = (int64_t)B * d;
-  hipLaunchKernelGGL(k_fill_f64, dim3((unsigned)((bd + 255) / 256)), dim3(256), 0, st, zero, bd,
-                     0.0);
-  hipLaunchKernelGGL(k_fill_f64, dim3((unsigned)((4 * B + 255) / 256)), dim3(256), 0, st, trs,
-                     (int64_t)4 * B, 0.0);
-  // mu = 0: x(0) is the unconstrained minimiser and a.L already its factor
-  e = launch_chol_solve_update(a.L, rdiag, d, B, xunc, zero, zk, a.status, st);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_trs_update, dim3(B), dim3(256), 0, st, xunc, zk, d, a.radius, tol, trs,
-                     a.x_out, a.status, 1);
+  hipLaunchKernelGGL(k_trs_init, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, st, trs, B,
+                     a.warm);
+  hipLaunchKernelGGL(k_trs_inside, dim3(B), dim3(256), 0, st, xunc, d, a.radius, trs, a.x_out,
+                     a.status);
+  const dim3 rows_grid((unsigned)((d + 3) / 4), B);
   for (int32_t k = 0; k < newton; ++k) {
     e = launch_cholesky(a.H, a.L, d, B, a.status, a.iter, 0.0, scratch, st, trs);
     if (e != hipSuccess) return e;
-    e = launch_chol_solve_update(a.L, rdiag, d, B, cbuf, zero, xk, a.status, st);
+    e = launch_chol_inverse(a.L, rdiag, d, B, hinv, linv, a.status, st, trs);
     if (e != hipSuccess) return e;
-    e = launch_chol_solve_update(a.L, rdiag, d, B, xk, zero, zk, a.status, st);
-    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_trs_symv, rows_grid, dim3(256), 0, st, hinv, d, cbuf, xk, trs,
+                       a.status);
+    hipLaunchKernelGGL(k_trs_symv, rows_grid, dim3(256), 0, st, hinv, d, xk, zk, trs, a.status);
     hipLaunchKernelGGL(k_trs_update, dim3(B), dim3(256), 0, st, xk, zk, d, a.radius, tol, trs,
-                       a.x_out, a.status, 0);
+                       a.x_out, a.status);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (k >= 1 && trs_all_done(trs, a.status, B, st)) break;
   }
   hipLaunchKernelGGL(k_trs_finish, dim3(B), dim3(256), 0, st, trs, d, a.x, a.x_out, a.status,
                      a.iter);

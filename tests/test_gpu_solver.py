@@ -231,7 +231,8 @@ def test_ihs_deterministic(gpu_lib):
     assert bool((a == b).all())
 
 
-@pytest.mark.parametrize("shape", [(30000, 64, 640, 1), (20000, 256, 2048, 1), (9000, 40, 400, 3)])
+@pytest.mark.parametrize("shape", [(30000, 64, 640, 1), (20000, 256, 2048, 1), (9000, 40, 400, 3),
+                                   (12000, 150, 1500, 2), (40000, 578, 5000, 1)])
 def test_overlap_schedule_matches_sequential(gpu_lib, shape):
     P = gpu_lib
     n, d, m, batch = shape
