@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--rows", type=int, default=None, help="override the row count")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-tol", action="store_true", help="skip time-to-tolerance runs")
+    ap.add_argument("--no-components", action="store_true",
+                    help="skip the per-row timings at the other workload shapes")
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--max-iter", type=int, default=60)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -151,7 +153,7 @@ def main():
                 "unconstrained" % (wl.n, wl.d, wl.m)
     elif args.workload == "lasso":
         wl = W.lasso_dense(rows=args.rows, backend="torch", device=dev)
-        wdesc = "lasso: AR(1) rows %d x %d fp64, CountSketch m=%d (QP taken unconstrained)" % (
+        wdesc = "lasso: AR(1) rows %d x %d fp64, CountSketch m=%d, l1 ball tau=0.9||x*||_1" % (
             wl.n, wl.d, wl.m)
     else:
         wl = W.ols_dense(rows=args.rows, backend="torch", device=dev)
@@ -163,11 +165,13 @@ def main():
     b = wl.b
 
     # -------------------------------------------------- timed IHS steps ----
-    opts_w = P.options(m, seed=wl.sketch_seed, max_iter=max(args.warmup, 1))
+    cons = dict(constraint=wl.constraint, radius=wl.radius) if wl.constraint != "none" else {}
+    opts_w = P.options(m, seed=wl.sketch_seed, max_iter=max(args.warmup, 1), **cons)
     ws = torch.empty(P.workspace_size(M, opts_w), dtype=torch.uint8, device=dev)
     res = P.solve(M, b, opts_w, ws=ws)
     x = res.x
-    opts = P.options(m, seed=wl.sketch_seed, iter0=max(args.warmup, 1), max_iter=args.steps)
+    opts = P.options(m, seed=wl.sketch_seed, iter0=max(args.warmup, 1), max_iter=args.steps,
+                     **cons)
     torch.cuda.synchronize()
     P.profile_enable(True)
     t0 = time.perf_counter()
@@ -251,12 +255,184 @@ def main():
                               "reference": "structural x_OPT refined in torch fp64",
                               "fp64_ms": fp64, "fastest": best[1], "variants": ttt}
 
+    # ---------------------------------------------- per-row timings ----
+    if not args.no_components and args.workload == "precision":
+        out["components"] = components(P, W, wl)
+
     # ------------------------------------------------- CPU baseline ----
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, m)
 
     out["gen_s"] = round(t_gen, 2)
     print(json.dumps(out), flush=True)
+
+
+PEAK_TFLOPS = {"float64": 78.6, "float32": 157.3, "bfloat16": 2500.0}
+
+
+def _event_ms(fn, reps=5, warm=1):
+    """Average device time of fn() over `reps` back-to-back calls, between
+    two events on the current stream (the stream the library launches on)."""
+    import torch
+    for _ in range(warm):
+        fn()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    s.record()
+    for _ in range(reps):
+        fn()
+    e.record()
+    e.synchronize()
+    return s.elapsed_time(e) / reps
+
+
+def _wall_ms(fn, reps=3, warm=1):
+    """Average wall time of a synchronising call."""
+    import torch
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return 1e3 * (time.perf_counter() - t) / reps
+
+
+def _apply_entry(P, M, spec, n, d, nbytes_in, reps=5):
+    """Sketch apply (sort + gather) timing and the gather alone."""
+    import torch
+    opts = P.options(spec.m, spec.s, spec.kind, spec.seed, spec.iter)
+    ws = torch.empty(P.workspace_size(M, opts), dtype=torch.uint8, device="cuda")
+    out = torch.empty(M.batch * spec.m, d, dtype=torch.float64, device="cuda")
+    fn = lambda: P.sketch_apply(M, spec, out=out, ws=ws)
+    fn()
+    P.profile_enable(True)
+    ms = _event_ms(fn, reps=reps, warm=0)
+    launches, gms = P.profile_read()
+    P.profile_enable(False)
+    gavg = gms / max(launches, 1)
+    alg = nbytes_in + M.batch * spec.m * d * 8
+    return {"ms": round(ms, 4), "gather_ms": round(gavg, 4),
+            "algorithmic_bytes": alg, "GB/s": round(alg / ms / 1e6, 1),
+            "gather_GB/s": round(alg / gavg / 1e6, 1),
+            "frac_of_hbm_peak": round(alg / ms / 1e6 / HBM_PEAK_GBS, 4)}
+
+
+def components(P, W, wl4):
+    """Per-row timings of the hot path at the workload shapes: sketch apply
+    (dense CountSketch/SJLT, CSR), gradient pass, Gram (FP64 and mixed, MFMA),
+    the QP steps, whole constrained solves, the sketch adjoint and the
+    adjoint solve. Device times from events on the launch stream; QP steps
+    and solves synchronise, so they are wall times."""
+    import numpy as np
+    import torch
+    out = {}
+    n4, d4, m4 = wl4.n, wl4.d, wl4.m
+    M4 = P.Matrix(dense=wl4.A)
+    # ---- a3 / a5 on the 2^22 x 512 precision matrix
+    out["a3_sketch_dense_2^22x512_cs_m4096"] = _apply_entry(
+        P, M4, P.SketchSpec(m4, seed=7), n4, d4, n4 * d4 * 8)
+    x4 = torch.zeros(1, d4, dtype=torch.float64, device="cuda")
+    gms = _event_ms(lambda: P.gradient(M4, wl4.b, x4), reps=3)
+    gbytes = n4 * d4 * 8 + n4 * 8
+    out["a5_gradient_2^22x512"] = {"ms": round(gms, 4), "algorithmic_bytes": gbytes,
+                                   "GB/s": round(gbytes / gms / 1e6, 1),
+                                   "frac_of_hbm_peak": round(gbytes / gms / 1e6 / HBM_PEAK_GBS, 4)}
+    # ---- a6 Gram at the 4096 x 512 and 8192 x 1024 shapes
+    for (m, d) in ((4096, 512), (8192, 1024)):
+        SA = torch.randn(m, d, dtype=torch.float64, device="cuda")
+        for gin, gacc in (("float64", "float64"), ("float32", "float32"),
+                          ("bfloat16", "float32")):
+            src = SA if gin == "float64" else SA.to(getattr(torch, gin))
+            H = torch.empty(1, d, d, dtype=torch.float64, device="cuda")
+            ms = _event_ms(lambda: P.gram(src, m, in_dtype=gin, acc_dtype=gacc, out=H), reps=10)
+            fl = m * d * (d + 1)
+            tf = fl / ms / 1e9
+            out[f"a6_gram_{m}x{d}_{gin}_in_{gacc}_acc"] = {
+                "ms": round(ms, 4), "flop": fl, "TFLOP/s": round(tf, 2),
+                "peak_TFLOP/s": PEAK_TFLOPS[gin], "mfma_frac": round(tf / PEAK_TFLOPS[gin], 4)}
+        del SA
+    # ---- a7 unconstrained QP at d = 512 and 1024
+    for d in (512, 1024):
+        g = torch.Generator(device="cuda").manual_seed(d)
+        Q = torch.randn(2 * d, d, generator=g, dtype=torch.float64, device="cuda")
+        H = (Q.T @ Q)[None].contiguous()
+        gv = torch.randn(1, d, generator=g, dtype=torch.float64, device="cuda")
+        xv = torch.zeros(1, d, dtype=torch.float64, device="cuda")
+        ms = _wall_ms(lambda: P.qp_step(H, gv, xv))
+        out[f"a7_qp_unconstrained_d{d}"] = {"ms_wall": round(ms, 4)}
+    torch.cuda.empty_cache()
+    # ---- lasso (2^20 x 256): CountSketch and SJLT apply, l1 QP, l1 solves
+    wl2 = W.lasso_dense(backend="torch", device="cuda")
+    M2 = P.Matrix(dense=wl2.A)
+    n2, d2 = wl2.n, wl2.d
+    for kind, s in (("countsketch", 1), ("sjlt", 4)):
+        out[f"a3_sketch_dense_2^20x256_{kind}_s{s}_m4096"] = _apply_entry(
+            P, M2, P.SketchSpec(4096, s, kind, seed=9), n2, d2, n2 * d2 * 8)
+    SA2 = P.sketch_apply(M2, P.SketchSpec(4096, seed=3))
+    H2 = P.gram(SA2, 4096)
+    g2, _, _ = P.gradient(M2, wl2.b, torch.zeros(1, d2, dtype=torch.float64, device="cuda"))
+    x0 = torch.zeros(1, d2, dtype=torch.float64, device="cuda")
+    ms = _wall_ms(lambda: P.qp_step(H2, g2, x0, constraint="l1", radius=wl2.radius))
+    out["a7_qp_l1_d256_lasso"] = {"ms_wall": round(ms, 4)}
+    for kind, s in (("countsketch", 1), ("sjlt", 4)):
+        o = P.options(4096, s=s, kind=kind, seed=wl2.sketch_seed, max_iter=wl2.iters,
+                      constraint="l1", radius=wl2.radius)
+        ms = _wall_ms(lambda: P.solve(M2, wl2.b, o), reps=1)
+        out[f"a8_solve_lasso_2^20x256_l1_{kind}_s{s}_{wl2.iters}steps"] = {
+            "ms_wall": round(ms, 3), "ms_per_step": round(ms / wl2.iters, 4)}
+    del wl2, M2, SA2
+    torch.cuda.empty_cache()
+    # ---- CSR ridge (2^22 x 1024, density 1e-3): CSR apply, l2 QP, l2 solve
+    wl3 = W.ridge_csr()
+    rp = torch.from_numpy(wl3.indptr).cuda()
+    ci = torch.from_numpy(wl3.indices).cuda()
+    va = torch.from_numpy(wl3.data).cuda()
+    b3 = torch.from_numpy(wl3.b).cuda()
+    M3 = P.Matrix(row_ptr=rp, col_idx=ci, values=va, n=wl3.n, d=wl3.d)
+    nnz = int(wl3.indptr[-1])
+    csr_bytes = nnz * 12 + (wl3.n + 1) * 4
+    out["a4_sketch_csr_2^22x1024_m8192"] = dict(
+        _apply_entry(P, M3, P.SketchSpec(8192, seed=4), wl3.n, wl3.d, csr_bytes), nnz=nnz)
+    SA3 = P.sketch_apply(M3, P.SketchSpec(8192, seed=5))
+    H3 = P.gram(SA3, 8192)
+    g3, _, _ = P.gradient(M3, b3, torch.zeros(1, wl3.d, dtype=torch.float64, device="cuda"))
+    x3 = torch.zeros(1, wl3.d, dtype=torch.float64, device="cuda")
+    ms = _wall_ms(lambda: P.qp_step(H3, g3, x3, constraint="l2", radius=wl3.radius))
+    out["a7_qp_l2_d1024_csr"] = {"ms_wall": round(ms, 4)}
+    for gin, gacc in (("float64", "float64"), ("bfloat16", "float32")):
+        o = P.options(8192, seed=wl3.sketch_seed, max_iter=wl3.iters, constraint="l2",
+                      radius=wl3.radius, gram_in=gin, gram_acc=gacc)
+        ms = _wall_ms(lambda: P.solve(M3, b3, o), reps=1)
+        out[f"a8_solve_csr_2^22x1024_l2_{gin}_gram_{wl3.iters}steps"] = {
+            "ms_wall": round(ms, 3), "ms_per_step": round(ms / wl3.iters, 4)}
+    del wl3, M3, SA3, rp, ci, va, b3
+    torch.cuda.empty_cache()
+    # ---- ragged batch (64 problems, d = 64): adjoint, autograd
+    from paper_1910_14166_amd import autograd as AG
+    wl5 = W.batch_ragged(backend="torch", device="cuda")
+    offs = wl5.row_offsets
+    G5 = torch.randn(64 * wl5.m, wl5.d, dtype=torch.float64, device="cuda")
+    spec5 = P.SketchSpec(wl5.m, seed=3)
+    adj = torch.empty(wl5.n, wl5.d, dtype=torch.float64, device="cuda")
+    ms = _event_ms(lambda: P.sketch_adjoint(G5, wl5.n, spec5, row_offsets=offs, out=adj))
+    ab = wl5.n * wl5.d * 8 + G5.numel() * 8
+    out["a9_sketch_adjoint_ragged64_d64"] = {"ms": round(ms, 4), "algorithmic_bytes": ab,
+                                             "GB/s": round(ab / ms / 1e6, 1)}
+    At = wl5.A.clone().requires_grad_(True)
+    bt = wl5.b.clone().requires_grad_(True)
+
+    def fwd_bwd():
+        x = AG.ihs_solve(At, bt, m=wl5.m, seed=wl5.sketch_seed, iters=wl5.iters,
+                         row_offsets=offs)
+        ((x - wl5.y) ** 2).sum().backward()
+    ms = _wall_ms(fwd_bwd, reps=2)
+    out["a10_autograd_ragged64_d64_20steps_fwd_bwd"] = {"ms_wall": round(ms, 3),
+                                                         "rows": wl5.n}
+    del wl5, At, bt, G5, adj
+    torch.cuda.empty_cache()
+    return out
 
 
 def cpu_baseline(wl, m, budget_s=15.0):

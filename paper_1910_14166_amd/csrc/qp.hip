@@ -42,6 +42,25 @@ __device__ __forceinline__ bool trs_skip(const double* trs, int p) {
   return trs != nullptr && trs[4 * p + 1] >= 2.0;
 }
 
+// Stages the lower triangle (with the diagonal) of the nb x nb block at
+// (r0, r0) of the d x d row-major matrix M into D, zeros elsewhere. Every
+// thread issues its 16 loads before the first LDS store, so the staging
+// costs one memory round trip. 256 threads.
+__device__ __forceinline__ void stage_lower64(double (*D)[kNb + 1], const double* __restrict__ M,
+                                              int64_t d, int64_t r0, int nb) {
+  double v[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int e = threadIdx.x + 256 * q, i = e >> 6, j = e & 63;
+    v[q] = (i < nb && j <= i) ? M[(r0 + i) * d + r0 + j] : 0.0;
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int e = threadIdx.x + 256 * q;
+    D[e >> 6][e & 63] = v[q];
+  }
+}
+
 __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -152,9 +171,19 @@ __global__ __launch_bounds__(256) void k_chol_small(const double* __restrict__ H
   const double* Hp = H + (int64_t)p * d * d;
   double* Lp = L + (int64_t)p * d * d;
   const int tid = threadIdx.x;
-  for (int64_t e = tid; e < d * d; e += 256) {
-    const int64_t i = e / d, j = e - (e / d) * d;
-    a[e] = (j <= i) ? Hp[e] + (i == j ? shift : 0.0) : 0.0;
+  for (int64_t e0 = 0; e0 < d * d; e0 += 256 * 8) {  // 8 loads in flight per thread
+    double v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int64_t e = e0 + tid + 256 * q;
+      const int64_t i = e / d, j = e - (e / d) * d;
+      v[q] = (e < d * d && j <= i) ? Hp[e] + (i == j ? shift : 0.0) : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int64_t e = e0 + tid + 256 * q;
+      if (e < d * d) a[e] = v[q];
+    }
   }
   __syncthreads();
   for (int64_t j = 0; j < d; ++j) {
@@ -204,12 +233,15 @@ __global__ __launch_bounds__(256) void k_chol_init(const double* __restrict__ H,
 }
 
 // Diagonal block of panel kb: one workgroup per problem factors the 64 x 64
-// block in LDS (right-looking, one barrier per column; thread t owns row t/4,
-// columns 16*(t%4) .. +15) and writes L_kk and 1/L_jj back.
+// block right-looking. Thread t keeps row t/4, columns 16*(t%4) .. +15, in
+// registers; for column j the threads holding it publish it to LDS (two
+// alternating buffers, so one barrier per column), every row below the pivot
+// updates its register segment, and the owners scale their element. Writes
+// L_kk and 1/L_jj back.
 __global__ __launch_bounds__(256) void k_chol_diag(double* L, int64_t d, int64_t kb,
                                                    double* rdiag, DeviceStatus* st,
                                                    int32_t iter, const double* __restrict__ trs) {
-  __shared__ double D[kNb][kNb + 1];
+  __shared__ double C[2][kNb];
   __shared__ double rd[kNb];
   __shared__ int flag;
   const int p = blockIdx.x;
@@ -219,44 +251,46 @@ __global__ __launch_bounds__(256) void k_chol_diag(double* L, int64_t d, int64_t
   if (flag != 0) return;
   double* W = L + (int64_t)p * d * d;
   const int nb = (int)min((int64_t)kNb, d - kb);
-  for (int e = tid; e < kNb * kNb; e += 256) {
-    const int i = e >> 6, j = e & 63;
-    D[i][j] = (i < nb && j <= i) ? W[(kb + i) * d + kb + j] : 0.0;
-  }
-  __syncthreads();
-  const int my_i = tid >> 2, k0 = (tid & 3) * 16;
+  const int i = tid >> 2, seg = tid & 3, k0 = 16 * seg;
+  double a[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q)
+    a[q] = (i < nb && k0 + q <= i) ? W[(kb + i) * d + kb + k0 + q] : 0.0;
   int bad = 0;
-  for (int j = 0; j < nb; ++j) {
-    const double piv = D[j][j];
+#pragma unroll
+  for (int j = 0; j < kNb; ++j) {
+    if (j >= nb) break;  // uniform
+    double* Cj = C[j & 1];
+    if (seg == (j >> 4)) Cj[i] = a[j & 15];
+    __syncthreads();
+    const double piv = Cj[j];
     if (!(piv > 0.0) || !isfinite(piv)) {  // the same pivot for every thread
       bad = 1;
       break;
     }
     const double r = 1.0 / sqrt(piv);
-    if (my_i > j && my_i < nb) {
-      const double lij = D[my_i][j] * r;
+    if (i > j && i < nb) {
+      const double lij = Cj[i] * r;
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
         const int k = k0 + q;
-        if (k > j && k <= my_i) D[my_i][k] = fma(-lij, D[k][j] * r, D[my_i][k]);
+        if (k > j && k <= i) a[q] = fma(-lij, Cj[k] * r, a[q]);
       }
     }
-    __syncthreads();  // column j is no longer read: scale it
-    if (tid == 0) {
-      D[j][j] = sqrt(piv);
-      rd[j] = r;
+    if (seg == (j >> 4)) {
+      if (i > j) a[j & 15] = Cj[i] * r;
+      else if (i == j) a[j & 15] = sqrt(piv);
     }
-    if (tid > j && tid < nb) D[tid][j] = D[tid][j] * r;
+    if (tid == 0) rd[j] = r;
   }
   __syncthreads();
   if (bad) {
     if (tid == 0) status_fail(st, 5 /* IHS_ERR_NOT_PD */, iter, p);
     return;
   }
-  for (int e = tid; e < kNb * kNb; e += 256) {
-    const int i = e >> 6, j = e & 63;
-    if (i < nb && j <= i) W[(kb + i) * d + kb + j] = D[i][j];
-  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q)
+    if (i < nb && k0 + q <= i) W[(kb + i) * d + kb + k0 + q] = a[q];
   if (tid < nb) rdiag[(int64_t)p * d + kb + tid] = rd[tid];
 }
 
@@ -276,10 +310,7 @@ __global__ __launch_bounds__(256) void k_chol_trsm(double* L, int64_t d, int64_t
   __syncthreads();
   if (flag != 0) return;
   double* W = L + (int64_t)p * d * d;
-  for (int e = tid; e < kNb * kNb; e += 256) {
-    const int i = e >> 6, j = e & 63;
-    D[i][j] = (j <= i) ? W[(kb + i) * d + kb + j] : 0.0;
-  }
+  stage_lower64(D, W, d, kb, kNb);  // below > 0, so the block is full
   if (tid < kNb) rd[tid] = rdiag[(int64_t)p * d + kb + tid];
   __syncthreads();
   const int64_t rows0 = kb + kNb;
@@ -331,7 +362,7 @@ __global__ __launch_bounds__(256) void k_chol_update(double* L, int64_t d, int64
   const int r = lane & 15, kk = lane >> 4;
   f64x4 acc = {0, 0, 0, 0};
   const bool ra = r0 + r < d, rb = c0 + r < d;
-#pragma unroll 4
+#pragma unroll
   for (int k = 0; k < kNb; k += 4) {
     const int64_t col = kb + k + kk;
     const double av = ra ? W[(r0 + r) * d + col] : 0.0;
@@ -415,10 +446,7 @@ __global__ __launch_bounds__(256) void k_chol_solve(const double* __restrict__ L
   for (int64_t bi = 0; bi < nblk; ++bi) {
     const int64_t jb = bi * 64;
     const int nb = (int)min((int64_t)64, d - jb);
-    for (int e = tid; e < 64 * 64; e += 256) {
-      const int i = e >> 6, j = e & 63;
-      D[i][j] = (i < nb && j < nb && j <= i) ? Lp[(jb + i) * d + jb + j] : 0.0;
-    }
+    stage_lower64(D, Lp, d, jb, nb);
     __syncthreads();
     if (wv == 0) {
       double yl = lane < nb ? y[jb + lane] : 0.0;
@@ -449,10 +477,7 @@ __global__ __launch_bounds__(256) void k_chol_solve(const double* __restrict__ L
   for (int64_t bi = nblk - 1; bi >= 0; --bi) {
     const int64_t jb = bi * 64;
     const int nb = (int)min((int64_t)64, d - jb);
-    for (int e = tid; e < 64 * 64; e += 256) {
-      const int i = e >> 6, j = e & 63;
-      D[i][j] = (i < nb && j < nb && j <= i) ? Lp[(jb + i) * d + jb + j] : 0.0;
-    }
+    stage_lower64(D, Lp, d, jb, nb);
     __syncthreads();
     if (wv == 0) {
       double yl = lane < nb ? y[jb + lane] : 0.0;
@@ -534,9 +559,18 @@ __global__ __launch_bounds__(64) void k_trtri_diag(const double* __restrict__ L,
   const int nb = (int)min((int64_t)kNb, d - jb);
   const double* Lp = L + (int64_t)p * d * d;
   const double* rp = rdiag + (int64_t)p * d + jb;
-  for (int r = 0; r < kNb; ++r) {
-    Ls[r][lane] = (r < nb && lane <= r) ? Lp[(jb + r) * d + jb + lane] : 0.0;
-    X[r][lane] = 0.0;
+  for (int r0 = 0; r0 < kNb; r0 += 16) {  // 16 loads in flight per lane
+    double v[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int r = r0 + q;
+      v[q] = (r < nb && lane <= r) ? Lp[(jb + r) * d + jb + lane] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      Ls[r0 + q][lane] = v[q];
+      X[r0 + q][lane] = 0.0;
+    }
   }
   __syncthreads();
   const int j = lane;
@@ -554,11 +588,38 @@ __global__ __launch_bounds__(64) void k_trtri_diag(const double* __restrict__ L,
     if (lane < nb) Op[(jb + r) * d + jb + lane] = X[r][lane];
 }
 
-// One 64 x 64 block product on a 256-thread workgroup: wave w owns the
-// 32 x 32 quadrant (w / 2, w % 2) as 2 x 2 tiles of 16 x 16 (f64 MFMA
-// 16x16x4). A(r, k) and B(k, c) are read through the functors.
-template <typename FA, typename FB>
-__device__ __forceinline__ void block_mma64(f64x4 (&acc)[2][2], FA a_at, FB b_at) {
+// Block tiles of the inverse stages: 64 x 64 doubles in LDS, one padding
+// column against bank conflicts.
+typedef double Tile64[kNb][kNb + 1];
+
+// Stages the 64 x 64 blocks at (ra, ca) of the d x d matrix MA and at
+// (rb, cb) of MB into TA and TB (entries at or beyond d read as zero). Each
+// thread issues all 32 coalesced loads before storing, so the pair costs one
+// memory round trip. 256 threads.
+__device__ __forceinline__ void stage64x2(Tile64& TA, const double* __restrict__ MA, int64_t ra,
+                                          int64_t ca, Tile64& TB, const double* __restrict__ MB,
+                                          int64_t rb, int64_t cb, int64_t d) {
+  double va[16], vb[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int e = threadIdx.x + 256 * q, rr = e >> 6, cc = e & 63;
+    va[q] = (ra + rr < d && ca + cc < d) ? MA[(ra + rr) * d + ca + cc] : 0.0;
+    vb[q] = (rb + rr < d && cb + cc < d) ? MB[(rb + rr) * d + cb + cc] : 0.0;
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int e = threadIdx.x + 256 * q;
+    TA[e >> 6][e & 63] = va[q];
+    TB[e >> 6][e & 63] = vb[q];
+  }
+}
+
+// acc += op(A) B for 64 x 64 tiles in LDS, op(A) = A or A^T, on a 256-thread
+// workgroup: wave w owns the 32 x 32 quadrant (w / 2, w % 2) as 2 x 2 tiles
+// of 16 x 16 (f64 MFMA 16x16x4).
+template <bool TRANS_A>
+__device__ __forceinline__ void tile_mma64(f64x4 (&acc)[2][2], const Tile64& A,
+                                           const Tile64& B) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int r = lane & 15, kk = lane >> 4;
   const int r0 = 32 * (wv >> 1), c0 = 32 * (wv & 1);
@@ -567,8 +628,8 @@ __device__ __forceinline__ void block_mma64(f64x4 (&acc)[2][2], FA a_at, FB b_at
     double av[2], bv[2];
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
-      av[t] = a_at(r0 + 16 * t + r, k0 + kk);
-      bv[t] = b_at(k0 + kk, c0 + 16 * t + r);
+      av[t] = TRANS_A ? A[k0 + kk][r0 + 16 * t + r] : A[r0 + 16 * t + r][k0 + kk];
+      bv[t] = B[k0 + kk][c0 + 16 * t + r];
     }
 #pragma unroll
     for (int ti = 0; ti < 2; ++ti)
@@ -580,7 +641,7 @@ __device__ __forceinline__ void block_mma64(f64x4 (&acc)[2][2], FA a_at, FB b_at
 
 // Calls f(row, col, value) for every element a wave holds in acc.
 template <typename F>
-__device__ __forceinline__ void block_store64(const f64x4 (&acc)[2][2], F f) {
+__device__ __forceinline__ void tile_store64(const f64x4 (&acc)[2][2], F f) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int r0 = 32 * (wv >> 1), c0 = 32 * (wv & 1);
 #pragma unroll
@@ -596,7 +657,7 @@ __global__ __launch_bounds__(256) void k_trtri_level(const double* __restrict__ 
                                                      int64_t d, int32_t s,
                                                      const DeviceStatus* st,
                                                      const double* __restrict__ trs) {
-  __shared__ double Ts[kNb][kNb + 1];
+  __shared__ Tile64 As, Bs;
   __shared__ int skip;
   const int p = blockIdx.y;
   if (threadIdx.x == 0) skip = inv_skip(st, trs, p) ? 1 : 0;
@@ -607,28 +668,29 @@ __global__ __launch_bounds__(256) void k_trtri_level(const double* __restrict__ 
   double* Xp = Linv + (int64_t)p * d * d;
   f64x4 acc[2][2] = {};
   for (int64_t kb = jb; kb < ib; kb += kNb) {  // T = sum_k L_ik Linv_kj
-    block_mma64(
-        acc,
-        [&](int rr, int cc) {
-          const int64_t row = ib + rr, col = kb + cc;
-          return (row < d && col < d) ? Lp[row * d + col] : 0.0;
-        },
-        [&](int rr, int cc) {
-          const int64_t row = kb + rr, col = jb + cc;
-          return (row < d && col < d) ? Xp[row * d + col] : 0.0;
-        });
+    stage64x2(As, Lp, ib, kb, Bs, Xp, kb, jb, d);
+    __syncthreads();
+    tile_mma64<false>(acc, As, Bs);
+    __syncthreads();
   }
-  block_store64(acc, [&](int rr, int cc, double v) { Ts[rr][cc] = v; });
+  tile_store64(acc, [&](int rr, int cc, double v) { Bs[rr][cc] = v; });
+  {
+    double v[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int e = threadIdx.x + 256 * q, rr = e >> 6, cc = e & 63;
+      v[q] = (ib + rr < d && ib + cc < d) ? Xp[(ib + rr) * d + ib + cc] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int e = threadIdx.x + 256 * q;
+      As[e >> 6][e & 63] = v[q];
+    }
+  }
   __syncthreads();
   f64x4 out[2][2] = {};
-  block_mma64(
-      out,
-      [&](int rr, int cc) {
-        const int64_t row = ib + rr, col = ib + cc;
-        return (row < d && col < d) ? Xp[row * d + col] : 0.0;
-      },
-      [&](int rr, int cc) { return Ts[rr][cc]; });
-  block_store64(out, [&](int rr, int cc, double v) {
+  tile_mma64<false>(out, As, Bs);  // Linv_ij = -Linv_ii T
+  tile_store64(out, [&](int rr, int cc, double v) {
     const int64_t row = ib + rr, col = jb + cc;
     if (row < d && col < d) Xp[row * d + col] = -v;
   });
@@ -637,6 +699,7 @@ __global__ __launch_bounds__(256) void k_trtri_level(const double* __restrict__ 
 __global__ __launch_bounds__(256) void k_lauum(const double* __restrict__ Linv, double* Hinv,
                                                int64_t d, int32_t nblk, const DeviceStatus* st,
                                                const double* __restrict__ trs) {
+  __shared__ Tile64 As, Bs;
   __shared__ int skip;
   const int p = blockIdx.y;
   if (threadIdx.x == 0) skip = inv_skip(st, trs, p) ? 1 : 0;
@@ -651,19 +714,13 @@ __global__ __launch_bounds__(256) void k_lauum(const double* __restrict__ Linv, 
   const double* Xp = Linv + (int64_t)p * d * d;
   double* Hp = Hinv + (int64_t)p * d * d;
   f64x4 acc[2][2] = {};
-  for (int64_t kb = Ib; kb < (int64_t)nblk * kNb; kb += kNb) {
-    block_mma64(
-        acc,
-        [&](int rr, int cc) {  // (Linv_kI)^T
-          const int64_t row = kb + cc, col = Ib + rr;
-          return (row < d && col < d) ? Xp[row * d + col] : 0.0;
-        },
-        [&](int rr, int cc) {
-          const int64_t row = kb + rr, col = Jb + cc;
-          return (row < d && col < d) ? Xp[row * d + col] : 0.0;
-        });
+  for (int64_t kb = Ib; kb < (int64_t)nblk * kNb; kb += kNb) {  // sum_k Linv_kI^T Linv_kJ
+    stage64x2(As, Xp, kb, Ib, Bs, Xp, kb, Jb, d);
+    __syncthreads();
+    tile_mma64<true>(acc, As, Bs);
+    __syncthreads();
   }
-  block_store64(acc, [&](int rr, int cc, double v) {
+  tile_store64(acc, [&](int rr, int cc, double v) {
     const int64_t row = Ib + rr, col = Jb + cc;
     if (row < d && col < d) {
       Hp[row * d + col] = v;
