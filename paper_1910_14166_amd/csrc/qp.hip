@@ -233,15 +233,17 @@ __global__ __launch_bounds__(256) void k_chol_init(const double* __restrict__ H,
 }
 
 // Diagonal block of panel kb: one workgroup per problem factors the 64 x 64
-// block right-looking. Thread t keeps row t/4, columns 16*(t%4) .. +15, in
-// registers; for column j the threads holding it publish it to LDS (two
-// alternating buffers, so one barrier per column), every row below the pivot
-// updates its register segment, and the owners scale their element. Writes
-// L_kk and 1/L_jj back.
+// block right-looking in steps of four columns. Thread t keeps row t/4,
+// columns 16*(t%4) .. +15, in registers. At each step the threads holding
+// the four columns publish them to LDS (two alternating buffers, so one
+// barrier per step); every thread factors the 4 x 4 pivot block itself,
+// forms its row's panel entries L_iJ = A_iJ L_JJ^{-T} and those of the rows
+// its columns stand for, and applies the rank-4 update to its segment.
+// Writes L_kk and 1/L_jj back.
 __global__ __launch_bounds__(256) void k_chol_diag(double* L, int64_t d, int64_t kb,
                                                    double* rdiag, DeviceStatus* st,
                                                    int32_t iter, const double* __restrict__ trs) {
-  __shared__ double C[2][kNb];
+  __shared__ double Pb[2][kNb][4];
   __shared__ double rd[kNb];
   __shared__ int flag;
   const int p = blockIdx.x;
@@ -258,30 +260,86 @@ __global__ __launch_bounds__(256) void k_chol_diag(double* L, int64_t d, int64_t
     a[q] = (i < nb && k0 + q <= i) ? W[(kb + i) * d + kb + k0 + q] : 0.0;
   int bad = 0;
 #pragma unroll
-  for (int j = 0; j < kNb; ++j) {
-    if (j >= nb) break;  // uniform
-    double* Cj = C[j & 1];
-    if (seg == (j >> 4)) Cj[i] = a[j & 15];
+  for (int J = 0; J < kNb / 4; ++J) {
+    const int j0 = 4 * J, jend = j0 + 4;
+    if (j0 >= nb) break;  // uniform
+    double(*Pj)[4] = Pb[J & 1];
+    if (seg == (j0 >> 4)) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) Pj[i][c] = a[(j0 & 15) + c];
+    }
     __syncthreads();
-    const double piv = Cj[j];
-    if (!(piv > 0.0) || !isfinite(piv)) {  // the same pivot for every thread
+    // the 4 x 4 pivot block, padded with the identity past nb
+    double pv[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        pv[r][c] = (j0 + r < nb) ? Pj[j0 + r][c] : (r == c ? 1.0 : 0.0);
+    const double d0 = pv[0][0];
+    if (!(d0 > 0.0) || !isfinite(d0)) {  // the same pivots in every thread
       bad = 1;
       break;
     }
-    const double r = 1.0 / sqrt(piv);
-    if (i > j && i < nb) {
-      const double lij = Cj[i] * r;
+    const double l00 = sqrt(d0), r0 = 1.0 / l00;
+    const double l10 = pv[1][0] * r0, l20 = pv[2][0] * r0, l30 = pv[3][0] * r0;
+    const double d1 = fma(-l10, l10, pv[1][1]);
+    if (!(d1 > 0.0) || !isfinite(d1)) {
+      bad = 1;
+      break;
+    }
+    const double l11 = sqrt(d1), r1 = 1.0 / l11;
+    const double l21 = fma(-l20, l10, pv[2][1]) * r1, l31 = fma(-l30, l10, pv[3][1]) * r1;
+    const double d2 = fma(-l21, l21, fma(-l20, l20, pv[2][2]));
+    if (!(d2 > 0.0) || !isfinite(d2)) {
+      bad = 1;
+      break;
+    }
+    const double l22 = sqrt(d2), r2 = 1.0 / l22;
+    const double l32 = fma(-l31, l21, fma(-l30, l20, pv[3][2])) * r2;
+    const double d3 = fma(-l32, l32, fma(-l31, l31, fma(-l30, l30, pv[3][3])));
+    if (!(d3 > 0.0) || !isfinite(d3)) {
+      bad = 1;
+      break;
+    }
+    const double l33 = sqrt(d3), r3 = 1.0 / l33;
+    // z = L_JJ^{-1} u: the panel entries of a row from its four A entries
+    auto panel = [&](const double* u, double (&z)[4]) {
+      z[0] = u[0] * r0;
+      z[1] = fma(-l10, z[0], u[1]) * r1;
+      z[2] = fma(-l21, z[1], fma(-l20, z[0], u[2])) * r2;
+      z[3] = fma(-l32, z[2], fma(-l31, z[1], fma(-l30, z[0], u[3]))) * r3;
+    };
+    if (i >= jend && i < nb) {
+      double zi[4];
+      panel(Pj[i], zi);
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
         const int k = k0 + q;
-        if (k > j && k <= i) a[q] = fma(-lij, Cj[k] * r, a[q]);
+        if (k >= jend && k <= i) {
+          double zk[4];
+          panel(Pj[k], zk);
+          a[q] = fma(-zi[3], zk[3], fma(-zi[2], zk[2], fma(-zi[1], zk[1], fma(-zi[0], zk[0], a[q]))));
+        }
       }
+      if (seg == (j0 >> 4)) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) a[(j0 & 15) + c] = zi[c];
+      }
+    } else if (i >= j0 && i < jend && i < nb && seg == (j0 >> 4)) {
+      const double lrow[4][4] = {{l00, 0.0, 0.0, 0.0},
+                                 {l10, l11, 0.0, 0.0},
+                                 {l20, l21, l22, 0.0},
+                                 {l30, l31, l32, l33}};
+#pragma unroll
+      for (int c = 0; c < 4; ++c) a[(j0 & 15) + c] = lrow[i - j0][c];
     }
-    if (seg == (j >> 4)) {
-      if (i > j) a[j & 15] = Cj[i] * r;
-      else if (i == j) a[j & 15] = sqrt(piv);
+    if (tid == 0) {
+      rd[j0] = r0;
+      rd[j0 + 1] = r1;
+      rd[j0 + 2] = r2;
+      rd[j0 + 3] = r3;
     }
-    if (tid == 0) rd[j] = r;
   }
   __syncthreads();
   if (bad) {
@@ -545,47 +603,57 @@ __device__ __forceinline__ bool inv_skip(const DeviceStatus* st, const double* t
   return status_failed_by(st, -1) || trs_skip(trs, p);
 }
 
-// Column j of L_ii^{-1} by lane j (forward substitution on e_j).
-__global__ __launch_bounds__(64) void k_trtri_diag(const double* __restrict__ L,
-                                                   const double* __restrict__ rdiag, int64_t d,
-                                                   double* Linv, const DeviceStatus* st,
-                                                   const double* __restrict__ trs) {
+// L_ii^{-1} by rows, right-looking: thread t keeps row t/4, columns
+// 16*(t%4) .. +15, of X (initially I) in registers. At step k row k is
+// final once divided by L_kk; its owners publish it to LDS (two alternating
+// buffers, one barrier per step) and every row below subtracts L_ik times
+// it. 256 threads per diagonal block.
+__global__ __launch_bounds__(256) void k_trtri_diag(const double* __restrict__ L,
+                                                    const double* __restrict__ rdiag, int64_t d,
+                                                    double* Linv, const DeviceStatus* st,
+                                                    const double* __restrict__ trs) {
   __shared__ double Ls[kNb][kNb + 1];
-  __shared__ double X[kNb][kNb + 1];
-  const int p = blockIdx.y, lane = threadIdx.x;
-  const int skip = __shfl(inv_skip(st, trs, p) ? 1 : 0, 0, 64);
+  __shared__ double R[2][kNb];
+  __shared__ int skip;
+  const int p = blockIdx.y, tid = threadIdx.x;
+  if (tid == 0) skip = inv_skip(st, trs, p) ? 1 : 0;
+  __syncthreads();
   if (skip) return;
   const int64_t jb = (int64_t)blockIdx.x * kNb;
   const int nb = (int)min((int64_t)kNb, d - jb);
   const double* Lp = L + (int64_t)p * d * d;
   const double* rp = rdiag + (int64_t)p * d + jb;
-  for (int r0 = 0; r0 < kNb; r0 += 16) {  // 16 loads in flight per lane
-    double v[16];
+  stage_lower64(Ls, Lp, d, jb, nb);
+  const int i = tid >> 2, seg = tid & 3, c0 = 16 * seg;
+  double x[16];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int r = r0 + q;
-      v[q] = (r < nb && lane <= r) ? Lp[(jb + r) * d + jb + lane] : 0.0;
+  for (int q = 0; q < 16; ++q) x[q] = (c0 + q == i) ? 1.0 : 0.0;
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kNb; ++k) {
+    if (k >= nb) break;  // uniform
+    double* Rk = R[k & 1];
+    if (i == k) {
+      const double r = rp[k];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        x[q] *= r;
+        Rk[c0 + q] = x[q];
+      }
     }
+    __syncthreads();
+    if (i > k && i < nb) {
+      const double lik = Ls[i][k];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      Ls[r0 + q][lane] = v[q];
-      X[r0 + q][lane] = 0.0;
+      for (int q = 0; q < 16; ++q) x[q] = fma(-lik, Rk[c0 + q], x[q]);
     }
   }
-  __syncthreads();
-  const int j = lane;
-  if (j < nb) {
-    X[j][j] = rp[j];
-    for (int i = j + 1; i < nb; ++i) {
-      double sacc = 0.0;
-      for (int k = j; k < i; ++k) sacc = fma(Ls[i][k], X[k][j], sacc);
-      X[i][j] = -sacc * rp[i];
-    }
-  }
-  __syncthreads();
   double* Op = Linv + (int64_t)p * d * d;
-  for (int r = 0; r < nb; ++r)
-    if (lane < nb) Op[(jb + r) * d + jb + lane] = X[r][lane];
+  if (i < nb) {
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+      if (c0 + q < nb) Op[(jb + i) * d + jb + c0 + q] = x[q];
+  }
 }
 
 // Block tiles of the inverse stages: 64 x 64 doubles in LDS, one padding
@@ -733,7 +801,7 @@ hipError_t launch_chol_inverse(const double* L, const double* rdiag, int64_t d, 
                                double* Hinv, double* Linv, DeviceStatus* status, hipStream_t st,
                                const double* trs) {
   const int32_t nblk = (int32_t)((d + kNb - 1) / kNb);
-  hipLaunchKernelGGL(k_trtri_diag, dim3(nblk, batch), dim3(64), 0, st, L, rdiag, d, Linv, status,
+  hipLaunchKernelGGL(k_trtri_diag, dim3(nblk, batch), dim3(256), 0, st, L, rdiag, d, Linv, status,
                      trs);
   for (int32_t s = 1; s < nblk; ++s)
     hipLaunchKernelGGL(k_trtri_level, dim3(nblk - s, batch), dim3(256), 0, st, L, Linv, d, s,

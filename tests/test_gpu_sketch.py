@@ -49,6 +49,9 @@ CASES = [  # n, d, m, s
     (900, 1, 32, 2),         # single column, SJLT s=2 (scale after the sum)
     (4000, 1024, 128, 1),    # widest dense path
     (1500, 600, 96, 3),      # 600 columns (paired loads), s = 3
+    (40000, 8, 16384, 1),    # largest sketch: two 7-bit radix digits
+    (300, 5, 1, 1),          # one sketch row: no radix bits
+    (70000, 16, 4096, 4),    # many sort tiles, SJLT over 4 blocks
 ]
 
 
