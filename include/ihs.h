@@ -116,14 +116,18 @@ typedef struct {
                                   max_iter steps (stopping rules read x_hist) */
   int32_t schedule;            /* 0: overlap the next step's sort, Gram and
                                   factorisation with the current pass over A
-                                  on a second stream (unconstrained problems;
+                                  on other streams (unconstrained problems;
                                   one extra sketch-only pass per solve);
-                                  1: strictly sequential steps. Both form
-                                  bitwise identical sketches and factors; the
-                                  iterates agree to rounding, since the fused
-                                  pass adds up A^T r in the row order of the
-                                  sketch it forms (S_{t+1} when overlapping,
-                                  S_t otherwise).                             */
+                                  1: strictly sequential steps;
+                                  2: as 0 but two steps ahead, so the
+                                  factorisation has two passes of time (for
+                                  short passes, e.g. float32 data; two
+                                  sketch-only passes per solve).
+                                  All form bitwise identical sketches and
+                                  factors; the iterates agree to rounding,
+                                  since the fused pass adds up A^T r in the
+                                  row order of the sketch it forms (S_{t+1} or
+                                  S_{t+2} when overlapping, S_t otherwise).   */
   int32_t reserved;
 } ihs_options;
 

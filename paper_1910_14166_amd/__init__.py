@@ -227,7 +227,8 @@ def options(m, s=1, kind="countsketch", seed=0, iter0=0, max_iter=10, constraint
     o.gram_in, o.gram_acc = _dt(gram_in), _dt(gram_acc)
     o.qp_max_inner, o.keep_factors = int(qp_max_inner), int(bool(keep_factors))
     o.qp_tol, o.tol = float(qp_tol), float(tol)
-    o.schedule = {"overlap": 0, "sequential": 1}[schedule] if isinstance(schedule, str) \
+    o.schedule = {"overlap": 0, "sequential": 1, "overlap2": 2}[schedule] \
+        if isinstance(schedule, str) \
         else int(schedule)
     return o
 

@@ -359,9 +359,14 @@ struct SolveBuffers {
   void* SA1 = nullptr;
   double* Lf1 = nullptr;
   double* work1 = nullptr;
+  // third set, when the overlapped schedule looks two steps ahead
+  void* SA2 = nullptr;
+  double* Lf2 = nullptr;
+  double* work2 = nullptr;
   DeviceStatus* side_status = nullptr;
   double* Hinv0 = nullptr;   // explicit inverses of the overlapped schedule
   double* Hinv1 = nullptr;
+  double* Hinv2 = nullptr;
   double* Linv = nullptr;    // triangular-inverse scratch of the second stream
   double* dx = nullptr;
 };
@@ -390,9 +395,16 @@ size_t carve_solve(Carver& c, const Layout& L, const ihs_options* o, SolveBuffer
   S.Lf1 = c.take<double>((size_t)(L.batch * L.d * L.d));
   S.work1 = c.take<double>((size_t)L.batch * qp_work_doubles(L.d, o->constraint));
   S.side_status = c.take<DeviceStatus>(1);
+  const bool ahead2 = o->schedule == 2 && o->constraint == IHS_UNCONSTRAINED;
+  if (ahead2) {
+    S.SA2 = c.take<char>((size_t)(L.batch * m * L.d * dtype_size(gram_in_of(o))));
+    S.Lf2 = c.take<double>((size_t)(L.batch * L.d * L.d));
+    S.work2 = c.take<double>((size_t)L.batch * qp_work_doubles(L.d, o->constraint));
+  }
   if (L.d >= kInverseMinD && o->constraint == IHS_UNCONSTRAINED) {
     S.Hinv0 = c.take<double>((size_t)(L.batch * L.d * L.d));
     S.Hinv1 = c.take<double>((size_t)(L.batch * L.d * L.d));
+    if (ahead2) S.Hinv2 = c.take<double>((size_t)(L.batch * L.d * L.d));
     S.Linv = c.take<double>((size_t)(L.batch * L.d * L.d));
   }
   S.dx = c.take<double>((size_t)(L.batch * L.d));
@@ -449,7 +461,7 @@ ihs_status check_options(const ihs_options* o, bool need_loop) {
   if (need_loop && o->max_iter < 1) return IHS_ERR_INVALID_ARG;
   if (!valid_gram_types(o->gram_in, o->gram_acc)) return IHS_ERR_INVALID_ARG;
   if (o->tol != 0.0 || o->qp_tol < 0.0 || o->qp_max_inner < 0) return IHS_ERR_INVALID_ARG;
-  if (o->schedule != 0 && o->schedule != 1) return IHS_ERR_INVALID_ARG;
+  if (o->schedule < 0 || o->schedule > 2) return IHS_ERR_INVALID_ARG;
   return IHS_OK;
 }
 
@@ -462,13 +474,16 @@ ihs_status read_status(DeviceStatus* dev, DeviceStatus* host, hipStream_t st) {
 
 // The overlapped schedule of the IHS loop (unconstrained problems). Step t
 // needs the factor of H_t = (S_t A)^T (S_t A) and g(x^t); since S_t does not
-// depend on x, the pass that forms g(x^t) also forms S_{t+1} A, and a second
-// stream sorts rows for S_{t+2}, forms H_{t+1}, factors it and (for wider
-// problems) inverts it while the main stream runs the next pass over A, so
-// the step itself only applies H_t^{-1} to g. A sketch-only pass first forms
-// S_0 A.
+// depend on x, the pass that forms g(x^t) also forms S_{t+LA} A (LA = 1, or 2
+// for schedule 2), a sorter stream sorts rows for the sketch after that, and
+// a side stream forms H_{t+LA}, factors it and (for wider problems) inverts
+// it during the next LA passes, so the step itself only applies H_t^{-1} to
+// g. LA sketch-only passes first form S_0 A .. S_{LA-1} A. Looking two steps
+// ahead gives the side stream two passes of time, for passes that are short
+// against the factorisation (float32 data), at the price of one more
+// sketch-only pass.
 // Sketches and factors are bitwise those of the sequential loop; g(x^t) is
-// summed in the row order of S_{t+1} instead of S_t, and H_t^{-1} g is a
+// summed in the row order of S_{t+LA} instead of S_t, and H_t^{-1} g is a
 // product with the explicit inverse, so iterates agree with the sequential
 // loop to rounding.
 ihs_status solve_overlap(const ihs_matrix* A, const Layout& L, const ihs_options* opt,
@@ -498,13 +513,26 @@ ihs_status solve_overlap(const ihs_matrix* A, const Layout& L, const ihs_options
     }
     return P;
   };
-  auto sa_buf = [&](int64_t k) { return (k % 2) ? S.SA1 : S.SA; };
-  auto l_buf = [&](int64_t k) {
-    return factors ? factors + k * L.batch * d * d : ((k % 2) ? S.Lf1 : S.Lf);
+  // LA: how many steps ahead the passes form sketches; slots k % (LA + 1)
+  const int LA = opt->schedule == 2 ? 2 : 1;
+  const int NS = LA + 1;
+  auto sa_buf = [&](int64_t k) {
+    const int64_t q = k % NS;
+    return q == 0 ? S.SA : (q == 1 ? S.SA1 : S.SA2);
   };
-  auto w_buf = [&](int64_t k) { return (k % 2) ? S.work1 : S.work; };
+  auto l_buf = [&](int64_t k) {
+    const int64_t q = k % NS;
+    return factors ? factors + k * L.batch * d * d : (q == 0 ? S.Lf : (q == 1 ? S.Lf1 : S.Lf2));
+  };
+  auto w_buf = [&](int64_t k) {
+    const int64_t q = k % NS;
+    return q == 0 ? S.work : (q == 1 ? S.work1 : S.work2);
+  };
   const bool use_inv = d >= kInverseMinD;
-  auto hinv_buf = [&](int64_t k) { return (k % 2) ? S.Hinv1 : S.Hinv0; };
+  auto hinv_buf = [&](int64_t k) {
+    const int64_t q = k % NS;
+    return q == 0 ? S.Hinv0 : (q == 1 ? S.Hinv1 : S.Hinv2);
+  };
   auto factor = [&](int64_t k) -> bool {  // side stream: H_k, its factor (and inverse)
     if (!ck(launch_gram(sa_buf(k), opt->gram_in, m, d, d, L.batch, opt->gram_acc, S.H,
                         S.gram_part, side)))
@@ -517,42 +545,54 @@ ihs_status solve_overlap(const ihs_matrix* A, const Layout& L, const ihs_options
                                   hinv_buf(k), S.Linv, S.side_status, side));
   };
 
-  // prologue: sort S_0 and S_1, sketch-only pass for S_0 A, factor H_0
-  if (!ck(launch_sort(plan_for(0), sorter)) || !ck(hipEventRecord(evSort.at(0), sorter)))
-    return IHS_ERR_HIP;
-  if (!ck(launch_sort(plan_for(1), sorter)) || !ck(hipEventRecord(evSort.at(1), sorter)))
-    return IHS_ERR_HIP;
-  if (!ck(hipStreamWaitEvent(stream, evSort.at(0), 0))) return IHS_ERR_HIP;
-  ihs_status s = run_gather(A, &opt->sketch, B, plan_for(0), sa_buf(0), opt->gram_in, d,
-                            nullptr, nullptr, nullptr, stream);
-  if (s != IHS_OK) return s;
-  if (!ck(hipEventRecord(evPass.at(-1), stream)) || !ck(hipStreamWaitEvent(side, evPass.at(-1), 0)))
-    return IHS_ERR_HIP;
-  if (!factor(0) || !ck(hipEventRecord(evChol.at(0), side))) return IHS_ERR_HIP;
+  // prologue: sketch-only passes for S_0 A .. S_{LA-1} A with the factors of
+  // H_0 .. H_{LA-1}, and the sorts of S_0 .. S_LA. The sorted rows live in two
+  // buffer sets (k % 2), so S_k is sorted only after the pass that read
+  // S_{k-2}'s rows has run.
+  for (int k = 0; k < 2; ++k)
+    if (!ck(launch_sort(plan_for(k), sorter)) || !ck(hipEventRecord(evSort.at(k), sorter)))
+      return IHS_ERR_HIP;
+  ihs_status s = IHS_OK;
+  for (int k = 0; k < LA; ++k) {
+    if (!ck(hipStreamWaitEvent(stream, evSort.at(k), 0))) return IHS_ERR_HIP;
+    s = run_gather(A, &opt->sketch, B, plan_for(k), sa_buf(k), opt->gram_in, d, nullptr,
+                   nullptr, nullptr, stream);
+    if (s != IHS_OK) return s;
+    if (!ck(hipEventRecord(evPass.at(k - LA), stream)) ||
+        !ck(hipStreamWaitEvent(side, evPass.at(k - LA), 0)))
+      return IHS_ERR_HIP;
+    if (k < N && (!factor(k) || !ck(hipEventRecord(evChol.at(k), side)))) return IHS_ERR_HIP;
+    if (k + 2 <= LA) {
+      if (!ck(hipStreamWaitEvent(sorter, evPass.at(k - LA), 0)) ||
+          !ck(launch_sort(plan_for(k + 2), sorter)) ||
+          !ck(hipEventRecord(evSort.at(k + 2), sorter)))
+        return IHS_ERR_HIP;
+    }
+  }
 
   for (int32_t t = 0; t < N; ++t) {
-    // main: pass P_t forms g(x^t) and S_{t+1} A
-    if (!ck(hipStreamWaitEvent(stream, evSort.at(t + 1), 0))) return IHS_ERR_HIP;
-    s = run_gather(A, &opt->sketch, B, plan_for(t + 1), sa_buf(t + 1), opt->gram_in, d, b, x,
+    // main: pass P_t forms g(x^t) and S_{t+LA} A
+    if (!ck(hipStreamWaitEvent(stream, evSort.at(t + LA), 0))) return IHS_ERR_HIP;
+    s = run_gather(A, &opt->sketch, B, plan_for(t + LA), sa_buf(t + LA), opt->gram_in, d, b, x,
                    nullptr, stream);
     if (s != IHS_OK) return s;
     if (!ck(hipEventRecord(evPass.at(t), stream))) return IHS_ERR_HIP;
     if (!ck(launch_reduce_partials(B.gpart, B.fpart, L.batch, pass_parts(A, &opt->sketch, L.batch),
                                    B.probs, d, B.g, B.f, B.status, t, B.red, stream)))
       return IHS_ERR_HIP;
-    // sorter: rows for S_{t+2}, once P_t is done (its scattered writes would
-    // slow the pass if they ran beside it); it shares the gap between passes
-    // with the tail of the side stream and the update of x
+    // sorter: rows for S_{t+LA+1}, once P_t is done (its scattered writes
+    // would slow the pass if they ran beside it); it shares the gap between
+    // passes with the tail of the side stream and the update of x
     if (t + 2 <= N) {
       if (!ck(hipStreamWaitEvent(sorter, evPass.at(t), 0)) ||
-          !ck(launch_sort(plan_for(t + 2), sorter)) ||
-          !ck(hipEventRecord(evSort.at(t + 2), sorter)))
+          !ck(launch_sort(plan_for(t + LA + 1), sorter)) ||
+          !ck(hipEventRecord(evSort.at(t + LA + 1), sorter)))
         return IHS_ERR_HIP;
     }
-    // side: H_{t+1} and its factor, during P_{t+1}
+    // side: H_{t+LA} and its factor, during the next LA passes
     if (!ck(hipStreamWaitEvent(side, evPass.at(t), 0))) return IHS_ERR_HIP;
-    if (t + 1 < N) {
-      if (!factor(t + 1) || !ck(hipEventRecord(evChol.at(t + 1), side))) return IHS_ERR_HIP;
+    if (t + LA < N) {
+      if (!factor(t + LA) || !ck(hipEventRecord(evChol.at(t + LA), side))) return IHS_ERR_HIP;
     }
     // main: x^{t+1} = x^t + H_t^{-1} g(x^t)
     if (!ck(hipStreamWaitEvent(stream, evChol.at(t), 0))) return IHS_ERR_HIP;
@@ -787,7 +827,7 @@ ihs_status ihs_solve(const ihs_matrix* A, const double* b, const ihs_options* op
   carve_solve(c, L, opt, S);
   PassBuffers& B = S.pass;
   if ((s = upload_probs(L, B, stream)) != IHS_OK) return s;
-  if (opt->schedule == 0 && opt->constraint == IHS_UNCONSTRAINED && opt->max_iter >= 2)
+  if (opt->schedule != 1 && opt->constraint == IHS_UNCONSTRAINED && opt->max_iter >= 2)
     return solve_overlap(A, L, opt, S, b, x, x_hist, factors, rep, stream);
   const int64_t d = A->d, m = opt->sketch.m;
   const int64_t bd = (int64_t)L.batch * d;

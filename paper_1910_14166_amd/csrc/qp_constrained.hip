@@ -349,7 +349,9 @@ __global__ __launch_bounds__(kQpThreads) void k_qp_l1(
     const double sig = red[3] + 4096.0 * red[4];
     stable = (sig == sig_prev) ? stable + 1 : 0;
     sig_prev = sig;
-    if (conv || stable == kPolishEvery) {
+    // polish when the support has settled, at convergence, and once at the
+    // start when the warm start's support fits the LDS path
+    if (conv || stable == kPolishEvery || (it == 0 && red[4] * red[4] <= (double)lds_mcap)) {
       stable = 0;
       const int64_t nsz = (int64_t)red[4];
       double* M = (nsz * nsz <= lds_mcap) ? Mlds : Lscratch + (int64_t)p * d * d;
@@ -384,6 +386,11 @@ __global__ __launch_bounds__(256) void k_form_c(const double* __restrict__ H, in
   for (int64_t k = lane; k < d; k += 64) s = fma(hr[k], xp[k], s);
   s = wave_sum(s);
   if (lane == 0) c[(int64_t)p * d + i] = s + g[(int64_t)p * d + i];
+}
+
+__global__ void k_fill_zero(double* v, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) v[i] = 0.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -426,10 +433,21 @@ __global__ __launch_bounds__(256) void k_trs_inside(const double* __restrict__ x
   if (tid == 0) trs[4 * p + 1] = 2.0;
 }
 
-// out = M v per problem (M symmetric, one wavefront per row), for problems
-// still iterating.
+// v = g - mu x^t per problem: with it x(mu) = x^t + (H + mu I)^{-1} v, the
+// same point as (H + mu I)^{-1} (H x^t + g) without forming H x^t.
+__global__ void k_trs_rhs(const double* __restrict__ g, const double* __restrict__ x,
+                          const double* __restrict__ trs, int64_t d, int32_t batch, double* v) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)batch * d) return;
+  const int p = (int)(e / d);
+  v[e] = fma(-trs[4 * p], x[e], g[e]);
+}
+
+// out = base + M v per problem (M symmetric, one wavefront per row; base
+// nullable), for problems still iterating.
 __global__ __launch_bounds__(256) void k_trs_symv(const double* __restrict__ M, int64_t d,
-                                                  const double* __restrict__ v, double* out,
+                                                  const double* __restrict__ v,
+                                                  const double* __restrict__ base, double* out,
                                                   const double* __restrict__ trs,
                                                   const DeviceStatus* st) {
   const int p = blockIdx.y;
@@ -442,7 +460,7 @@ __global__ __launch_bounds__(256) void k_trs_symv(const double* __restrict__ M, 
   double s = 0.0;
   for (int64_t k = lane; k < d; k += 64) s = fma(mr[k], vp[k], s);
   s = wave_sum(s);
-  if (lane == 0) out[(int64_t)p * d + i] = s;
+  if (lane == 0) out[(int64_t)p * d + i] = base ? base[(int64_t)p * d + i] + s : s;
 }
 
 // Given x = x(mu) and z = (H + mu I)^{-1} x, applies the Newton step
@@ -450,7 +468,9 @@ __global__ __launch_bounds__(256) void k_trs_symv(const double* __restrict__ M, 
 // | ||x|| - r | <= tol r the problem takes that one more step (phase 1) and
 // accepts the next x, which the quadratic rate puts at rounding level. From
 // a warm start above the root, the first step lands below it (the tangent of
-// a concave function lies above it) and the rest rise monotonically.
+// a concave function lies above it) and the rest rise monotonically; at
+// mu = 0 a point inside the ball is the unconstrained minimiser and is
+// accepted as it is.
 __global__ __launch_bounds__(256) void k_trs_update(const double* __restrict__ xk,
                                                     const double* __restrict__ zk, int64_t d,
                                                     double r, double tol, double* trs,
@@ -471,7 +491,8 @@ __global__ __launch_bounds__(256) void k_trs_update(const double* __restrict__ x
   const double nx2 = block256_sum(sx, red);
   const double q = block256_sum(sq, red);
   const double nx = sqrt(nx2);
-  if (trs[4 * p + 1] == 1.0) {
+  // one last step taken, or the unconstrained minimiser (mu = 0) in the ball
+  if (trs[4 * p + 1] == 1.0 || (trs[4 * p] == 0.0 && nx <= r)) {
     for (int64_t i = tid; i < d; i += 256) xout[(int64_t)p * d + i] = xp[i];
     if (tid == 0) trs[4 * p + 1] = 2.0;
     return;
@@ -521,16 +542,18 @@ hipError_t launch_qp_constrained(const QpArgs& a, hipStream_t st) {
   double* xunc = cbuf + (int64_t)B * d;
   double* xk = xunc + (int64_t)B * d;
   double* zk = xk + (int64_t)B * d;
+  double* zero = zk + (int64_t)B * d;
   double* trs = zk + (int64_t)B * 2 * d;
   double* hinv = trs + (int64_t)B * 8;
   double* linv = hinv + (int64_t)B * d * d;
-  hipLaunchKernelGGL(k_form_c, dim3((unsigned)((d + 3) / 4), B), dim3(256), 0, st, a.H, d, a.x,
-                     a.g, cbuf);
-  hipError_t e = launch_cholesky(a.H, a.L, d, B, a.status, a.iter, 0.0, scratch, st);
-  if (e != hipSuccess) return e;
-  e = launch_chol_solve_update(a.L, rdiag, d, B, a.g, a.x, xunc, a.status, st);
-  if (e != hipSuccess) return e;
+  hipError_t e;
   if (a.constraint == 1) {
+    hipLaunchKernelGGL(k_form_c, dim3((unsigned)((d + 3) / 4), B), dim3(256), 0, st, a.H, d,
+                       a.x, a.g, cbuf);
+    if ((e = launch_cholesky(a.H, a.L, d, B, a.status, a.iter, 0.0, scratch, st)) != hipSuccess)
+      return e;
+    e = launch_chol_solve_update(a.L, rdiag, d, B, a.g, a.x, xunc, a.status, st);
+    if (e != hipSuccess) return e;
     const int32_t max_iter = a.max_inner > 0 ? a.max_inner : 5000;
     const double tol = a.tol > 0 ? a.tol : 1e-15;
     const size_t fixed = (size_t)(3 * d + 2 * kPolishMax) * sizeof(double);
@@ -540,25 +563,45 @@ hipError_t launch_qp_constrained(const QpArgs& a, hipStream_t st) {
                        a.iter);
     return hipGetLastError();
   }
+  // l2 ball. A cold start (mu = 0) first takes the unconstrained step
+  // x^t + H^{-1} g, the answer when it lies in the ball, and the Newton step
+  // from it; a warm start begins at the previous step's shift.
   const int32_t newton = a.max_inner > 0 ? a.max_inner : 30;
   const double tol = a.tol > 0 ? a.tol : 1e-10;
+  const int64_t bd = (int64_t)B * d;
+  const dim3 rows_grid((unsigned)((d + 3) / 4), B);
   hipLaunchKernelGGL(k_trs_init, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, st, trs, B,
                      a.warm);
-  hipLaunchKernelGGL(k_trs_inside, dim3(B), dim3(256), 0, st, xunc, d, a.radius, trs, a.x_out,
-                     a.status);
-  const dim3 rows_grid((unsigned)((d + 3) / 4), B);
-  for (int32_t k = 0; k < newton; ++k) {
-    e = launch_cholesky(a.H, a.L, d, B, a.status, a.iter, 0.0, scratch, st, trs);
+  if (!a.warm) {
+    if ((e = launch_cholesky(a.H, a.L, d, B, a.status, a.iter, 0.0, scratch, st)) != hipSuccess)
+      return e;
+    e = launch_chol_solve_update(a.L, rdiag, d, B, a.g, a.x, xunc, a.status, st);
     if (e != hipSuccess) return e;
-    e = launch_chol_inverse(a.L, rdiag, d, B, hinv, linv, a.status, st, trs);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_trs_symv, rows_grid, dim3(256), 0, st, hinv, d, cbuf, xk, trs,
+    hipLaunchKernelGGL(k_trs_inside, dim3(B), dim3(256), 0, st, xunc, d, a.radius, trs, a.x_out,
                        a.status);
-    hipLaunchKernelGGL(k_trs_symv, rows_grid, dim3(256), 0, st, hinv, d, xk, zk, trs, a.status);
+    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((bd + 255) / 256)), dim3(256), 0, st, zero,
+                       bd);
+    e = launch_chol_solve_update(a.L, rdiag, d, B, xunc, zero, zk, a.status, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_trs_update, dim3(B), dim3(256), 0, st, xunc, zk, d, a.radius, tol, trs,
+                       a.x_out, a.status);
+  }
+  for (int32_t k = 0; k < newton; ++k) {
+    if ((e = launch_cholesky(a.H, a.L, d, B, a.status, a.iter, 0.0, scratch, st, trs)) !=
+        hipSuccess)
+      return e;
+    if ((e = launch_chol_inverse(a.L, rdiag, d, B, hinv, linv, a.status, st, trs)) != hipSuccess)
+      return e;
+    hipLaunchKernelGGL(k_trs_rhs, dim3((unsigned)((bd + 255) / 256)), dim3(256), 0, st, a.g, a.x,
+                       trs, d, B, cbuf);
+    hipLaunchKernelGGL(k_trs_symv, rows_grid, dim3(256), 0, st, hinv, d, cbuf, a.x, xk, trs,
+                       a.status);
+    hipLaunchKernelGGL(k_trs_symv, rows_grid, dim3(256), 0, st, hinv, d, xk, nullptr, zk, trs,
+                       a.status);
     hipLaunchKernelGGL(k_trs_update, dim3(B), dim3(256), 0, st, xk, zk, d, a.radius, tol, trs,
                        a.x_out, a.status);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (k >= 1 && trs_all_done(trs, a.status, B, st)) break;
+    if (trs_all_done(trs, a.status, B, st)) break;
   }
   hipLaunchKernelGGL(k_trs_finish, dim3(B), dim3(256), 0, st, trs, d, a.x, a.x_out, a.status,
                      a.iter);

@@ -316,30 +316,29 @@ hipError_t launch_sort(const SketchPlan& P, hipStream_t st) {
 // Dense bucket gather, optionally fused with r = b - A x, g = A^T r, f.
 // Lane l owns columns c*64*VEC + l*VEC + v (c < NCH, v < VEC).
 // ---------------------------------------------------------------------------
+// VEC consecutive elements of a row in one load, kept in the row's own
+// type until use (so float rows take half the registers).
 template <typename TA, int VEC>
-struct VecLoad;
-template <>
-struct VecLoad<double, 1> {
-  static __device__ __forceinline__ void ld(const double* p, double* o) { o[0] = *p; }
-};
-template <>
-struct VecLoad<double, 2> {
-  static __device__ __forceinline__ void ld(const double* p, double* o) {
-    const double2 v = *reinterpret_cast<const double2*>(p);
-    o[0] = v.x;
-    o[1] = v.y;
-  }
-};
-template <>
-struct VecLoad<float, 1> {
-  static __device__ __forceinline__ void ld(const float* p, double* o) { o[0] = (double)*p; }
-};
-template <>
-struct VecLoad<float, 2> {
-  static __device__ __forceinline__ void ld(const float* p, double* o) {
-    const float2 v = *reinterpret_cast<const float2*>(p);
-    o[0] = (double)v.x;
-    o[1] = (double)v.y;
+struct VecLoad {
+  static __device__ __forceinline__ void ld(const TA* p, TA* o) {
+    if constexpr (VEC == 1) {
+      o[0] = *p;
+    } else if constexpr (sizeof(TA) == 8 && VEC == 2) {
+      const double2 v = *reinterpret_cast<const double2*>(p);
+      o[0] = v.x;
+      o[1] = v.y;
+    } else if constexpr (sizeof(TA) == 4 && VEC == 2) {
+      const float2 v = *reinterpret_cast<const float2*>(p);
+      o[0] = v.x;
+      o[1] = v.y;
+    } else {
+      static_assert(sizeof(TA) == 4 && VEC == 4, "16-byte loads of floats");
+      const float4 v = *reinterpret_cast<const float4*>(p);
+      o[0] = v.x;
+      o[1] = v.y;
+      o[2] = v.z;
+      o[3] = v.w;
+    }
   }
 };
 
@@ -483,7 +482,7 @@ __global__ __launch_bounds__(256, (BPW > 1 ? 3 : (NCH <= 4 ? 4 : 2))) void k_gat
       double bv = 0.0;
       if (grad && lane < cnt) bv = G.b ? G.b[pe & 0x7FFFFFFFu] : 0.0;
       for (int j = 0; j < cnt; j += U) {
-        double val[U][NCH][VEC];
+        TA val[U][NCH][VEC];
         uint32_t ent[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -498,7 +497,7 @@ __global__ __launch_bounds__(256, (BPW > 1 ? 3 : (NCH <= 4 ? 4 : 2))) void k_gat
               VecLoad<TA, VEC>::ld(rp + col, val[u][c]);
             } else {
 #pragma unroll
-              for (int v = 0; v < VEC; ++v) val[u][c][v] = 0.0;
+              for (int v = 0; v < VEC; ++v) val[u][c][v] = TA(0);
             }
           }
         }
@@ -510,7 +509,7 @@ __global__ __launch_bounds__(256, (BPW > 1 ? 3 : (NCH <= 4 ? 4 : 2))) void k_gat
 #pragma unroll
             for (int c = 0; c < NCH; ++c)
 #pragma unroll
-              for (int v = 0; v < VEC; ++v) s = fma(val[u][c][v], xr[c][v], s);
+              for (int v = 0; v < VEC; ++v) s = fma((double)val[u][c][v], xr[c][v], s);
             dot[u] = s;
           }
           const double red = multi_row_sum<U>(dot, lane);
@@ -522,7 +521,8 @@ __global__ __launch_bounds__(256, (BPW > 1 ? 3 : (NCH <= 4 ? 4 : 2))) void k_gat
 #pragma unroll
               for (int c = 0; c < NCH; ++c)
 #pragma unroll
-                for (int v = 0; v < VEC; ++v) ga[c][v] = fma(ri, val[u][c][v], ga[c][v]);
+                for (int v = 0; v < VEC; ++v)
+                  ga[c][v] = fma(ri, (double)val[u][c][v], ga[c][v]);
               if (G.r_out != nullptr && lane == 0) G.r_out[ent[u] & 0x7FFFFFFFu] = ri;
             }
           }
@@ -535,8 +535,10 @@ __global__ __launch_bounds__(256, (BPW > 1 ? 3 : (NCH <= 4 ? 4 : 2))) void k_gat
 #pragma unroll
               for (int c = 0; c < NCH; ++c)
 #pragma unroll
-                for (int v = 0; v < VEC; ++v)
-                  acc[c][v] = neg ? (acc[c][v] - val[u][c][v]) : (acc[c][v] + val[u][c][v]);
+                for (int v = 0; v < VEC; ++v) {
+                  const double a = (double)val[u][c][v];
+                  acc[c][v] = neg ? (acc[c][v] - a) : (acc[c][v] + a);
+                }
             }
           }
         }
@@ -574,23 +576,26 @@ int32_t gather_rows_per_wave(int64_t m, int32_t batch, int64_t d) {
 template <typename TA, int VEC, int NCH, bool GRAD, bool IDENT>
 static hipError_t gather_inst(const SketchPlan& P, const GatherArgs& G, int32_t total_seg,
                               int32_t seg_rows, hipStream_t st) {
+  // NE: chunks of 16 bytes per lane that a row occupies once converted
+  constexpr int NE = VEC == 4 ? 2 * NCH : NCH;
+  constexpr int UF = 1;
   if (IDENT) {
     // rows in flight per wavefront: enough with 16 wavefronts per CU, while the
     // register budget keeps 4 wavefronts per SIMD
-    constexpr int U = NCH == 1 ? 8 : (NCH == 2 ? 4 : 2);
+    constexpr int U = std::min(8, UF * (NE == 1 ? 8 : (NE == 2 ? 4 : 2)));
     const unsigned blocks = (unsigned)((total_seg + 3) / 4);
     if (blocks == 0) return hipSuccess;
     hipLaunchKernelGGL((k_gather<TA, VEC, NCH, U, 1, GRAD, IDENT>), dim3(blocks), dim3(256), 0,
                        st, P, G, total_seg, seg_rows);
   } else if (gather_rows_per_wave(P.m, P.batch, G.d) == 2) {
     // half the wavefronts, twice the rows in flight each
-    constexpr int U = NCH == 1 ? 8 : (NCH <= 4 ? 4 : 2);
+    constexpr int U = std::min(8, UF * (NE == 1 ? 8 : (NE <= 4 ? 4 : 2)));
     const int64_t waves = (P.m + 1) / 2;
     hipLaunchKernelGGL((k_gather<TA, VEC, NCH, U, 2, GRAD, IDENT>),
                        dim3((unsigned)((waves + 3) / 4), P.batch), dim3(256), 0, st, P, G,
                        total_seg, seg_rows);
   } else {
-    constexpr int U = NCH == 1 ? 8 : (NCH == 2 ? 4 : 2);
+    constexpr int U = std::min(8, UF * (NE == 1 ? 8 : (NE == 2 ? 4 : 2)));
     hipLaunchKernelGGL((k_gather<TA, VEC, NCH, U, 1, GRAD, IDENT>),
                        dim3((unsigned)((P.m + 3) / 4), P.batch), dim3(256), 0, st, P, G,
                        total_seg, seg_rows);
@@ -603,23 +608,36 @@ static hipError_t gather_nch(const SketchPlan& P, const GatherArgs& G, int32_t t
                              hipStream_t st) {
   const int64_t span = 64 * VEC;
   const int64_t nch = (G.d + span - 1) / span;
+  // at most 1024 columns, i.e. 8 values per lane and row at VEC = 2
   switch (nch) {
     case 1: return gather_inst<TA, VEC, 1, GRAD, IDENT>(P, G, ts, sr, st);
     case 2: return gather_inst<TA, VEC, 2, GRAD, IDENT>(P, G, ts, sr, st);
     case 3: return gather_inst<TA, VEC, 3, GRAD, IDENT>(P, G, ts, sr, st);
     case 4: return gather_inst<TA, VEC, 4, GRAD, IDENT>(P, G, ts, sr, st);
-    case 5: return gather_inst<TA, VEC, 5, GRAD, IDENT>(P, G, ts, sr, st);
-    case 6: return gather_inst<TA, VEC, 6, GRAD, IDENT>(P, G, ts, sr, st);
-    case 7: return gather_inst<TA, VEC, 7, GRAD, IDENT>(P, G, ts, sr, st);
-    case 8: return gather_inst<TA, VEC, 8, GRAD, IDENT>(P, G, ts, sr, st);
-    default: return hipErrorInvalidValue;
+    default: break;
   }
+  if constexpr (VEC <= 2) {
+    switch (nch) {
+      case 5: return gather_inst<TA, VEC, 5, GRAD, IDENT>(P, G, ts, sr, st);
+      case 6: return gather_inst<TA, VEC, 6, GRAD, IDENT>(P, G, ts, sr, st);
+      case 7: return gather_inst<TA, VEC, 7, GRAD, IDENT>(P, G, ts, sr, st);
+      case 8: return gather_inst<TA, VEC, 8, GRAD, IDENT>(P, G, ts, sr, st);
+      default: break;
+    }
+  }
+  return hipErrorInvalidValue;
 }
 
-// Two doubles (or floats) per lane per load when rows allow aligned pairs.
+// 16 bytes per lane per load when rows allow it: pairs of doubles, quads of
+// floats; otherwise pairs of floats or single elements.
 template <typename TA, bool GRAD, bool IDENT>
 static hipError_t gather_vec(const SketchPlan& P, const GatherArgs& G, int32_t ts, int32_t sr,
                              hipStream_t st) {
+  if constexpr (sizeof(TA) == 4) {
+    const bool v4 = (G.d % 4 == 0) && (G.ld % 4 == 0) &&
+                    ((reinterpret_cast<uintptr_t>(G.A) % 16) == 0) && G.d > 128;
+    if (v4) return gather_nch<TA, 4, GRAD, IDENT>(P, G, ts, sr, st);
+  }
   const bool v2 = (G.d % 2 == 0) && (G.ld % 2 == 0) &&
                   ((reinterpret_cast<uintptr_t>(G.A) % (2 * sizeof(TA))) == 0) && G.d > 64;
   if (v2) return gather_nch<TA, 2, GRAD, IDENT>(P, G, ts, sr, st);

@@ -82,6 +82,18 @@ def test_dense_sketch_reduced_outputs_and_f32_input(gpu_lib):
     assert np.array_equal(out, OS.sketch_apply_dense(A32, 4, 1, 128, 1))
 
 
+@pytest.mark.parametrize("n,d", [(3000, 512), (2000, 1000), (5000, 132), (700, 130)])
+def test_dense_sketch_f32_rows_bit_exact(gpu_lib, n, d):
+    """float32 rows: quads of floats per lane when the width allows, pairs or
+    single elements otherwise; the sum is still formed in float64."""
+    P = gpu_lib
+    g = np.random.default_rng(d)
+    A32 = g.standard_normal((n, d)).astype(np.float32)
+    spec = P.SketchSpec(256, 1, seed=12, iter=2)
+    out = host(P.sketch_apply(P.Matrix(dense=dev(A32)), spec))
+    assert np.array_equal(out, OS.sketch_apply_dense(A32, 12, 2, 256, 1))
+
+
 def test_dense_sketch_strided_rows(gpu_lib):
     P = gpu_lib
     g = np.random.default_rng(2)

@@ -242,19 +242,22 @@ def test_overlap_schedule_matches_sequential(gpu_lib, shape):
     offs = None if batch == 1 else np.linspace(0, n, batch + 1).astype(np.int64)
     M = P.Matrix(dense=dev(A), row_offsets=offs)
     out = {}
-    for sched in ("overlap", "sequential"):
+    for sched in ("overlap", "overlap2", "sequential"):
         opts = P.options(m, seed=17, iter0=5, max_iter=7, schedule=sched)
         r = P.solve(M, dev(b), opts, history=True, factors=True)
         out[sched] = (host(r.x), host(r.history), host(r.factors), r.report)
-    a, s = out["overlap"], out["sequential"]
-    # same sketches, so the same factors bit for bit; the gradient is summed in
-    # another row order (and wide problems apply an explicit inverse), so
-    # iterates agree to rounding
-    assert np.array_equal(a[2], s[2])
-    for t in range(7):
-        assert np.allclose(a[1][t], s[1][t], rtol=1e-12, atol=1e-14 * np.abs(s[1][t]).max())
-    assert a[3].status == s[3].status == 0
-    assert abs(a[3].objective - s[3].objective) <= 1e-12 * s[3].objective
+    s = out["sequential"]
+    for sched in ("overlap", "overlap2"):
+        a = out[sched]
+        # same sketches, so the same factors bit for bit; the gradient is summed
+        # in another row order (and wide problems apply an explicit inverse),
+        # so iterates agree to rounding
+        assert np.array_equal(a[2], s[2]), sched
+        for t in range(7):
+            assert np.allclose(a[1][t], s[1][t], rtol=1e-12,
+                               atol=1e-14 * np.abs(s[1][t]).max()), (sched, t)
+        assert a[3].status == s[3].status == 0
+        assert abs(a[3].objective - s[3].objective) <= 1e-12 * s[3].objective
 
 
 def test_overlap_reports_not_pd_step(gpu_lib):
