@@ -239,7 +239,10 @@ __global__ __launch_bounds__(256) void k_chol_init(const double* __restrict__ H,
 // barrier per step); every thread factors the 4 x 4 pivot block itself,
 // forms its row's panel entries L_iJ = A_iJ L_JJ^{-T} and those of the rows
 // its columns stand for, and applies the rank-4 update to its segment.
-// Writes L_kk and 1/L_jj back.
+// Writes L_kk and 1/L_jj back. The steps run as four groups of four with
+// the inner four unrolled, so every register index is a constant, and the
+// block is loaded before the status is read: one memory round trip in all,
+// which matters when a memory-bound pass runs beside this kernel.
 __global__ __launch_bounds__(256) void k_chol_diag(double* L, int64_t d, int64_t kb,
                                                    double* rdiag, DeviceStatus* st,
                                                    int32_t iter, const double* __restrict__ trs) {
@@ -248,9 +251,6 @@ __global__ __launch_bounds__(256) void k_chol_diag(double* L, int64_t d, int64_t
   __shared__ int flag;
   const int p = blockIdx.x;
   const int tid = threadIdx.x;
-  if (tid == 0) flag = (st->code != 0 || trs_skip(trs, p)) ? 1 : 0;
-  __syncthreads();
-  if (flag != 0) return;
   double* W = L + (int64_t)p * d * d;
   const int nb = (int)min((int64_t)kNb, d - kb);
   const int i = tid >> 2, seg = tid & 3, k0 = 16 * seg;
@@ -258,88 +258,95 @@ __global__ __launch_bounds__(256) void k_chol_diag(double* L, int64_t d, int64_t
 #pragma unroll
   for (int q = 0; q < 16; ++q)
     a[q] = (i < nb && k0 + q <= i) ? W[(kb + i) * d + kb + k0 + q] : 0.0;
+  if (tid == 0) flag = (st->code != 0 || trs_skip(trs, p)) ? 1 : 0;
+  __syncthreads();
+  if (flag != 0) return;
   int bad = 0;
+  for (int S = 0; S < 4; ++S) {
 #pragma unroll
-  for (int J = 0; J < kNb / 4; ++J) {
-    const int j0 = 4 * J, jend = j0 + 4;
-    if (j0 >= nb) break;  // uniform
-    double(*Pj)[4] = Pb[J & 1];
-    if (seg == (j0 >> 4)) {
+    for (int JJ = 0; JJ < 4; ++JJ) {
+      const int J = 4 * S + JJ;
+      const int j0 = 4 * J, jend = j0 + 4;
+      if (j0 >= nb) break;  // uniform
+      double(*Pj)[4] = Pb[J & 1];
+      if (seg == S) {
 #pragma unroll
-      for (int c = 0; c < 4; ++c) Pj[i][c] = a[(j0 & 15) + c];
-    }
-    __syncthreads();
-    // the 4 x 4 pivot block, padded with the identity past nb
-    double pv[4][4];
+        for (int c = 0; c < 4; ++c) Pj[i][c] = a[4 * JJ + c];
+      }
+      __syncthreads();
+      // the 4 x 4 pivot block, padded with the identity past nb
+      double pv[4][4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+      for (int r = 0; r < 4; ++r)
 #pragma unroll
-      for (int c = 0; c < 4; ++c)
-        pv[r][c] = (j0 + r < nb) ? Pj[j0 + r][c] : (r == c ? 1.0 : 0.0);
-    const double d0 = pv[0][0];
-    if (!(d0 > 0.0) || !isfinite(d0)) {  // the same pivots in every thread
-      bad = 1;
-      break;
-    }
-    const double l00 = sqrt(d0), r0 = 1.0 / l00;
-    const double l10 = pv[1][0] * r0, l20 = pv[2][0] * r0, l30 = pv[3][0] * r0;
-    const double d1 = fma(-l10, l10, pv[1][1]);
-    if (!(d1 > 0.0) || !isfinite(d1)) {
-      bad = 1;
-      break;
-    }
-    const double l11 = sqrt(d1), r1 = 1.0 / l11;
-    const double l21 = fma(-l20, l10, pv[2][1]) * r1, l31 = fma(-l30, l10, pv[3][1]) * r1;
-    const double d2 = fma(-l21, l21, fma(-l20, l20, pv[2][2]));
-    if (!(d2 > 0.0) || !isfinite(d2)) {
-      bad = 1;
-      break;
-    }
-    const double l22 = sqrt(d2), r2 = 1.0 / l22;
-    const double l32 = fma(-l31, l21, fma(-l30, l20, pv[3][2])) * r2;
-    const double d3 = fma(-l32, l32, fma(-l31, l31, fma(-l30, l30, pv[3][3])));
-    if (!(d3 > 0.0) || !isfinite(d3)) {
-      bad = 1;
-      break;
-    }
-    const double l33 = sqrt(d3), r3 = 1.0 / l33;
-    // z = L_JJ^{-1} u: the panel entries of a row from its four A entries
-    auto panel = [&](const double* u, double (&z)[4]) {
-      z[0] = u[0] * r0;
-      z[1] = fma(-l10, z[0], u[1]) * r1;
-      z[2] = fma(-l21, z[1], fma(-l20, z[0], u[2])) * r2;
-      z[3] = fma(-l32, z[2], fma(-l31, z[1], fma(-l30, z[0], u[3]))) * r3;
-    };
-    if (i >= jend && i < nb) {
-      double zi[4];
-      panel(Pj[i], zi);
+        for (int c = 0; c < 4; ++c)
+          pv[r][c] = (j0 + r < nb) ? Pj[j0 + r][c] : (r == c ? 1.0 : 0.0);
+      const double d0 = pv[0][0];
+      if (!(d0 > 0.0) || !isfinite(d0)) {  // the same pivots in every thread
+        bad = 1;
+        break;
+      }
+      const double l00 = sqrt(d0), r0 = 1.0 / l00;
+      const double l10 = pv[1][0] * r0, l20 = pv[2][0] * r0, l30 = pv[3][0] * r0;
+      const double d1 = fma(-l10, l10, pv[1][1]);
+      if (!(d1 > 0.0) || !isfinite(d1)) {
+        bad = 1;
+        break;
+      }
+      const double l11 = sqrt(d1), r1 = 1.0 / l11;
+      const double l21 = fma(-l20, l10, pv[2][1]) * r1, l31 = fma(-l30, l10, pv[3][1]) * r1;
+      const double d2 = fma(-l21, l21, fma(-l20, l20, pv[2][2]));
+      if (!(d2 > 0.0) || !isfinite(d2)) {
+        bad = 1;
+        break;
+      }
+      const double l22 = sqrt(d2), r2 = 1.0 / l22;
+      const double l32 = fma(-l31, l21, fma(-l30, l20, pv[3][2])) * r2;
+      const double d3 = fma(-l32, l32, fma(-l31, l31, fma(-l30, l30, pv[3][3])));
+      if (!(d3 > 0.0) || !isfinite(d3)) {
+        bad = 1;
+        break;
+      }
+      const double l33 = sqrt(d3), r3 = 1.0 / l33;
+      // z = L_JJ^{-1} u: the panel entries of a row from its four A entries
+      auto panel = [&](const double* u, double (&z)[4]) {
+        z[0] = u[0] * r0;
+        z[1] = fma(-l10, z[0], u[1]) * r1;
+        z[2] = fma(-l21, z[1], fma(-l20, z[0], u[2])) * r2;
+        z[3] = fma(-l32, z[2], fma(-l31, z[1], fma(-l30, z[0], u[3]))) * r3;
+      };
+      if (i >= jend && i < nb) {
+        double zi[4];
+        panel(Pj[i], zi);
 #pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        const int k = k0 + q;
-        if (k >= jend && k <= i) {
-          double zk[4];
-          panel(Pj[k], zk);
-          a[q] = fma(-zi[3], zk[3], fma(-zi[2], zk[2], fma(-zi[1], zk[1], fma(-zi[0], zk[0], a[q]))));
+        for (int q = 0; q < 16; ++q) {
+          const int k = k0 + q;
+          if (k >= jend && k <= i) {
+            double zk[4];
+            panel(Pj[k], zk);
+            a[q] = fma(-zi[3], zk[3], fma(-zi[2], zk[2], fma(-zi[1], zk[1], fma(-zi[0], zk[0], a[q]))));
+          }
         }
-      }
-      if (seg == (j0 >> 4)) {
+        if (seg == S) {
 #pragma unroll
-        for (int c = 0; c < 4; ++c) a[(j0 & 15) + c] = zi[c];
+          for (int c = 0; c < 4; ++c) a[4 * JJ + c] = zi[c];
+        }
+      } else if (i >= j0 && i < jend && i < nb && seg == S) {
+        // row i - j0 of the 4 x 4 factor
+        const int rr = i - j0;
+        a[4 * JJ + 0] = rr == 0 ? l00 : (rr == 1 ? l10 : (rr == 2 ? l20 : l30));
+        a[4 * JJ + 1] = rr == 0 ? 0.0 : (rr == 1 ? l11 : (rr == 2 ? l21 : l31));
+        a[4 * JJ + 2] = rr <= 1 ? 0.0 : (rr == 2 ? l22 : l32);
+        a[4 * JJ + 3] = rr <= 2 ? 0.0 : l33;
       }
-    } else if (i >= j0 && i < jend && i < nb && seg == (j0 >> 4)) {
-      const double lrow[4][4] = {{l00, 0.0, 0.0, 0.0},
-                                 {l10, l11, 0.0, 0.0},
-                                 {l20, l21, l22, 0.0},
-                                 {l30, l31, l32, l33}};
-#pragma unroll
-      for (int c = 0; c < 4; ++c) a[(j0 & 15) + c] = lrow[i - j0][c];
+      if (tid == 0) {
+        rd[j0] = r0;
+        rd[j0 + 1] = r1;
+        rd[j0 + 2] = r2;
+        rd[j0 + 3] = r3;
+      }
     }
-    if (tid == 0) {
-      rd[j0] = r0;
-      rd[j0 + 1] = r1;
-      rd[j0 + 2] = r2;
-      rd[j0 + 3] = r3;
-    }
+    if (bad || 16 * (S + 1) >= nb) break;  // uniform
   }
   __syncthreads();
   if (bad) {
@@ -356,6 +363,8 @@ __global__ __launch_bounds__(256) void k_chol_diag(double* L, int64_t d, int64_t
 // wavefront pass with lanes over the 64 columns; the factored block is staged
 // in LDS and x_c is broadcast from lane c (column-oriented substitution).
 // Four rows are interleaved per wavefront for independent dependency chains.
+// The rows, the block and the pivots are requested together with the status,
+// so the kernel waits for memory once.
 __global__ __launch_bounds__(256) void k_chol_trsm(double* L, int64_t d, int64_t kb,
                                                    const double* __restrict__ rdiag,
                                                    DeviceStatus* st, const double* __restrict__ trs) {
@@ -364,13 +373,7 @@ __global__ __launch_bounds__(256) void k_chol_trsm(double* L, int64_t d, int64_t
   __shared__ int flag;
   const int p = blockIdx.y;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  if (tid == 0) flag = (st->code != 0 || trs_skip(trs, p)) ? 1 : 0;
-  __syncthreads();
-  if (flag != 0) return;
   double* W = L + (int64_t)p * d * d;
-  stage_lower64(D, W, d, kb, kNb);  // below > 0, so the block is full
-  if (tid < kNb) rd[tid] = rdiag[(int64_t)p * d + kb + tid];
-  __syncthreads();
   const int64_t rows0 = kb + kNb;
   const int64_t r_first = rows0 + ((int64_t)blockIdx.x * 4 + wv) * 4;
   double a[4];
@@ -380,6 +383,12 @@ __global__ __launch_bounds__(256) void k_chol_trsm(double* L, int64_t d, int64_t
     ok[u] = r_first + u < d;
     a[u] = ok[u] ? W[(r_first + u) * d + kb + lane] : 0.0;
   }
+  const double rdv = tid < kNb ? rdiag[(int64_t)p * d + kb + tid] : 0.0;
+  if (tid == 0) flag = (st->code != 0 || trs_skip(trs, p)) ? 1 : 0;
+  stage_lower64(D, W, d, kb, kNb);  // below > 0, so the block is full
+  if (tid < kNb) rd[tid] = rdv;
+  __syncthreads();
+  if (flag != 0) return;
   for (int c = 0; c < kNb; ++c) {
     const double lkc = D[lane][c];
     const double rc = rd[c];
@@ -397,11 +406,12 @@ __global__ __launch_bounds__(256) void k_chol_trsm(double* L, int64_t d, int64_t
 
 // Trailing update W[i][j] -= sum_k P[i][k] P[j][k], kb+64 <= j <= i < d, with
 // P = W[:, kb:kb+64]. One wavefront per 16 x 16 lower tile (small register
-// footprint, so these tiles also run beside a memory-bound pass).
+// footprint, so these tiles also run beside a memory-bound pass). All operand
+// loads, the tile's own entries and the status are requested up front: one
+// memory round trip before the MFMA chain.
 __global__ __launch_bounds__(256) void k_chol_update(double* L, int64_t d, int64_t kb,
                                                      int32_t batch, DeviceStatus* st,
                                                      const double* __restrict__ trs) {
-  if (st->code != 0) return;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t t0 = kb + kNb;
   const int64_t T = (d - t0 + 15) / 16;
@@ -409,7 +419,6 @@ __global__ __launch_bounds__(256) void k_chol_update(double* L, int64_t d, int64
   const int64_t w = (int64_t)blockIdx.x * 4 + wv;
   if (w >= ntri * batch) return;
   const int p = (int)(w / ntri);
-  if (trs_skip(trs, p)) return;
   const int64_t t = w - (int64_t)p * ntri;
   int64_t ti = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
   while (ti * (ti + 1) / 2 > t) --ti;
@@ -418,20 +427,30 @@ __global__ __launch_bounds__(256) void k_chol_update(double* L, int64_t d, int64
   double* W = L + (int64_t)p * d * d;
   const int64_t r0 = t0 + ti * 16, c0 = t0 + tj * 16;
   const int r = lane & 15, kk = lane >> 4;
-  f64x4 acc = {0, 0, 0, 0};
   const bool ra = r0 + r < d, rb = c0 + r < d;
+  double av[kNb / 4], bv[kNb / 4];
 #pragma unroll
-  for (int k = 0; k < kNb; k += 4) {
-    const int64_t col = kb + k + kk;
-    const double av = ra ? W[(r0 + r) * d + col] : 0.0;
-    const double bv = rb ? W[(c0 + r) * d + col] : 0.0;
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+  for (int k = 0; k < kNb / 4; ++k) {
+    const int64_t col = kb + 4 * k + kk;
+    av[k] = ra ? W[(r0 + r) * d + col] : 0.0;
+    bv[k] = rb ? W[(c0 + r) * d + col] : 0.0;
   }
   const int col = lane & 15, rq = lane >> 4;
+  double cur[4];
 #pragma unroll
   for (int reg = 0; reg < 4; ++reg) {
     const int64_t ii = r0 + 4 * reg + rq, jj = c0 + col;
-    if (ii < d && jj < d && jj <= ii) W[ii * d + jj] -= acc[reg];
+    cur[reg] = (ii < d && jj < d && jj <= ii) ? W[ii * d + jj] : 0.0;
+  }
+  if (st->code != 0 || trs_skip(trs, p)) return;
+  f64x4 acc = {0, 0, 0, 0};
+#pragma unroll
+  for (int k = 0; k < kNb / 4; ++k)
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[k], bv[k], acc, 0, 0, 0);
+#pragma unroll
+  for (int reg = 0; reg < 4; ++reg) {
+    const int64_t ii = r0 + 4 * reg + rq, jj = c0 + col;
+    if (ii < d && jj < d && jj <= ii) W[ii * d + jj] = cur[reg] - acc[reg];
   }
 }
 
@@ -607,7 +626,8 @@ __device__ __forceinline__ bool inv_skip(const DeviceStatus* st, const double* t
 // 16*(t%4) .. +15, of X (initially I) in registers. At step k row k is
 // final once divided by L_kk; its owners publish it to LDS (two alternating
 // buffers, one barrier per step) and every row below subtracts L_ik times
-// it. 256 threads per diagonal block.
+// it. 256 threads per diagonal block. The block, the thread's pivot
+// reciprocal and the status are requested together (one memory round trip).
 __global__ __launch_bounds__(256) void k_trtri_diag(const double* __restrict__ L,
                                                     const double* __restrict__ rdiag, int64_t d,
                                                     double* Linv, const DeviceStatus* st,
@@ -616,28 +636,24 @@ __global__ __launch_bounds__(256) void k_trtri_diag(const double* __restrict__ L
   __shared__ double R[2][kNb];
   __shared__ int skip;
   const int p = blockIdx.y, tid = threadIdx.x;
-  if (tid == 0) skip = inv_skip(st, trs, p) ? 1 : 0;
-  __syncthreads();
-  if (skip) return;
   const int64_t jb = (int64_t)blockIdx.x * kNb;
   const int nb = (int)min((int64_t)kNb, d - jb);
   const double* Lp = L + (int64_t)p * d * d;
-  const double* rp = rdiag + (int64_t)p * d + jb;
-  stage_lower64(Ls, Lp, d, jb, nb);
   const int i = tid >> 2, seg = tid & 3, c0 = 16 * seg;
+  const double ri = i < nb ? rdiag[(int64_t)p * d + jb + i] : 0.0;
+  if (tid == 0) skip = inv_skip(st, trs, p) ? 1 : 0;
+  stage_lower64(Ls, Lp, d, jb, nb);
   double x[16];
 #pragma unroll
   for (int q = 0; q < 16; ++q) x[q] = (c0 + q == i) ? 1.0 : 0.0;
   __syncthreads();
-#pragma unroll
-  for (int k = 0; k < kNb; ++k) {
-    if (k >= nb) break;  // uniform
+  if (skip) return;
+  for (int k = 0; k < nb; ++k) {
     double* Rk = R[k & 1];
     if (i == k) {
-      const double r = rp[k];
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
-        x[q] *= r;
+        x[q] *= ri;
         Rk[c0 + q] = x[q];
       }
     }
@@ -660,25 +676,32 @@ __global__ __launch_bounds__(256) void k_trtri_diag(const double* __restrict__ L
 // column against bank conflicts.
 typedef double Tile64[kNb][kNb + 1];
 
-// Stages the 64 x 64 blocks at (ra, ca) of the d x d matrix MA and at
-// (rb, cb) of MB into TA and TB (entries at or beyond d read as zero). Each
-// thread issues all 32 coalesced loads before storing, so the pair costs one
-// memory round trip. 256 threads.
-__device__ __forceinline__ void stage64x2(Tile64& TA, const double* __restrict__ MA, int64_t ra,
-                                          int64_t ca, Tile64& TB, const double* __restrict__ MB,
-                                          int64_t rb, int64_t cb, int64_t d) {
-  double va[16], vb[16];
+// A pair of 64 x 64 blocks in flight: every thread holds 16 + 16 entries.
+// load64x2 requests the blocks at (ra, ca) of the d x d matrix MA and at
+// (rb, cb) of MB (entries at or beyond d read as zero, coalesced rows);
+// store64x2 writes them to LDS. Splitting the two lets a kernel fetch the
+// next pair while the MFMAs run on the current one. 256 threads.
+struct Pair64 {
+  double a[16], b[16];
+};
+
+__device__ __forceinline__ void load64x2(Pair64& v, const double* __restrict__ MA, int64_t ra,
+                                         int64_t ca, const double* __restrict__ MB, int64_t rb,
+                                         int64_t cb, int64_t d) {
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
     const int e = threadIdx.x + 256 * q, rr = e >> 6, cc = e & 63;
-    va[q] = (ra + rr < d && ca + cc < d) ? MA[(ra + rr) * d + ca + cc] : 0.0;
-    vb[q] = (rb + rr < d && cb + cc < d) ? MB[(rb + rr) * d + cb + cc] : 0.0;
+    v.a[q] = (ra + rr < d && ca + cc < d) ? MA[(ra + rr) * d + ca + cc] : 0.0;
+    v.b[q] = (rb + rr < d && cb + cc < d) ? MB[(rb + rr) * d + cb + cc] : 0.0;
   }
+}
+
+__device__ __forceinline__ void store64x2(const Pair64& v, Tile64& TA, Tile64& TB) {
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
     const int e = threadIdx.x + 256 * q;
-    TA[e >> 6][e & 63] = va[q];
-    TB[e >> 6][e & 63] = vb[q];
+    TA[e >> 6][e & 63] = v.a[q];
+    TB[e >> 6][e & 63] = v.b[q];
   }
 }
 
@@ -721,38 +744,44 @@ __device__ __forceinline__ void tile_store64(const f64x4 (&acc)[2][2], F f) {
         f(r0 + 16 * ti + 4 * reg + (lane >> 4), c0 + 16 * tj + (lane & 15), acc[ti][tj][reg]);
 }
 
-__global__ __launch_bounds__(256) void k_trtri_level(const double* __restrict__ L, double* Linv,
-                                                     int64_t d, int32_t s,
-                                                     const DeviceStatus* st,
-                                                     const double* __restrict__ trs) {
+// One block of block diagonal s per workgroup. The first operand pair is
+// requested together with the status, later pairs and then the diagonal
+// block Linv_ii one at a time: a small register footprint, so a workgroup
+// fits on a CU beside the bucket gather's waves.
+__global__ __launch_bounds__(256, 3) void k_trtri_level(const double* __restrict__ L,
+                                                        double* Linv, int64_t d, int32_t s,
+                                                        const DeviceStatus* st,
+                                                        const double* __restrict__ trs) {
   __shared__ Tile64 As, Bs;
   __shared__ int skip;
   const int p = blockIdx.y;
-  if (threadIdx.x == 0) skip = inv_skip(st, trs, p) ? 1 : 0;
-  __syncthreads();
-  if (skip) return;
   const int64_t jb = (int64_t)blockIdx.x * kNb, ib = jb + (int64_t)s * kNb;
   const double* Lp = L + (int64_t)p * d * d;
   double* Xp = Linv + (int64_t)p * d * d;
   f64x4 acc[2][2] = {};
   for (int64_t kb = jb; kb < ib; kb += kNb) {  // T = sum_k L_ik Linv_kj
-    stage64x2(As, Lp, ib, kb, Bs, Xp, kb, jb, d);
+    Pair64 nx;
+    load64x2(nx, Lp, ib, kb, Xp, kb, jb, d);
+    if (kb == jb && threadIdx.x == 0) skip = inv_skip(st, trs, p) ? 1 : 0;
+    if (kb > jb) __syncthreads();  // the previous MFMAs are done with As, Bs
+    store64x2(nx, As, Bs);
     __syncthreads();
+    if (skip) return;
     tile_mma64<false>(acc, As, Bs);
-    __syncthreads();
   }
-  tile_store64(acc, [&](int rr, int cc, double v) { Bs[rr][cc] = v; });
   {
-    double v[16];
+    double vd[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
       const int e = threadIdx.x + 256 * q, rr = e >> 6, cc = e & 63;
-      v[q] = (ib + rr < d && ib + cc < d) ? Xp[(ib + rr) * d + ib + cc] : 0.0;
+      vd[q] = (ib + rr < d && ib + cc < d) ? Xp[(ib + rr) * d + ib + cc] : 0.0;
     }
+    __syncthreads();
+    tile_store64(acc, [&](int rr, int cc, double v) { Bs[rr][cc] = v; });
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
       const int e = threadIdx.x + 256 * q;
-      As[e >> 6][e & 63] = v[q];
+      As[e >> 6][e & 63] = vd[q];
     }
   }
   __syncthreads();
@@ -764,15 +793,15 @@ __global__ __launch_bounds__(256) void k_trtri_level(const double* __restrict__ 
   });
 }
 
-__global__ __launch_bounds__(256) void k_lauum(const double* __restrict__ Linv, double* Hinv,
+// H^{-1} block (I, J), I >= J, per workgroup; the first operand pair is
+// requested together with the status, later pairs one at a time (a small
+// register footprint, so a workgroup fits beside the bucket gather's waves).
+__global__ __launch_bounds__(256, 3) void k_lauum(const double* __restrict__ Linv, double* Hinv,
                                                int64_t d, int32_t nblk, const DeviceStatus* st,
                                                const double* __restrict__ trs) {
   __shared__ Tile64 As, Bs;
   __shared__ int skip;
   const int p = blockIdx.y;
-  if (threadIdx.x == 0) skip = inv_skip(st, trs, p) ? 1 : 0;
-  __syncthreads();
-  if (skip) return;
   const int64_t t = blockIdx.x;
   int64_t I = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
   while (I * (I + 1) / 2 > t) --I;
@@ -781,12 +810,17 @@ __global__ __launch_bounds__(256) void k_lauum(const double* __restrict__ Linv, 
   const int64_t Ib = I * kNb, Jb = J * kNb;
   const double* Xp = Linv + (int64_t)p * d * d;
   double* Hp = Hinv + (int64_t)p * d * d;
+  const int64_t kend = (int64_t)nblk * kNb;
   f64x4 acc[2][2] = {};
-  for (int64_t kb = Ib; kb < (int64_t)nblk * kNb; kb += kNb) {  // sum_k Linv_kI^T Linv_kJ
-    stage64x2(As, Xp, kb, Ib, Bs, Xp, kb, Jb, d);
+  for (int64_t kb = Ib; kb < kend; kb += kNb) {  // sum_k Linv_kI^T Linv_kJ
+    Pair64 nx;
+    load64x2(nx, Xp, kb, Ib, Xp, kb, Jb, d);
+    if (kb == Ib && threadIdx.x == 0) skip = inv_skip(st, trs, p) ? 1 : 0;
+    if (kb > Ib) __syncthreads();  // the previous MFMAs are done with As, Bs
+    store64x2(nx, As, Bs);
     __syncthreads();
+    if (skip) return;
     tile_mma64<true>(acc, As, Bs);
-    __syncthreads();
   }
   tile_store64(acc, [&](int rr, int cc, double v) {
     const int64_t row = Ib + rr, col = Jb + cc;
