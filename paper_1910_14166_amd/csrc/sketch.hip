@@ -140,6 +140,11 @@ __global__ __launch_bounds__(256) void k_hash_count(SketchPlan P) {
   }
 }
 
+// The scan steps walk a column of counts (one sketch row, many tiles or
+// chunks); each thread requests kScanBatch entries at once, so a column costs
+// a round trip per kScanBatch entries rather than per entry.
+constexpr int kScanBatch = 16;
+
 // Sort step 2a: per (chunk of tiles, sketch row) totals.
 __global__ __launch_bounds__(256) void k_scan_chunks(SketchPlan P) {
   const int c = blockIdx.x;
@@ -150,7 +155,14 @@ __global__ __launch_bounds__(256) void k_scan_chunks(SketchPlan P) {
   const int t0 = pi.tile0 + (c - pi.chunk0) * P.tiles_per_chunk;
   const int t1 = min(t0 + P.tiles_per_chunk, pi.tile0 + pi.ntiles);
   int32_t sum = 0;
-  for (int t = t0; t < t1; ++t) sum += P.tile_count[(int64_t)t * P.m + b];
+  for (int t = t0; t < t1; t += kScanBatch) {
+    int32_t v[kScanBatch];
+#pragma unroll
+    for (int u = 0; u < kScanBatch; ++u)
+      v[u] = t + u < t1 ? P.tile_count[(int64_t)(t + u) * P.m + b] : 0;
+#pragma unroll
+    for (int u = 0; u < kScanBatch; ++u) sum += v[u];
+  }
   P.chunk_part[(int64_t)c * P.m + b] = sum;
 }
 
@@ -163,22 +175,17 @@ __global__ __launch_bounds__(256) void k_scan_rows(SketchPlan P) {
   if (b >= P.m) return;
   const ProbInfo pi = P.probs[p];
   int32_t run = 0;
-  int c = pi.chunk0;
   const int c1 = pi.chunk0 + pi.nchunks;
-  for (; c + 4 <= c1; c += 4) {
-    int32_t* q0 = P.chunk_part + (int64_t)c * P.m + b;
-    const int32_t v0 = q0[0], v1 = q0[P.m], v2 = q0[2 * P.m], v3 = q0[3 * P.m];
-    q0[0] = run;
-    q0[P.m] = run + v0;
-    q0[2 * P.m] = run + v0 + v1;
-    q0[3 * P.m] = run + v0 + v1 + v2;
-    run += v0 + v1 + v2 + v3;
-  }
-  for (; c < c1; ++c) {
-    int32_t* ptr = P.chunk_part + (int64_t)c * P.m + b;
-    const int32_t v = *ptr;
-    *ptr = run;
-    run += v;
+  for (int c = pi.chunk0; c < c1; c += kScanBatch) {
+    int32_t v[kScanBatch];
+#pragma unroll
+    for (int u = 0; u < kScanBatch; ++u)
+      v[u] = c + u < c1 ? P.chunk_part[(int64_t)(c + u) * P.m + b] : 0;
+#pragma unroll
+    for (int u = 0; u < kScanBatch; ++u) {
+      if (c + u < c1) P.chunk_part[(int64_t)(c + u) * P.m + b] = run;
+      run += v[u];
+    }
   }
   P.bucket_start[(int64_t)p * P.m + b] = run;
 }
@@ -232,56 +239,76 @@ __global__ __launch_bounds__(256) void k_scan_tiles(SketchPlan P) {
   const int t0 = pi.tile0 + (c - pi.chunk0) * P.tiles_per_chunk;
   const int t1 = min(t0 + P.tiles_per_chunk, pi.tile0 + pi.ntiles);
   int32_t run = P.bucket_start[(int64_t)p * P.m + b] + P.chunk_part[(int64_t)c * P.m + b];
-  for (int t = t0; t < t1; ++t) {
-    int32_t* ptr = P.tile_count + (int64_t)t * P.m + b;
-    const int32_t v = *ptr;
-    *ptr = run;
-    run += v;
+  for (int t = t0; t < t1; t += kScanBatch) {
+    int32_t v[kScanBatch];
+#pragma unroll
+    for (int u = 0; u < kScanBatch; ++u)
+      v[u] = t + u < t1 ? P.tile_count[(int64_t)(t + u) * P.m + b] : 0;
+#pragma unroll
+    for (int u = 0; u < kScanBatch; ++u) {
+      if (t + u < t1) P.tile_count[(int64_t)(t + u) * P.m + b] = run;
+      run += v[u];
+    }
   }
 }
 
 // Sort step 3: stable scatter. The tile's rows are taken 256 at a time in
-// ascending order; the four wavefronts take turns, each ranking its lanes
-// among equal keys with one ballot per key bit.
+// ascending order, one block of the SJLT at a time (blocks own disjoint
+// sketch rows, so their order does not matter). Every wavefront ranks its
+// lanes among equal keys with one ballot per key bit; then the four
+// wavefronts take turns to claim positions from the LDS cursors. The keys of
+// the next step are requested before the turns of the current one, so the
+// turns never wait for memory.
+// Workgroups are dispatched to the XCDs round-robin; the scatter hands each
+// XCD a contiguous run of tiles, so consecutive entries of a sketch row's list
+// are written through one L2, which assembles whole lines before they go out.
+constexpr int kXcds = 8;
+
 __global__ __launch_bounds__(256) void k_scatter(SketchPlan P) {
   extern __shared__ int32_t pos[];
-  for (int tile = blockIdx.x; tile < P.total_tiles; tile += gridDim.x) {
-  const int p = find_by_tile(P.probs, P.batch, tile);
-  const ProbInfo pi = P.probs[p];
-  const int64_t lr0 = (int64_t)(tile - pi.tile0) * P.tile_rows;
-  const int64_t nr = min((int64_t)P.tile_rows, pi.rows - lr0);
-  const int32_t* start = P.tile_count + (int64_t)tile * P.m;
-  for (int64_t b = threadIdx.x; b < P.m; b += blockDim.x) pos[b] = start[b];
-  __syncthreads();
   const int wv = threadIdx.x >> 6;
   const uint64_t lt = lanemask_lt();
-  for (int64_t base = 0; base < nr; base += 256) {
-    const int64_t i = base + threadIdx.x;
-    const bool valid = i < nr;
-    const int64_t grow = pi.row0 + lr0 + (valid ? i : 0);
-    for (int w = 0; w < 4; ++w) {
-      if (wv == w) {
-        for (int k = 0; k < P.s; ++k) {
-          const uint32_t kv = valid ? P.keys[grow * P.s + k] : 0u;
-          const uint32_t bkt = kv & 0x7FFFFFFFu;
-          uint64_t peers = __ballot(valid);
-          for (int bit = 0; bit < P.bucket_bits; ++bit) {
-            const bool on = (bkt >> bit) & 1u;
-            const uint64_t bb = __ballot(on);
-            peers &= on ? bb : ~bb;
-          }
-          if (valid) {
-            const int rank = __popcll(peers & lt);
-            const int32_t p0 = pos[bkt];
-            P.perm[p0 + rank] = (uint32_t)grow | (kv & 0x80000000u);
-            if (rank == 0) pos[bkt] = p0 + __popcll(peers);
-          }
-        }
+  const int G = gridDim.x, q = G / kXcds, r = G % kXcds;
+  const int x = blockIdx.x % kXcds, j = blockIdx.x / kXcds;
+  const int first = x * q + min(x, r) + j;  // a bijection of [0, G)
+  for (int tile = first; tile < P.total_tiles; tile += G) {
+    const int p = find_by_tile(P.probs, P.batch, tile);
+    const ProbInfo pi = P.probs[p];
+    const int64_t lr0 = (int64_t)(tile - pi.tile0) * P.tile_rows;
+    const int64_t nr = min((int64_t)P.tile_rows, pi.rows - lr0);
+    const int64_t row0 = pi.row0 + lr0;
+    const int64_t nsteps = ((nr + 255) / 256) * P.s;
+    auto key_at = [&](int64_t step) -> uint32_t {
+      const int64_t i = (step / P.s) * 256 + threadIdx.x;
+      return i < nr ? P.keys[(row0 + i) * P.s + (int)(step % P.s)] : 0u;
+    };
+    uint32_t kv_next = nsteps > 0 ? key_at(0) : 0u;
+    const int32_t* start = P.tile_count + (int64_t)tile * P.m;
+    for (int64_t b = threadIdx.x; b < P.m; b += blockDim.x) pos[b] = start[b];
+    __syncthreads();
+    for (int64_t step = 0; step < nsteps; ++step) {
+      const uint32_t kv = kv_next;
+      if (step + 1 < nsteps) kv_next = key_at(step + 1);
+      const int64_t i = (step / P.s) * 256 + threadIdx.x;
+      const bool valid = i < nr;
+      const uint32_t bkt = kv & 0x7FFFFFFFu;
+      uint64_t peers = __ballot(valid);
+      for (int bit = 0; bit < P.bucket_bits; ++bit) {
+        const bool on = (bkt >> bit) & 1u;
+        const uint64_t bb = __ballot(on);
+        peers &= on ? bb : ~bb;
       }
-      __syncthreads();
+      const int rank = __popcll(peers & lt);
+      for (int w = 0; w < 4; ++w) {
+        if (wv == w && valid) {
+          const int32_t p0 = pos[bkt];
+          P.perm[p0 + rank] = (uint32_t)(row0 + i) | (kv & 0x80000000u);
+          if (rank == 0) pos[bkt] = p0 + __popcll(peers);
+        }
+        __syncthreads();
+      }
     }
-  }
-  __syncthreads();  // pos is reloaded for the next tile
+    __syncthreads();  // pos is reloaded for the next tile
   }
 }
 
@@ -513,6 +540,16 @@ __global__ __launch_bounds__(256, (BPW > 1 ? 3 : (NCH <= 4 ? 4 : 2))) void k_gat
             dot[u] = s;
           }
           const double red = multi_row_sum<U>(dot, lane);
+          if constexpr (sizeof(TA) == 4) {
+            // convert the float rows again below rather than keep their
+            // float64 copies live across the reduction (fewer registers)
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+              for (int c = 0; c < NCH; ++c)
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) asm volatile("" : "+v"(val[u][c][v]));
+          }
 #pragma unroll
           for (int u = 0; u < U; ++u) {
             if (j + u < cnt) {
