@@ -394,8 +394,17 @@ __global__ void k_fill_zero(double* v, int64_t n) {
 }
 
 // ---------------------------------------------------------------------------
+// Largest contraction rho for which a Newton step reuses the held inverse,
+// and the most Richardson sweeps it takes (0.04^13 < 1e-18 at the limit).
+// Twelve sweeps (two mat-vecs each, for x and for z) cost under half of a
+// factorisation and inverse at d = 1024.
+constexpr double kReuseRho = 0.04;
+constexpr int32_t kMaxSweeps = 12;
+
 // l2 ball. State per problem: trs[4p] = mu, trs[4p+1] = phase
-// (0 iterating, 1 one last Newton step, 2 done).
+// (0 iterating, 1 one last Newton step, 2 done), trs[4p+2] = the shift mu0
+// of the held inverse (H + mu0 I)^{-1}, trs[4p+3] = a bound on its 2-norm
+// (infinite while no inverse is held).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double block256_sum(double v, double* red) {
   const int tid = threadIdx.x;
@@ -413,6 +422,8 @@ __global__ void k_trs_init(double* trs, int32_t batch, int32_t warm) {
   if (p >= batch) return;
   trs[4 * p] = warm ? fmax(trs[4 * p], 0.0) : 0.0;
   trs[4 * p + 1] = 0.0;
+  trs[4 * p + 2] = 0.0;
+  trs[4 * p + 3] = INFINITY;
 }
 
 // The unconstrained minimiser inside the ball is the answer.
@@ -503,6 +514,78 @@ __global__ __launch_bounds__(256) void k_trs_update(const double* __restrict__ x
   }
 }
 
+// Row sums of |M| per problem (one wavefront per row), for the norm bound.
+__global__ __launch_bounds__(256) void k_trs_abs_rows(const double* __restrict__ M, int64_t d,
+                                                      const double* __restrict__ trs,
+                                                      double* rows, const DeviceStatus* st) {
+  const int p = blockIdx.y;
+  if (trs[4 * p + 1] >= 2.0 || status_failed_by(st, -1)) return;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * 4 + wv;
+  if (i >= d) return;
+  const double* mr = M + ((int64_t)p * d + i) * d;
+  double s = 0.0;
+  for (int64_t k = lane; k < d; k += 64) s += fabs(mr[k]);
+  s = wave_sum(s);
+  if (lane == 0) rows[(int64_t)p * d + i] = s;
+}
+
+// Records the shift of the inverse just formed and a bound on its 2-norm: the
+// largest absolute row sum (the infinity norm, which bounds the 2-norm of a
+// symmetric matrix), and 1/mu0 when mu0 > 0 (H is positive semidefinite).
+__global__ __launch_bounds__(256) void k_trs_inv_norm(const double* __restrict__ rows, int64_t d,
+                                                      double* trs, const DeviceStatus* st) {
+  __shared__ double red[4];
+  const int p = blockIdx.x, tid = threadIdx.x;
+  if (trs[4 * p + 1] >= 2.0 || status_failed_by(st, -1)) return;
+  double mx = 0.0;
+  for (int64_t i = tid; i < d; i += 256) mx = fmax(mx, rows[(int64_t)p * d + i]);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+  if ((tid & 63) == 0) red[tid >> 6] = mx;
+  __syncthreads();
+  if (tid == 0) {
+    const double mu0 = trs[4 * p];
+    double nrm = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    if (mu0 > 0.0) nrm = fmin(nrm, 1.0 / mu0);
+    trs[4 * p + 2] = mu0;
+    trs[4 * p + 3] = nrm;
+  }
+}
+
+// out = v - (H + mu I) w per problem (one wavefront per row), for problems
+// still iterating: the residual of a Richardson sweep.
+__global__ __launch_bounds__(256) void k_trs_resid(const double* __restrict__ H, int64_t d,
+                                                   const double* __restrict__ w,
+                                                   const double* __restrict__ v, double* out,
+                                                   const double* __restrict__ trs,
+                                                   const DeviceStatus* st) {
+  const int p = blockIdx.y;
+  if (trs[4 * p + 1] >= 2.0 || status_failed_by(st, -1)) return;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * 4 + wv;
+  if (i >= d) return;
+  const double* hr = H + ((int64_t)p * d + i) * d;
+  const double* wp = w + (int64_t)p * d;
+  double s = 0.0;
+  for (int64_t k = lane; k < d; k += 64) s = fma(hr[k], wp[k], s);
+  s = wave_sum(s);
+  if (lane == 0) {
+    const int64_t e = (int64_t)p * d + i;
+    out[e] = v[e] - s - trs[4 * p] * w[e];
+  }
+}
+
+// x = base + w per problem, for problems still iterating.
+__global__ void k_trs_axpy(const double* __restrict__ base, const double* __restrict__ w,
+                           const double* __restrict__ trs, int64_t d, int32_t batch, double* x) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)batch * d) return;
+  const int p = (int)(e / d);
+  if (trs[4 * p + 1] >= 2.0) return;
+  x[e] = base[e] + w[e];
+}
+
 // Problems still iterating after the last Newton step keep x^t and report.
 __global__ void k_trs_finish(const double* trs, int64_t d, const double* x, double* xout,
                              DeviceStatus* st, int32_t iter) {
@@ -513,10 +596,10 @@ __global__ void k_trs_finish(const double* trs, int64_t d, const double* x, doub
 }
 
 // True when every problem has finished its Newton iteration or a failure is
-// recorded. Synchronises the stream.
+// recorded; leaves the shift state in h. Synchronises the stream.
 static bool trs_all_done(const double* trs, const DeviceStatus* status, int32_t batch,
-                         hipStream_t st) {
-  std::vector<double> h((size_t)4 * batch);
+                         hipStream_t st, std::vector<double>& h) {
+  h.assign((size_t)4 * batch, 0.0);
   int32_t code = 0;
   if (hipMemcpyAsync(h.data(), trs, h.size() * sizeof(double), hipMemcpyDeviceToHost, st) !=
           hipSuccess ||
@@ -586,22 +669,74 @@ hipError_t launch_qp_constrained(const QpArgs& a, hipStream_t st) {
     hipLaunchKernelGGL(k_trs_update, dim3(B), dim3(256), 0, st, xunc, zk, d, a.radius, tol, trs,
                        a.x_out, a.status);
   }
+  // Each Newton step needs x(mu) = x^t + (H + mu I)^{-1} (g - mu x^t) and
+  // z = (H + mu I)^{-1} x(mu). It factors H + mu I and forms the inverse,
+  // unless the inverse held from an earlier shift mu0 is close enough: with
+  // rho = |mu - mu0| ||(H + mu0 I)^{-1}|| the preconditioned Richardson
+  // sweep w <- w + (H + mu0 I)^{-1} (v - (H + mu I) w) contracts the error by
+  // rho, and a few sweeps reach rounding level (the last Newton step, whose
+  // shift moves at rounding level, always qualifies).
+  double* wbuf = xunc;  // free once the cold start is done
+  double* rbuf = zero;
+  std::vector<double> h;
+  bool held = false;
+  // out = base + (H + mu I)^{-1} v by S sweeps from (H + mu0 I)^{-1} v (base
+  // nullable; out must differ from v)
+  auto richardson = [&](const double* v, const double* base, double* out, int32_t S) {
+    double* w = base ? wbuf : out;
+    hipLaunchKernelGGL(k_trs_symv, rows_grid, dim3(256), 0, st, hinv, d, v, nullptr, w, trs,
+                       a.status);
+    for (int32_t j = 0; j < S; ++j) {
+      hipLaunchKernelGGL(k_trs_resid, rows_grid, dim3(256), 0, st, a.H, d, w, v, rbuf, trs,
+                         a.status);
+      hipLaunchKernelGGL(k_trs_symv, rows_grid, dim3(256), 0, st, hinv, d, rbuf, w, w, trs,
+                         a.status);
+    }
+    if (base)
+      hipLaunchKernelGGL(k_trs_axpy, dim3((unsigned)((bd + 255) / 256)), dim3(256), 0, st, base, w,
+                         trs, d, B, out);
+  };
   for (int32_t k = 0; k < newton; ++k) {
-    if ((e = launch_cholesky(a.H, a.L, d, B, a.status, a.iter, 0.0, scratch, st, trs)) !=
-        hipSuccess)
-      return e;
-    if ((e = launch_chol_inverse(a.L, rdiag, d, B, hinv, linv, a.status, st, trs)) != hipSuccess)
-      return e;
+    double rho = INFINITY;
+    if (held) {
+      rho = 0.0;
+      for (int32_t p = 0; p < B; ++p)
+        if (h[(size_t)4 * p + 1] < 2.0)
+          rho = std::max(rho, std::fabs(h[(size_t)4 * p] - h[(size_t)4 * p + 2]) *
+                                  h[(size_t)4 * p + 3]);
+    }
+    int32_t sweeps = 0;
+    if (!(rho <= kReuseRho)) {
+      if ((e = launch_cholesky(a.H, a.L, d, B, a.status, a.iter, 0.0, scratch, st, trs)) !=
+          hipSuccess)
+        return e;
+      if ((e = launch_chol_inverse(a.L, rdiag, d, B, hinv, linv, a.status, st, trs)) !=
+          hipSuccess)
+        return e;
+      hipLaunchKernelGGL(k_trs_abs_rows, rows_grid, dim3(256), 0, st, hinv, d, trs, rbuf,
+                         a.status);
+      hipLaunchKernelGGL(k_trs_inv_norm, dim3(B), dim3(256), 0, st, rbuf, d, trs, a.status);
+      held = true;
+    } else {
+      // error after j sweeps <= rho^(j+1) relative to the solution
+      sweeps = 1;
+      while (sweeps < kMaxSweeps && std::pow(rho, sweeps + 1) > 1e-17) ++sweeps;
+    }
     hipLaunchKernelGGL(k_trs_rhs, dim3((unsigned)((bd + 255) / 256)), dim3(256), 0, st, a.g, a.x,
                        trs, d, B, cbuf);
-    hipLaunchKernelGGL(k_trs_symv, rows_grid, dim3(256), 0, st, hinv, d, cbuf, a.x, xk, trs,
-                       a.status);
-    hipLaunchKernelGGL(k_trs_symv, rows_grid, dim3(256), 0, st, hinv, d, xk, nullptr, zk, trs,
-                       a.status);
+    if (sweeps == 0) {
+      hipLaunchKernelGGL(k_trs_symv, rows_grid, dim3(256), 0, st, hinv, d, cbuf, a.x, xk, trs,
+                         a.status);
+      hipLaunchKernelGGL(k_trs_symv, rows_grid, dim3(256), 0, st, hinv, d, xk, nullptr, zk, trs,
+                         a.status);
+    } else {
+      richardson(cbuf, a.x, xk, sweeps);
+      richardson(xk, nullptr, zk, sweeps);
+    }
     hipLaunchKernelGGL(k_trs_update, dim3(B), dim3(256), 0, st, xk, zk, d, a.radius, tol, trs,
                        a.x_out, a.status);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (trs_all_done(trs, a.status, B, st)) break;
+    if (trs_all_done(trs, a.status, B, st, h)) break;
   }
   hipLaunchKernelGGL(k_trs_finish, dim3(B), dim3(256), 0, st, trs, d, a.x, a.x_out, a.status,
                      a.iter);
