@@ -232,46 +232,50 @@ __global__ __launch_bounds__(256) void k_chol_init(const double* __restrict__ H,
   L[idx] = (j <= i) ? H[idx] + (i == j ? shift : 0.0) : 0.0;
 }
 
-// Diagonal block of panel kb: one workgroup per problem factors the 64 x 64
-// block right-looking in steps of four columns. Thread t keeps row t/4,
-// columns 16*(t%4) .. +15, in registers. At each step the threads holding
-// the four columns publish them to LDS (two alternating buffers, so one
-// barrier per step); every thread factors the 4 x 4 pivot block itself,
-// forms its row's panel entries L_iJ = A_iJ L_JJ^{-T} and those of the rows
-// its columns stand for, and applies the rank-4 update to its segment.
-// Writes L_kk and 1/L_jj back. The steps run as four groups of four with
-// the inner four unrolled, so every register index is a constant, and the
-// block is loaded before the status is read: one memory round trip in all,
-// which matters when a memory-bound pass runs beside this kernel.
-__global__ __launch_bounds__(256) void k_chol_diag(double* L, int64_t d, int64_t kb,
-                                                   double* rdiag, DeviceStatus* st,
-                                                   int32_t iter, const double* __restrict__ trs) {
-  __shared__ double Pb[2][kNb][4];
+// Diagonal block of panel kb: one workgroup of 512 threads per problem
+// factors the 64 x 64 block right-looking in steps of four columns. Thread t
+// keeps row t/8, columns 8*(t%8) .. +7, in registers. At each step:
+//  1. the threads holding the four columns publish them to LDS;
+//  2. every thread factors the 4 x 4 pivot block itself and forms its row's
+//     panel entries L_iJ = A_iJ L_JJ^{-T}; the holder of the four columns
+//     keeps them and publishes them;
+//  3. every thread applies the rank-4 update to its entries with the
+//     published panel entries of their columns.
+// The steps run as eight groups of two with the inner two unrolled, so every
+// register index is a constant. Writes L_kk and 1/L_jj back. The block is
+// loaded before the status is read (one memory round trip), and two waves
+// per SIMD of at most 96 registers fit beside the bucket gather.
+constexpr int kDiagThreads = 512;
+
+__global__ __launch_bounds__(kDiagThreads) void k_chol_diag(double* L, int64_t d, int64_t kb,
+                                                            double* rdiag, DeviceStatus* st,
+                                                            int32_t iter,
+                                                            const double* __restrict__ trs) {
+  __shared__ double Pb[kNb][4];  // the step's four columns of every row
+  __shared__ double Zb[kNb][4];  // the step's panel entries of every row
   __shared__ double rd[kNb];
   __shared__ int flag;
   const int p = blockIdx.x;
   const int tid = threadIdx.x;
   double* W = L + (int64_t)p * d * d;
   const int nb = (int)min((int64_t)kNb, d - kb);
-  const int i = tid >> 2, seg = tid & 3, k0 = 16 * seg;
-  double a[16];
+  const int i = tid >> 3, seg = tid & 7, k0 = 8 * seg;
+  double a[8];
 #pragma unroll
-  for (int q = 0; q < 16; ++q)
+  for (int q = 0; q < 8; ++q)
     a[q] = (i < nb && k0 + q <= i) ? W[(kb + i) * d + kb + k0 + q] : 0.0;
   if (tid == 0) flag = (st->code != 0 || trs_skip(trs, p)) ? 1 : 0;
   __syncthreads();
   if (flag != 0) return;
   int bad = 0;
-  for (int S = 0; S < 4; ++S) {
+  for (int S = 0; S < 8 && !bad; ++S) {
 #pragma unroll
-    for (int JJ = 0; JJ < 4; ++JJ) {
-      const int J = 4 * S + JJ;
-      const int j0 = 4 * J, jend = j0 + 4;
+    for (int JJ = 0; JJ < 2; ++JJ) {
+      const int j0 = 8 * S + 4 * JJ, jend = j0 + 4;
       if (j0 >= nb) break;  // uniform
-      double(*Pj)[4] = Pb[J & 1];
       if (seg == S) {
 #pragma unroll
-        for (int c = 0; c < 4; ++c) Pj[i][c] = a[4 * JJ + c];
+        for (int c = 0; c < 4; ++c) Pb[i][c] = a[4 * JJ + c];
       }
       __syncthreads();
       // the 4 x 4 pivot block, padded with the identity past nb
@@ -280,7 +284,7 @@ __global__ __launch_bounds__(256) void k_chol_diag(double* L, int64_t d, int64_t
       for (int r = 0; r < 4; ++r)
 #pragma unroll
         for (int c = 0; c < 4; ++c)
-          pv[r][c] = (j0 + r < nb) ? Pj[j0 + r][c] : (r == c ? 1.0 : 0.0);
+          pv[r][c] = (j0 + r < nb) ? Pb[j0 + r][c] : (r == c ? 1.0 : 0.0);
       const double d0 = pv[0][0];
       if (!(d0 > 0.0) || !isfinite(d0)) {  // the same pivots in every thread
         bad = 1;
@@ -308,28 +312,20 @@ __global__ __launch_bounds__(256) void k_chol_diag(double* L, int64_t d, int64_t
         break;
       }
       const double l33 = sqrt(d3), r3 = 1.0 / l33;
-      // z = L_JJ^{-1} u: the panel entries of a row from its four A entries
-      auto panel = [&](const double* u, double (&z)[4]) {
-        z[0] = u[0] * r0;
-        z[1] = fma(-l10, z[0], u[1]) * r1;
-        z[2] = fma(-l21, z[1], fma(-l20, z[0], u[2])) * r2;
-        z[3] = fma(-l32, z[2], fma(-l31, z[1], fma(-l30, z[0], u[3]))) * r3;
-      };
+      double zi[4] = {0.0, 0.0, 0.0, 0.0};
       if (i >= jend && i < nb) {
-        double zi[4];
-        panel(Pj[i], zi);
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-          const int k = k0 + q;
-          if (k >= jend && k <= i) {
-            double zk[4];
-            panel(Pj[k], zk);
-            a[q] = fma(-zi[3], zk[3], fma(-zi[2], zk[2], fma(-zi[1], zk[1], fma(-zi[0], zk[0], a[q]))));
-          }
-        }
+        // z = L_JJ^{-1} u: the panel entries of row i from its four A entries
+        const double* u = Pb[i];
+        zi[0] = u[0] * r0;
+        zi[1] = fma(-l10, zi[0], u[1]) * r1;
+        zi[2] = fma(-l21, zi[1], fma(-l20, zi[0], u[2])) * r2;
+        zi[3] = fma(-l32, zi[2], fma(-l31, zi[1], fma(-l30, zi[0], u[3]))) * r3;
         if (seg == S) {
 #pragma unroll
-          for (int c = 0; c < 4; ++c) a[4 * JJ + c] = zi[c];
+          for (int c = 0; c < 4; ++c) {
+            a[4 * JJ + c] = zi[c];
+            Zb[i][c] = zi[c];
+          }
         }
       } else if (i >= j0 && i < jend && i < nb && seg == S) {
         // row i - j0 of the 4 x 4 factor
@@ -345,8 +341,18 @@ __global__ __launch_bounds__(256) void k_chol_diag(double* L, int64_t d, int64_t
         rd[j0 + 2] = r2;
         rd[j0 + 3] = r3;
       }
+      __syncthreads();
+      if (i >= jend && i < nb && seg >= S) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int k = k0 + q;
+          if (k >= jend && k <= i) {
+            const double* zk = Zb[k];
+            a[q] = fma(-zi[3], zk[3], fma(-zi[2], zk[2], fma(-zi[1], zk[1], fma(-zi[0], zk[0], a[q]))));
+          }
+        }
+      }
     }
-    if (bad || 16 * (S + 1) >= nb) break;  // uniform
   }
   __syncthreads();
   if (bad) {
@@ -354,7 +360,7 @@ __global__ __launch_bounds__(256) void k_chol_diag(double* L, int64_t d, int64_t
     return;
   }
 #pragma unroll
-  for (int q = 0; q < 16; ++q)
+  for (int q = 0; q < 8; ++q)
     if (i < nb && k0 + q <= i) W[(kb + i) * d + kb + k0 + q] = a[q];
   if (tid < nb) rdiag[(int64_t)p * d + kb + tid] = rd[tid];
 }
@@ -467,8 +473,8 @@ hipError_t launch_cholesky(const double* H, double* L, int64_t d, int32_t batch,
   hipLaunchKernelGGL(k_chol_init, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, H, L, d,
                      batch, shift, trs);
   for (int64_t kb = 0; kb < d; kb += kNb) {
-    hipLaunchKernelGGL(k_chol_diag, dim3(batch), dim3(256), 0, st, L, d, kb, rdiag, status, iter,
-                       trs);
+    hipLaunchKernelGGL(k_chol_diag, dim3(batch), dim3(kDiagThreads), 0, st, L, d, kb, rdiag, status,
+                       iter, trs);
     const int64_t below = std::max<int64_t>(0, d - kb - kNb);
     if (below == 0) break;
     const unsigned gx = (unsigned)((below + 15) / 16);  // 16 rows per workgroup
