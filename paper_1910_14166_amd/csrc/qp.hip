@@ -615,14 +615,17 @@ hipError_t launch_chol_solve_update(const double* L, const double* rdiag, int64_
 
 // ---------------------------------------------------------------------------
 // Explicit inverse H^{-1} = L^{-T} L^{-1} from the Cholesky factor, in three
-// stages over 64 x 64 blocks (the blocked triangular inverse followed by the
-// product L^{-T} L^{-1}), the last two on f64 MFMA:
-//   1. diagonal blocks Linv_ii = L_ii^{-1}, one wavefront per block;
-//   2. block diagonals s = 1 .. nblk-1 in turn, every block of a diagonal in
-//      parallel: Linv_{j+s,j} = -Linv_{j+s,j+s} sum_{k=j}^{j+s-1} L_{j+s,k} Linv_{kj};
+// stages over 64 x 64 blocks, the last two on f64 MFMA:
+//   1. diagonal blocks Linv_ii = L_ii^{-1}, one workgroup per block;
+//   2. recursive doubling: adjacent inverted segments A (h blocks) and C
+//      (up to h blocks) of L = [[A, 0], [B, C]] merge into one by
+//      [[A, 0], [B, C]]^{-1} = [[A^{-1}, 0], [-C^{-1} B A^{-1}, C^{-1}]],
+//      T = B A^{-1} first and then -C^{-1} T, every 64 x 64 output tile in
+//      parallel; h = 1, 2, 4, ... so there are log2(blocks) merge stages;
 //   3. H^{-1}_{IJ} = sum_{k >= I} Linv_{kI}^T Linv_{kJ} for I >= J, mirrored.
-// Entries at or beyond d read as zero, so a ragged last block needs no
-// padding. Problems with trs[4p+1] >= 2 (nullable) are skipped.
+// T is kept in the H^{-1} buffer at the position of its block, which the
+// last stage overwrites. Entries at or beyond d read as zero, so a ragged last
+// block needs no padding. Problems with trs[4p+1] >= 2 (nullable) are skipped.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ bool inv_skip(const DeviceStatus* st, const double* trs, int p) {
   return status_failed_by(st, -1) || trs_skip(trs, p);
@@ -750,52 +753,52 @@ __device__ __forceinline__ void tile_store64(const f64x4 (&acc)[2][2], F f) {
         f(r0 + 16 * ti + 4 * reg + (lane >> 4), c0 + 16 * tj + (lane & 15), acc[ti][tj][reg]);
 }
 
-// One block of block diagonal s per workgroup. The first operand pair is
-// requested together with the status, later pairs and then the diagonal
-// block Linv_ii one at a time: a small register footprint, so a workgroup
-// fits on a CU beside the bucket gather's waves.
-__global__ __launch_bounds__(256, 3) void k_trtri_level(const double* __restrict__ L,
-                                                        double* Linv, int64_t d, int32_t s,
-                                                        const DeviceStatus* st,
+// One merge stage (segment size h blocks) of the triangular inverse. Block
+// (x, y) of the grid is output tile (i, j) = (x / h, x % h) of pair y, whose
+// segments start at a0 = 2 h y (A) and c0 = a0 + h (C, hc <= h blocks).
+// PHASE 0: T_ij = sum_{k=j}^{h-1} L_{c0+i, a0+k} Linv_{a0+k, a0+j} -> Tb;
+// PHASE 1: Linv_{c0+i, a0+j} = -sum_{k=0}^{i} Linv_{c0+i, c0+k} T_kj.
+// Each operand pair is requested while the previous products are summed only
+// through the LDS staging; the register footprint stays small enough for a
+// workgroup to fit on a CU beside the bucket gather's waves.
+template <int PHASE>
+__global__ __launch_bounds__(256, 3) void k_trtri_merge(const double* __restrict__ L, double* Linv,
+                                                        double* Tb, int64_t d, int32_t nblk,
+                                                        int32_t h, const DeviceStatus* st,
                                                         const double* __restrict__ trs) {
   __shared__ Tile64 As, Bs;
   __shared__ int skip;
-  const int p = blockIdx.y;
-  const int64_t jb = (int64_t)blockIdx.x * kNb, ib = jb + (int64_t)s * kNb;
-  const double* Lp = L + (int64_t)p * d * d;
-  double* Xp = Linv + (int64_t)p * d * d;
+  const int p = blockIdx.z;
+  const int i = (int)blockIdx.x / h, j = (int)blockIdx.x % h;
+  const int a0 = 2 * h * (int)blockIdx.y, c0 = a0 + h;
+  const int hc = min(h, nblk - c0);
+  if (i >= hc) return;  // uniform per workgroup
+  const int64_t off = (int64_t)p * d * d;
+  const double* Lp = L + off;
+  double* Xp = Linv + off;
+  double* Tp = Tb + off;
+  const int kbeg = PHASE == 0 ? j : 0, kend = PHASE == 0 ? h : i + 1;
   f64x4 acc[2][2] = {};
-  for (int64_t kb = jb; kb < ib; kb += kNb) {  // T = sum_k L_ik Linv_kj
+  for (int k = kbeg; k < kend; ++k) {
     Pair64 nx;
-    load64x2(nx, Lp, ib, kb, Xp, kb, jb, d);
-    if (kb == jb && threadIdx.x == 0) skip = inv_skip(st, trs, p) ? 1 : 0;
-    if (kb > jb) __syncthreads();  // the previous MFMAs are done with As, Bs
+    if (PHASE == 0)
+      load64x2(nx, Lp, (int64_t)(c0 + i) * kNb, (int64_t)(a0 + k) * kNb, Xp,
+               (int64_t)(a0 + k) * kNb, (int64_t)(a0 + j) * kNb, d);
+    else
+      load64x2(nx, Xp, (int64_t)(c0 + i) * kNb, (int64_t)(c0 + k) * kNb, Tp,
+               (int64_t)(c0 + k) * kNb, (int64_t)(a0 + j) * kNb, d);
+    if (k == kbeg && threadIdx.x == 0) skip = inv_skip(st, trs, p) ? 1 : 0;
+    if (k > kbeg) __syncthreads();  // the previous MFMAs are done with As, Bs
     store64x2(nx, As, Bs);
     __syncthreads();
     if (skip) return;
     tile_mma64<false>(acc, As, Bs);
   }
-  {
-    double vd[16];
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int e = threadIdx.x + 256 * q, rr = e >> 6, cc = e & 63;
-      vd[q] = (ib + rr < d && ib + cc < d) ? Xp[(ib + rr) * d + ib + cc] : 0.0;
-    }
-    __syncthreads();
-    tile_store64(acc, [&](int rr, int cc, double v) { Bs[rr][cc] = v; });
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int e = threadIdx.x + 256 * q;
-      As[e >> 6][e & 63] = vd[q];
-    }
-  }
-  __syncthreads();
-  f64x4 out[2][2] = {};
-  tile_mma64<false>(out, As, Bs);  // Linv_ij = -Linv_ii T
-  tile_store64(out, [&](int rr, int cc, double v) {
-    const int64_t row = ib + rr, col = jb + cc;
-    if (row < d && col < d) Xp[row * d + col] = -v;
+  const int64_t r0 = (int64_t)(c0 + i) * kNb, q0 = (int64_t)(a0 + j) * kNb;
+  double* out = PHASE == 0 ? Tp : Xp;
+  tile_store64(acc, [&](int rr, int cc, double v) {
+    const int64_t row = r0 + rr, col = q0 + cc;
+    if (row < d && col < d) out[row * d + col] = PHASE == 0 ? v : -v;
   });
 }
 
@@ -843,9 +846,13 @@ hipError_t launch_chol_inverse(const double* L, const double* rdiag, int64_t d, 
   const int32_t nblk = (int32_t)((d + kNb - 1) / kNb);
   hipLaunchKernelGGL(k_trtri_diag, dim3(nblk, batch), dim3(256), 0, st, L, rdiag, d, Linv, status,
                      trs);
-  for (int32_t s = 1; s < nblk; ++s)
-    hipLaunchKernelGGL(k_trtri_level, dim3(nblk - s, batch), dim3(256), 0, st, L, Linv, d, s,
+  for (int32_t h = 1; h < nblk; h *= 2) {
+    const dim3 grid((unsigned)(h * h), (unsigned)((nblk + 2 * h - 1) / (2 * h)), batch);
+    hipLaunchKernelGGL(k_trtri_merge<0>, grid, dim3(256), 0, st, L, Linv, Hinv, d, nblk, h,
                        status, trs);
+    hipLaunchKernelGGL(k_trtri_merge<1>, grid, dim3(256), 0, st, L, Linv, Hinv, d, nblk, h,
+                       status, trs);
+  }
   const unsigned ntri = (unsigned)(nblk * (nblk + 1) / 2);
   hipLaunchKernelGGL(k_lauum, dim3(ntri, batch), dim3(256), 0, st, Linv, Hinv, d, nblk, status,
                      trs);
