@@ -358,3 +358,92 @@ def test_precision_variants_on_scaled_ill_conditioned_problem():
         e[dt] = O.error_A(wl.A, xs[-1], xo)
     assert e["float64"] < 1e-9 and e["float32"] < 1e-9
     assert e["bfloat16"] > 1e-4
+
+
+# ------------------------------------------------- penalised LASSO step ----
+def brute_force_l1_penalty(H, c, lam):
+    """Exact minimiser of 1/2 x^T H x - c^T x + lam ||x||_1 by enumerating every
+    support/sign pattern: on a pattern the objective is a smooth quadratic whose
+    stationary point solves H_SS x_S = c_S - lam sigma_S; among the patterns
+    whose solution keeps its signs, the smallest objective is the minimum."""
+    d = len(c)
+    obj = lambda x: 0.5 * x @ H @ x - c @ x + lam * np.abs(x).sum()
+    best_x = np.zeros(d)
+    best = obj(best_x)
+    for pattern in itertools.product((-1, 0, 1), repeat=d):
+        sig = np.array(pattern, dtype=float)
+        S = np.nonzero(sig)[0]
+        if len(S) == 0:
+            continue
+        xs = np.linalg.solve(H[np.ix_(S, S)], c[S] - lam * sig[S])
+        if np.any(np.sign(xs) != sig[S]):
+            continue
+        x = np.zeros(d)
+        x[S] = xs
+        if obj(x) < best:
+            best, best_x = obj(x), x
+    return best_x
+
+
+def test_l1_penalty_closed_forms():
+    g = np.random.default_rng(21)
+    c = g.standard_normal(9) * 2
+    lam = 0.7
+    # H = I: the soft threshold of c; H diagonal: its per-coordinate scaling
+    assert np.allclose(O.qp_l1_penalty(np.eye(9), c, lam), O.soft_threshold(c, lam),
+                       rtol=1e-14, atol=0)
+    h = g.uniform(0.5, 3.0, 9)
+    assert np.allclose(O.qp_l1_penalty(np.diag(h), c, lam),
+                       np.sign(c) * np.maximum(np.abs(c) - lam, 0) / h, rtol=1e-14, atol=0)
+    # hand-checked soft threshold values
+    assert np.array_equal(O.soft_threshold(np.array([3.0, -2.5, 0.4, -0.1, 1.0]), 1.0),
+                          np.array([2.0, -1.5, 0.0, -0.0, 0.0]))
+    # a weight at or above max |c| gives 0
+    H = random_spd(9, g, 10.0)
+    assert np.array_equal(O.qp_l1_penalty(H, c, np.abs(c).max()), np.zeros(9))
+
+
+def test_l1_penalty_qp_matches_brute_force():
+    g = np.random.default_rng(22)
+    for trial in range(12):
+        d = 5
+        H = random_spd(d, g, 20.0)
+        c = g.standard_normal(d) * 3
+        lam = g.uniform(0.05, 0.8) * np.abs(c).max()
+        x = O.qp_l1_penalty(H, c, lam)
+        assert np.allclose(x, brute_force_l1_penalty(H, c, lam), rtol=1e-10, atol=1e-12), trial
+
+
+def test_l1_penalty_kkt_larger_and_zero_weight():
+    g = np.random.default_rng(23)
+    d = 40
+    H = random_spd(d, g, 9.0)
+    c = g.standard_normal(d) * 2
+    lam = 0.5
+    x = O.qp_l1_penalty(H, c, lam)
+    grad = c - H @ x
+    S = x != 0
+    assert 0 < S.sum() < d
+    assert np.allclose(grad[S], lam * np.sign(x[S]), atol=1e-11)
+    assert np.all(np.abs(grad[~S]) <= lam + 1e-11)
+    # lambda = 0 is the unconstrained minimiser
+    d0 = 8
+    H0 = random_spd(d0, g, 5.0)
+    c0 = g.standard_normal(d0)
+    assert np.allclose(O.qp_l1_penalty(H0, c0, 0.0), np.linalg.solve(H0, c0), rtol=1e-12)
+
+
+def test_ihs_l1_penalty_converges():
+    wl = W.lasso_dense(rows=6000, d=24, m=192, penalty=40.0)
+    xo = O.x_opt(wl.A, wl.b, "l1_penalty", wl.radius)
+    AtA, Atb = wl.A.T @ wl.A, wl.A.T @ wl.b
+    grad = Atb - AtA @ xo
+    S = xo != 0
+    assert 0 < S.sum() < wl.d        # the weight zeroes some coefficients
+    assert np.allclose(grad[S], wl.radius * np.sign(xo[S]), rtol=1e-9)
+    assert np.all(np.abs(grad[~S]) <= wl.radius * (1 + 1e-9))
+    xs = O.ihs(wl.A, wl.b, wl.m, seed=wl.sketch_seed, iters=14, constraint="l1_penalty",
+               radius=wl.radius)
+    errs = [O.error_A(wl.A, x, xo) for x in xs[1:]]
+    assert errs[-1] < 1e-8
+    assert errs[6] < errs[0] * 1e-2

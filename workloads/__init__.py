@@ -53,8 +53,8 @@ class Workload:
     d: int
     b: object                      # (n,) float64
     x_star: object                 # (d,) or (B, d)
-    constraint: str                # "none" | "l1" | "l2"
-    radius: float
+    constraint: str                # "none" | "l1" | "l2" | "l1_penalty"
+    radius: float                  # ball radius, or lambda for "l1_penalty"
     sketch_kind: str               # "countsketch" | "sjlt"
     m: int
     s: int
@@ -111,7 +111,10 @@ def ols_dense(rows=None, d=50, m=500, iters=10, seed=BASE_SEED + 0,
 # lasso_dense: AR(1) rows, sparse ground truth, active l1 ball
 # --------------------------------------------------------------------------
 def lasso_dense(rows=None, d=256, m=4096, sketch="countsketch", s=None,
-                iters=20, seed=BASE_SEED + 1, backend="numpy", device=None):
+                iters=20, seed=BASE_SEED + 1, backend="numpy", device=None, penalty=None):
+    """LASSO data. By default the constrained form with the ball ||x||_1 <=
+    0.9 ||x*||_1; with `penalty` = lambda, the penalised form
+    1/2 ||Ax - b||^2 + lambda ||x||_1 of the paper's experiments (lambda = 5)."""
     n = FULL_ROWS["lasso_dense"] if rows is None else int(rows)
     if s is None:
         s = 4 if sketch == "sjlt" else 1
@@ -147,6 +150,9 @@ def lasso_dense(rows=None, d=256, m=4096, sketch="countsketch", s=None,
         b = A @ x_star + 0.1 * torch.randn(n, generator=gen, device=device,
                                            dtype=torch.float64)
         tau = 0.9 * float(x_star.abs().sum())
+    if penalty is not None:
+        return Workload("lasso_dense", n, d, b, x_star, "l1_penalty", float(penalty), sketch,
+                        m, s, iters, seed + 1000, A=A)
     return Workload("lasso_dense", n, d, b, x_star, "l1", tau, sketch, m, s,
                     iters, seed + 1000, A=A)
 
