@@ -432,6 +432,22 @@ def components(P, W, wl4):
         ms = _wall_ms(lambda: P.solve(M2, wl2.b, o), reps=1)
         out[f"a8_solve_lasso_2^20x256_l1_{kind}_s{s}_{wl2.iters}steps"] = {
             "ms_wall": round(ms, 3), "ms_per_step": round(ms / wl2.iters, 4)}
+    # the penalised form of the experiments, lambda = 5 (same data): time and
+    # the optimality residual of the last iterate for the full problem,
+    # max_j | |A^T (b - A x)|_j - lambda sign-condition | / max |A^T b|
+    lam = 5.0
+    o = P.options(4096, seed=wl2.sketch_seed, max_iter=wl2.iters, constraint="l1_penalty",
+                  radius=lam)
+    res = {}
+    ms = _wall_ms(lambda: res.update(x=P.solve(M2, wl2.b, o).x[0]), reps=1)
+    xl = res["x"]
+    gl = wl2.A.T @ (wl2.b - wl2.A @ xl)
+    on = xl != 0
+    viol = torch.where(on, (gl - lam * torch.sign(xl)).abs(), (gl.abs() - lam).clamp(min=0))
+    out[f"a8_solve_lasso_penalised_2^20x256_lambda5_countsketch_{wl2.iters}steps"] = {
+        "ms_wall": round(ms, 3), "ms_per_step": round(ms / wl2.iters, 4),
+        "support": int(on.sum()),
+        "kkt_residual_rel": float(viol.max() / (wl2.A.T @ wl2.b).abs().max())}
     del wl2, M2, SA2
     torch.cuda.empty_cache()
     # ---- CSR ridge (2^22 x 1024, density 1e-3): CSR apply, l2 QP, l2 solve

@@ -51,7 +51,14 @@ typedef enum {
 
 typedef enum { IHS_F64 = 0, IHS_F32 = 1, IHS_BF16 = 2 } ihs_dtype;
 typedef enum { IHS_COUNTSKETCH = 0, IHS_SJLT = 1 } ihs_sketch_kind;
-typedef enum { IHS_UNCONSTRAINED = 0, IHS_L1_BALL = 1, IHS_L2_BALL = 2 } ihs_constraint;
+/* The set C of Eq.(1), or (IHS_L1_PENALTY) the weight lambda ||x||_1 added to
+ * the objective over R^d: the penalised LASSO of the experiments of Sec. 3. */
+typedef enum {
+  IHS_UNCONSTRAINED = 0,
+  IHS_L1_BALL = 1,
+  IHS_L2_BALL = 2,
+  IHS_L1_PENALTY = 3
+} ihs_constraint;
 typedef enum { IHS_DENSE = 0, IHS_CSR = 1 } ihs_format;
 
 /* The data matrix A (n x d). Dense: `values` (device) holds n rows of `ld`
@@ -97,17 +104,18 @@ typedef struct {
 typedef struct {
   int32_t constraint;          /* ihs_constraint                              */
   int32_t max_iter;            /* number of IHS steps N >= 1                  */
-  double radius;               /* ball radius (> 0 for ball constraints)      */
+  double radius;               /* ball radius (> 0 for ball constraints), or
+                                  lambda >= 0 for IHS_L1_PENALTY               */
   ihs_sketch sketch;
   int32_t gram_in;             /* dtype SA is stored in for the Gram          */
   int32_t gram_acc;            /* dtype the Gram accumulates in (F64 or F32)  */
   int32_t qp_max_inner;        /* cap on inner QP iterations; 0 = default:
-                                  l1 ball: accelerated projected-gradient
-                                  iterations (5000); l2 ball: Newton steps on
-                                  the shift (20)                               */
+                                  l1 ball and penalty: accelerated (projected
+                                  or proximal) gradient iterations (5000); l2
+                                  ball: Newton steps on the shift (30)         */
   int32_t keep_factors;        /* store each step's Cholesky factor           */
   double qp_tol;               /* inner stopping tolerance; 0 = default:
-                                  l1 ball: max |x_{k+1} - x_k| <= qp_tol
+                                  l1 ball and penalty: max |x_{k+1} - x_k| <= qp_tol
                                   max(1, |x|_inf) (1e-15; a KKT-certified
                                   polish usually ends the iteration first);
                                   l2 ball: | ||x|| - r | <= qp_tol r, then one
@@ -209,7 +217,9 @@ size_t ihs_qp_workspace_size(int64_t d, int32_t batch, const ihs_options* opt);
  * batch x d), writes x^{t+1} (device, batch x d) = argmin over C of
  * 1/2 (x - x^t)^T H (x - x^t) - g^T (x - x^t), with C from Eq.(1): R^d, the
  * l1 ball or the l2 ball of radius opt->radius centred at 0 (d <= 1024 for
- * the balls). Only opt->constraint, radius, qp_max_inner and qp_tol are read.
+ * the balls); for IHS_L1_PENALTY, argmin over R^d of the same plus
+ * opt->radius ||x||_1 (d <= 1024). Only opt->constraint, radius, qp_max_inner
+ * and qp_tol are read.
  * x_out may alias x. Synchronises; returns IHS_ERR_NOT_PD when a
  * factorisation meets a non-positive pivot and IHS_ERR_NOT_CONVERGED when a
  * ball QP ends its iteration budget unsolved (x_out then holds x^t). */

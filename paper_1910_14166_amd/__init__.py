@@ -20,10 +20,10 @@ OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_WORKSPACE, ERR_HIP, ERR_NOT_PD, \
     ERR_NOT_CONVERGED, ERR_NONFINITE = range(8)
 F64, F32, BF16 = 0, 1, 2
 COUNTSKETCH, SJLT = 0, 1
-UNCONSTRAINED, L1_BALL, L2_BALL = 0, 1, 2
+UNCONSTRAINED, L1_BALL, L2_BALL, L1_PENALTY = 0, 1, 2, 3
 DENSE, CSR = 0, 1
 
-_CONSTRAINTS = {"none": UNCONSTRAINED, "l1": L1_BALL, "l2": L2_BALL}
+_CONSTRAINTS = {"none": UNCONSTRAINED, "l1": L1_BALL, "l2": L2_BALL, "l1_penalty": L1_PENALTY}
 _DTYPES = {"float64": F64, "float32": F32, "bfloat16": BF16,
            "f64": F64, "f32": F32, "bf16": BF16}
 

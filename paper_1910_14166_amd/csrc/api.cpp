@@ -445,6 +445,14 @@ struct EventRing {
   hipEvent_t at(int64_t i) { return ev[(size_t)(((i % (int64_t)ev.size()) + ev.size()) % ev.size())]; }
 };
 
+// Balls need a positive radius; the penalty a finite weight >= 0.
+bool valid_constraint(int32_t c, double radius) {
+  if (c == IHS_UNCONSTRAINED) return true;
+  if (c == IHS_L1_BALL || c == IHS_L2_BALL) return radius > 0.0 && std::isfinite(radius);
+  if (c == IHS_L1_PENALTY) return radius >= 0.0 && std::isfinite(radius);
+  return false;
+}
+
 bool valid_gram_types(int32_t in, int32_t acc) {
   if (in == IHS_F64) return acc == IHS_F64;
   if (in == IHS_F32) return acc == IHS_F64 || acc == IHS_F32;
@@ -456,8 +464,7 @@ ihs_status check_options(const ihs_options* o, bool need_loop) {
   if (!o) return IHS_ERR_INVALID_ARG;
   ihs_status s = check_sketch(&o->sketch);
   if (s != IHS_OK) return s;
-  if (o->constraint < IHS_UNCONSTRAINED || o->constraint > IHS_L2_BALL) return IHS_ERR_INVALID_ARG;
-  if (o->constraint != IHS_UNCONSTRAINED && !(o->radius > 0.0)) return IHS_ERR_INVALID_ARG;
+  if (!valid_constraint(o->constraint, o->radius)) return IHS_ERR_INVALID_ARG;
   if (need_loop && o->max_iter < 1) return IHS_ERR_INVALID_ARG;
   if (!valid_gram_types(o->gram_in, o->gram_acc)) return IHS_ERR_INVALID_ARG;
   if (o->tol != 0.0 || o->qp_tol < 0.0 || o->qp_max_inner < 0) return IHS_ERR_INVALID_ARG;
@@ -773,8 +780,7 @@ ihs_status ihs_qp_step(int64_t d, int32_t batch, const double* H, const double* 
                        const double* x, double* x_out, const ihs_options* opt, void* ws,
                        size_t ws_bytes, hipStream_t stream) {
   if (d < 1 || batch < 1 || !H || !g || !x || !x_out || !opt || !ws) return IHS_ERR_INVALID_ARG;
-  if (opt->constraint < IHS_UNCONSTRAINED || opt->constraint > IHS_L2_BALL) return IHS_ERR_INVALID_ARG;
-  if (opt->constraint != IHS_UNCONSTRAINED && !(opt->radius > 0.0)) return IHS_ERR_INVALID_ARG;
+  if (!valid_constraint(opt->constraint, opt->radius)) return IHS_ERR_INVALID_ARG;
   if (ws_bytes < ihs_qp_workspace_size(d, batch, opt) - 256) return IHS_ERR_WORKSPACE;
   Carver c(ws);
   DeviceStatus* st = c.take<DeviceStatus>(1);

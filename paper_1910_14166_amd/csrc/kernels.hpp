@@ -149,7 +149,7 @@ struct QpArgs {
 };
 size_t qp_work_doubles(int64_t d, int32_t constraint);
 hipError_t launch_qp_step(const QpArgs& a, hipStream_t st);
-// The l1- and l2-ball steps (constraint 1 and 2); a.work holds
+// The l1-ball, l2-ball and l1-penalty steps (constraint 1, 2, 3); a.work holds
 // qp_work_doubles(d, constraint) doubles per problem.
 hipError_t launch_qp_constrained(const QpArgs& a, hipStream_t st);
 

@@ -16,6 +16,11 @@
 //   and is accepted when it keeps the signs, has mu >= 0 and leaves every
 //   off-support |c_j - (H x)_j| <= mu (to 1e-9 max(1, |c|_inf)). An accepted
 //   KKT point is the minimiser, which ends the iteration.
+// l1 penalty lambda ||x||_1 added to the objective (the penalised LASSO of
+// the experiments of Sec. 3): the same kernel with the soft threshold by
+// lambda / L as the proximal map in place of the projection, and the polish
+// with mu fixed at lambda (H_SS x_S = c_S - lambda sigma). An empty support
+// is the answer when every |c_j| <= lambda. No unconstrained solve first.
 // l2 ball ||x||_2 <= r:
 //   Newton's method on phi(mu) = 1/||x(mu)|| - 1/r, x(mu) = (H + mu I)^{-1} c
 //   (More and Sorensen, 1983). 1/||x(mu)|| is concave and increasing, so from
@@ -144,10 +149,11 @@ __device__ double project_l1(double vi, int64_t d, double tau, BlockShared& sh) 
 
 // KKT polish on the support of x (thread i holds x_i in *xi). M: ns*ns
 // doubles (LDS or global), u, w: kPolishMax doubles, idx: kPolishMax ints,
-// cand, hc: d doubles of LDS. On success returns true with the polished x_i.
+// cand, hc: d doubles of LDS. Ball (penalty false): mu from sigma^T x_S = tau;
+// penalty: mu = tau = lambda. On success returns true with the polished x_i.
 __device__ __attribute__((noinline)) bool l1_polish(const double* __restrict__ H, int64_t d, double ci, double tau,
-                          double* xi, double* M, double* u, double* w, int* idx, double* cand,
-                          double* hc, double cscale, BlockShared& sh) {
+                          bool penalty, double* xi, double* M, double* u, double* w, int* idx,
+                          double* cand, double* hc, double cscale, BlockShared& sh) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const bool on = tid < d && *xi != 0.0;
   // ascending support indices by wave ballots
@@ -159,7 +165,11 @@ __device__ __attribute__((noinline)) bool l1_polish(const double* __restrict__ H
     if (k < wv) base += sh.wave_count[k];
     ns += sh.wave_count[k];
   }
-  if (ns == 0 || ns > kPolishMax) return false;
+  if (ns == 0) {  // x = 0: optimal for the penalty when every |c_j| <= lambda
+    if (!penalty) return false;
+    return block_max(tid < d ? fabs(ci) - tau : -1.0, sh) <= 1e-9 * cscale;
+  }
+  if (ns > kPolishMax) return false;
   const int slot = on ? base + __popcll(bal & lanemask_lt()) : -1;
   if (on) idx[slot] = tid;
   __syncthreads();
@@ -230,7 +240,7 @@ __device__ __attribute__((noinline)) bool l1_polish(const double* __restrict__ H
   __syncthreads();
   const double SU = block_sum(on ? sg * u[slot] : 0.0, sh);
   const double SW = block_sum(on ? sg * w[slot] : 0.0, sh);
-  const double mu = (SU - tau) / SW;
+  const double mu = penalty ? tau : (SU - tau) / SW;
   double xs = 0.0;
   bool bad = false;
   if (on) {
@@ -259,8 +269,8 @@ __device__ __attribute__((noinline)) bool l1_polish(const double* __restrict__ H
 __global__ __launch_bounds__(kQpThreads) void k_qp_l1(
     const double* __restrict__ Hall, const double* __restrict__ call,
     const double* __restrict__ xunc_all, const double* x0_all, double* xout_all,
-    double* Lscratch, int64_t d, double tau, int32_t max_iter, double tol, int32_t lds_mcap,
-    DeviceStatus* st, int32_t iter) {
+    double* Lscratch, int64_t d, double tau, int32_t penalty, int32_t max_iter, double tol,
+    int32_t lds_mcap, DeviceStatus* st, int32_t iter) {
   extern __shared__ double lds[];
   double* vec = lds;            // d: the vector being multiplied
   double* cand = vec + d;       // d: polish candidate
@@ -282,12 +292,16 @@ __global__ __launch_bounds__(kQpThreads) void k_qp_l1(
     return;
   }
   const double ci = tid < d ? call[(int64_t)p * d + tid] : 0.0;
-  const double xu = tid < d ? xunc_all[(int64_t)p * d + tid] : 0.0;
+  const double xu = (!penalty && tid < d) ? xunc_all[(int64_t)p * d + tid] : 0.0;
   double r0[2] = {fabs(xu), 0.0};
   r0[1] = fabs(ci);
   block_reduce<1, 1>(r0, sh);
-  if (r0[0] <= tau) {  // the ball is inactive
+  if (!penalty && r0[0] <= tau) {  // the ball is inactive
     if (tid < d) xout[tid] = xu;
+    return;
+  }
+  if (penalty && r0[1] <= tau) {  // 0 satisfies the optimality conditions
+    if (tid < d) xout[tid] = 0.0;
     return;
   }
   const double cscale = fmax(1.0, r0[1]);
@@ -305,8 +319,9 @@ __global__ __launch_bounds__(kQpThreads) void k_qp_l1(
     pv = hp / sqrt(fmax(q[1], 1e-300));
   }
   double Lip = 1.05 * rq;
-  // FISTA from the projection of x^t; thread i keeps x_i, (Hx)_i, y_i, (Hy)_i
-  double xi = project_l1(x0, d, tau, sh);
+  // FISTA from the projection of x^t (from x^t itself for the penalty);
+  // thread i keeps x_i, (Hx)_i, y_i, (Hy)_i
+  double xi = penalty ? x0 : project_l1(x0, d, tau, sh);
   if (tid < d) vec[tid] = xi;
   __syncthreads();
   block_rows<false>(H, d, vec, hv);
@@ -318,7 +333,8 @@ __global__ __launch_bounds__(kQpThreads) void k_qp_l1(
   bool done = false;
   for (int it = 0; it < max_iter && !done; ++it) {
     const double vi = tid < d ? yi - (hyi - ci) / Lip : 0.0;
-    const double xn = project_l1(vi, d, tau, sh);
+    const double xn = penalty ? copysign(fmax(fabs(vi) - tau / Lip, 0.0), vi)
+                              : project_l1(vi, d, tau, sh);
     if (tid < d) vec[tid] = xn;
     __syncthreads();
     block_rows<false>(H, d, vec, hv);
@@ -356,7 +372,7 @@ __global__ __launch_bounds__(kQpThreads) void k_qp_l1(
       const int64_t nsz = (int64_t)red[4];
       double* M = (nsz * nsz <= lds_mcap) ? Mlds : Lscratch + (int64_t)p * d * d;
       double xp = xi;
-      if (l1_polish(H, d, ci, tau, &xp, M, u, w, idx, cand, hv, cscale, sh)) {
+      if (l1_polish(H, d, ci, tau, penalty != 0, &xp, M, u, w, idx, cand, hv, cscale, sh)) {
         xi = xp;
         done = true;
       } else if (conv) {
@@ -630,20 +646,24 @@ hipError_t launch_qp_constrained(const QpArgs& a, hipStream_t st) {
   double* hinv = trs + (int64_t)B * 8;
   double* linv = hinv + (int64_t)B * d * d;
   hipError_t e;
-  if (a.constraint == 1) {
+  if (a.constraint == 1 || a.constraint == 3) {
+    const bool penalty = a.constraint == 3;
     hipLaunchKernelGGL(k_form_c, dim3((unsigned)((d + 3) / 4), B), dim3(256), 0, st, a.H, d,
                        a.x, a.g, cbuf);
-    if ((e = launch_cholesky(a.H, a.L, d, B, a.status, a.iter, 0.0, scratch, st)) != hipSuccess)
-      return e;
-    e = launch_chol_solve_update(a.L, rdiag, d, B, a.g, a.x, xunc, a.status, st);
-    if (e != hipSuccess) return e;
+    if (!penalty) {  // the unconstrained minimiser, the answer when the ball is inactive
+      if ((e = launch_cholesky(a.H, a.L, d, B, a.status, a.iter, 0.0, scratch, st)) !=
+          hipSuccess)
+        return e;
+      e = launch_chol_solve_update(a.L, rdiag, d, B, a.g, a.x, xunc, a.status, st);
+      if (e != hipSuccess) return e;
+    }
     const int32_t max_iter = a.max_inner > 0 ? a.max_inner : 5000;
     const double tol = a.tol > 0 ? a.tol : 1e-15;
     const size_t fixed = (size_t)(3 * d + 2 * kPolishMax) * sizeof(double);
     const int32_t lds_mcap = (int32_t)((kQpLdsBytes - fixed) / sizeof(double));
     hipLaunchKernelGGL(k_qp_l1, dim3(B), dim3(kQpThreads), kQpLdsBytes, st, a.H, cbuf, xunc,
-                       a.x, a.x_out, a.L, d, a.radius, max_iter, tol, lds_mcap, a.status,
-                       a.iter);
+                       a.x, a.x_out, a.L, d, a.radius, penalty ? 1 : 0, max_iter, tol, lds_mcap,
+                       a.status, a.iter);
     return hipGetLastError();
   }
   // l2 ball. A cold start (mu = 0) first takes the unconstrained step

@@ -211,3 +211,96 @@ def test_ihs_l2_csr_bf16_gram_converges(gpu_lib):
         errs[gin] = O.error_A(Asp, host(res.x)[0], xo)
     assert errs["float64"] < 1e-2
     assert errs["bfloat16"] < 3 * errs["float64"] + 1e-6
+
+
+# -------------------------------------------- l1 penalty (Sec. 3 LASSO) ----
+def kkt_l1_penalty_residual(H, c, x, lam):
+    """Max violation (scaled) of the optimality conditions of
+    1/2 x^T H x - c^T x + lam ||x||_1 at x."""
+    grad = c - H @ x
+    S = x != 0
+    scale = max(1.0, np.abs(c).max())
+    on = np.abs(grad[S] - lam * np.sign(x[S])).max() / scale if S.any() else 0.0
+    off = max(0.0, (np.abs(grad[~S]).max() - lam) / scale) if (~S).any() else 0.0
+    return max(on, off)
+
+
+@pytest.mark.parametrize("d,batch,frac,cond", [
+    (8, 1, 0.3, 10.0), (50, 2, 0.2, 1e2), (64, 3, 0.5, 1e2), (256, 1, 0.1, 1e2),
+    (600, 1, 0.3, 10.0), (1, 1, 0.5, 1.0), (97, 2, 0.01, 1e3)])
+def test_qp_l1_penalty_matches_oracle(gpu_lib, d, batch, frac, cond):
+    P = gpu_lib
+    g = np.random.default_rng(3000 + d)
+    Hs = np.stack([spd(d, g, cond) for _ in range(batch)])
+    gs = g.standard_normal((batch, d))
+    xs = 0.1 * g.standard_normal((batch, d))
+    # one weight for the batch: a fraction of the smallest max |c|
+    lam = frac * min(np.abs(Hs[p] @ xs[p] + gs[p]).max() for p in range(batch))
+    out = host(P.qp_step(dev(Hs), dev(gs), dev(xs), constraint="l1_penalty", radius=lam))
+    for p in range(batch):
+        ref = O.qp_step(Hs[p], gs[p], xs[p], "l1_penalty", lam)
+        assert np.linalg.norm(out[p] - ref) <= 1e-9 * cond * max(np.linalg.norm(ref), 1e-300), p
+        assert np.array_equal(out[p] != 0, ref != 0), p   # the same support
+        c = Hs[p] @ xs[p] + gs[p]
+        assert kkt_l1_penalty_residual(Hs[p], c, out[p], lam) < 1e-8 * cond
+
+
+def test_qp_l1_penalty_special_cases(gpu_lib):
+    """H = I gives the soft threshold of c (hand-checkable values); a weight at
+    or above max |c| gives exactly 0; a zero weight gives the unconstrained step."""
+    P = gpu_lib
+    H = np.eye(5)[None]
+    c = np.array([[3.0, -2.5, 0.4, -0.1, 1.0]])
+    out = host(P.qp_step(dev(H), dev(c), dev(np.zeros((1, 5))), constraint="l1_penalty",
+                         radius=1.0))
+    np.testing.assert_allclose(out[0], [2.0, -1.5, 0.0, 0.0, 0.0], atol=1e-14)
+    g = np.random.default_rng(31)
+    d = 40
+    Hr, gv, x = spd(d, g, 1e2)[None], g.standard_normal((1, d)), 0.1 * g.standard_normal((1, d))
+    lam = np.abs(Hr[0] @ x[0] + gv[0]).max()
+    out = host(P.qp_step(dev(Hr), dev(gv), dev(x), constraint="l1_penalty", radius=lam))
+    assert np.array_equal(out, np.zeros((1, d)))
+    free = host(P.qp_step(dev(Hr), dev(gv), dev(x)))
+    out = host(P.qp_step(dev(Hr), dev(gv), dev(x), constraint="l1_penalty", radius=0.0))
+    assert np.linalg.norm(out - free) <= 1e-10 * np.linalg.norm(free)
+
+
+def test_ihs_l1_penalty_iterates_match_oracle(gpu_lib):
+    P = gpu_lib
+    wl = W.lasso_dense(rows=6000, d=24, m=192, penalty=40.0)
+    for kind, s in (("countsketch", 1), ("sjlt", 4)):
+        opts = P.options(wl.m, s=s, kind=kind, seed=wl.sketch_seed, max_iter=10,
+                         constraint="l1_penalty", radius=wl.radius)
+        res = P.solve(P.Matrix(dense=dev(wl.A)), dev(wl.b), opts, history=True)
+        hist = host(res.history)[:, 0]
+        xs = O.ihs(wl.A, wl.b, wl.m, s=s, seed=wl.sketch_seed, iters=10,
+                   constraint="l1_penalty", radius=wl.radius)
+        for t in range(10):
+            assert np.linalg.norm(hist[t] - xs[t + 1]) <= 1e-8 * np.linalg.norm(xs[t + 1]), (kind, t)
+        xo = O.x_opt(wl.A, wl.b, "l1_penalty", wl.radius)
+        assert O.error_A(wl.A, hist[-1], xo) < 1e-7, kind
+
+
+def test_ihs_l1_penalty_full_size_kkt(gpu_lib):
+    """The penalised LASSO of the experiments (lambda = 5) at the full lasso
+    shape (2^20 x 256, CountSketch m = 4096): after 20 steps the iterate meets
+    the optimality conditions of the full problem, |A^T (b - A x)|_j <= lambda
+    off the support and = lambda sign(x_j) on it, to a relative 1e-6 of
+    max |A^T b| (a property that holds at any size; A^T r formed in float64 by
+    torch)."""
+    import torch
+    P = gpu_lib
+    wl = W.lasso_dense(backend="torch", device="cuda", penalty=5.0)
+    opts = P.options(wl.m, seed=wl.sketch_seed, max_iter=wl.iters, constraint="l1_penalty",
+                     radius=wl.radius)
+    x = P.solve(P.Matrix(dense=wl.A), wl.b, opts).x[0]
+    grad = (wl.A.T @ (wl.b - wl.A @ x)).cpu().numpy()
+    scale = float((wl.A.T @ wl.b).abs().max())
+    xh = x.cpu().numpy()
+    S = xh != 0
+    assert S.any()
+    assert np.abs(grad[S] - wl.radius * np.sign(xh[S])).max() <= 1e-6 * scale
+    if (~S).any():
+        assert np.abs(grad[~S]).max() <= wl.radius + 1e-6 * scale
+    del wl
+    torch.cuda.empty_cache()
