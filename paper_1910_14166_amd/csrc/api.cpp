@@ -716,18 +716,18 @@ ihs_status ihs_sketch_adjoint(const ihs_sketch* sk, int64_t n, int64_t d, int32_
       if (row_offsets[p + 1] < row_offsets[p]) return IHS_ERR_INVALID_ARG;
   }
   if (n >= (int64_t(1) << 31)) return IHS_ERR_UNSUPPORTED;
-  for (int32_t p = 0; p < batch; ++p) {
-    const int64_t r0 = batch > 1 ? row_offsets[p] : 0;
-    const int64_t r1 = batch > 1 ? row_offsets[p + 1] : n;
-    if (r1 == r0) continue;
-    SketchPlan P{};
-    P.s = sk->s;
-    P.m = sk->m;
-    P.m_blk = sk->m / sk->s;
-    P.seed = sk->seed;
-    P.iter = sk->iter;
-    if (launch_sketch_adjoint(P, G + (int64_t)p * sk->m * ld_g, ld_g, d, out + r0 * ld_out,
-                              ld_out, r1 - r0, p, stream) != hipSuccess)
+  if (sk->s > 16) return IHS_ERR_UNSUPPORTED;
+  for (int32_t p0 = 0; p0 < batch; p0 += kAdjointBatch) {
+    AdjointBatch ab{};
+    ab.count = std::min<int32_t>(kAdjointBatch, batch - p0);
+    ab.first = p0;
+    for (int i = 0; i <= kAdjointBatch; ++i) {
+      const int32_t p = p0 + std::min<int32_t>(i, ab.count);
+      ab.off[i] = batch > 1 ? row_offsets[p] : (p == 0 ? 0 : n);
+    }
+    if (launch_sketch_adjoint(ab, sk->s, sk->m, sk->seed, sk->iter,
+                              G + (int64_t)p0 * sk->m * ld_g, ld_g, d, out, ld_out,
+                              stream) != hipSuccess)
       return IHS_ERR_HIP;
   }
   return IHS_OK;

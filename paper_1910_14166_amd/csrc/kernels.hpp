@@ -182,9 +182,18 @@ hipError_t launch_chol_solve_update(const double* L, const double* rdiag, int64_
 
 // Adjoint and solution-gradient passes.
 // S^T G for the nrows rows of one problem (G points at that problem's m rows).
-hipError_t launch_sketch_adjoint(const SketchPlan& p, const double* G, int64_t ld_g,
-                                 int64_t d, double* out, int64_t ld_out, int64_t nrows,
-                                 int32_t problem, hipStream_t st);
+// Rows [off[0], off[count]) of problems first .. first+count-1 (global row
+// offsets; problem p's rows start at off[p - first]).
+constexpr int kAdjointBatch = 64;
+struct AdjointBatch {
+  int64_t off[kAdjointBatch + 1];
+  int32_t count;
+  int32_t first;
+};
+// out = S^T G for those rows; G points at problem `first`'s m x d block.
+hipError_t launch_sketch_adjoint(const AdjointBatch& ab, int32_t s, int64_t m, uint64_t seed,
+                                 uint64_t iter, const double* G, int64_t ld_g, int64_t d,
+                                 double* out, int64_t ld_out, hipStream_t st);
 hipError_t launch_solution_grads(const ProbInfo* probs, int32_t batch, int64_t n,
                                  int64_t d, const void* A, bool a_f32, int64_t ld,
                                  const double* b, const double* x,

@@ -889,53 +889,107 @@ hipError_t launch_gradient_rows_csr(const ProbInfo* probs, int32_t batch, int32_
 }
 
 // ---------------------------------------------------------------------------
-// Adjoint S^T G for the rows of one problem: row i re-derives its s (bucket,
-// sign) pairs from the hash and sums c_s * sign * G[bucket][:] over blocks in
-// ascending order. One wavefront per row, lanes over columns.
+// Adjoint S^T G over the rows of up to kAdjointBatch problems in one launch:
+// row i of problem p re-derives its s (bucket, sign) pairs from the hash and
+// receives the sum over blocks, ascending from +0.0, of sign * (c_s * G row).
+// Each wave takes 64 consecutive rows; lane l hashes row l of the group, so a
+// Philox block is computed once per (row, block pair) rather than once per
+// lane. The keys and each row's problem go through LDS; the wave then walks
+// its rows kAdjU at a time, lanes over columns, so that every lane has kAdjU
+// independent G loads in flight before its stores.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_adjoint(int32_t s, int64_t m_blk, uint64_t seed,
-                                                 uint64_t iter, int32_t problem,
+constexpr int kAdjU = 8;
+
+__global__ __launch_bounds__(256) void k_adjoint(AdjointBatch ab, int32_t s, int64_t m,
+                                                 int64_t m_blk, uint64_t seed, uint64_t iter,
                                                  const double* __restrict__ Gm, int64_t ld_g,
-                                                 int64_t d, double* out, int64_t ld_out,
-                                                 double scale, int64_t nrows) {
+                                                 int64_t d, double* __restrict__ out,
+                                                 int64_t ld_out, double scale) {
+  __shared__ int64_t off[kAdjointBatch + 1];
+  __shared__ uint32_t keys[4][16][64];  // [wave][block][row of the group]
+  __shared__ int32_t prob[4][64];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t waves = (int64_t)gridDim.x * 4;
-  for (int64_t row = (int64_t)blockIdx.x * 4 + wv; row < nrows; row += waves) {
-    uint32_t keys[16];
-    const int sk = s < 16 ? s : 16;
-    for (int q = 0; q < (sk + 1) / 2; ++q) {
-      const U64x4 w = philox4x64_10((uint64_t)row, (uint64_t)q, (uint64_t)problem, 0ull, seed,
-                                    iter);
+  if (threadIdx.x == 0) {
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int k = 2 * q + h;
-        if (k < sk) {
-          const uint32_t bkt = (uint32_t)(k * m_blk) + range_reduce(w.w[2 * h], (uint64_t)m_blk);
-          keys[k] = bkt | ((uint32_t)(w.w[2 * h + 1] >> 63) << 31);
+    for (int i = 0; i <= kAdjointBatch; ++i) off[i] = ab.off[i];
+  }
+  __syncthreads();
+  const int count = ab.count;
+  const int64_t row0 = off[0], row_end = off[count];
+  const int64_t groups = (row_end - row0 + 63) / 64;
+  const int64_t waves = (int64_t)gridDim.x * 4;
+  for (int64_t gi = (int64_t)blockIdx.x * 4 + wv; gi < groups; gi += waves) {
+    const int64_t base = row0 + gi * 64;
+    const int64_t row = base + lane;
+    // problem of this lane's row: the last p with off[p] <= row
+    int lo = 0, hi = count;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (off[mid] <= row) lo = mid;
+      else hi = mid;
+    }
+    const uint64_t local = (uint64_t)(row - off[lo]);
+    if (row < row_end) {
+      for (int q = 0; q < (s + 1) / 2; ++q) {
+        const U64x4 w = philox4x64_10(local, (uint64_t)q, (uint64_t)(ab.first + lo), 0ull,
+                                      seed, iter);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int k = 2 * q + h;
+          if (k < s)
+            keys[wv][k][lane] =
+                ((uint32_t)(k * m_blk) + range_reduce(w.w[2 * h], (uint64_t)m_blk)) |
+                ((uint32_t)(w.w[2 * h + 1] >> 63) << 31);
         }
       }
     }
-    for (int64_t c = lane; c < d; c += 64) {
-      double acc = 0.0;
-      for (int k = 0; k < sk; ++k) {
-        double t = Gm[(int64_t)(keys[k] & 0x7FFFFFFFu) * ld_g + c];
-        if (s > 1) t = t * scale;
-        acc = (keys[k] >> 31) ? (acc - t) : (acc + t);
+    prob[wv][lane] = lo;
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    const int nr = (int)((row_end - base) < 64 ? (row_end - base) : 64);
+    for (int r0 = 0; r0 < nr; r0 += kAdjU) {
+      int64_t gbase[kAdjU];
+#pragma unroll
+      for (int j = 0; j < kAdjU; ++j) gbase[j] = (int64_t)prob[wv][r0 + j < 64 ? r0 + j : 63] * m;
+      for (int64_t c = lane; c < d; c += 64) {
+        double acc[kAdjU];
+#pragma unroll
+        for (int j = 0; j < kAdjU; ++j) acc[j] = 0.0;
+        for (int k = 0; k < s; ++k) {
+          double t[kAdjU];
+#pragma unroll
+          for (int j = 0; j < kAdjU; ++j) {
+            const uint32_t key = keys[wv][k][r0 + j < 64 ? r0 + j : 63];
+            t[j] = (r0 + j < nr) ? Gm[(gbase[j] + (int64_t)(key & 0x7FFFFFFFu)) * ld_g + c] : 0.0;
+          }
+#pragma unroll
+          for (int j = 0; j < kAdjU; ++j) {
+            const uint32_t key = keys[wv][k][r0 + j < 64 ? r0 + j : 63];
+            const double v = s > 1 ? t[j] * scale : t[j];
+            acc[j] = (key >> 31) ? (acc[j] - v) : (acc[j] + v);
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < kAdjU; ++j)
+          if (r0 + j < nr) out[(base + r0 + j) * ld_out + c] = acc[j];
       }
-      out[row * ld_out + c] = acc;
     }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
   }
 }
 
-hipError_t launch_sketch_adjoint(const SketchPlan& P, const double* G, int64_t ld_g, int64_t d,
-                                 double* out, int64_t ld_out, int64_t nrows, int32_t problem,
-                                 hipStream_t st) {
-  if (nrows == 0) return hipSuccess;
-  if (P.s > 16) return hipErrorInvalidValue;
-  const double scale = 1.0 / sqrt((double)P.s);
-  const unsigned blocks = (unsigned)std::min<int64_t>((nrows + 3) / 4, 65536);
-  hipLaunchKernelGGL(k_adjoint, dim3(blocks), dim3(256), 0, st, P.s, P.m_blk, P.seed, P.iter,
-                     problem, G, ld_g, d, out, ld_out, scale, nrows);
+hipError_t launch_sketch_adjoint(const AdjointBatch& ab, int32_t s, int64_t m, uint64_t seed,
+                                 uint64_t iter, const double* G, int64_t ld_g, int64_t d,
+                                 double* out, int64_t ld_out, hipStream_t st) {
+  if (ab.count < 1 || ab.count > kAdjointBatch || s < 1 || s > 16) return hipErrorInvalidValue;
+  const int64_t rows = ab.off[ab.count] - ab.off[0];
+  if (rows == 0) return hipSuccess;
+  const double scale = 1.0 / sqrt((double)s);
+  const int64_t groups = (rows + 63) / 64;
+  const unsigned blocks = (unsigned)std::min<int64_t>((groups + 3) / 4, 16384);
+  hipLaunchKernelGGL(k_adjoint, dim3(blocks), dim3(256), 0, st, ab, s, m, m / s, seed, iter, G,
+                     ld_g, d, out, ld_out, scale);
   return hipGetLastError();
 }
 

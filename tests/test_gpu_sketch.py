@@ -189,3 +189,22 @@ def test_sketch_adjoint_ragged(gpu_lib):
     for p in range(len(sizes)):
         ref = OS.sketch_adjoint(G[p * m:(p + 1) * m], sizes[p], 2, 0, m, 1, problem=p)
         assert np.array_equal(out[offs[p]:offs[p + 1]], ref)
+
+
+def test_sketch_adjoint_many_problems(gpu_lib):
+    """More problems than one launch takes (70 > 64), empty and one-row
+    problems, 64-row groups that straddle problems, d = 100 (a ragged column
+    tail) and an SJLT with s = 4: bit-exact per problem."""
+    P = gpu_lib
+    g = np.random.default_rng(71)
+    sizes = g.integers(0, 200, 70)
+    sizes[[3, 40, 64]] = 0
+    sizes[[5, 65]] = 1
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    m, d, s = 48, 100, 4
+    G = g.standard_normal((len(sizes) * m, d))
+    out = host(P.sketch_adjoint(dev(G), int(offs[-1]), P.SketchSpec(m, s, "sjlt", seed=12, iter=3),
+                                row_offsets=offs))
+    for p in range(len(sizes)):
+        ref = OS.sketch_adjoint(G[p * m:(p + 1) * m], int(sizes[p]), 12, 3, m, s, problem=p)
+        assert np.array_equal(out[offs[p]:offs[p + 1]], ref), p
