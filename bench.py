@@ -498,7 +498,51 @@ def components(P, W, wl4):
                                                          "rows": wl5.n}
     del wl5, At, bt, G5, adj
     torch.cuda.empty_cache()
+    out["f3_sketch_error_sweep_w8a_like"] = sketch_error_sweep(P, W)
     return out
+
+
+def sketch_error_sweep(P, W, trials=10, gammas=(1, 2, 5, 10, 20)):
+    """App. B, Fig. 2: mean empirical sketch error ||A^T S^T S A - A^T A||_F /
+    ||A^T A||_F over `trials` seeds, and the sketch time (hash, sort and
+    gather, HIP events), against m = gamma d on the W8A-shaped stand-in
+    (49749 x 300, 4% dense, binary values). `err_predicted` is the closed form
+    sqrt(E err^2), which `err_rms` estimates; err^2 has a heavy right tail on
+    this data, so a few trials usually fall below it. A^T A comes from scipy in float64."""
+    import numpy as np
+    import scipy.sparse as sp
+    import torch
+    wl = W.table1_like("w8a")
+    A = sp.csr_matrix((wl.data, wl.indices, wl.indptr), shape=(wl.n, wl.d))
+    AtA = (A.T @ A).toarray()
+    rn = np.asarray(A.multiply(A).sum(axis=1)).ravel()
+    e2m = rn.sum() ** 2 + (AtA ** 2).sum() - 2 * (rn ** 2).sum()
+    nrm = float(np.linalg.norm(AtA))
+    AtA_dev = torch.from_numpy(AtA).cuda()
+    M = P.Matrix(row_ptr=torch.from_numpy(wl.indptr).cuda(),
+                 col_idx=torch.from_numpy(wl.indices).cuda(),
+                 values=torch.from_numpy(wl.data).cuda(), n=wl.n, d=wl.d)
+    rows = []
+    for kind, s in (("countsketch", 1), ("sjlt", 4)):
+        for gm in gammas:
+            m = gm * wl.d
+            opts = P.options(m, s, kind)
+            ws = torch.empty(P.workspace_size(M, opts), dtype=torch.uint8, device="cuda")
+            SA = torch.empty(m, wl.d, dtype=torch.float64, device="cuda")
+            errs, times = [], []
+            for t in range(trials):
+                spec = P.SketchSpec(m, s, kind, seed=500 + t, iter=0)
+                times.append(_event_ms(lambda: P.sketch_apply(M, spec, out=SA, ws=ws),
+                                       reps=1, warm=1))
+                H = P.gram(SA, m)[0]
+                errs.append(float(torch.linalg.norm(H - AtA_dev)) / nrm)
+            rows.append({"sketch": kind, "s": s, "m": m, "gamma": gm,
+                         "err_mean": float(np.mean(errs)), "err_std": float(np.std(errs)),
+                         "err_rms": float(np.sqrt(np.mean(np.square(errs)))),
+                         "err_predicted": math.sqrt(e2m / m) / nrm,
+                         "sketch_ms_median": round(float(np.median(times)), 4)})
+    return {"data": "W8A-shaped: 49749 x 300, %d nonzeros, binary" % int(wl.indptr[-1]),
+            "trials": trials, "rows": rows}
 
 
 def cpu_baseline(wl, m, budget_s=15.0):

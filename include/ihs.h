@@ -151,6 +151,14 @@ typedef struct {
 
 const char* ihs_status_string(int32_t status);
 
+/* The HIP runtime error behind the most recent IHS_ERR_HIP returned on the
+ * calling thread: its name (hipGetErrorName), and its hipError_t value in
+ * *code when code is not NULL ("hipSuccess" and 0 before any such failure).
+ * Every entry point first clears an error that earlier, unrelated HIP calls
+ * left pending on the thread, so IHS_ERR_HIP always names a failure of the
+ * library's own launches or runtime calls. Host only. */
+const char* ihs_last_hip_error(int32_t* code);
+
 /* Bucket and sign of every (row, block) pair of one problem's sketch, exactly
  * as defined under ihs_sketch. bucket (device, n*s int32) receives the sketch
  * row in [0, m) of pair (i, k) at index i*s + k; sign (device, n*s int8)

@@ -27,7 +27,7 @@ _CONSTRAINTS = {"none": UNCONSTRAINED, "l1": L1_BALL, "l2": L2_BALL, "l1_penalty
 _DTYPES = {"float64": F64, "float32": F32, "bfloat16": BF16,
            "f64": F64, "f32": F32, "bf16": BF16}
 
-EXPORTS = ["ihs_status_string", "ihs_sketch_hash", "ihs_workspace_size",
+EXPORTS = ["ihs_status_string", "ihs_last_hip_error", "ihs_sketch_hash", "ihs_workspace_size",
            "ihs_sketch_apply", "ihs_sketch_adjoint", "ihs_gram_workspace_size",
            "ihs_gram", "ihs_gradient", "ihs_qp_workspace_size", "ihs_qp_step",
            "ihs_solve", "ihs_adjoint_solve", "ihs_solution_grads",
@@ -93,6 +93,7 @@ def load(path: Optional[str] = None):
                   ctypes.POINTER(Options_t), ctypes.POINTER(Report_t))
     sig = {
         "ihs_status_string": (ctypes.c_char_p, [i32]),
+        "ihs_last_hip_error": (ctypes.c_char_p, [ctypes.POINTER(i32)]),
         "ihs_sketch_hash": (i32, [S, i64, i32, vp, vp, vp]),
         "ihs_workspace_size": (sz, [M, O]),
         "ihs_sketch_apply": (i32, [S, M, vp, i32, i64, vp, sz, vp]),
@@ -124,6 +125,10 @@ def _status_text(code):
 
 
 def _check(code, where):
+    if code == ERR_HIP:
+        hc = ctypes.c_int32(0)
+        name = load().ihs_last_hip_error(ctypes.byref(hc)).decode()
+        raise IHSError(code, "%s (%s, %d)" % (where, name, hc.value))
     if code != OK:
         raise IHSError(code, where)
 

@@ -24,6 +24,23 @@ constexpr int32_t kTilesPerChunk = 32;
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+// The HIP error behind the most recent IHS_ERR_HIP returned on this thread.
+thread_local int32_t t_last_hip_error = 0;
+
+// True, and recorded for ihs_last_hip_error, when e reports a failure.
+bool hip_failed(hipError_t e) {
+  if (e == hipSuccess) return false;
+  t_last_hip_error = (int32_t)e;
+  return true;
+}
+
+ihs_status hip_status(hipError_t e) { return hip_failed(e) ? IHS_ERR_HIP : IHS_OK; }
+
+// Drops an error that earlier HIP calls of the caller left pending on this
+// thread, so that the checks after this library's own launches see only
+// theirs. Called once argument checks pass, before the first launch.
+void clear_stale_error() { (void)hipGetLastError(); }
+
 // Bump allocator over the caller's workspace (or a size count when base is null).
 struct Carver {
   char* base;
@@ -230,9 +247,9 @@ hipError_t fill(double* p, int64_t n, double v, hipStream_t st) {
 }
 
 ihs_status upload_probs(const Layout& L, PassBuffers& B, hipStream_t st) {
-  if (launch_write_probs(L.probs.data(), L.batch, B.probs, st) != hipSuccess) return IHS_ERR_HIP;
+  if (hip_failed(launch_write_probs(L.probs.data(), L.batch, B.probs, st))) return IHS_ERR_HIP;
   hipLaunchKernelGGL(k_zero_status, dim3(1), dim3(64), 0, st, B.status);
-  return hipGetLastError() == hipSuccess ? IHS_OK : IHS_ERR_HIP;
+  return hip_status(hipGetLastError());
 }
 
 // ---- profiling of the gather pass ----
@@ -245,7 +262,7 @@ struct Profiler {
 void prof_begin(hipStream_t st, hipEvent_t* a) {
   *a = nullptr;
   if (!g_prof.on) return;
-  if (hipEventCreate(a) != hipSuccess) {
+  if (hip_failed(hipEventCreate(a))) {
     *a = nullptr;
     return;
   }
@@ -255,7 +272,7 @@ void prof_begin(hipStream_t st, hipEvent_t* a) {
 void prof_end(hipStream_t st, hipEvent_t a) {
   if (!a) return;
   hipEvent_t b;
-  if (hipEventCreate(&b) != hipSuccess) return;
+  if (hip_failed(hipEventCreate(&b))) return;
   (void)hipEventRecord(b, st);
   std::lock_guard<std::mutex> lk(g_prof.mu);
   g_prof.ev.emplace_back(a, b);
@@ -272,7 +289,7 @@ ihs_status run_pass(const ihs_matrix* A, const Layout& L, const ihs_sketch* sk,
                     int64_t ld_sa, const double* b, const double* x, double* r_out,
                     hipStream_t st) {
   SketchPlan P = make_plan(L, sk, B, iter);
-  if (launch_sort(P, st) != hipSuccess) return IHS_ERR_HIP;
+  if (hip_failed(launch_sort(P, st))) return IHS_ERR_HIP;
   return run_gather(A, sk, B, P, SA, sa_dtype, ld_sa, b, x, r_out, st);
 }
 
@@ -318,7 +335,7 @@ ihs_status run_gather(const ihs_matrix* A, const ihs_sketch* sk, const PassBuffe
     err = launch_sketch_gather_csr(P, G, st);
   }
   prof_end(st, e0);
-  return err == hipSuccess ? IHS_OK : IHS_ERR_HIP;
+  return hip_status(err);
 }
 
 // Natural-order gradient pass + reduction into B.g / B.f.
@@ -335,15 +352,15 @@ ihs_status run_gradient(const ihs_matrix* A, const Layout& L, const PassBuffers&
                                    A->col_idx, static_cast<const double*>(A->values), A->d, bb,
                                    x, B.gpart, B.fpart, r_out, st);
   }
-  if (err != hipSuccess) return IHS_ERR_HIP;
+  if (hip_failed(err)) return IHS_ERR_HIP;
   if (L.total_seg == 0) {
-    if (fill(g, (int64_t)L.batch * L.d, 0.0, st) != hipSuccess) return IHS_ERR_HIP;
-    if (f && fill(f, L.batch, 0.0, st) != hipSuccess) return IHS_ERR_HIP;
+    if (hip_failed(fill(g, (int64_t)L.batch * L.d, 0.0, st))) return IHS_ERR_HIP;
+    if (f && hip_failed(fill(f, L.batch, 0.0, st))) return IHS_ERR_HIP;
     return IHS_OK;
   }
   err = launch_reduce_partials(B.gpart, B.fpart, L.batch, 0, B.probs, L.d, g, f, status, iter,
                                B.red, st);
-  return err == hipSuccess ? IHS_OK : IHS_ERR_HIP;
+  return hip_status(err);
 }
 
 struct SolveBuffers {
@@ -417,13 +434,13 @@ hipStream_t side_stream(int which) {
   static std::mutex mu;
   static std::vector<hipStream_t> streams;
   int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  if (hip_failed(hipGetDevice(&dev))) return nullptr;
   std::lock_guard<std::mutex> lk(mu);
   const size_t slot = (size_t)dev * 2 + (size_t)which;
   if (streams.size() <= slot) streams.resize(slot + 1, nullptr);
   if (!streams[slot]) {
     hipStream_t s = nullptr;
-    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return nullptr;
+    if (hip_failed(hipStreamCreateWithFlags(&s, hipStreamNonBlocking))) return nullptr;
     streams[slot] = s;
   }
   return streams[slot];
@@ -436,7 +453,7 @@ struct EventRing {
   bool ok = true;
   explicit EventRing(int n) : ev(n, nullptr) {
     for (auto& e : ev)
-      if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) ok = false;
+      if (hip_failed(hipEventCreateWithFlags(&e, hipEventDisableTiming))) ok = false;
   }
   ~EventRing() {
     for (auto& e : ev)
@@ -473,9 +490,9 @@ ihs_status check_options(const ihs_options* o, bool need_loop) {
 }
 
 ihs_status read_status(DeviceStatus* dev, DeviceStatus* host, hipStream_t st) {
-  if (hipMemcpyAsync(host, dev, sizeof(DeviceStatus), hipMemcpyDeviceToHost, st) != hipSuccess)
+  if (hip_failed(hipMemcpyAsync(host, dev, sizeof(DeviceStatus), hipMemcpyDeviceToHost, st)))
     return IHS_ERR_HIP;
-  if (hipStreamSynchronize(st) != hipSuccess) return IHS_ERR_HIP;
+  if (hip_failed(hipStreamSynchronize(st))) return IHS_ERR_HIP;
   return IHS_OK;
 }
 
@@ -505,7 +522,7 @@ ihs_status solve_overlap(const ihs_matrix* A, const Layout& L, const ihs_options
   const int64_t bd = (int64_t)L.batch * d;
   EventRing evSort(4), evPass(4), evChol(4), evMisc(3);
   if (!evSort.ok || !evPass.ok || !evChol.ok || !evMisc.ok) return IHS_ERR_HIP;
-  auto ck = [](hipError_t e) { return e == hipSuccess; };
+  auto ck = [](hipError_t e) { return !hip_failed(e); };
   // the extra streams start after everything already queued on the caller's stream
   if (!ck(hipEventRecord(evMisc.at(0), stream)) || !ck(hipStreamWaitEvent(side, evMisc.at(0), 0)) ||
       !ck(hipStreamWaitEvent(sorter, evMisc.at(0), 0)))
@@ -657,6 +674,11 @@ const char* ihs_status_string(int32_t status) {
   }
 }
 
+const char* ihs_last_hip_error(int32_t* code) {
+  if (code) *code = t_last_hip_error;
+  return t_last_hip_error ? hipGetErrorName((hipError_t)t_last_hip_error) : "hipSuccess";
+}
+
 ihs_status ihs_sketch_hash(const ihs_sketch* sk, int64_t n, int32_t problem, int32_t* bucket,
                            int8_t* sign, hipStream_t stream) {
   if (!valid_sketch(sk) || n < 0 || problem < 0) return IHS_ERR_INVALID_ARG;
@@ -668,8 +690,8 @@ ihs_status ihs_sketch_hash(const ihs_sketch* sk, int64_t n, int32_t problem, int
   P.m_blk = sk->m / sk->s;
   P.seed = sk->seed;
   P.iter = sk->iter;
-  return launch_sketch_hash(P, n, problem, bucket, sign, stream) == hipSuccess ? IHS_OK
-                                                                              : IHS_ERR_HIP;
+  clear_stale_error();
+  return hip_status(launch_sketch_hash(P, n, problem, bucket, sign, stream));
 }
 
 size_t ihs_workspace_size(const ihs_matrix* A, const ihs_options* opt) {
@@ -696,6 +718,7 @@ ihs_status ihs_sketch_apply(const ihs_sketch* sk, const ihs_matrix* A, void* SA,
   PassBuffers tmp;
   carve_pass(need, L, sk, tmp);
   if (ws_bytes < need.used) return IHS_ERR_WORKSPACE;
+  clear_stale_error();
   Carver c(ws);
   PassBuffers B;
   carve_pass(c, L, sk, B);
@@ -717,6 +740,7 @@ ihs_status ihs_sketch_adjoint(const ihs_sketch* sk, int64_t n, int64_t d, int32_
   }
   if (n >= (int64_t(1) << 31)) return IHS_ERR_UNSUPPORTED;
   if (sk->s > 16) return IHS_ERR_UNSUPPORTED;
+  clear_stale_error();
   for (int32_t p0 = 0; p0 < batch; p0 += kAdjointBatch) {
     AdjointBatch ab{};
     ab.count = std::min<int32_t>(kAdjointBatch, batch - p0);
@@ -725,9 +749,9 @@ ihs_status ihs_sketch_adjoint(const ihs_sketch* sk, int64_t n, int64_t d, int32_
       const int32_t p = p0 + std::min<int32_t>(i, ab.count);
       ab.off[i] = batch > 1 ? row_offsets[p] : (p == 0 ? 0 : n);
     }
-    if (launch_sketch_adjoint(ab, sk->s, sk->m, sk->seed, sk->iter,
+    if (hip_failed(launch_sketch_adjoint(ab, sk->s, sk->m, sk->seed, sk->iter,
                               G + (int64_t)p0 * sk->m * ld_g, ld_g, d, out, ld_out,
-                              stream) != hipSuccess)
+                              stream)))
       return IHS_ERR_HIP;
   }
   return IHS_OK;
@@ -745,9 +769,8 @@ ihs_status ihs_gram(const void* SA, int32_t in_dtype, int64_t m, int64_t d, int6
   if (!SA || !H || !ws || m < 1 || d < 1 || batch < 1 || ld < d) return IHS_ERR_INVALID_ARG;
   if (!valid_gram_types(in_dtype, acc_dtype)) return IHS_ERR_INVALID_ARG;
   if (ws_bytes < gram_partials_bytes(m, d, batch, in_dtype, acc_dtype)) return IHS_ERR_WORKSPACE;
-  return launch_gram(SA, in_dtype, m, d, ld, batch, acc_dtype, H, ws, stream) == hipSuccess
-             ? IHS_OK
-             : IHS_ERR_HIP;
+  clear_stale_error();
+  return hip_status(launch_gram(SA, in_dtype, m, d, ld, batch, acc_dtype, H, ws, stream));
 }
 
 ihs_status ihs_gradient(const ihs_matrix* A, const double* b, const double* x, double* g,
@@ -760,6 +783,7 @@ ihs_status ihs_gradient(const ihs_matrix* A, const double* b, const double* x, d
   PassBuffers tmp;
   carve_pass(need, L, nullptr, tmp);
   if (ws_bytes < need.used) return IHS_ERR_WORKSPACE;
+  clear_stale_error();
   Carver c(ws);
   PassBuffers B;
   carve_pass(c, L, nullptr, B);
@@ -782,6 +806,7 @@ ihs_status ihs_qp_step(int64_t d, int32_t batch, const double* H, const double* 
   if (d < 1 || batch < 1 || !H || !g || !x || !x_out || !opt || !ws) return IHS_ERR_INVALID_ARG;
   if (!valid_constraint(opt->constraint, opt->radius)) return IHS_ERR_INVALID_ARG;
   if (ws_bytes < ihs_qp_workspace_size(d, batch, opt) - 256) return IHS_ERR_WORKSPACE;
+  clear_stale_error();
   Carver c(ws);
   DeviceStatus* st = c.take<DeviceStatus>(1);
   double* Lf = c.take<double>((size_t)(batch * d * d));
@@ -804,7 +829,7 @@ ihs_status ihs_qp_step(int64_t d, int32_t batch, const double* H, const double* 
   a.iter = 0;
   const hipError_t e = launch_qp_step(a, stream);
   if (e == hipErrorNotSupported) return IHS_ERR_UNSUPPORTED;
-  if (e != hipSuccess) return IHS_ERR_HIP;
+  if (hip_failed(e)) return IHS_ERR_HIP;
   DeviceStatus host;
   if (read_status(st, &host, stream) != IHS_OK) return IHS_ERR_HIP;
   return (ihs_status)host.code;
@@ -828,6 +853,7 @@ ihs_status ihs_solve(const ihs_matrix* A, const double* b, const ihs_options* op
   SolveBuffers tmp;
   carve_solve(need, L, opt, tmp);
   if (ws_bytes < need.used) return IHS_ERR_WORKSPACE;
+  clear_stale_error();
   Carver c(ws);
   SolveBuffers S;
   carve_solve(c, L, opt, S);
@@ -841,11 +867,11 @@ ihs_status ihs_solve(const ihs_matrix* A, const double* b, const ihs_options* op
     const uint64_t iter = opt->sketch.iter + (uint64_t)t;
     s = run_pass(A, L, &opt->sketch, B, iter, S.SA, opt->gram_in, d, b, x, nullptr, stream);
     if (s != IHS_OK) return s;
-    if (launch_reduce_partials(B.gpart, B.fpart, L.batch, pass_parts(A, &opt->sketch, L.batch), B.probs,
-                               d, B.g, B.f, B.status, t, B.red, stream) != hipSuccess)
+    if (hip_failed(launch_reduce_partials(B.gpart, B.fpart, L.batch, pass_parts(A, &opt->sketch, L.batch), B.probs,
+                               d, B.g, B.f, B.status, t, B.red, stream)))
       return IHS_ERR_HIP;
-    if (launch_gram(S.SA, opt->gram_in, m, d, d, L.batch, opt->gram_acc, S.H, S.gram_part,
-                    stream) != hipSuccess)
+    if (hip_failed(launch_gram(S.SA, opt->gram_in, m, d, d, L.batch, opt->gram_acc, S.H, S.gram_part,
+                    stream)))
       return IHS_ERR_HIP;
     QpArgs a{};
     a.d = d;
@@ -865,9 +891,9 @@ ihs_status ihs_solve(const ihs_matrix* A, const double* b, const ihs_options* op
     a.warm = t > 0 ? 1 : 0;
     const hipError_t e = launch_qp_step(a, stream);
     if (e == hipErrorNotSupported) return IHS_ERR_UNSUPPORTED;
-    if (e != hipSuccess) return IHS_ERR_HIP;
-    if (x_hist && hipMemcpyAsync(x_hist + (int64_t)t * bd, x, bd * sizeof(double),
-                                 hipMemcpyDeviceToDevice, stream) != hipSuccess)
+    if (hip_failed(e)) return IHS_ERR_HIP;
+    if (x_hist && hip_failed(hipMemcpyAsync(x_hist + (int64_t)t * bd, x, bd * sizeof(double),
+                                 hipMemcpyDeviceToDevice, stream)))
       return IHS_ERR_HIP;
   }
   DeviceStatus host;
@@ -896,14 +922,15 @@ ihs_status ihs_adjoint_solve(const ihs_matrix* A, const double* xbar, const doub
   carve_pass(need, L, nullptr, tmp);
   need.take<double>((size_t)(2 * L.batch * A->d));
   if (ws_bytes < need.used) return IHS_ERR_WORKSPACE;
+  clear_stale_error();
   Carver c(ws);
   PassBuffers B;
   carve_pass(c, L, nullptr, B);
   double* v = c.take<double>((size_t)(L.batch * A->d));
   if ((s = upload_probs(L, B, stream)) != IHS_OK) return s;
   const int64_t bd = (int64_t)L.batch * A->d;
-  if (fill(B.bzero, A->n, 0.0, stream) != hipSuccess) return IHS_ERR_HIP;
-  if (fill(lambda, bd, 0.0, stream) != hipSuccess) return IHS_ERR_HIP;
+  if (hip_failed(fill(B.bzero, A->n, 0.0, stream))) return IHS_ERR_HIP;
+  if (hip_failed(fill(lambda, bd, 0.0, stream))) return IHS_ERR_HIP;
   for (int32_t k = 0; k < n_factors; ++k) {
     // v = xbar - A^T A lambda = xbar + A^T (0 - A lambda)
     if ((s = run_gradient(A, L, B, B.bzero, lambda, B.g, nullptr, nullptr, B.status, k,
@@ -912,12 +939,12 @@ ihs_status ihs_adjoint_solve(const ihs_matrix* A, const double* xbar, const doub
     hipLaunchKernelGGL(k_add, dim3((unsigned)((bd + 255) / 256)), dim3(256), 0, stream, xbar,
                        B.g, v, bd);
     const double* Lk = factors + (int64_t)k * L.batch * A->d * A->d;
-    if (launch_recip_diag(Lk, A->d, L.batch, B.rdiag, stream) != hipSuccess) return IHS_ERR_HIP;
-    if (launch_chol_solve_update(Lk, B.rdiag, A->d, L.batch, v, lambda, lambda, B.status,
-                                 stream) != hipSuccess)
+    if (hip_failed(launch_recip_diag(Lk, A->d, L.batch, B.rdiag, stream))) return IHS_ERR_HIP;
+    if (hip_failed(launch_chol_solve_update(Lk, B.rdiag, A->d, L.batch, v, lambda, lambda, B.status,
+                                 stream)))
       return IHS_ERR_HIP;
   }
-  return hipGetLastError() == hipSuccess ? IHS_OK : IHS_ERR_HIP;
+  return hip_status(hipGetLastError());
 }
 
 ihs_status ihs_solution_grads(const ihs_matrix* A, const double* b, const double* x,
@@ -931,18 +958,17 @@ ihs_status ihs_solution_grads(const ihs_matrix* A, const double* b, const double
   const size_t esz = f32 ? sizeof(float) : sizeof(double);
   if (dl_da && ld_da < A->d) return IHS_ERR_INVALID_ARG;
   const Layout L = make_layout(A, 1);
-  // per-row problem index comes from the row offsets; pass them as a small
-  // device table through the per-problem launches
+  clear_stale_error();
   for (int32_t p = 0; p < L.batch; ++p) {
     const ProbInfo& q = L.probs[p];
     if (q.rows == 0) continue;
-    if (launch_solution_grads(nullptr, 1, q.rows, A->d,
+    if (hip_failed(launch_solution_grads(nullptr, 1, q.rows, A->d,
                               static_cast<const char*>(A->values) + q.row0 * A->ld * esz, f32,
                               A->ld,
                               b + q.row0, x + (int64_t)p * A->d, lambda + (int64_t)p * A->d,
                               dl_db ? dl_db + q.row0 : nullptr,
                               dl_da ? dl_da + q.row0 * ld_da : nullptr, ld_da,
-                              stream) != hipSuccess)
+                              stream)))
       return IHS_ERR_HIP;
   }
   return IHS_OK;
@@ -963,9 +989,9 @@ ihs_status ihs_profile_read(int64_t* launches, double* total_ms) {
   std::lock_guard<std::mutex> lk(g_prof.mu);
   double tot = 0.0;
   for (auto& e : g_prof.ev) {
-    if (hipEventSynchronize(e.second) != hipSuccess) return IHS_ERR_HIP;
+    if (hip_failed(hipEventSynchronize(e.second))) return IHS_ERR_HIP;
     float ms = 0.f;
-    if (hipEventElapsedTime(&ms, e.first, e.second) != hipSuccess) return IHS_ERR_HIP;
+    if (hip_failed(hipEventElapsedTime(&ms, e.first, e.second))) return IHS_ERR_HIP;
     tot += ms;
   }
   *launches = (int64_t)g_prof.ev.size();

@@ -129,3 +129,12 @@ def test_hash_validation(lib):
     sk = P.Sketch_t(P.COUNTSKETCH, 1, 10, 0, 0)
     assert lib.ihs_sketch_hash(ctypes.byref(sk), -1, 0, ctypes.c_void_p(8), ctypes.c_void_p(8),
                                None) == P.ERR_INVALID_ARG
+
+
+def test_last_hip_error_before_any_failure(lib):
+    """Host only: with no failed HIP call on this thread the query names
+    hipSuccess and writes code 0."""
+    code = ctypes.c_int32(-1)
+    assert lib.ihs_last_hip_error(ctypes.byref(code)) == b"hipSuccess"
+    assert code.value == 0
+    assert lib.ihs_last_hip_error(None) == b"hipSuccess"

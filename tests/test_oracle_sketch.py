@@ -199,3 +199,25 @@ def test_adjoint_dot_identity_and_explicit(s):
     Gi = g.integers(-20, 20, size=(m, d)).astype(float)
     S = dense_sketch_matrix(6, 1, n, m, s)
     assert np.array_equal(sketch_adjoint(Gi, n, 6, 1, m, s), S.T @ Gi)
+
+
+def test_table1_like_shapes_and_values():
+    """The Table 1 stand-ins have the table's shape and density, canonical CSR
+    (sorted distinct columns per row) and the stated values."""
+    import json
+    import os
+    import workloads as W
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                       "table1_datasets.json")))
+    for ds in gold["datasets"]:
+        if ds["name"] == "W8A" or ds["name"] == "Abtaha":
+            wl = W.table1_like(ds["name"])
+            assert (wl.n, wl.d) == (ds["n"], ds["d"])
+            assert wl.indptr[-1] == round(ds["density"] * ds["n"] * ds["d"])
+            for r in range(0, wl.n, 997):
+                cols = wl.indices[wl.indptr[r]:wl.indptr[r + 1]]
+                assert np.all(np.diff(cols) > 0)
+            if ds["name"] == "W8A":
+                assert np.all(wl.data == 1.0)
+            else:
+                assert abs(wl.data.mean()) < 0.01 and abs(wl.data.std() - 1) < 0.01

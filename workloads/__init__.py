@@ -22,6 +22,11 @@ run the same recipe at small n):
                  CountSketch m=4096, C = R^d
   batch_ragged   64 problems, n_i uniform in [16384, 131072], d = 64,
                  m = 10 d, 20 steps, target y ~ N(0,1) for L = ||x - y||^2
+  table1_like    CSR stand-ins with the shape and density of the datasets of
+                 App. B, Table 1 (default: W8A, 49749 x 300 at 4%): rows
+                 uniform, columns from a truncated Zipf(1.1) pmf, values 1.0
+                 for the binary-feature W*A sets and N(0,1) otherwise; used
+                 for the sketch-error sweep of App. B, Fig. 2
 
 Two backends draw the same recipe: "numpy" (CPU float64, used at test sizes)
 and "torch" (any torch device, used at full size on the GPU). They use
@@ -295,6 +300,60 @@ def batch_ragged(num=64, n_lo=16384, n_hi=131072, d=64, m=None, iters=20,
     return Workload("batch_ragged", N, d, b, x_star, "none", 0.0,
                     "countsketch", m, 1, iters, seed + 1000, A=A,
                     row_offsets=row_offsets, y=y)
+
+
+# --------------------------------------------------------------------------
+# table1_like: sparse stand-ins with the shapes and densities of Table 1
+# --------------------------------------------------------------------------
+TABLE1 = {  # name: (n, d, density), App. B, Table 1
+    "abtaha": (37932, 330, 0.01),
+    "specular": (477976, 50, 0.01),
+    "w4a": (7366, 300, 0.04),
+    "w6a": (17188, 300, 0.04),
+    "w8a": (49749, 300, 0.04),
+    "yearpredictionmsd": (515344, 90, 1.0),
+}
+
+
+def table1_like(name="w8a", rows=None, seed=BASE_SEED + 5, values=None):
+    """CSR matrix with Table 1's shape and density for `name`. Nonzero
+    positions: rows uniform, columns from the Zipf(1.1) pmf truncated to d;
+    repeated positions are drawn again until the target count of distinct
+    positions is reached. Values: 1.0 for the W*A sets (binary features),
+    N(0,1) otherwise (or as `values` says: "binary" | "gaussian").
+    b = A x* + 0.1 w with x* ~ N(0,1); the LASSO weight of Sec. 3 (5.0) is
+    carried as the radius."""
+    n0, d, density = TABLE1[name.lower()]
+    n = n0 if rows is None else int(rows)
+    if values is None:
+        values = "binary" if name.lower().startswith("w") else "gaussian"
+    g = _np_rng(seed)
+    target = int(round(density * n * d))
+    pmf = zipf_pmf(d)
+    keys = np.empty(0, dtype=np.int64)
+    while len(keys) < target:
+        need = target - len(keys)
+        r = g.integers(0, n, size=need + need // 8 + 16, dtype=np.int64)
+        c = g.choice(d, size=len(r), p=pmf).astype(np.int64)
+        keys = np.unique(np.concatenate([keys, r * d + c]))
+    keys = np.sort(g.permutation(keys)[:target])   # an unbiased subset, sorted
+    rows_u = keys // d
+    cols_u = (keys % d).astype(np.int32)
+    if values == "binary":
+        data = np.ones(target)
+    else:
+        data = g.standard_normal(target)
+    counts = np.bincount(rows_u, minlength=n)
+    indptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(counts, out=indptr[1:])
+    x_star = g.standard_normal(d)
+    prod = np.zeros(n)
+    np.add.at(prod, rows_u, data * x_star[cols_u])
+    b = prod + 0.1 * g.standard_normal(n)
+    return Workload(name.lower() + "_like", n, d, b, x_star, "l1_penalty", 5.0,
+                    "countsketch", 10 * d, 1, 20, seed + 1000,
+                    indptr=indptr.astype(np.int32), indices=cols_u, data=data,
+                    meta={"nnz": target, "density": density})
 
 
 def csr_to_dense(indptr, indices, data, n, d):
