@@ -215,11 +215,11 @@ def main():
         xo = reference_solution(wl)
         Axo = float(chunked_matvec(wl.A, xo).norm())
 
-        def time_to_tol(Mv, Aerr, xref, Axref, gin, gacc, schedule="overlap"):
-            o = P.options(m, seed=wl.sketch_seed, max_iter=args.steps, gram_in=gin,
+        def time_to_tol(Mv, Aerr, xref, Axref, gin, gacc, schedule="overlap", mm=m):
+            o = P.options(mm, seed=wl.sketch_seed, max_iter=args.steps, gram_in=gin,
                           gram_acc=gacc, schedule=schedule)
             ws_v = torch.empty(P.workspace_size(Mv, o), dtype=torch.uint8, device=dev)
-            P.solve(Mv, b, P.options(m, seed=wl.sketch_seed + 7, max_iter=2, gram_in=gin,
+            P.solve(Mv, b, P.options(mm, seed=wl.sketch_seed + 7, max_iter=2, gram_in=gin,
                                      gram_acc=gacc, schedule=schedule), ws=ws_v,
                     raise_on_error=False)
             torch.cuda.synchronize()
@@ -227,7 +227,7 @@ def main():
             P.solve(Mv, b, o, ws=ws_v, raise_on_error=False)
             torch.cuda.synchronize()
             step_ms = 1e3 * (time.perf_counter() - t1) / args.steps
-            o2 = P.options(m, seed=wl.sketch_seed, max_iter=args.max_iter, gram_in=gin,
+            o2 = P.options(mm, seed=wl.sketch_seed, max_iter=args.max_iter, gram_in=gin,
                            gram_acc=gacc, schedule=schedule)
             rh = P.solve(Mv, b, o2, history=True, ws=ws_v, raise_on_error=False)
             errs = []
@@ -264,45 +264,69 @@ def main():
         # mixed storage: the first K steps read the float32 copy (half the
         # bytes per pass), the rest read A itself, so the iterate converges to
         # A's own x_OPT; both copies are resident
-        K = args.mixed_switch
         M32 = P.Matrix(dense=A32)
-        o32 = P.options(m, seed=wl.sketch_seed, max_iter=K)
-        r32 = P.solve(M32, b, o32, raise_on_error=False)
-        o64 = P.options(m, seed=wl.sketch_seed, iter0=K, max_iter=args.max_iter - K)
-        rh = P.solve(M, b, o64, x0=r32.x, history=True, raise_on_error=False)
-        errs = [rel_err_A(wl.A, r32.x[0], xo, Axo)]
-        hit = None
-        upto = rh.report.iters if rh.report.status else args.max_iter - K
-        for t in range(upto):
-            e = rel_err_A(wl.A, rh.history[t, 0], xo, Axo)
-            errs.append(e)
-            if e <= args.tol:
-                hit = K + t + 1
-                break
-        mixed = {"switch_after": K, "iters_to_tol": hit,
-                 "err_A_at_switch": errs[0], "final_err_A": errs[-1],
-                 "status": P._status_text(rh.report.status) if rh.report.status else "ok",
-                 "reference": "x_OPT of A (float64), the same problem as the float64 path"}
-        if hit:
-            o64b = P.options(m, seed=wl.sketch_seed, iter0=K, max_iter=hit - K)
-            for _ in range(2):  # the second run is timed
-                torch.cuda.synchronize()
-                t1 = time.perf_counter()
-                r32 = P.solve(M32, b, o32, raise_on_error=False)
-                P.solve(M, b, o64b, x0=r32.x, raise_on_error=False)
-                torch.cuda.synchronize()
-            mixed["time_to_tol_ms"] = round(1e3 * (time.perf_counter() - t1), 3)
+
+        def mixed_run(mm, K):
+            o32 = P.options(mm, seed=wl.sketch_seed, max_iter=K)
+            r32 = P.solve(M32, b, o32, raise_on_error=False)
+            o64 = P.options(mm, seed=wl.sketch_seed, iter0=K, max_iter=args.max_iter - K)
+            rh = P.solve(M, b, o64, x0=r32.x, history=True, raise_on_error=False)
+            errs = [rel_err_A(wl.A, r32.x[0], xo, Axo)]
+            hit = None
+            upto = rh.report.iters if rh.report.status else args.max_iter - K
+            for t in range(upto):
+                e = rel_err_A(wl.A, rh.history[t, 0], xo, Axo)
+                errs.append(e)
+                if e <= args.tol:
+                    hit = K + t + 1
+                    break
+            res = {"m": mm, "switch_after": K, "iters_to_tol": hit,
+                   "err_A_at_switch": errs[0], "final_err_A": errs[-1],
+                   "status": P._status_text(rh.report.status) if rh.report.status else "ok",
+                   "reference": "x_OPT of A (float64), the same problem as the float64 path"}
+            if hit:
+                o64b = P.options(mm, seed=wl.sketch_seed, iter0=K, max_iter=hit - K)
+                for _ in range(2):  # the second run is timed
+                    torch.cuda.synchronize()
+                    t1 = time.perf_counter()
+                    r32 = P.solve(M32, b, o32, raise_on_error=False)
+                    P.solve(M, b, o64b, x0=r32.x, raise_on_error=False)
+                    torch.cuda.synchronize()
+                res["time_to_tol_ms"] = round(1e3 * (time.perf_counter() - t1), 3)
+            return res
+
+        def switch_point(mm):
+            """First step at which the float32 iterate is within 5x of the
+            distance between the two problems' minimisers (the float32 floor)."""
+            rh = P.solve(M32, b, P.options(mm, seed=wl.sketch_seed, max_iter=args.max_iter),
+                         history=True, raise_on_error=False)
+            floor = 5 * v32["x_opt_shift"]
+            for t in range(args.max_iter):
+                if rel_err_A(wl.A, rh.history[t, 0], xo, Axo) <= floor:
+                    return t + 1
+            return args.max_iter // 2
+
+        mixed = mixed_run(m, args.mixed_switch)
         ttt["A-float32-then-float64"] = mixed
-        del A32, M32
         fp64 = ttt["float64-in/float64-acc"]["time_to_tol_ms"]
         same = {k: v for k, v in ttt.items() if k != "A-float32/float64-in/float64-acc"}
         best = min((v["time_to_tol_ms"], k) for k, v in same.items()
                    if v.get("time_to_tol_ms") is not None) if any(
             v.get("time_to_tol_ms") for v in same.values()) else (None, None)
+        # the sketch size is a parameter of the method, not of the problem: a
+        # larger m contracts the error faster per step (Thm 2.2) while a step
+        # still reads A once; the Gram and factorisation grow beside the pass
+        larger = {}
+        for mm in (8192, 16384):
+            larger[f"float64, m={mm}"] = time_to_tol(M, wl.A, xo, Axo, "float64", "float64",
+                                                     mm=mm)
+        larger["A-float32-then-float64, m=16384"] = mixed_run(16384, switch_point(16384))
+        del A32, M32
         out["time_to_tol"] = {"tol": args.tol, "norm": "||A(x - x_OPT)|| / ||A x_OPT||",
                               "reference": "structural x_OPT refined in torch fp64",
                               "fp64_ms": fp64, "fastest_same_problem": best[1],
-                              "variants": ttt}
+                              "variants": ttt,
+                              "larger_sketch": larger}
         torch.cuda.empty_cache()
 
     # ---------------------------------------------- per-row timings ----

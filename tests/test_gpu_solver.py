@@ -269,3 +269,22 @@ def test_overlap_reports_not_pd_step(gpu_lib):
                   P.options(320, max_iter=4), raise_on_error=False, history=True)
     assert res.report.status == P.ERR_NOT_PD and res.report.failed_iter == 0
     assert bool((res.x == 0).all())
+
+
+def test_largest_sketch_overlapped_iterates_match_oracle(gpu_lib):
+    """m = 16384, the largest sketch the library takes per problem, on the
+    overlapped schedule the benchmark times for its larger-sketch variants:
+    every iterate matches the oracle's, and the error contracts faster per
+    step than at m = 8 d."""
+    P = gpu_lib
+    wl = W.ols_dense(rows=60000, d=96, m=16384, iters=6)
+    opts = P.options(wl.m, seed=wl.sketch_seed, max_iter=wl.iters, schedule="overlap")
+    res = P.solve(P.Matrix(dense=dev(wl.A)), dev(wl.b), opts, history=True)
+    assert res.report.status == 0 and res.report.iters == wl.iters
+    xs = O.ihs(wl.A, wl.b, wl.m, seed=wl.sketch_seed, iters=wl.iters)
+    hist = host(res.history)[:, 0, :]
+    xo = O.x_opt(wl.A, wl.b)
+    for t in range(wl.iters):
+        assert np.linalg.norm(hist[t] - xs[t + 1]) <= 1e-11 * np.linalg.norm(xs[t + 1]), t
+    errs = [O.error_A(wl.A, hist[t], xo) for t in range(wl.iters)]
+    assert errs[3] < 0.2 ** 4
