@@ -7,15 +7,17 @@
 // Cholesky kernels) and return it when it already lies in the ball.
 //
 // l1 ball ||x||_1 <= tau (one 1024-thread workgroup per problem, d <= 1024):
-//   accelerated projected gradient (FISTA) with step 1/B, B the Gershgorin
-//   bound of lambda_max(H), momentum restart by the gradient-mapping test of
+//   accelerated projected gradient (FISTA) with step 1/L, L from power steps
+//   raised by backtracking, momentum restart by the gradient-mapping test of
 //   O'Donoghue and Candes (2015), and the exact finite projection of
 //   Michelot (1986). Once the support and signs stop changing (and at the
 //   end), a KKT polish solves the face exactly,
 //       H_SS x_S + mu sigma = c_S,   sigma^T x_S = tau,
-//   and is accepted when it keeps the signs, has mu >= 0 and leaves every
-//   off-support |c_j - (H x)_j| <= mu (to 1e-9 max(1, |c|_inf)). An accepted
-//   KKT point is the minimiser, which ends the iteration.
+//   (a Cholesky factor of H_SS in LDS when it fits, conjugate gradients on
+//   the two right-hand sides otherwise) and is accepted when it keeps the
+//   signs, has mu >= 0 and leaves every off-support |c_j - (H x)_j| <= mu
+//   (to 1e-9 max(1, |c|_inf)). An accepted KKT point is the minimiser, which
+//   ends the iteration.
 // l1 penalty lambda ||x||_1 added to the objective (the penalised LASSO of
 // the experiments of Sec. 3): the same kernel with the soft threshold by
 // lambda / L as the proximal map in place of the projection, and the polish
@@ -39,11 +41,20 @@ constexpr int kQpThreads = 1024;
 constexpr int kQpWaves = kQpThreads / 64;
 constexpr int kPolishMax = 256;   // largest support the KKT polish takes on
 constexpr int kPolishEvery = 16;  // unchanged iterations before a polish attempt
+constexpr int kPowerSteps = 8;    // power steps for the first Lipschitz estimate
 constexpr size_t kQpLdsBytes = 61440;
 
 constexpr int kRed = 8;  // values one fused block reduction carries
 
+constexpr int kColChunk = 256;  // columns per pass of the symmetric product
+constexpr int kRowsPer = 4;     // rows whose loads a wavefront issues together
+
+struct ColPartials {
+  double v[kQpWaves][kColChunk];
+};
+
 struct BlockShared {
+  ColPartials part;
   double red[kQpWaves];
   double redv[kQpWaves][kRed];
   int flag[4];
@@ -102,23 +113,65 @@ __device__ __forceinline__ void block_reduce(double (&v)[NS + NM], BlockShared& 
   }
 }
 
-// out[i] = sum_k |H[i][k]| (ABS) or (H v)[i], one wavefront per row so each
-// row is read coalesced; v and out in LDS. Ends with a barrier.
-template <bool ABS>
-__device__ __forceinline__ void block_rows(const double* __restrict__ H, int64_t d,
-                                           const double* v, double* out) {
+// out = H v for the symmetric H, v and out in LDS, formed by columns:
+// (H v)_j = sum_i v_i H[i][j]. Lane l of wavefront w accumulates columns
+// c0 + l + 64 q (q < 4) of a 256-column chunk over rows w, w + 16, ..., four
+// rows' loads at a time (rows read coalesced, no cross-lane reduction); the
+// 16 wavefronts' partial sums are then added through LDS in a fixed order.
+// Ends with a barrier.
+template <int NV>
+__device__ __forceinline__ void sym_products(const double* __restrict__ H, int64_t d,
+                                             const double* const (&v)[NV], double* const (&out)[NV],
+                                             ColPartials& part) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int64_t i = wv; i < d; i += kQpWaves) {
-    const double* hr = H + i * d;
-    double s = 0.0;
-    for (int64_t k = lane; k < d; k += 64) {
-      if constexpr (ABS) s += fabs(hr[k]);
-      else s = fma(hr[k], v[k], s);
+  for (int64_t c0 = 0; c0 < d; c0 += kColChunk) {
+    double acc[NV][4];
+#pragma unroll
+    for (int n = 0; n < NV; ++n)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[n][q] = 0.0;
+    for (int64_t i0 = (int64_t)wv * kRowsPer; i0 < d; i0 += kQpWaves * kRowsPer) {
+      double h[kRowsPer][4];
+#pragma unroll
+      for (int r = 0; r < kRowsPer; ++r) {
+        const int64_t i = i0 + r < d ? i0 + r : d - 1;
+        const double* hr = H + i * d + c0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int64_t j = lane + 64 * q;
+          h[r][q] = (c0 + j < d) ? hr[j] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < kRowsPer; ++r)
+#pragma unroll
+        for (int n = 0; n < NV; ++n) {
+          const double vi = i0 + r < d ? v[n][i0 + r] : 0.0;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) acc[n][q] = fma(h[r][q], vi, acc[n][q]);
+        }
     }
-    s = wave_sum(s);
-    if (lane == 0) out[i] = s;
+#pragma unroll
+    for (int n = 0; n < NV; ++n) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) part.v[wv][lane + 64 * q] = acc[n][q];
+      __syncthreads();
+      if (threadIdx.x < kColChunk && c0 + threadIdx.x < d) {
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < kQpWaves; ++w) s += part.v[w][threadIdx.x];
+        out[n][c0 + threadIdx.x] = s;
+      }
+      __syncthreads();
+    }
   }
-  __syncthreads();
+}
+
+__device__ __forceinline__ void block_rows(const double* __restrict__ H, int64_t d,
+                                           const double* v, double* out, BlockShared& sh) {
+  const double* const vs[1] = {v};
+  double* const os[1] = {out};
+  sym_products<1>(H, d, vs, os, sh.part);
 }
 
 // Euclidean projection onto {||x||_1 <= tau}, thread i < d holding v_i: when
@@ -147,13 +200,46 @@ __device__ double project_l1(double vi, int64_t d, double tau, BlockShared& sh) 
   return (tid < d && a > theta) ? copysign(a - theta, vi) : 0.0;
 }
 
+// Outcomes of a KKT polish on a face (support and signs).
+constexpr int kPolishAccepted = 0;  // the candidate meets the KKT conditions
+constexpr int kPolishRejected = 1;  // a candidate was formed but fails them
+constexpr int kPolishNone = 2;      // no candidate (factorisation or solve failed)
+
+// Common end of the polish variants: thread i holds the candidate xs (on the
+// support, signs sg) and the multiplier mu. The candidate is accepted when it
+// keeps the signs, mu >= 0, and every off-support |c_j - (H x)_j| <= mu (to
+// 1e-9 max(1, |c|_inf)). Unless the result is kPolishNone, *xi receives the
+// candidate, *gi = c_i - (H x)_i and *mu_out = mu, for an active-set update.
+// buf, hbuf: d doubles of LDS.
+__device__ int polish_finish(const double* __restrict__ H, int64_t d, double ci, bool on,
+                             double sg, double xs, double mu, double* buf, double* hbuf,
+                             double cscale, double* xi, double* gi, double* mu_out,
+                             BlockShared& sh) {
+  const int tid = threadIdx.x;
+  if (!(mu >= 0.0) || !isfinite(mu)) return kPolishNone;  // the same value in every thread
+  const bool bad = on && (!(copysign(1.0, xs) == sg) || xs == 0.0 || !isfinite(xs));
+  if (tid < d) buf[tid] = on ? xs : 0.0;
+  __syncthreads();
+  block_rows(H, d, buf, hbuf, sh);
+  const double g = tid < d ? ci - hbuf[tid] : 0.0;
+  double r[2] = {bad ? 1.0 : 0.0, (tid < d && !on) ? fabs(g) - mu : -1.0};
+  block_reduce<0, 2>(r, sh);
+  *xi = on ? xs : 0.0;
+  *gi = g;
+  *mu_out = mu;
+  return (r[0] == 0.0 && r[1] <= 1e-9 * cscale) ? kPolishAccepted : kPolishRejected;
+}
+
 // KKT polish on the support of x (thread i holds x_i in *xi). M: ns*ns
 // doubles (LDS or global), u, w: kPolishMax doubles, idx: kPolishMax ints,
 // cand, hc: d doubles of LDS. Ball (penalty false): mu from sigma^T x_S = tau;
 // penalty: mu = tau = lambda. On success returns true with the polished x_i.
-__device__ __attribute__((noinline)) bool l1_polish(const double* __restrict__ H, int64_t d, double ci, double tau,
-                          bool penalty, double* xi, double* M, double* u, double* w, int* idx,
-                          double* cand, double* hc, double cscale, BlockShared& sh) {
+__device__ __attribute__((noinline)) int l1_polish(const double* __restrict__ H, int64_t d,
+                                                   double ci, double tau, bool penalty,
+                                                   double* xi, double* gi, double* mu_out,
+                                                   double* M, double* u, double* w, int* idx,
+                                                   double* cand, double* hc, double cscale,
+                                                   BlockShared& sh) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const bool on = tid < d && *xi != 0.0;
   // ascending support indices by wave ballots
@@ -166,10 +252,10 @@ __device__ __attribute__((noinline)) bool l1_polish(const double* __restrict__ H
     ns += sh.wave_count[k];
   }
   if (ns == 0) {  // x = 0: optimal for the penalty when every |c_j| <= lambda
-    if (!penalty) return false;
-    return block_max(tid < d ? fabs(ci) - tau : -1.0, sh) <= 1e-9 * cscale;
+    if (!penalty) return kPolishNone;
+    return polish_finish(H, d, ci, false, 0.0, 0.0, tau, cand, hc, cscale, xi, gi, mu_out, sh);
   }
-  if (ns > kPolishMax) return false;
+  if (ns > kPolishMax) return kPolishNone;
   const int slot = on ? base + __popcll(bal & lanemask_lt()) : -1;
   if (on) idx[slot] = tid;
   __syncthreads();
@@ -198,7 +284,7 @@ __device__ __attribute__((noinline)) bool l1_polish(const double* __restrict__ H
     __syncthreads();
   }
   __syncthreads();
-  if (!sh.flag[2]) return false;
+  if (!sh.flag[2]) return kPolishNone;
   // u = H_SS^{-1} c_S and w = H_SS^{-1} sigma: forward then backward sweep
   for (int a = tid; a < ns; a += kQpThreads) u[a] = w[a] = 0.0;
   __syncthreads();
@@ -241,35 +327,120 @@ __device__ __attribute__((noinline)) bool l1_polish(const double* __restrict__ H
   const double SU = block_sum(on ? sg * u[slot] : 0.0, sh);
   const double SW = block_sum(on ? sg * w[slot] : 0.0, sh);
   const double mu = penalty ? tau : (SU - tau) / SW;
-  double xs = 0.0;
-  bool bad = false;
-  if (on) {
-    xs = u[slot] - mu * w[slot];
-    bad = !(copysign(1.0, xs) == sg) || xs == 0.0;
-  }
-  const double anybad = block_max(bad ? 1.0 : 0.0, sh);
-  if (anybad != 0.0 || !(mu >= 0.0) || !isfinite(mu)) return false;
-  if (tid < d) cand[tid] = xs;
-  __syncthreads();
-  block_rows<false>(H, d, cand, hc);
-  const double viol = (tid < d && !on) ? fabs(ci - hc[tid]) - mu : -1.0;
-  if (block_max(viol, sh) > 1e-9 * cscale) return false;
-  *xi = xs;
-  return true;
+  const double xs = on ? u[slot] - mu * w[slot] : 0.0;
+  return polish_finish(H, d, ci, on, sg, xs, mu, cand, hc, cscale, xi, gi, mu_out, sh);
 }
 
-// One workgroup per problem. xunc: the unconstrained minimiser; Lscratch:
-// d*d doubles per problem for a polish matrix too large for LDS.
+// KKT polish for a support too large to factor in LDS: the reduced systems
+// are solved by conjugate gradients instead of a Cholesky factor, with no
+// ns x ns storage. Ball: u = H_SS^{-1} c_S and w = H_SS^{-1} sigma_S from 0,
+// both right-hand sides advancing through the same sweeps over H; then
+// mu = (sigma^T u - tau) / sigma^T w and x_S = u - mu w. Penalty: x_S =
+// H_SS^{-1} (c_S - lambda sigma_S) from the current x_S. Each recurrence
+// stops once its residual is 1e-15 of its right-hand side (or after max_cg
+// sweeps). Acceptance as in l1_polish. pa, pb, qa, qb: d doubles of LDS.
+__device__ int l1_polish_cg(const double* __restrict__ H, int64_t d, double ci, double tau,
+                            bool penalty, double* xi, double* gi, double* mu_out, double* pa,
+                            double* pb, double* qa, double* qb, double cscale, int max_cg,
+                            BlockShared& sh) {
+  const int tid = threadIdx.x;
+  const bool on = tid < d && *xi != 0.0;
+  const double sg = on ? copysign(1.0, *xi) : 0.0;
+  const double fa = on ? (penalty ? ci - tau * sg : ci) : 0.0;
+  const double fb = (on && !penalty) ? sg : 0.0;
+  double a = (penalty && on) ? *xi : 0.0, b = 0.0;
+  double ra = fa, rb = fb;
+  if (penalty) {  // residual of the warm start
+    if (tid < d) pa[tid] = a;
+    __syncthreads();
+    block_rows(H, d, pa, qa, sh);
+    ra = on ? fa - qa[tid] : 0.0;
+  }
+  double n0[4] = {ra * ra, rb * rb, fa * fa, fb * fb};
+  block_reduce<4, 0>(n0, sh);
+  double rra = n0[0], rrb = n0[1];
+  const double tola = 1e-30 * n0[2], tolb = 1e-30 * n0[3];
+  double qA = ra, qB = rb;  // search directions
+  for (int k = 0; k < max_cg && (rra > tola || rrb > tolb); ++k) {
+    if (tid < d) {
+      pa[tid] = qA;
+      pb[tid] = qB;
+    }
+    __syncthreads();
+    {
+      const double* const vs[2] = {pa, pb};
+      double* const os[2] = {qa, qb};
+      sym_products<2>(H, d, vs, os, sh.part);
+    }
+    const double ha = on ? qa[tid] : 0.0, hb = on ? qb[tid] : 0.0;
+    double cv[2] = {qA * ha, qB * hb};
+    block_reduce<2, 0>(cv, sh);
+    const double al_a = (rra > tola && cv[0] > 0.0) ? rra / cv[0] : 0.0;
+    const double al_b = (rrb > tolb && cv[1] > 0.0) ? rrb / cv[1] : 0.0;
+    a = fma(al_a, qA, a);
+    b = fma(al_b, qB, b);
+    ra = fma(-al_a, ha, ra);
+    rb = fma(-al_b, hb, rb);
+    double nn[2] = {ra * ra, rb * rb};
+    block_reduce<2, 0>(nn, sh);
+    if (!(cv[0] > 0.0) && rra > tola) break;  // H_SS not positive definite
+    if (!(cv[1] > 0.0) && rrb > tolb) break;
+    const double be_a = rra > 0.0 ? nn[0] / rra : 0.0;
+    const double be_b = rrb > 0.0 ? nn[1] / rrb : 0.0;
+    qA = ra + be_a * qA;
+    qB = rb + be_b * qB;
+    rra = nn[0];
+    rrb = nn[1];
+  }
+  if (rra > tola || rrb > tolb || !isfinite(rra) || !isfinite(rrb)) return kPolishNone;
+  double mu = tau;
+  if (!penalty) {
+    double sw[2] = {sg * a, sg * b};
+    block_reduce<2, 0>(sw, sh);
+    mu = (sw[0] - tau) / sw[1];
+  }
+  const double xs = on ? (penalty ? a : a - mu * b) : 0.0;
+  return polish_finish(H, d, ci, on, sg, xs, mu, pa, qa, cscale, xi, gi, mu_out, sh);
+}
+
+// The polish on the face of *xi (its support and signs): factored in LDS
+// when the support is small enough, by conjugate gradients otherwise.
+struct PolishLds {
+  double* vec;
+  double* cand;
+  double* hv;
+  double* u;
+  double* w;
+  double* M;
+  int* idx;
+  int32_t mcap;  // doubles of M
+};
+
+__device__ int polish_face(const double* __restrict__ H, int64_t d, double ci, double tau,
+                           bool penalty, double* xi, double* gi, double* mu_out,
+                           const PolishLds& L, double cscale, BlockShared& sh) {
+  double nz[1] = {*xi != 0.0 ? 1.0 : 0.0};
+  block_reduce<1, 0>(nz, sh);
+  const int64_t nsz = (int64_t)nz[0];
+  if (nsz * nsz <= L.mcap)
+    return l1_polish(H, d, ci, tau, penalty, xi, gi, mu_out, L.M, L.u, L.w, L.idx, L.cand, L.hv,
+                     cscale, sh);
+  return l1_polish_cg(H, d, ci, tau, penalty, xi, gi, mu_out, L.vec, L.cand, L.hv, L.M, cscale,
+                      (int)(2 * nsz + 40), sh);
+}
+
+// One workgroup per problem. xunc: the unconstrained minimiser. The polish
+// factors H_SS in LDS when it fits and runs conjugate gradients otherwise.
 //
 // The Lipschitz constant L of the gradient starts at 1.05 x the Rayleigh
-// quotient of 24 power steps and is raised by backtracking (Beck and
+// quotient of kPowerSteps power steps and is raised by backtracking (Beck and
 // Teboulle, 2009): for this quadratic the sufficient-decrease test reads
 // (x+ - y)^T H (x+ - y) <= L ||x+ - y||^2. The kernel forms H x+ once per
 // iteration and gets H y by linearity, y = x+ + beta (x+ - x).
 __global__ __launch_bounds__(kQpThreads) void k_qp_l1(
     const double* __restrict__ Hall, const double* __restrict__ call,
     const double* __restrict__ xunc_all, const double* x0_all, double* xout_all,
-    double* Lscratch, int64_t d, double tau, int32_t penalty, int32_t max_iter, double tol,
+    int64_t d, double tau, int32_t penalty, int32_t max_iter, double tol,
     int32_t lds_mcap, DeviceStatus* st, int32_t iter) {
   extern __shared__ double lds[];
   double* vec = lds;            // d: the vector being multiplied
@@ -305,13 +476,30 @@ __global__ __launch_bounds__(kQpThreads) void k_qp_l1(
     return;
   }
   const double cscale = fmax(1.0, r0[1]);
+  // The warm start: x^t for the penalty, its projection for the ball. Across
+  // IHS steps the support and signs of the solution rarely change once the
+  // iterates settle, so the KKT polish is tried on the warm start's face
+  // first; an accepted polish is the minimiser and needs no Lipschitz
+  // estimate and no iteration. Otherwise FISTA runs from the warm start.
+  // (Primal-dual active-set corrections of a rejected face were measured
+  // here: the faces of the early steps differ too much for them to settle.)
+  const PolishLds pl{vec, cand, hv, u, w, Mlds, idx, lds_mcap};
+  const double xw = penalty ? x0 : project_l1(x0, d, tau, sh);
+  {
+    double xp = xw, gp = 0.0, mup = 0.0;
+    if (polish_face(H, d, ci, tau, penalty != 0, &xp, &gp, &mup, pl, cscale, sh) ==
+        kPolishAccepted) {
+      if (tid < d) xout[tid] = xp;
+      return;
+    }
+  }
   // power steps for the initial Lipschitz estimate
   double pv = tid < d ? 1.0 + 0.25 * (double)((tid * 7) % 5) : 0.0;
   double rq = 0.0;
-  for (int k = 0; k < 24; ++k) {
+  for (int k = 0; k < kPowerSteps; ++k) {
     if (tid < d) vec[tid] = pv;
     __syncthreads();
-    block_rows<false>(H, d, vec, hv);
+    block_rows(H, d, vec, hv, sh);
     const double hp = tid < d ? hv[tid] : 0.0;
     double q[3] = {pv * hp, hp * hp, pv * pv};
     block_reduce<3, 0>(q, sh);
@@ -319,12 +507,11 @@ __global__ __launch_bounds__(kQpThreads) void k_qp_l1(
     pv = hp / sqrt(fmax(q[1], 1e-300));
   }
   double Lip = 1.05 * rq;
-  // FISTA from the projection of x^t (from x^t itself for the penalty);
-  // thread i keeps x_i, (Hx)_i, y_i, (Hy)_i
-  double xi = penalty ? x0 : project_l1(x0, d, tau, sh);
+  // FISTA from the warm start; thread i keeps x_i, (Hx)_i, y_i, (Hy)_i
+  double xi = xw;
   if (tid < d) vec[tid] = xi;
   __syncthreads();
-  block_rows<false>(H, d, vec, hv);
+  block_rows(H, d, vec, hv, sh);
   double hxi = tid < d ? hv[tid] : 0.0;
   double yi = xi, hyi = hxi;
   double tk = 1.0;
@@ -337,7 +524,7 @@ __global__ __launch_bounds__(kQpThreads) void k_qp_l1(
                               : project_l1(vi, d, tau, sh);
     if (tid < d) vec[tid] = xn;
     __syncthreads();
-    block_rows<false>(H, d, vec, hv);
+    block_rows(H, d, vec, hv, sh);
     const double hxn = tid < d ? hv[tid] : 0.0;
     const double e = xn - yi;
     // sums: curvature, |e|^2, restart test, support signature, support size;
@@ -365,14 +552,12 @@ __global__ __launch_bounds__(kQpThreads) void k_qp_l1(
     const double sig = red[3] + 4096.0 * red[4];
     stable = (sig == sig_prev) ? stable + 1 : 0;
     sig_prev = sig;
-    // polish when the support has settled, at convergence, and once at the
-    // start when the warm start's support fits the LDS path
-    if (conv || stable == kPolishEvery || (it == 0 && red[4] * red[4] <= (double)lds_mcap)) {
+    // polish when the support has settled, and at convergence
+    if (conv || stable == kPolishEvery) {
       stable = 0;
-      const int64_t nsz = (int64_t)red[4];
-      double* M = (nsz * nsz <= lds_mcap) ? Mlds : Lscratch + (int64_t)p * d * d;
-      double xp = xi;
-      if (l1_polish(H, d, ci, tau, penalty != 0, &xp, M, u, w, idx, cand, hv, cscale, sh)) {
+      double xp = xi, gp = 0.0, mup = 0.0;
+      if (polish_face(H, d, ci, tau, penalty != 0, &xp, &gp, &mup, pl, cscale, sh) ==
+          kPolishAccepted) {
         xi = xp;
         done = true;
       } else if (conv) {
@@ -662,7 +847,7 @@ hipError_t launch_qp_constrained(const QpArgs& a, hipStream_t st) {
     const size_t fixed = (size_t)(3 * d + 2 * kPolishMax) * sizeof(double);
     const int32_t lds_mcap = (int32_t)((kQpLdsBytes - fixed) / sizeof(double));
     hipLaunchKernelGGL(k_qp_l1, dim3(B), dim3(kQpThreads), kQpLdsBytes, st, a.H, cbuf, xunc,
-                       a.x, a.x_out, a.L, d, a.radius, penalty ? 1 : 0, max_iter, tol, lds_mcap,
+                       a.x, a.x_out, d, a.radius, penalty ? 1 : 0, max_iter, tol, lds_mcap,
                        a.status, a.iter);
     return hipGetLastError();
   }
