@@ -15,13 +15,16 @@ Contents and the passages they follow:
   ihs      Gram (SA)^T SA and the gradient A^T (b - A x) (Sec. 1 after Eq.(2);
            App. A.1.1 "Iteration Time Costs"), the QP of Eq.(2) over R^d, the
            l1 ball and the l2 ball, the outer loop (Eq.(2), Thm 2.2), x_OPT of
-           Eq.(1), the error of Def. A.1, and the derivative of x_OPT
+           Eq.(1), the error of Def. A.1, the derivative of x_OPT, and the
+           reduced-access variant of the conclusion (one fixed sketch as the
+           preconditioner of conjugate gradients)
 
 Pins (tests/test_oracle_*.py) tie each function to something other than
 itself: numpy's Philox stream, a dense S built entry by entry, integer-valued
 data (exact in any order), Lemmas A.5-A.7, closed-form sketch variance,
 math.fsum, hand-solved projections, KKT conditions, brute-force enumeration of
-l1 faces, the exact IHS error recurrence, finite differences.
+l1 faces, the exact IHS error recurrence, finite differences, finite
+termination and the Chebyshev bound of conjugate gradients.
 
 Parity unpinned: the inner iterates of the l1 and l2 QP solvers (only their
 solutions are pinned, through KKT and brute force), and the float rounding

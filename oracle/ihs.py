@@ -286,6 +286,53 @@ def ihs(A, b, m, s=1, seed=0, iter0=0, iters=10, constraint="none", radius=0.0,
     return (xs, Hs) if return_hessians else xs
 
 
+def fixed_sketch_cg(A, b, m, s=1, seed=0, iter0=0, iters=10, x0=None, csr=None,
+                    problem=0):
+    """The reduced-data-access variant the paper's conclusion points to, for
+    C = R^d: one sketch S (key (seed, iter0)) is drawn once, and its Hessian
+    sketch H = (SA)^T SA preconditions conjugate gradients on the normal
+    equations A^T A x = A^T b (preconditioned CG as in Hestenes and Stiefel,
+    1952; the preconditioner enters through z = H^{-1} r). Each iteration
+    reads A twice here (A p, then A^T (A p)); the GPU forms A^T A p in one
+    pass. Returns the iterates x^0 .. x^iters.
+
+    The steps, from x^0 (default 0):
+        r = A^T (b - A x^0),  z = H^{-1} r,  p = z,  rho = r^T z
+        repeat: q = A^T A p,  alpha = rho / p^T q,  x += alpha p,
+                r -= alpha q,  z = H^{-1} r,  rho' = r^T z,
+                p = z + (rho' / rho) p,  rho = rho'
+    """
+    if csr is not None:
+        indptr, indices, data, n, d = csr
+        Aop = csr_matrix(indptr, indices, data, n, d)
+        SA = sketch_apply_csr(indptr, indices, data, n, d, seed, iter0, m, s, problem=problem)
+    else:
+        Aop = np.asarray(A, dtype=np.float64)
+        n, d = Aop.shape
+        SA = sketch_apply_dense(Aop, seed, iter0, m, s, problem=problem)
+    H = gram(SA)
+    factor = sla.cho_factor(H, lower=True)
+    x = np.zeros(d) if x0 is None else np.asarray(x0, dtype=np.float64).copy()
+    r = Aop.T @ (np.asarray(b, dtype=np.float64) - Aop @ x)
+    z = sla.cho_solve(factor, r)
+    p = z.copy()
+    rho = float(r @ z)
+    xs = [x.copy()]
+    for _ in range(iters):
+        q = Aop.T @ (Aop @ p)
+        pq = float(p @ q)
+        alpha = rho / pq if rho != 0.0 else 0.0
+        x = x + alpha * p
+        r = r - alpha * q
+        z = sla.cho_solve(factor, r)
+        rho_new = float(r @ z)
+        beta = rho_new / rho if rho != 0.0 else 0.0
+        p = z + beta * p
+        rho = rho_new
+        xs.append(x.copy())
+    return xs
+
+
 def x_opt(A, b, constraint="none", radius=0.0):
     """x_OPT of Eq.(1), or of the penalised LASSO of Sec. 3 ("l1_penalty",
     radius = lambda). A dense array or a scipy sparse matrix."""

@@ -447,3 +447,67 @@ def test_ihs_l1_penalty_converges():
     errs = [O.error_A(wl.A, x, xo) for x in xs[1:]]
     assert errs[-1] < 1e-8
     assert errs[6] < errs[0] * 1e-2
+
+
+# ---------------------------------- one fixed sketch + conjugate gradients ----
+def test_fixed_sketch_cg_collision_free_is_one_step():
+    """With no bucket collisions H = A^T A, so the preconditioned residual is
+    the Newton step and the first iterate is x_OPT."""
+    g = np.random.default_rng(41)
+    n, d, m = 12, 4, 1 << 22
+    A = g.standard_normal((n, d))
+    b = g.standard_normal(n)
+    bucket, _ = sketch_hash(3, 0, n, m, 1)
+    assert len(np.unique(bucket)) == n
+    xs = O.fixed_sketch_cg(A, b, m, seed=3, iters=2)
+    xo = O.x_opt(A, b)
+    assert np.allclose(xs[1], xo, rtol=1e-12, atol=1e-13)
+
+
+def test_fixed_sketch_cg_finite_termination_and_monotone_error():
+    """Conjugate gradients end in at most d iterations in exact arithmetic,
+    and the A^T A-norm of the error never grows (CG minimises it over the
+    Krylov space); the Chebyshev bound 2 ((sqrt k - 1)/(sqrt k + 1))^t holds
+    with k the condition number of H^{-1} A^T A."""
+    g = np.random.default_rng(42)
+    n, d, m = 400, 6, 24
+    A = g.standard_normal((n, d)) * np.linspace(1, 30, d)
+    b = g.standard_normal(n)
+    xs = O.fixed_sketch_cg(A, b, m, seed=5, iters=d)
+    xo = O.x_opt(A, b)
+    err = [O.error_A(A, x, xo) for x in xs]
+    assert err[d] < 1e-10 * err[0]
+    assert all(err[t + 1] <= err[t] * (1 + 1e-9) for t in range(d))
+    from oracle.sketch import sketch_apply_dense
+    SA = sketch_apply_dense(A, 5, 0, m, 1)
+    ev = sla_eigh(A.T @ A, SA.T @ SA)
+    kappa = ev.max() / ev.min()
+    rate = (np.sqrt(kappa) - 1) / (np.sqrt(kappa) + 1)
+    for t in range(1, d):
+        assert err[t] <= 2 * rate ** t * err[0] * (1 + 1e-9), t
+
+
+def sla_eigh(a, b):
+    import scipy.linalg as sla
+    return sla.eigh(a, b, eigvals_only=True)
+
+
+def test_fixed_sketch_cg_fewer_passes_than_ihs():
+    """On a tall problem with m = 8 d the preconditioned system is well
+    conditioned, and CG contracts faster per pass over A than IHS with fresh
+    sketches (0.32 against 0.43 per step here; the point of the variant);
+    CSR input gives the same iterates as its dense copy."""
+    wl = W.ols_dense(rows=20000, d=50, m=400, iters=12)
+    xo = O.x_opt(wl.A, wl.b)
+    cg = O.fixed_sketch_cg(wl.A, wl.b, wl.m, seed=wl.sketch_seed, iters=12)
+    ih = O.ihs(wl.A, wl.b, wl.m, seed=wl.sketch_seed, iters=12)
+    e_cg = O.error_A(wl.A, cg[12], xo)
+    e_ih = O.error_A(wl.A, ih[12], xo)
+    assert e_cg < 1e-5 and e_cg < 0.1 * e_ih
+    import scipy.sparse as sp
+    C = sp.csr_matrix(wl.A[:3000])
+    csr = (C.indptr.astype(np.int32), C.indices.astype(np.int32), C.data, 3000, wl.d)
+    xd = O.fixed_sketch_cg(wl.A[:3000], wl.b[:3000], 100, seed=4, iters=5)
+    xc = O.fixed_sketch_cg(None, wl.b[:3000], 100, seed=4, iters=5, csr=csr)
+    for t in range(6):
+        assert np.allclose(xd[t], xc[t], rtol=1e-12, atol=1e-14)
