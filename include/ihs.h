@@ -60,6 +60,13 @@ typedef enum {
   IHS_L1_PENALTY = 3
 } ihs_constraint;
 typedef enum { IHS_DENSE = 0, IHS_CSR = 1 } ihs_format;
+/* How ihs_solve iterates. IHS_METHOD_IHS: the Iterative Hessian Sketch,
+ * Eq.(2) with a fresh sketch at every step (Sec. 1, Thm 2.2).
+ * IHS_METHOD_FIXED_SKETCH_CG: the direction the conclusion names, fewer
+ * passes over the data: one sketch S_0 is drawn once and its Hessian sketch
+ * H_0 = (S_0 A)^T S_0 A preconditions conjugate gradients on the normal
+ * equations A^T A x = A^T b (C = R^d only). */
+typedef enum { IHS_METHOD_IHS = 0, IHS_METHOD_FIXED_SKETCH_CG = 1 } ihs_method;
 
 /* The data matrix A (n x d). Dense: `values` (device) holds n rows of `ld`
  * elements, dtype F64 or F32. CSR: `row_ptr` (device, n+1), `col_idx`
@@ -136,7 +143,13 @@ typedef struct {
                                   since the fused pass adds up A^T r in the
                                   row order of the sketch it forms (S_{t+1} or
                                   S_{t+2} when overlapping, S_t otherwise).   */
-  int32_t reserved;
+  int32_t method;              /* ihs_method. IHS_METHOD_FIXED_SKETCH_CG:
+                                  max_iter conjugate-gradient iterations after
+                                  one pass that forms S_0 A (key (sketch.seed,
+                                  sketch.iter)) and A^T (b - A x^0); each
+                                  iteration is one more pass over A. Requires
+                                  C = R^d and factors = NULL; schedule is not
+                                  read.                                        */
 } ihs_options;
 
 /* Filled by ihs_solve (host memory). */
@@ -145,7 +158,8 @@ typedef struct {
   int32_t status;              /* ihs_status of the device work               */
   int32_t failed_iter;         /* step at which a device error occurred, or -1 */
   int32_t failed_problem;      /* problem index of that error, or -1          */
-  double objective;            /* 1/2 ||A x^{N-1} - b||^2 (problem 0), from the last pass */
+  double objective;            /* 1/2 ||A x^{N-1} - b||^2 (problem 0), from the last
+                                  pass (IHS_METHOD_FIXED_SKETCH_CG: at x^0)     */
   double last_step;            /* sqrt(dx^T H dx) of the last step (problem 0) */
 } ihs_report;
 

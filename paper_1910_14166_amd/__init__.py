@@ -22,6 +22,7 @@ F64, F32, BF16 = 0, 1, 2
 COUNTSKETCH, SJLT = 0, 1
 UNCONSTRAINED, L1_BALL, L2_BALL, L1_PENALTY = 0, 1, 2, 3
 DENSE, CSR = 0, 1
+METHOD_IHS, METHOD_FIXED_SKETCH_CG = 0, 1
 
 _CONSTRAINTS = {"none": UNCONSTRAINED, "l1": L1_BALL, "l2": L2_BALL, "l1_penalty": L1_PENALTY}
 _DTYPES = {"float64": F64, "float32": F32, "bfloat16": BF16,
@@ -61,7 +62,7 @@ class Options_t(ctypes.Structure):
                 ("gram_in", ctypes.c_int32), ("gram_acc", ctypes.c_int32),
                 ("qp_max_inner", ctypes.c_int32), ("keep_factors", ctypes.c_int32),
                 ("qp_tol", ctypes.c_double), ("tol", ctypes.c_double),
-                ("schedule", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("schedule", ctypes.c_int32), ("method", ctypes.c_int32)]
 
 
 class Report_t(ctypes.Structure):
@@ -223,7 +224,7 @@ class Matrix:
 
 def options(m, s=1, kind="countsketch", seed=0, iter0=0, max_iter=10, constraint="none",
             radius=0.0, gram_in="float64", gram_acc="float64", keep_factors=False,
-            qp_max_inner=0, qp_tol=0.0, tol=0.0, schedule="overlap"):
+            qp_max_inner=0, qp_tol=0.0, tol=0.0, schedule="overlap", method="ihs"):
     o = Options_t()
     o.constraint = _CONSTRAINTS[constraint] if isinstance(constraint, str) else constraint
     o.max_iter = int(max_iter)
@@ -235,6 +236,8 @@ def options(m, s=1, kind="countsketch", seed=0, iter0=0, max_iter=10, constraint
     o.schedule = {"overlap": 0, "sequential": 1, "overlap2": 2}[schedule] \
         if isinstance(schedule, str) \
         else int(schedule)
+    o.method = {"ihs": METHOD_IHS, "fixed_sketch_cg": METHOD_FIXED_SKETCH_CG}[method] \
+        if isinstance(method, str) else int(method)
     return o
 
 

@@ -386,6 +386,13 @@ struct SolveBuffers {
   double* Hinv2 = nullptr;
   double* Linv = nullptr;    // triangular-inverse scratch of the second stream
   double* dx = nullptr;
+  // conjugate gradients with a fixed sketch: residual A^T (b - A x), its
+  // preconditioned copy, -p, r^T z per problem, and a zero vector
+  double* cg_r = nullptr;
+  double* cg_z = nullptr;
+  double* cg_pm = nullptr;
+  double* cg_rho = nullptr;
+  double* cg_zero = nullptr;
 };
 
 // Above this width the overlapped schedule forms H^{-1} on the second stream
@@ -425,6 +432,14 @@ size_t carve_solve(Carver& c, const Layout& L, const ihs_options* o, SolveBuffer
     S.Linv = c.take<double>((size_t)(L.batch * L.d * L.d));
   }
   S.dx = c.take<double>((size_t)(L.batch * L.d));
+  if (o->method == IHS_METHOD_FIXED_SKETCH_CG) {
+    const size_t bd = (size_t)(L.batch * L.d);
+    S.cg_r = c.take<double>(bd);
+    S.cg_z = c.take<double>(bd);
+    S.cg_pm = c.take<double>(bd);
+    S.cg_rho = c.take<double>((size_t)L.batch);
+    S.cg_zero = c.take<double>(bd);
+  }
   return c.used;
 }
 
@@ -486,6 +501,10 @@ ihs_status check_options(const ihs_options* o, bool need_loop) {
   if (!valid_gram_types(o->gram_in, o->gram_acc)) return IHS_ERR_INVALID_ARG;
   if (o->tol != 0.0 || o->qp_tol < 0.0 || o->qp_max_inner < 0) return IHS_ERR_INVALID_ARG;
   if (o->schedule < 0 || o->schedule > 2) return IHS_ERR_INVALID_ARG;
+  if (o->method != IHS_METHOD_IHS && o->method != IHS_METHOD_FIXED_SKETCH_CG)
+    return IHS_ERR_INVALID_ARG;
+  if (o->method == IHS_METHOD_FIXED_SKETCH_CG && o->constraint != IHS_UNCONSTRAINED)
+    return IHS_ERR_UNSUPPORTED;
   return IHS_OK;
 }
 
@@ -654,6 +673,72 @@ ihs_status solve_overlap(const ihs_matrix* A, const Layout& L, const ihs_options
     rep->last_step = hm.last_step;
   }
   return (ihs_status)f.code;
+}
+
+// The reduced-access variant: one sketch S_0 (key (seed, iter)) held fixed,
+// its Hessian sketch H_0 = (S_0 A)^T S_0 A as the preconditioner of conjugate
+// gradients on the normal equations A^T A x = A^T b. The first pass forms
+// S_0 A and A^T (b - A x^0) in one read of A; each of the max_iter
+// iterations is one natural-order pass forming q = A^T A p (the gradient
+// pass with b = 0 at x = -p), then the d-sized recurrences and z = H_0^{-1} r
+// (explicit inverse for d >= kInverseMinD, triangular solves below).
+ihs_status solve_fixed_sketch_cg(const ihs_matrix* A, const Layout& L, const ihs_options* opt,
+                                 SolveBuffers& S, const double* b, double* x, double* x_hist,
+                                 ihs_report* rep, hipStream_t stream) {
+  PassBuffers& B = S.pass;
+  const int64_t d = A->d, m = opt->sketch.m;
+  const int64_t bd = (int64_t)L.batch * d;
+  const bool use_inv = d >= kInverseMinD;
+  auto ck = [](hipError_t e) { return !hip_failed(e); };
+  if (!ck(fill(B.bzero, A->n, 0.0, stream)) || !ck(fill(S.cg_zero, bd, 0.0, stream)))
+    return IHS_ERR_HIP;
+  ihs_status s = run_pass(A, L, &opt->sketch, B, opt->sketch.iter, S.SA, opt->gram_in, d, b, x,
+                          nullptr, stream);
+  if (s != IHS_OK) return s;
+  if (!ck(launch_reduce_partials(B.gpart, B.fpart, L.batch, pass_parts(A, &opt->sketch, L.batch),
+                                 B.probs, d, S.cg_r, B.f, B.status, 0, B.red, stream)) ||
+      !ck(launch_gram(S.SA, opt->gram_in, m, d, d, L.batch, opt->gram_acc, S.H, S.gram_part,
+                      stream)) ||
+      !ck(launch_cholesky(S.H, S.Lf, d, L.batch, B.status, 0, 0.0, S.work, stream)))
+    return IHS_ERR_HIP;
+  double* rdiag = chol_rdiag(S.work, L.batch);
+  if (use_inv && !ck(launch_chol_inverse(S.Lf, rdiag, d, L.batch, S.Hinv0, S.Linv, B.status,
+                                         stream)))
+    return IHS_ERR_HIP;
+  auto precondition = [&]() {  // z = H_0^{-1} r
+    if (use_inv)
+      return ck(launch_inv_apply(S.Hinv0, d, L.batch, S.cg_r, S.cg_zero, S.cg_z, S.dx, B.status,
+                                 stream, nullptr, -1));
+    return ck(launch_chol_solve_update(S.Lf, rdiag, d, L.batch, S.cg_r, S.cg_zero, S.cg_z,
+                                       B.status, stream));
+  };
+  if (!precondition() ||
+      !ck(launch_pcg_begin(S.cg_r, S.cg_z, S.cg_pm, S.cg_rho, d, L.batch, B.status, stream)))
+    return IHS_ERR_HIP;
+  for (int32_t t = 0; t < opt->max_iter; ++t) {
+    // q = A^T (0 - A (-p)) into B.g; the objective of the pass at x^0 stays recorded
+    if ((s = run_gradient(A, L, B, nullptr, S.cg_pm, B.g, nullptr, nullptr, nullptr, t,
+                          stream)) != IHS_OK)
+      return s;
+    if (!ck(launch_pcg_x(S.cg_pm, B.g, S.cg_rho, x, S.cg_r, d, L.batch, B.status, t, stream)) ||
+        !precondition() ||
+        !ck(launch_pcg_p(S.cg_r, S.cg_z, S.cg_pm, S.cg_rho, d, L.batch, B.status, stream)))
+      return IHS_ERR_HIP;
+    if (x_hist && !ck(hipMemcpyAsync(x_hist + (int64_t)t * bd, x, bd * sizeof(double),
+                                     hipMemcpyDeviceToDevice, stream)))
+      return IHS_ERR_HIP;
+  }
+  DeviceStatus host;
+  if (read_status(B.status, &host, stream) != IHS_OK) return IHS_ERR_HIP;
+  if (rep) {
+    rep->status = host.code;
+    rep->failed_iter = host.code ? host.failed_iter : -1;
+    rep->failed_problem = host.code ? host.failed_problem : -1;
+    rep->iters = host.code ? std::max(0, host.failed_iter) : opt->max_iter;
+    rep->objective = host.objective;
+    rep->last_step = host.last_step;
+  }
+  return (ihs_status)host.code;
 }
 
 }  // namespace
@@ -844,6 +929,7 @@ ihs_status ihs_solve(const ihs_matrix* A, const double* b, const ihs_options* op
   if (!b || !x || !ws) return IHS_ERR_INVALID_ARG;
   if (factors && (!opt->keep_factors || opt->constraint != IHS_UNCONSTRAINED))
     return IHS_ERR_INVALID_ARG;
+  if (factors && opt->method != IHS_METHOD_IHS) return IHS_ERR_UNSUPPORTED;
   if (A->n * (int64_t)opt->sketch.s >= (int64_t(1) << 31)) return IHS_ERR_UNSUPPORTED;
   if (A->format == IHS_CSR && opt->gram_in != IHS_F64 && opt->gram_in != IHS_F32 &&
       opt->gram_in != IHS_BF16)
@@ -859,6 +945,8 @@ ihs_status ihs_solve(const ihs_matrix* A, const double* b, const ihs_options* op
   carve_solve(c, L, opt, S);
   PassBuffers& B = S.pass;
   if ((s = upload_probs(L, B, stream)) != IHS_OK) return s;
+  if (opt->method == IHS_METHOD_FIXED_SKETCH_CG)
+    return solve_fixed_sketch_cg(A, L, opt, S, b, x, x_hist, rep, stream);
   if (opt->schedule != 1 && opt->constraint == IHS_UNCONSTRAINED && opt->max_iter >= 2)
     return solve_overlap(A, L, opt, S, b, x, x_hist, factors, rep, stream);
   const int64_t d = A->d, m = opt->sketch.m;

@@ -180,6 +180,17 @@ hipError_t launch_chol_solve_update(const double* L, const double* rdiag, int64_
                                     const DeviceStatus* gate = nullptr,
                                     int32_t gate_iter = -1);
 
+// Conjugate gradients preconditioned by a fixed Hessian sketch (pm = -p):
+// begin: rho = r^T z, pm = -z; x: alpha = rho / p^T q, x += alpha p,
+// r -= alpha q; p: rho' = r^T z, pm = -z + (rho'/rho) pm, rho = rho'.
+hipError_t launch_pcg_begin(const double* r, const double* z, double* pm, double* rho, int64_t d,
+                            int32_t batch, const DeviceStatus* status, hipStream_t st);
+hipError_t launch_pcg_x(const double* pm, const double* q, const double* rho, double* x,
+                        double* r, int64_t d, int32_t batch, DeviceStatus* status, int32_t iter,
+                        hipStream_t st);
+hipError_t launch_pcg_p(const double* r, const double* z, double* pm, double* rho, int64_t d,
+                        int32_t batch, const DeviceStatus* status, hipStream_t st);
+
 // Adjoint and solution-gradient passes.
 // S^T G for the nrows rows of one problem (G points at that problem's m rows).
 // Rows [off[0], off[count]) of problems first .. first+count-1 (global row

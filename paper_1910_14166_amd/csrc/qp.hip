@@ -936,6 +936,126 @@ hipError_t launch_recip_diag(const double* L, int64_t d, int32_t batch, double* 
 // Reciprocal pivots inside the Cholesky scratch (after the side buffers).
 double* chol_rdiag(double* scratch, int32_t batch) { return scratch + (int64_t)batch * kNb * kNb; }
 
+// ---------------------------------------------------------------------------
+// Recurrences of conjugate gradients preconditioned by a fixed Hessian sketch
+// (one 256-thread workgroup per problem; every dot product is summed in a
+// fixed order, strided per-thread partials and then a tree). pm holds -p, so
+// that the natural-order gradient pass with b = 0 and x = pm returns
+// q = A^T A p. rho[p] carries r^T z between iterations.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double block_dot256(double v, double* red) {
+  const int tid = threadIdx.x;
+  red[tid] = v;
+  __syncthreads();
+  for (int stride = 128; stride > 0; stride >>= 1) {
+    if (tid < stride) red[tid] += red[tid + stride];
+    __syncthreads();
+  }
+  const double s = red[0];
+  __syncthreads();
+  return s;
+}
+
+// rho = r^T z, pm = -z.
+__global__ __launch_bounds__(256) void k_pcg_begin(const double* __restrict__ r,
+                                                   const double* __restrict__ z, double* pm,
+                                                   double* rho, int64_t d,
+                                                   const DeviceStatus* st) {
+  __shared__ double red[256];
+  __shared__ int skip;
+  const int p = blockIdx.x, tid = threadIdx.x;
+  if (tid == 0) skip = status_failed_by(st, -1) ? 1 : 0;
+  __syncthreads();
+  if (skip) return;
+  const double* rp = r + (int64_t)p * d;
+  const double* zp = z + (int64_t)p * d;
+  double part = 0.0;
+  for (int64_t i = tid; i < d; i += 256) {
+    part = fma(rp[i], zp[i], part);
+    pm[(int64_t)p * d + i] = -zp[i];
+  }
+  const double rz = block_dot256(part, red);
+  if (tid == 0) rho[p] = rz;
+}
+
+// alpha = rho / p^T q, x += alpha p, r -= alpha q. A non-positive curvature
+// p^T q (A^T A not positive definite) is recorded as IHS_ERR_NOT_PD, a
+// non-finite one as IHS_ERR_NONFINITE; a zero rho (r = 0: the solution is
+// reached) leaves x and r as they are.
+__global__ __launch_bounds__(256) void k_pcg_x(const double* __restrict__ pm,
+                                               const double* __restrict__ q,
+                                               const double* __restrict__ rho, double* x,
+                                               double* r, int64_t d, DeviceStatus* st,
+                                               int32_t iter) {
+  __shared__ double red[256];
+  __shared__ int skip;
+  const int p = blockIdx.x, tid = threadIdx.x;
+  if (tid == 0) skip = status_failed_by(st, -1) ? 1 : 0;
+  __syncthreads();
+  if (skip) return;
+  const double* pp = pm + (int64_t)p * d;
+  const double* qp = q + (int64_t)p * d;
+  double part = 0.0;
+  for (int64_t i = tid; i < d; i += 256) part = fma(-pp[i], qp[i], part);
+  const double pq = block_dot256(part, red);
+  const double rz = rho[p];
+  if (rz == 0.0) return;
+  if (!(pq > 0.0) || !isfinite(pq)) {
+    if (tid == 0)
+      status_fail(st, isfinite(pq) ? 5 /* IHS_ERR_NOT_PD */ : 7 /* IHS_ERR_NONFINITE */, iter, p);
+    return;
+  }
+  const double alpha = rz / pq;
+  for (int64_t i = tid; i < d; i += 256) {
+    const int64_t k = (int64_t)p * d + i;
+    x[k] = fma(-alpha, pp[i], x[k]);
+    r[k] = fma(-alpha, qp[i], r[k]);
+  }
+}
+
+// rho' = r^T z, pm = -z + (rho' / rho) pm, rho = rho'.
+__global__ __launch_bounds__(256) void k_pcg_p(const double* __restrict__ r,
+                                               const double* __restrict__ z, double* pm,
+                                               double* rho, int64_t d, const DeviceStatus* st) {
+  __shared__ double red[256];
+  __shared__ int skip;
+  const int p = blockIdx.x, tid = threadIdx.x;
+  if (tid == 0) skip = status_failed_by(st, -1) ? 1 : 0;
+  __syncthreads();
+  if (skip) return;
+  const double* rp = r + (int64_t)p * d;
+  const double* zp = z + (int64_t)p * d;
+  double part = 0.0;
+  for (int64_t i = tid; i < d; i += 256) part = fma(rp[i], zp[i], part);
+  const double rz_old = rho[p];
+  const double rz = block_dot256(part, red);
+  const double beta = rz_old > 0.0 ? rz / rz_old : 0.0;
+  for (int64_t i = tid; i < d; i += 256) {
+    const int64_t k = (int64_t)p * d + i;
+    pm[k] = fma(beta, pm[k], -zp[i]);
+  }
+  if (tid == 0) rho[p] = rz;
+}
+
+hipError_t launch_pcg_begin(const double* r, const double* z, double* pm, double* rho, int64_t d,
+                            int32_t batch, const DeviceStatus* status, hipStream_t st) {
+  hipLaunchKernelGGL(k_pcg_begin, dim3(batch), dim3(256), 0, st, r, z, pm, rho, d, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_pcg_x(const double* pm, const double* q, const double* rho, double* x,
+                        double* r, int64_t d, int32_t batch, DeviceStatus* status, int32_t iter,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(k_pcg_x, dim3(batch), dim3(256), 0, st, pm, q, rho, x, r, d, status, iter);
+  return hipGetLastError();
+}
+
+hipError_t launch_pcg_p(const double* r, const double* z, double* pm, double* rho, int64_t d,
+                        int32_t batch, const DeviceStatus* status, hipStream_t st) {
+  hipLaunchKernelGGL(k_pcg_p, dim3(batch), dim3(256), 0, st, r, z, pm, rho, d, status);
+  return hipGetLastError();
+}
+
 // Per-problem scratch of the QP kernels: the 64 x 64 diagonal-block side
 // buffer of the blocked Cholesky plus vectors.
 size_t qp_work_doubles(int64_t d, int32_t constraint) {

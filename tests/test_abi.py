@@ -110,6 +110,17 @@ def test_invalid_solve_options(lib):
     o = P.options(16, constraint="l1", radius=1.0)
     assert lib.ihs_solve(ctypes.byref(A), x, ctypes.byref(o), x, None, ctypes.c_void_p(8),
                          ctypes.byref(rep), ws, 1 << 30, None) == P.ERR_INVALID_ARG
+    # the fixed-sketch method: an unknown method code, a constraint set, and
+    # stored factors are refused before any launch
+    o = P.options(16, method=2)
+    assert lib.ihs_solve(ctypes.byref(A), x, ctypes.byref(o), x, None, None,
+                         ctypes.byref(rep), ws, 1 << 30, None) == P.ERR_INVALID_ARG
+    o = P.options(16, constraint="l2", radius=1.0, method="fixed_sketch_cg")
+    assert lib.ihs_solve(ctypes.byref(A), x, ctypes.byref(o), x, None, None,
+                         ctypes.byref(rep), ws, 1 << 30, None) == P.ERR_UNSUPPORTED
+    o = P.options(16, method="fixed_sketch_cg", keep_factors=True)
+    assert lib.ihs_solve(ctypes.byref(A), x, ctypes.byref(o), x, None, ctypes.c_void_p(8),
+                         ctypes.byref(rep), ws, 1 << 30, None) == P.ERR_UNSUPPORTED
 
 
 def test_gram_and_qp_validation(lib):

@@ -288,3 +288,71 @@ def test_largest_sketch_overlapped_iterates_match_oracle(gpu_lib):
         assert np.linalg.norm(hist[t] - xs[t + 1]) <= 1e-11 * np.linalg.norm(xs[t + 1]), t
     errs = [O.error_A(wl.A, hist[t], xo) for t in range(wl.iters)]
     assert errs[3] < 0.2 ** 4
+
+
+# ---------------------------------- one fixed sketch + conjugate gradients ----
+@pytest.mark.parametrize("n,d,m,iters", [(20000, 50, 400, 12), (30000, 120, 960, 10),
+                                         (5000, 7, 56, 7)])
+def test_fixed_sketch_cg_iterates_match_oracle(gpu_lib, n, d, m, iters):
+    """Dense A through both preconditioner paths (triangular solves below
+    d = 89, the explicit inverse above): every iterate matches the oracle's,
+    and the A-norm error falls below IHS's after the same number of passes."""
+    P = gpu_lib
+    wl = W.ols_dense(rows=n, d=d, m=m, iters=iters)
+    opts = P.options(wl.m, seed=wl.sketch_seed, iter0=3, max_iter=iters,
+                     method="fixed_sketch_cg")
+    res = P.solve(P.Matrix(dense=dev(wl.A)), dev(wl.b), opts, history=True)
+    assert res.report.status == 0 and res.report.iters == iters
+    xs = O.fixed_sketch_cg(wl.A, wl.b, wl.m, seed=wl.sketch_seed, iter0=3, iters=iters)
+    hist = host(res.history)[:, 0, :]
+    xo = O.x_opt(wl.A, wl.b)
+    for t in range(iters):
+        scale = max(np.linalg.norm(xs[t + 1]), 1e-300)
+        assert np.linalg.norm(hist[t] - xs[t + 1]) <= 1e-10 * scale, t
+    r0 = wl.b  # the objective is reported at x^0 = 0
+    assert abs(res.report.objective - 0.5 * r0 @ r0) <= 1e-12 * (0.5 * r0 @ r0)
+    if d < n // 100:
+        ih = O.ihs(wl.A, wl.b, wl.m, seed=wl.sketch_seed, iter0=3, iters=iters)
+        assert O.error_A(wl.A, hist[-1], xo) < O.error_A(wl.A, ih[-1], xo)
+
+
+def test_fixed_sketch_cg_csr_and_ragged_batch(gpu_lib):
+    P = gpu_lib
+    # CSR
+    wl = W.ridge_csr(rows=40000, d=64, density=0.05, m=512, iters=8)
+    import torch
+    M = P.Matrix(row_ptr=torch.from_numpy(wl.indptr).cuda(),
+                 col_idx=torch.from_numpy(wl.indices).cuda(),
+                 values=torch.from_numpy(wl.data).cuda(), n=wl.n, d=wl.d)
+    opts = P.options(wl.m, seed=wl.sketch_seed, max_iter=8, method="fixed_sketch_cg")
+    res = P.solve(M, dev(wl.b), opts, history=True)
+    assert res.report.status == 0
+    csr = (wl.indptr, wl.indices, wl.data, wl.n, wl.d)
+    xs = O.fixed_sketch_cg(None, wl.b, wl.m, seed=wl.sketch_seed, iters=8, csr=csr)
+    hist = host(res.history)[:, 0, :]
+    for t in range(8):
+        assert np.linalg.norm(hist[t] - xs[t + 1]) <= 1e-10 * np.linalg.norm(xs[t + 1]), t
+    # ragged batch: problem p draws its sketch with problem index p
+    wb = W.batch_ragged(num=5, n_lo=1500, n_hi=7000, d=32, iters=6)
+    opts = P.options(wb.m, seed=wb.sketch_seed, max_iter=6, method="fixed_sketch_cg")
+    res = P.solve(P.Matrix(dense=dev(wb.A), row_offsets=wb.row_offsets), dev(wb.b), opts)
+    X = host(res.x)
+    for p in range(wb.batch):
+        r0, r1 = wb.row_offsets[p], wb.row_offsets[p + 1]
+        ref = O.fixed_sketch_cg(wb.A[r0:r1], wb.b[r0:r1], wb.m, seed=wb.sketch_seed, iters=6,
+                                problem=p)[-1]
+        assert np.linalg.norm(X[p] - ref) <= 1e-10 * np.linalg.norm(ref), p
+
+
+def test_fixed_sketch_cg_rank_deficient_reports_not_pd(gpu_lib):
+    """An empty column makes H_0 exactly singular: the factorisation reports
+    it and x keeps its start."""
+    P = gpu_lib
+    g = np.random.default_rng(5)
+    A = g.standard_normal((3000, 6))
+    A[:, 4] = 0.0
+    opts = P.options(60, seed=2, max_iter=4, method="fixed_sketch_cg")
+    res = P.solve(P.Matrix(dense=dev(A)), dev(g.standard_normal(3000)), opts,
+                  raise_on_error=False)
+    assert res.report.status == P.ERR_NOT_PD
+    assert np.array_equal(host(res.x), np.zeros((1, 6)))
