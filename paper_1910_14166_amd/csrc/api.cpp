@@ -1043,20 +1043,19 @@ ihs_status ihs_solution_grads(const ihs_matrix* A, const double* b, const double
   if (A->format != IHS_DENSE) return IHS_ERR_UNSUPPORTED;
   if (!b || !x || !lambda) return IHS_ERR_INVALID_ARG;
   const bool f32 = A->dtype == IHS_F32;
-  const size_t esz = f32 ? sizeof(float) : sizeof(double);
   if (dl_da && ld_da < A->d) return IHS_ERR_INVALID_ARG;
   const Layout L = make_layout(A, 1);
   clear_stale_error();
-  for (int32_t p = 0; p < L.batch; ++p) {
-    const ProbInfo& q = L.probs[p];
-    if (q.rows == 0) continue;
-    if (hip_failed(launch_solution_grads(nullptr, 1, q.rows, A->d,
-                              static_cast<const char*>(A->values) + q.row0 * A->ld * esz, f32,
-                              A->ld,
-                              b + q.row0, x + (int64_t)p * A->d, lambda + (int64_t)p * A->d,
-                              dl_db ? dl_db + q.row0 : nullptr,
-                              dl_da ? dl_da + q.row0 * ld_da : nullptr, ld_da,
-                              stream)))
+  for (int32_t p0 = 0; p0 < L.batch; p0 += kAdjointBatch) {
+    AdjointBatch ab{};
+    ab.count = std::min<int32_t>(kAdjointBatch, L.batch - p0);
+    ab.first = p0;
+    for (int i = 0; i <= kAdjointBatch; ++i) {
+      const int32_t p = p0 + std::min<int32_t>(i, ab.count);
+      ab.off[i] = p < L.batch ? L.probs[p].row0 : A->n;
+    }
+    if (hip_failed(launch_solution_grads(ab, A->d, A->values, f32, A->ld, b, x, lambda, dl_db,
+                                         dl_da, ld_da, stream)))
       return IHS_ERR_HIP;
   }
   return IHS_OK;

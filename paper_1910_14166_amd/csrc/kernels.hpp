@@ -205,9 +205,10 @@ struct AdjointBatch {
 hipError_t launch_sketch_adjoint(const AdjointBatch& ab, int32_t s, int64_t m, uint64_t seed,
                                  uint64_t iter, const double* G, int64_t ld_g, int64_t d,
                                  double* out, int64_t ld_out, hipStream_t st);
-hipError_t launch_solution_grads(const ProbInfo* probs, int32_t batch, int64_t n,
-                                 int64_t d, const void* A, bool a_f32, int64_t ld,
-                                 const double* b, const double* x,
+// dL/db and dL/dA for the rows of problems first .. first+count-1 (global
+// row indices into A, b, dl_db, dl_da; x and lambda indexed by problem).
+hipError_t launch_solution_grads(const AdjointBatch& ab, int64_t d, const void* A, bool a_f32,
+                                 int64_t ld, const double* b, const double* x,
                                  const double* lambda, double* dl_db, double* dl_da,
                                  int64_t ld_da, hipStream_t st);
 

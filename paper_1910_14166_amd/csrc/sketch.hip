@@ -994,47 +994,68 @@ hipError_t launch_sketch_adjoint(const AdjointBatch& ab, int32_t s, int64_t m, u
 }
 
 // ---------------------------------------------------------------------------
-// dL/db = A lambda and dL/dA = r lambda^T - (A lambda) x^T, r = b - A x,
-// for the rows of one problem. One wavefront per row.
+// dL/db = A lambda and dL/dA = r lambda^T - (A lambda) x^T, r = b - A x, for
+// the rows of up to kAdjointBatch problems in one launch (global row indices;
+// each row finds its problem in the offsets staged in LDS). One wavefront
+// per row.
 // ---------------------------------------------------------------------------
 template <typename TA>
-__global__ __launch_bounds__(256) void k_solution_grads(int64_t nrows, int64_t d,
+__global__ __launch_bounds__(256) void k_solution_grads(AdjointBatch ab, int64_t d,
                                                         const TA* __restrict__ A, int64_t ld,
                                                         const double* __restrict__ b,
                                                         const double* __restrict__ x,
                                                         const double* __restrict__ lam,
                                                         double* dl_db, double* dl_da,
                                                         int64_t ld_da) {
+  __shared__ int64_t off[kAdjointBatch + 1];
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i <= kAdjointBatch; ++i) off[i] = ab.off[i];
+  }
+  __syncthreads();
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int count = ab.count;
+  const int64_t row_end = off[count];
   const int64_t waves = (int64_t)gridDim.x * 4;
-  for (int64_t row = (int64_t)blockIdx.x * 4 + wv; row < nrows; row += waves) {
+  for (int64_t row = off[0] + (int64_t)blockIdx.x * 4 + wv; row < row_end; row += waves) {
+    int lo = 0, hi = count;  // the last problem whose rows start at or before `row`
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (off[mid] <= row) lo = mid;
+      else hi = mid;
+    }
+    const int64_t pq = (int64_t)ab.first + lo;
+    const double* xp = x + pq * d;
+    const double* lp = lam + pq * d;
     const TA* ar = A + row * ld;
     double sl = 0.0, sx = 0.0;
     for (int64_t c = lane; c < d; c += 64) {
       const double a = (double)ar[c];
-      sl = fma(a, lam[c], sl);
-      sx = fma(a, x[c], sx);
+      sl = fma(a, lp[c], sl);
+      sx = fma(a, xp[c], sx);
     }
     sl = wave_sum(sl);
     sx = wave_sum(sx);
     const double r = b[row] - sx;
     if (dl_db != nullptr && lane == 0) dl_db[row] = sl;
     if (dl_da != nullptr)
-      for (int64_t c = lane; c < d; c += 64) dl_da[row * ld_da + c] = r * lam[c] - sl * x[c];
+      for (int64_t c = lane; c < d; c += 64) dl_da[row * ld_da + c] = r * lp[c] - sl * xp[c];
   }
 }
 
-hipError_t launch_solution_grads(const ProbInfo*, int32_t, int64_t n, int64_t d, const void* A,
-                                 bool a_f32, int64_t ld, const double* b, const double* x,
+hipError_t launch_solution_grads(const AdjointBatch& ab, int64_t d, const void* A, bool a_f32,
+                                 int64_t ld, const double* b, const double* x,
                                  const double* lambda, double* dl_db, double* dl_da,
                                  int64_t ld_da, hipStream_t st) {
-  if (n == 0) return hipSuccess;
-  const unsigned blocks = (unsigned)std::min<int64_t>((n + 3) / 4, 65536);
+  if (ab.count < 1 || ab.count > kAdjointBatch) return hipErrorInvalidValue;
+  const int64_t rows = ab.off[ab.count] - ab.off[0];
+  if (rows == 0) return hipSuccess;
+  const unsigned blocks = (unsigned)std::min<int64_t>((rows + 3) / 4, 65536);
   if (a_f32)
-    hipLaunchKernelGGL(k_solution_grads<float>, dim3(blocks), dim3(256), 0, st, n, d,
+    hipLaunchKernelGGL(k_solution_grads<float>, dim3(blocks), dim3(256), 0, st, ab, d,
                        static_cast<const float*>(A), ld, b, x, lambda, dl_db, dl_da, ld_da);
   else
-    hipLaunchKernelGGL(k_solution_grads<double>, dim3(blocks), dim3(256), 0, st, n, d,
+    hipLaunchKernelGGL(k_solution_grads<double>, dim3(blocks), dim3(256), 0, st, ab, d,
                        static_cast<const double*>(A), ld, b, x, lambda, dl_db, dl_da, ld_da);
   return hipGetLastError();
 }

@@ -138,3 +138,36 @@ def test_ragged_batch_grads_full_size_sampled(gpu_lib):
         # 20 steps at m = 10 d contract the IHS error to about 1e-9
         assert np.linalg.norm(host(bt.grad[r0:r1]) - db) <= 1e-6 * np.linalg.norm(db), p
         assert np.linalg.norm(host(At.grad[r0:r1]) - dA) <= 1e-6 * np.linalg.norm(dA), p
+
+
+def test_solution_grads_many_problems(gpu_lib):
+    """ihs_solution_grads over more problems than one launch takes (70 > 64),
+    with empty and one-row problems, for float64 and float32 data:
+    dL/db = A lambda and dL/dA = r lambda^T - (A lambda) x^T per problem,
+    against the same formulas in numpy (float64, within the rounding of
+    d-term dot products)."""
+    import torch
+    P = gpu_lib
+    g = np.random.default_rng(77)
+    sizes = g.integers(0, 120, 70)
+    sizes[[0, 33, 65]] = 0
+    sizes[[2, 64]] = 1
+    offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    n, d = int(offs[-1]), 20
+    for dt in (np.float64, np.float32):
+        A = g.standard_normal((n, d)).astype(dt)
+        b = g.standard_normal(n)
+        x = g.standard_normal((70, d))
+        lam = g.standard_normal((70, d))
+        M = P.Matrix(dense=torch.from_numpy(A).cuda(), row_offsets=offs)
+        db, dA = P.solution_grads(M, dev(b), dev(x), dev(lam))
+        db, dA = host(db), host(dA)
+        A64 = A.astype(np.float64)
+        for p in range(70):
+            r0, r1 = offs[p], offs[p + 1]
+            Al = A64[r0:r1] @ lam[p]
+            r = b[r0:r1] - A64[r0:r1] @ x[p]
+            ref = np.outer(r, lam[p]) - np.outer(Al, x[p])
+            scale = np.abs(A64[r0:r1]).sum(1, keepdims=True) + 1.0
+            assert np.allclose(db[r0:r1], Al, rtol=0, atol=1e-13 * 20 * 10), p
+            assert np.all(np.abs(dA[r0:r1] - ref) <= 1e-12 * scale * 10), p
