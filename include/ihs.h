@@ -130,14 +130,18 @@ typedef struct {
   double tol;                  /* reserved, must be 0: a solve always runs
                                   max_iter steps (stopping rules read x_hist) */
   int32_t schedule;            /* 0: overlap the next step's sort, Gram and
-                                  factorisation with the current pass over A
-                                  on other streams (unconstrained problems;
-                                  one extra sketch-only pass per solve);
+                                  (unconstrained) factorisation with the
+                                  current pass over A on other streams (one
+                                  extra sketch-only pass per solve); the
+                                  constrained QP of the step then runs on the
+                                  caller's stream from the Gram formed beside
+                                  the previous pass;
                                   1: strictly sequential steps;
                                   2: as 0 but two steps ahead, so the
                                   factorisation has two passes of time (for
                                   short passes, e.g. float32 data; two
-                                  sketch-only passes per solve).
+                                  sketch-only passes per solve; constrained
+                                  problems look one step ahead).
                                   All form bitwise identical sketches and
                                   factors; the iterates agree to rounding,
                                   since the fused pass adds up A^T r in the

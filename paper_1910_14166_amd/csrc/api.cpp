@@ -368,6 +368,7 @@ struct SolveBuffers {
   void* SA = nullptr;
   double* H = nullptr;
   void* gram_part = nullptr;
+  double* H1 = nullptr;      // second sketched Hessian of the overlapped constrained schedule
   double* Lf = nullptr;
   double* work = nullptr;
   // second set of the double-buffered arrays of the overlapped schedule
@@ -419,6 +420,8 @@ size_t carve_solve(Carver& c, const Layout& L, const ihs_options* o, SolveBuffer
   S.Lf1 = c.take<double>((size_t)(L.batch * L.d * L.d));
   S.work1 = c.take<double>((size_t)L.batch * qp_work_doubles(L.d, o->constraint));
   S.side_status = c.take<DeviceStatus>(1);
+  if (o->constraint != IHS_UNCONSTRAINED && o->schedule != 1)
+    S.H1 = c.take<double>((size_t)(L.batch * L.d * L.d));
   const bool ahead2 = o->schedule == 2 && o->constraint == IHS_UNCONSTRAINED;
   if (ahead2) {
     S.SA2 = c.take<char>((size_t)(L.batch * m * L.d * dtype_size(gram_in_of(o))));
@@ -556,8 +559,10 @@ ihs_status solve_overlap(const ihs_matrix* A, const Layout& L, const ihs_options
     }
     return P;
   };
-  // LA: how many steps ahead the passes form sketches; slots k % (LA + 1)
-  const int LA = opt->schedule == 2 ? 2 : 1;
+  // LA: how many steps ahead the passes form sketches; slots k % (LA + 1).
+  // Constrained steps look one step ahead: their side work is the Gram only.
+  const bool constrained = opt->constraint != IHS_UNCONSTRAINED;
+  const int LA = (opt->schedule == 2 && !constrained) ? 2 : 1;
   const int NS = LA + 1;
   auto sa_buf = [&](int64_t k) {
     const int64_t q = k % NS;
@@ -576,10 +581,12 @@ ihs_status solve_overlap(const ihs_matrix* A, const Layout& L, const ihs_options
     const int64_t q = k % NS;
     return q == 0 ? S.Hinv0 : (q == 1 ? S.Hinv1 : S.Hinv2);
   };
+  auto h_buf = [&](int64_t k) { return (constrained && k % 2) ? S.H1 : S.H; };
   auto factor = [&](int64_t k) -> bool {  // side stream: H_k, its factor (and inverse)
-    if (!ck(launch_gram(sa_buf(k), opt->gram_in, m, d, d, L.batch, opt->gram_acc, S.H,
+    if (!ck(launch_gram(sa_buf(k), opt->gram_in, m, d, d, L.batch, opt->gram_acc, h_buf(k),
                         S.gram_part, side)))
       return false;
+    if (constrained) return true;  // the QP of the step works from H_k itself
     if (!ck(launch_cholesky(S.H, l_buf(k), d, L.batch, S.side_status, (int32_t)k, 0.0,
                             w_buf(k), side)))
       return false;
@@ -637,9 +644,30 @@ ihs_status solve_overlap(const ihs_matrix* A, const Layout& L, const ihs_options
     if (t + LA < N) {
       if (!factor(t + LA) || !ck(hipEventRecord(evChol.at(t + LA), side))) return IHS_ERR_HIP;
     }
-    // main: x^{t+1} = x^t + H_t^{-1} g(x^t)
+    // main: x^{t+1} = x^t + H_t^{-1} g(x^t), or the constrained QP of Eq.(2)
+    // with H_t (its l2 shift state carries over in S.work from step to step)
     if (!ck(hipStreamWaitEvent(stream, evChol.at(t), 0))) return IHS_ERR_HIP;
-    if (use_inv) {
+    if (constrained) {
+      QpArgs a{};
+      a.d = d;
+      a.batch = L.batch;
+      a.constraint = opt->constraint;
+      a.radius = opt->radius;
+      a.max_inner = opt->qp_max_inner;
+      a.tol = opt->qp_tol;
+      a.H = h_buf(t);
+      a.g = B.g;
+      a.x = x;
+      a.x_out = x;
+      a.L = S.Lf;
+      a.work = S.work;
+      a.status = B.status;
+      a.iter = t;
+      a.warm = t > 0 ? 1 : 0;
+      const hipError_t e = launch_qp_step(a, stream);
+      if (e == hipErrorNotSupported) return IHS_ERR_UNSUPPORTED;
+      if (hip_failed(e)) return IHS_ERR_HIP;
+    } else if (use_inv) {
       if (!ck(launch_inv_apply(hinv_buf(t), d, L.batch, B.g, x, x, S.dx, B.status, stream,
                                S.side_status, t)))
         return IHS_ERR_HIP;
@@ -947,7 +975,7 @@ ihs_status ihs_solve(const ihs_matrix* A, const double* b, const ihs_options* op
   if ((s = upload_probs(L, B, stream)) != IHS_OK) return s;
   if (opt->method == IHS_METHOD_FIXED_SKETCH_CG)
     return solve_fixed_sketch_cg(A, L, opt, S, b, x, x_hist, rep, stream);
-  if (opt->schedule != 1 && opt->constraint == IHS_UNCONSTRAINED && opt->max_iter >= 2)
+  if (opt->schedule != 1 && opt->max_iter >= 2)
     return solve_overlap(A, L, opt, S, b, x, x_hist, factors, rep, stream);
   const int64_t d = A->d, m = opt->sketch.m;
   const int64_t bd = (int64_t)L.batch * d;

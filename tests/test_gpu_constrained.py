@@ -304,3 +304,32 @@ def test_ihs_l1_penalty_full_size_kkt(gpu_lib):
         assert np.abs(grad[~S]).max() <= wl.radius + 1e-6 * scale
     del wl
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("constraint,csr", [("l1", False), ("l1_penalty", False), ("l2", True)])
+def test_overlapped_constrained_matches_sequential(gpu_lib, constraint, csr):
+    """The overlapped schedule (the next step's sort and Gram beside the
+    current pass) forms the same sketches; the gradient is summed in another
+    row order, so the iterates agree with the sequential schedule to
+    rounding."""
+    P = gpu_lib
+    if csr:
+        wl = W.ridge_csr(rows=1 << 15, d=128, density=8e-3, m=1024, iters=6, radius_factor=0.5)
+        M = P.Matrix(row_ptr=dev(wl.indptr), col_idx=dev(wl.indices), values=dev(wl.data),
+                     n=wl.n, d=wl.d)
+        radius = wl.radius
+    else:
+        wl = W.lasso_dense(rows=20000, d=64, m=512, iters=6,
+                           penalty=40.0 if constraint == "l1_penalty" else None)
+        M = P.Matrix(dense=dev(wl.A))
+        radius = wl.radius
+    runs = {}
+    for sched in ("sequential", "overlap"):
+        o = P.options(wl.m, seed=wl.sketch_seed, max_iter=6, constraint=constraint,
+                      radius=radius, schedule=sched)
+        r = P.solve(M, dev(wl.b), o, history=True)
+        assert r.report.status == 0, sched
+        runs[sched] = host(r.history)[:, 0, :]
+    for t in range(6):
+        ref = runs["sequential"][t]
+        assert np.linalg.norm(runs["overlap"][t] - ref) <= 1e-9 * np.linalg.norm(ref), t
