@@ -318,7 +318,9 @@ def main():
             return args.max_iter // 2
 
         mixed = mixed_run(m, args.mixed_switch)
+        mixed_cg = mixed_run(m, switch_point(m, "fixed_sketch_cg"), "fixed_sketch_cg")
         ttt["A-float32-then-float64"] = mixed
+        ttt["A-float32-then-float64, fixed sketch + CG"] = mixed_cg
         fp64 = ttt["float64-in/float64-acc"]["time_to_tol_ms"]
         same = {k: v for k, v in ttt.items() if k != "A-float32/float64-in/float64-acc"}
         best = min((v["time_to_tol_ms"], k) for k, v in same.items()
