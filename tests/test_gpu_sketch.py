@@ -52,6 +52,7 @@ CASES = [  # n, d, m, s
     (40000, 8, 16384, 1),    # largest sketch: two 7-bit radix digits
     (300, 5, 1, 1),          # one sketch row: no radix bits
     (70000, 16, 4096, 4),    # many sort tiles, SJLT over 4 blocks
+    (600, 20, 16, 16),       # SJLT with one bucket per block: every row in every sketch row
 ]
 
 
@@ -123,7 +124,8 @@ def test_empty_matrix_gives_zero_sketch(gpu_lib):
 
 
 @pytest.mark.parametrize("n,d,density,m,s", [(3000, 40, 0.05, 64, 1), (20000, 300, 0.01, 512, 4),
-                                             (500, 1024, 0.002, 16, 1), (100, 5, 0.0, 8, 1)])
+                                             (500, 1024, 0.002, 16, 1), (100, 5, 0.0, 8, 1),
+                                             (800, 30, 0.2, 8, 8)])
 def test_csr_sketch_bit_exact(gpu_lib, n, d, density, m, s):
     P = gpu_lib
     import torch
@@ -167,7 +169,7 @@ def test_ragged_batch_sketch(gpu_lib):
         assert np.array_equal(out[p * m:(p + 1) * m], ref), p
 
 
-@pytest.mark.parametrize("s", [1, 4])
+@pytest.mark.parametrize("s", [1, 4, 16])
 def test_sketch_adjoint(gpu_lib, s):
     P = gpu_lib
     g = np.random.default_rng(6)
