@@ -207,7 +207,8 @@ ihs_status ihs_sketch_apply(const ihs_sketch* sk, const ihs_matrix* A,
  * is n x d F64 with leading dimension ld_out. Row i of problem p receives the
  * sum over blocks k, ascending from +0.0, of sign(i,k) * (c_s * G[p*m +
  * bucket(i,k)][:]), c_s = 1/sqrt(s) (the factor is skipped for s = 1).
- * row_offsets: HOST, batch+1 entries (NULL when batch = 1). Asynchronous. */
+ * row_offsets: HOST, batch+1 entries (NULL when batch = 1). s > 16 returns
+ * IHS_ERR_UNSUPPORTED. Asynchronous. */
 ihs_status ihs_sketch_adjoint(const ihs_sketch* sk, int64_t n, int64_t d,
                               int32_t batch, const int64_t* row_offsets,
                               const double* G, int64_t ld_g,
