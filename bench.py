@@ -370,6 +370,10 @@ def main():
     # ------------------------------------------------- CPU baseline ----
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, m)
+        # the dense OLS configuration the paper quotes in CPU seconds
+        # (20000 x 50, CountSketch m = 500, 10 IHS steps): the oracle's time and
+        # the library's on the same inputs
+        out["cpu_baseline"]["ols_20000x50_m500_10steps"] = ols_small(P, W)
 
     out["gen_s"] = round(t_gen, 2)
     print(json.dumps(out), flush=True)
@@ -638,6 +642,39 @@ def cpu_baseline(wl, m, budget_s=15.0):
             "sample": f"{steps} full IHS steps (sketch, Gram, gradient, QP) on the first "
                       f"{rows} of {wl.n} rows, m={m}; {per * 1e3:.1f} ms per step",
             "cpu_count": len(os.sched_getaffinity(0))}
+
+
+def ols_small(P, W):
+    """Seconds of 10 IHS steps on the 20000 x 50 dense OLS problem (m = 500):
+    the CPU oracle (median of 3) and the library (median of 5 wall-clock
+    solves, synchronised), with the final A-norm error of each against
+    x_OPT."""
+    import numpy as np
+    import torch
+    from oracle import ihs as O
+    wl = W.ols_dense()
+    cpu = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        xs = O.ihs(wl.A, wl.b, wl.m, seed=wl.sketch_seed, iters=wl.iters)
+        cpu.append(time.perf_counter() - t0)
+    A = torch.from_numpy(wl.A).cuda()
+    b = torch.from_numpy(wl.b).cuda()
+    M = P.Matrix(dense=A)
+    o = P.options(wl.m, seed=wl.sketch_seed, max_iter=wl.iters)
+    ws = torch.empty(P.workspace_size(M, o), dtype=torch.uint8, device="cuda")
+    gpu = []
+    for _ in range(6):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = P.solve(M, b, o, ws=ws)
+        torch.cuda.synchronize()
+        gpu.append(time.perf_counter() - t0)
+    xo = O.x_opt(wl.A, wl.b)
+    return {"oracle_s": round(float(np.median(cpu)), 4),
+            "gpu_s": round(float(np.median(gpu[1:])), 5),
+            "oracle_err_A": O.error_A(wl.A, xs[-1], xo),
+            "gpu_err_A": O.error_A(wl.A, r.x[0].cpu().numpy(), xo)}
 
 
 if __name__ == "__main__":
