@@ -4,7 +4,9 @@ Every function marshals torch tensors (device memory) into the C ABI of
 include/ihs.h and calls it on the current HIP stream. All arithmetic runs in
 the library's HIP kernels; nothing here computes a result. The library must be
 built (`python -m paper_1910_14166_amd.build`); importing works without it,
-but every call raises IHSError until it is loaded.
+but load() and every call raise RuntimeError while libihs.so is missing, and
+a failing library call raises IHSError (for IHS_ERR_HIP with the HIP error
+behind it).
 """
 from __future__ import annotations
 
