@@ -232,6 +232,13 @@ __global__ __launch_bounds__(256) void k_chol_init(const double* __restrict__ H,
   L[idx] = (j <= i) ? H[idx] + (i == j ? shift : 0.0) : 0.0;
 }
 
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  const uint64_t u = (uint64_t)__double_as_longlong(v);
+  const uint64_t lo = readlane_u32((uint32_t)u, lane);
+  const uint64_t hi = readlane_u32((uint32_t)(u >> 32), lane);
+  return __longlong_as_double((long long)((hi << 32) | lo));
+}
+
 // Diagonal block of panel kb: one workgroup of 512 threads per problem
 // factors the 64 x 64 block right-looking in steps of four columns. Thread t
 // keeps row t/8, columns 8*(t%8) .. +7, in registers. At each step:
@@ -367,7 +374,7 @@ __global__ __launch_bounds__(kDiagThreads) void k_chol_diag(double* L, int64_t d
 
 // Panel rows below the diagonal block: x L_kk^T = a for each row, one row per
 // wavefront pass with lanes over the 64 columns; the factored block is staged
-// in LDS and x_c is broadcast from lane c (column-oriented substitution).
+// in LDS and x_c is read from lane c (column-oriented substitution).
 // Four rows are interleaved per wavefront for independent dependency chains.
 // The rows, the block and the pivots are requested together with the status,
 // so the kernel waits for memory once.
@@ -400,9 +407,8 @@ __global__ __launch_bounds__(256) void k_chol_trsm(double* L, int64_t d, int64_t
     const double rc = rd[c];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const double xc = __shfl(a[u], c, 64) * rc;
-      if (lane == c) a[u] = xc;
-      else if (lane > c) a[u] = fma(-xc, lkc, a[u]);
+      const double xc = readlane_f64(a[u], c) * rc;
+      a[u] = lane == c ? xc : (lane > c ? fma(-xc, lkc, a[u]) : a[u]);
     }
   }
 #pragma unroll
@@ -491,7 +497,7 @@ hipError_t launch_cholesky(const double* H, double* L, int64_t d, int32_t batch,
 // ---------------------------------------------------------------------------
 // out = base + (L L^T)^{-1} v, one workgroup (256 threads) per problem.
 // Per 64-row block: the diagonal block is staged in LDS and solved by
-// wavefront 0 (lane c holds y_c; x_c is broadcast from lane c, reciprocal
+// wavefront 0 (lane c holds y_c; x_c is read from lane c, reciprocal
 // pivots from the factorisation); the remaining rows are updated by all four
 // wavefronts, four rows at a time with one transposing butterfly.
 // Also records sqrt(dx^T v) for problem 0.
@@ -533,11 +539,11 @@ __global__ __launch_bounds__(256) void k_chol_solve(const double* __restrict__ L
     __syncthreads();
     if (wv == 0) {
       double yl = lane < nb ? y[jb + lane] : 0.0;
+      const double rl = lane < nb ? rp[jb + lane] : 0.0;
       for (int c = 0; c < nb; ++c) {
         const double lkc = D[lane][c];
-        const double xc = __shfl(yl, c, 64) * rp[jb + c];
-        if (lane == c) yl = xc;
-        else if (lane > c) yl = fma(-xc, lkc, yl);
+        const double xc = readlane_f64(yl, c) * readlane_f64(rl, c);
+        yl = lane == c ? xc : (lane > c ? fma(-xc, lkc, yl) : yl);
       }
       if (lane < nb) y[jb + lane] = yl;
     }
@@ -564,11 +570,11 @@ __global__ __launch_bounds__(256) void k_chol_solve(const double* __restrict__ L
     __syncthreads();
     if (wv == 0) {
       double yl = lane < nb ? y[jb + lane] : 0.0;
+      const double rl = lane < nb ? rp[jb + lane] : 0.0;
       for (int c = nb - 1; c >= 0; --c) {
         const double lck = D[c][lane];
-        const double xc = __shfl(yl, c, 64) * rp[jb + c];
-        if (lane == c) yl = xc;
-        else if (lane < c) yl = fma(-xc, lck, yl);
+        const double xc = readlane_f64(yl, c) * readlane_f64(rl, c);
+        yl = lane == c ? xc : (lane < c ? fma(-xc, lck, yl) : yl);
       }
       if (lane < nb) y[jb + lane] = yl;
     }
