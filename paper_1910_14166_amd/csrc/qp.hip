@@ -3,14 +3,13 @@
 // the gradient partials produced by the row passes.
 //
 // Unconstrained step: x^{t+1} = x^t + H^{-1} g with H = L L^T.
-//  * d <= 88: one workgroup per problem factors H in LDS.
-//  * d  > 88: right-looking blocked Cholesky, 64-column panels. A panel
-//    launch factors the 64 x 64 diagonal block in LDS (every workgroup of the
-//    launch redundantly, so no inter-workgroup wait is needed) and solves its
-//    share of the panel rows; an update launch subtracts P P^T from the
-//    trailing lower triangle with FP64 matrix-core tiles.
+//  * Right-looking blocked Cholesky, 64-column panels: per panel one launch
+//    factors the 64 x 64 diagonal block (padded with the identity when d is
+//    not a multiple of 64, so d <= 64 is one such launch), one solves the
+//    panel rows below it, and one subtracts P P^T from the trailing lower
+//    triangle with FP64 matrix-core tiles.
 //  * Triangular solves: one workgroup; each 64-block is solved by one
-//    wavefront with lane shuffles, the rest of the vector is updated by all.
+//    wavefront with cross-lane reads, the rest of the vector is updated by all.
 #include <algorithm>
 
 #include "kernels.hpp"
@@ -18,8 +17,6 @@
 namespace ihs {
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
-
-constexpr int kSmallChol = 88;
 
 // Sum four per-lane partial values across the wavefront (transposing
 // butterfly, fixed order): afterwards lane row_lane4(u) holds row u's total.
@@ -155,69 +152,7 @@ hipError_t launch_reduce_partials(const double* gpart, const double* fpart, int3
 }
 
 // ---------------------------------------------------------------------------
-// Small Cholesky in LDS: one workgroup (256 threads) per problem.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_chol_small(const double* __restrict__ H, double* L,
-                                                    int64_t d, DeviceStatus* st, int32_t iter,
-                                                    double shift, double* rdiag,
-                                                    const double* __restrict__ trs) {
-  extern __shared__ double a[];
-  __shared__ int fail;
-  const int p = blockIdx.x;
-  if (threadIdx.x == 0) fail = (st->code != 0 || trs_skip(trs, p)) ? 1 : 0;
-  __syncthreads();
-  if (fail != 0) return;  // one read per workgroup keeps the exit uniform
-  if (trs) shift = trs[4 * p];
-  const double* Hp = H + (int64_t)p * d * d;
-  double* Lp = L + (int64_t)p * d * d;
-  const int tid = threadIdx.x;
-  for (int64_t e0 = 0; e0 < d * d; e0 += 256 * 8) {  // 8 loads in flight per thread
-    double v[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int64_t e = e0 + tid + 256 * q;
-      const int64_t i = e / d, j = e - (e / d) * d;
-      v[q] = (e < d * d && j <= i) ? Hp[e] + (i == j ? shift : 0.0) : 0.0;
-    }
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int64_t e = e0 + tid + 256 * q;
-      if (e < d * d) a[e] = v[q];
-    }
-  }
-  __syncthreads();
-  for (int64_t j = 0; j < d; ++j) {
-    const double piv = a[j * d + j];
-    const bool bad = !(piv > 0.0) || !isfinite(piv);
-    if (bad) {
-      if (tid == 0) {
-        fail = 1;
-        status_fail(st, 5 /* IHS_ERR_NOT_PD */, iter, p);
-      }
-      break;
-    }
-    const double ljj = sqrt(piv);
-    __syncthreads();
-    if (tid == 0) {
-      a[j * d + j] = ljj;
-      rdiag[(int64_t)p * d + j] = 1.0 / ljj;
-    }
-    for (int64_t i = j + 1 + tid; i < d; i += 256) a[i * d + j] = a[i * d + j] / ljj;
-    __syncthreads();
-    const int64_t w = d - j - 1;
-    for (int64_t e = tid; e < w * w; e += 256) {
-      const int64_t i = j + 1 + e / w, k = j + 1 + (e - (e / w) * w);
-      if (k <= i) a[i * d + k] = fma(-a[i * d + j], a[k * d + j], a[i * d + k]);
-    }
-    __syncthreads();
-  }
-  __syncthreads();
-  if (fail) return;
-  for (int64_t e = tid; e < d * d; e += 256) Lp[e] = a[e];
-}
-
-// ---------------------------------------------------------------------------
-// Blocked Cholesky for larger d, in place on L (lower triangle).
+// Blocked Cholesky, in place on L (lower triangle).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_chol_init(const double* __restrict__ H, double* L,
                                                    int64_t d, int32_t batch, double shift,
@@ -470,11 +405,6 @@ hipError_t launch_cholesky(const double* H, double* L, int64_t d, int32_t batch,
                            DeviceStatus* status, int32_t iter, double shift, double* scratch,
                            hipStream_t st, const double* trs) {
   double* rdiag = chol_rdiag(scratch, batch);
-  if (d <= kSmallChol) {
-    hipLaunchKernelGGL(k_chol_small, dim3(batch), dim3(256), (size_t)(d * d * sizeof(double)),
-                       st, H, L, d, status, iter, shift, rdiag, trs);
-    return hipGetLastError();
-  }
   const int64_t tot = (int64_t)batch * d * d;
   hipLaunchKernelGGL(k_chol_init, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, H, L, d,
                      batch, shift, trs);
