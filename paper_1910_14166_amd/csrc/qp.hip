@@ -453,9 +453,14 @@ hipError_t launch_cholesky(const double* H, double* L, int64_t d, int32_t batch,
 // Per 64-row block: the diagonal block is staged in LDS and solved by
 // wavefront 0 (lane c holds y_c; x_c is read from lane c, reciprocal
 // pivots from the factorisation); the remaining rows are updated by all four
-// wavefronts, four rows at a time with one transposing butterfly.
+// wavefronts, four rows at a time with one transposing butterfly. The loads
+// of several passes are issued together (kSolveGroups passes forward,
+// kSolveCols columns backward), since one workgroup is bound by the latency
+// of its reads of L, not by their bandwidth.
 // Also records sqrt(dx^T v) for problem 0.
 // ---------------------------------------------------------------------------
+constexpr int kSolveGroups = 4, kSolveCols = 32;
+
 __global__ __launch_bounds__(256) void k_chol_solve(const double* __restrict__ L, int64_t d,
                                                     const double* __restrict__ rdiag,
                                                     const double* __restrict__ v,
@@ -502,16 +507,25 @@ __global__ __launch_bounds__(256) void k_chol_solve(const double* __restrict__ L
       if (lane < nb) y[jb + lane] = yl;
     }
     __syncthreads();
-    for (int64_t i0 = jb + nb + (int64_t)wv * 4; i0 < d; i0 += 16) {
-      double t[4];
-      const double yb = lane < nb ? y[jb + lane] : 0.0;
+    const double yb = lane < nb ? y[jb + lane] : 0.0;
+    for (int64_t i0 = jb + nb + (int64_t)wv * 4; i0 < d; i0 += 16 * kSolveGroups) {
+      // the rows of kSolveGroups passes are requested before any is reduced
+      double t[kSolveGroups][4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
-        t[u] = (i0 + u < d && lane < nb) ? Lp[(i0 + u) * d + jb + lane] * yb : 0.0;
-      const double s = multi_row_sum4(t, lane);
+      for (int g = 0; g < kSolveGroups; ++g)
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        if (lane == row_lane4(u) && i0 + u < d) y[i0 + u] -= s;
+        for (int u = 0; u < 4; ++u) {
+          const int64_t r = i0 + 16 * g + u;
+          t[g][u] = (r < d && lane < nb) ? Lp[r * d + jb + lane] * yb : 0.0;
+        }
+#pragma unroll
+      for (int g = 0; g < kSolveGroups; ++g) {
+        const double s = multi_row_sum4(t[g], lane);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int64_t r = i0 + 16 * g + u;
+          if (lane == row_lane4(u) && r < d) y[r] -= s;
+        }
       }
     }
     __syncthreads();
@@ -535,8 +549,15 @@ __global__ __launch_bounds__(256) void k_chol_solve(const double* __restrict__ L
     __syncthreads();
     for (int64_t i = tid; i < jb; i += 256) {
       double s = 0.0;
-#pragma unroll 8
-      for (int c = 0; c < nb; ++c) s = fma(Lp[(jb + c) * d + i], y[jb + c], s);
+      for (int c0 = 0; c0 < nb; c0 += kSolveCols) {
+        double lv[kSolveCols];  // requested together, summed in column order
+#pragma unroll
+        for (int q = 0; q < kSolveCols; ++q)
+          lv[q] = c0 + q < nb ? Lp[(jb + c0 + q) * d + i] : 0.0;
+#pragma unroll
+        for (int q = 0; q < kSolveCols; ++q)
+          if (c0 + q < nb) s = fma(lv[q], y[jb + c0 + q], s);
+      }
       y[i] -= s;
     }
     __syncthreads();
