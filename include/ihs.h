@@ -130,12 +130,13 @@ typedef struct {
   double tol;                  /* reserved, must be 0: a solve always runs
                                   max_iter steps (stopping rules read x_hist) */
   int32_t schedule;            /* 0: overlap the next step's sort, Gram and
-                                  (unconstrained) factorisation with the
-                                  current pass over A on other streams (one
-                                  extra sketch-only pass per solve); the
-                                  constrained QP of the step then runs on the
-                                  caller's stream from the Gram formed beside
-                                  the previous pass;
+                                  (unconstrained and l1 ball) factorisation
+                                  with the current pass over A on other
+                                  streams (one extra sketch-only pass per
+                                  solve); the constrained QP of the step then
+                                  runs on the caller's stream from the Gram
+                                  (and factor) formed beside the previous
+                                  pass;
                                   1: strictly sequential steps;
                                   2: as 0 but two steps ahead, so the
                                   factorisation has two passes of time (for

@@ -217,6 +217,13 @@ SketchPlan make_plan(const Layout& L, const ihs_sketch* sk, const PassBuffers& B
   return P;
 }
 
+// Carries a failure that another stream recorded at or before step `iter`
+// into `to`, so that the kernels reading `to` in that step see it.
+__global__ void k_adopt_status(const DeviceStatus* from, int32_t iter, DeviceStatus* to) {
+  if (threadIdx.x == 0 && status_failed_by(from, iter))
+    status_fail(to, from->code, from->failed_iter, from->failed_problem);
+}
+
 __global__ void k_zero_status(DeviceStatus* st) {
   if (threadIdx.x == 0) {
     st->code = 0;
@@ -586,7 +593,12 @@ ihs_status solve_overlap(const ihs_matrix* A, const Layout& L, const ihs_options
     if (!ck(launch_gram(sa_buf(k), opt->gram_in, m, d, d, L.batch, opt->gram_acc, h_buf(k),
                         S.gram_part, side)))
       return false;
-    if (constrained) return true;  // the QP of the step works from H_k itself
+    // The constrained QPs work from H_k itself; the l1 ball's also needs the
+    // unconstrained minimiser, so H_k is factored here, beside the pass.
+    if (constrained)
+      return opt->constraint != IHS_L1_BALL ||
+             ck(launch_cholesky(h_buf(k), l_buf(k), d, L.batch, S.side_status, (int32_t)k, 0.0,
+                                w_buf(k), side));
     if (!ck(launch_cholesky(S.H, l_buf(k), d, L.batch, S.side_status, (int32_t)k, 0.0,
                             w_buf(k), side)))
       return false;
@@ -664,6 +676,12 @@ ihs_status solve_overlap(const ihs_matrix* A, const Layout& L, const ihs_options
       a.status = B.status;
       a.iter = t;
       a.warm = t > 0 ? 1 : 0;
+      if (opt->constraint == IHS_L1_BALL) {  // H_t's factor comes from the side stream
+        hipLaunchKernelGGL(k_adopt_status, dim3(1), dim3(64), 0, stream, S.side_status, t,
+                           B.status);
+        a.L = l_buf(t);
+        a.rdiag_pre = chol_rdiag(w_buf(t), L.batch);
+      }
       const hipError_t e = launch_qp_step(a, stream);
       if (e == hipErrorNotSupported) return IHS_ERR_UNSUPPORTED;
       if (hip_failed(e)) return IHS_ERR_HIP;

@@ -836,10 +836,14 @@ hipError_t launch_qp_constrained(const QpArgs& a, hipStream_t st) {
     hipLaunchKernelGGL(k_form_c, dim3((unsigned)((d + 3) / 4), B), dim3(256), 0, st, a.H, d,
                        a.x, a.g, cbuf);
     if (!penalty) {  // the unconstrained minimiser, the answer when the ball is inactive
-      if ((e = launch_cholesky(a.H, a.L, d, B, a.status, a.iter, 0.0, scratch, st)) !=
-          hipSuccess)
-        return e;
-      e = launch_chol_solve_update(a.L, rdiag, d, B, a.g, a.x, xunc, a.status, st);
+      const double* rd = a.rdiag_pre;
+      if (!rd) {
+        if ((e = launch_cholesky(a.H, a.L, d, B, a.status, a.iter, 0.0, scratch, st)) !=
+            hipSuccess)
+          return e;
+        rd = rdiag;
+      }
+      e = launch_chol_solve_update(a.L, rd, d, B, a.g, a.x, xunc, a.status, st);
       if (e != hipSuccess) return e;
     }
     const int32_t max_iter = a.max_inner > 0 ? a.max_inner : 5000;
