@@ -13,6 +13,7 @@
 #include <algorithm>
 
 #include "kernels.hpp"
+#include "rowdot.hpp"
 
 namespace ihs {
 
@@ -855,9 +856,7 @@ __global__ __launch_bounds__(256) void k_inv_apply(const double* __restrict__ Hi
   const bool skip = status_failed_by(st, -1) || (gate && status_failed_by(gate, gate_iter));
   const double* hr = Hinv + ((int64_t)p * d + i) * d;
   const double* gp = g + (int64_t)p * d;
-  double s = 0.0;
-  for (int64_t c = lane; c < d; c += 64) s = fma(hr[c], gp[c], s);
-  s = wave_sum(s);
+  const double s = row_dot<false>(hr, gp, d, lane);
   if (lane == 0) {
     const int64_t k = (int64_t)p * d + i;
     dx[k] = skip ? 0.0 : s;

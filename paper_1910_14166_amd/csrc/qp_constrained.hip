@@ -34,6 +34,7 @@
 #include <vector>
 
 #include "kernels.hpp"
+#include "rowdot.hpp"
 
 namespace ihs {
 
@@ -583,9 +584,7 @@ __global__ __launch_bounds__(256) void k_form_c(const double* __restrict__ H, in
   if (i >= d) return;
   const double* hr = H + ((int64_t)p * d + i) * d;
   const double* xp = x + (int64_t)p * d;
-  double s = 0.0;
-  for (int64_t k = lane; k < d; k += 64) s = fma(hr[k], xp[k], s);
-  s = wave_sum(s);
+  const double s = row_dot<false>(hr, xp, d, lane);
   if (lane == 0) c[(int64_t)p * d + i] = s + g[(int64_t)p * d + i];
 }
 
@@ -669,9 +668,7 @@ __global__ __launch_bounds__(256) void k_trs_symv(const double* __restrict__ M, 
   if (i >= d) return;
   const double* mr = M + ((int64_t)p * d + i) * d;
   const double* vp = v + (int64_t)p * d;
-  double s = 0.0;
-  for (int64_t k = lane; k < d; k += 64) s = fma(mr[k], vp[k], s);
-  s = wave_sum(s);
+  const double s = row_dot<false>(mr, vp, d, lane);
   if (lane == 0) out[(int64_t)p * d + i] = base ? base[(int64_t)p * d + i] + s : s;
 }
 
@@ -725,9 +722,7 @@ __global__ __launch_bounds__(256) void k_trs_abs_rows(const double* __restrict__
   const int64_t i = (int64_t)blockIdx.x * 4 + wv;
   if (i >= d) return;
   const double* mr = M + ((int64_t)p * d + i) * d;
-  double s = 0.0;
-  for (int64_t k = lane; k < d; k += 64) s += fabs(mr[k]);
-  s = wave_sum(s);
+  const double s = row_dot<true>(mr, nullptr, d, lane);
   if (lane == 0) rows[(int64_t)p * d + i] = s;
 }
 
@@ -768,9 +763,7 @@ __global__ __launch_bounds__(256) void k_trs_resid(const double* __restrict__ H,
   if (i >= d) return;
   const double* hr = H + ((int64_t)p * d + i) * d;
   const double* wp = w + (int64_t)p * d;
-  double s = 0.0;
-  for (int64_t k = lane; k < d; k += 64) s = fma(hr[k], wp[k], s);
-  s = wave_sum(s);
+  const double s = row_dot<false>(hr, wp, d, lane);
   if (lane == 0) {
     const int64_t e = (int64_t)p * d + i;
     out[e] = v[e] - s - trs[4 * p] * w[e];
