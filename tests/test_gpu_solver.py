@@ -121,7 +121,8 @@ def spd(d, g, cond):
 
 
 @pytest.mark.parametrize("d,batch", [(50, 1), (64, 4), (256, 1), (512, 1), (130, 2), (1, 1),
-                                     (1024, 1)])
+                                     (1024, 1), (2, 1), (63, 2), (65, 1), (88, 1), (89, 1),
+                                     (127, 1), (128, 1), (129, 3), (577, 1)])
 def test_qp_unconstrained(gpu_lib, d, batch):
     P = gpu_lib
     g = np.random.default_rng(d)
@@ -135,11 +136,14 @@ def test_qp_unconstrained(gpu_lib, d, batch):
         assert np.linalg.norm(dx - dref) <= 1e-12 * 1e3 * np.linalg.norm(dref) * max(1, d / 64)
 
 
-def test_qp_not_positive_definite(gpu_lib):
+@pytest.mark.parametrize("d,bad,value", [(200, 150, -1.0), (40, 10, -1.0), (64, 63, 0.0),
+                                         (100, 70, float("nan"))])
+def test_qp_not_positive_definite(gpu_lib, d, bad, value):
+    """A negative, zero or NaN pivot, in the first diagonal block, its last
+    column or a later block, is reported as not positive definite."""
     P = gpu_lib
-    d = 200
     H = np.eye(d)
-    H[150, 150] = -1.0
+    H[bad, bad] = value
     with pytest.raises(P.IHSError) as e:
         P.qp_step(dev(H[None]), dev(np.ones((1, d))), dev(np.zeros((1, d))))
     assert e.value.code == P.ERR_NOT_PD
