@@ -460,12 +460,6 @@ hipError_t launch_cholesky(const double* H, double* L, int64_t d, int32_t batch,
 // of its reads of L, not by their bandwidth.
 // Also records sqrt(dx^T v) for problem 0.
 // ---------------------------------------------------------------------------
-// From this width on the unconstrained step forms H^{-1} (blocked triangular
-// inverse on matrix cores) and applies it with one product per row: the two
-// triangular solves of one workgroup take 2 d / 64 block steps one after the
-// other (about 0.8 ms at d = 1024 against about 0.3 ms for the inverse).
-constexpr int64_t kQpInverseMinD = 89;
-
 constexpr int kSolveGroups = 4, kSolveCols = 32;
 
 __global__ __launch_bounds__(256) void k_chol_solve(const double* __restrict__ L, int64_t d,

@@ -860,14 +860,29 @@ hipError_t launch_qp_constrained(const QpArgs& a, hipStream_t st) {
   if (!a.warm) {
     if ((e = launch_cholesky(a.H, a.L, d, B, a.status, a.iter, 0.0, scratch, st)) != hipSuccess)
       return e;
-    e = launch_chol_solve_update(a.L, rdiag, d, B, a.g, a.x, xunc, a.status, st);
-    if (e != hipSuccess) return e;
+    // the unconstrained step computed as the unconstrained QP computes it
+    // (so an inactive ball returns that step bit for bit), then z
+    const bool inv = d >= kQpInverseMinD;
+    if (inv) {
+      if ((e = launch_chol_inverse(a.L, rdiag, d, B, hinv, linv, a.status, st)) != hipSuccess)
+        return e;
+      hipLaunchKernelGGL(k_trs_symv, rows_grid, dim3(256), 0, st, hinv, d, a.g, a.x, xunc, trs,
+                         a.status);
+    } else if ((e = launch_chol_solve_update(a.L, rdiag, d, B, a.g, a.x, xunc, a.status, st)) !=
+               hipSuccess) {
+      return e;
+    }
     hipLaunchKernelGGL(k_trs_inside, dim3(B), dim3(256), 0, st, xunc, d, a.radius, trs, a.x_out,
                        a.status);
-    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((bd + 255) / 256)), dim3(256), 0, st, zero,
-                       bd);
-    e = launch_chol_solve_update(a.L, rdiag, d, B, xunc, zero, zk, a.status, st);
-    if (e != hipSuccess) return e;
+    if (inv) {
+      hipLaunchKernelGGL(k_trs_symv, rows_grid, dim3(256), 0, st, hinv, d, xunc, nullptr, zk, trs,
+                         a.status);
+    } else {
+      hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((bd + 255) / 256)), dim3(256), 0, st, zero,
+                         bd);
+      e = launch_chol_solve_update(a.L, rdiag, d, B, xunc, zero, zk, a.status, st);
+      if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(k_trs_update, dim3(B), dim3(256), 0, st, xunc, zk, d, a.radius, tol, trs,
                        a.x_out, a.status);
   }

@@ -1,5 +1,6 @@
 // Row products of the d x d step kernels (H, its inverse or a shifted copy
-// against a d-vector), one wavefront per row.
+// against a d-vector), one wavefront per row, and the width from which the
+// step applies an explicit inverse.
 #pragma once
 
 #include "kernels.hpp"
@@ -12,6 +13,13 @@ namespace ihs {
 // wavefront's product is bound by the latency of its reads, not by their
 // bandwidth, so for d <= 64 * kRowDotLoads it waits for memory once.
 constexpr int kRowDotLoads = 16;
+
+// From this width on the unconstrained step (and the l2 ball's cold start)
+// forms H^{-1} (blocked triangular inverse on matrix cores) and applies it
+// with these row products: the two triangular solves of one workgroup take
+// 2 d / 64 block steps one after the other (about 0.8 ms at d = 1024 against
+// about 0.3 ms for the inverse).
+constexpr int64_t kQpInverseMinD = 89;
 
 template <bool ABS>
 __device__ __forceinline__ double row_dot(const double* __restrict__ row,
