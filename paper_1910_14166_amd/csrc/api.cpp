@@ -435,7 +435,8 @@ size_t carve_solve(Carver& c, const Layout& L, const ihs_options* o, SolveBuffer
     S.Lf2 = c.take<double>((size_t)(L.batch * L.d * L.d));
     S.work2 = c.take<double>((size_t)L.batch * qp_work_doubles(L.d, o->constraint));
   }
-  if (L.d >= kInverseMinD && o->constraint == IHS_UNCONSTRAINED) {
+  if (L.d >= kInverseMinD &&
+      (o->constraint == IHS_UNCONSTRAINED || o->constraint == IHS_L1_BALL)) {
     S.Hinv0 = c.take<double>((size_t)(L.batch * L.d * L.d));
     S.Hinv1 = c.take<double>((size_t)(L.batch * L.d * L.d));
     if (ahead2) S.Hinv2 = c.take<double>((size_t)(L.batch * L.d * L.d));
@@ -594,11 +595,17 @@ ihs_status solve_overlap(const ihs_matrix* A, const Layout& L, const ihs_options
                         S.gram_part, side)))
       return false;
     // The constrained QPs work from H_k itself; the l1 ball's also needs the
-    // unconstrained minimiser, so H_k is factored here, beside the pass.
-    if (constrained)
-      return opt->constraint != IHS_L1_BALL ||
-             ck(launch_cholesky(h_buf(k), l_buf(k), d, L.batch, S.side_status, (int32_t)k, 0.0,
-                                w_buf(k), side));
+    // unconstrained minimiser, so H_k is factored (and, from kInverseMinD
+    // on, inverted) here, beside the pass.
+    if (constrained) {
+      if (opt->constraint != IHS_L1_BALL) return true;
+      if (!ck(launch_cholesky(h_buf(k), l_buf(k), d, L.batch, S.side_status, (int32_t)k, 0.0,
+                              w_buf(k), side)))
+        return false;
+      return !use_inv ||
+             ck(launch_chol_inverse(l_buf(k), chol_rdiag(w_buf(k), L.batch), d, L.batch,
+                                    hinv_buf(k), S.Linv, S.side_status, side));
+    }
     if (!ck(launch_cholesky(S.H, l_buf(k), d, L.batch, S.side_status, (int32_t)k, 0.0,
                             w_buf(k), side)))
       return false;
@@ -679,8 +686,12 @@ ihs_status solve_overlap(const ihs_matrix* A, const Layout& L, const ihs_options
       if (opt->constraint == IHS_L1_BALL) {  // H_t's factor comes from the side stream
         hipLaunchKernelGGL(k_adopt_status, dim3(1), dim3(64), 0, stream, S.side_status, t,
                            B.status);
-        a.L = l_buf(t);
-        a.rdiag_pre = chol_rdiag(w_buf(t), L.batch);
+        if (use_inv) {
+          a.hinv_pre = hinv_buf(t);
+        } else {
+          a.L = l_buf(t);
+          a.rdiag_pre = chol_rdiag(w_buf(t), L.batch);
+        }
       }
       const hipError_t e = launch_qp_step(a, stream);
       if (e == hipErrorNotSupported) return IHS_ERR_UNSUPPORTED;

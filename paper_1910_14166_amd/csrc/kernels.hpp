@@ -148,6 +148,8 @@ struct QpArgs {
   int32_t warm;            // l2 ball: start the shift from the previous step's root
   const double* rdiag_pre; // l1 ball (nullable): L already holds the factor of H and
                            // this its reciprocal pivots, so the step does not factor H
+  const double* hinv_pre;  // l1 ball (nullable): H^{-1} formed elsewhere; the step
+                           // then uses neither L nor rdiag_pre
 };
 size_t qp_work_doubles(int64_t d, int32_t constraint);
 hipError_t launch_qp_step(const QpArgs& a, hipStream_t st);

@@ -575,6 +575,24 @@ __global__ __launch_bounds__(kQpThreads) void k_qp_l1(
 }
 
 // c = H x + g per problem (one wavefront per row).
+// out = x + H^{-1} g per problem, one wavefront per row: the unconstrained
+// step as the wide unconstrained QP forms it. Keeps x after a failure.
+__global__ __launch_bounds__(256) void k_apply_inverse(const double* __restrict__ Hinv, int64_t d,
+                                                       const double* __restrict__ g,
+                                                       const double* __restrict__ x, double* out,
+                                                       const DeviceStatus* st) {
+  const int p = blockIdx.y;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * 4 + wv;
+  if (i >= d) return;
+  const int64_t e = (int64_t)p * d + i;
+  if (status_failed_by(st, -1)) {
+    if (lane == 0) out[e] = x[e];
+    return;
+  }
+  const double s = row_dot<false>(Hinv + e * d, g + (int64_t)p * d, d, lane);
+  if (lane == 0) out[e] = x[e] + s;
+}
 __global__ __launch_bounds__(256) void k_form_c(const double* __restrict__ H, int64_t d,
                                                 const double* __restrict__ x,
                                                 const double* __restrict__ g, double* c) {
@@ -828,7 +846,10 @@ hipError_t launch_qp_constrained(const QpArgs& a, hipStream_t st) {
     const bool penalty = a.constraint == 3;
     hipLaunchKernelGGL(k_form_c, dim3((unsigned)((d + 3) / 4), B), dim3(256), 0, st, a.H, d,
                        a.x, a.g, cbuf);
-    if (!penalty) {  // the unconstrained minimiser, the answer when the ball is inactive
+    if (!penalty && a.hinv_pre) {  // the unconstrained minimiser from a given inverse
+      hipLaunchKernelGGL(k_apply_inverse, dim3((unsigned)((d + 3) / 4), B), dim3(256), 0, st,
+                         a.hinv_pre, d, a.g, a.x, xunc, a.status);
+    } else if (!penalty) {  // the unconstrained minimiser, the answer when the ball is inactive
       const double* rd = a.rdiag_pre;
       if (!rd) {
         if ((e = launch_cholesky(a.H, a.L, d, B, a.status, a.iter, 0.0, scratch, st)) !=

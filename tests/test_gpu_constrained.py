@@ -313,7 +313,8 @@ def test_ihs_l1_penalty_full_size_kkt(gpu_lib):
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("constraint,csr", [("l1", False), ("l1_penalty", False), ("l2", True)])
+@pytest.mark.parametrize("constraint,csr", [("l1", False), ("l1_penalty", False), ("l2", True),
+                                            ("l1", True)])
 def test_overlapped_constrained_matches_sequential(gpu_lib, constraint, csr):
     """The overlapped schedule (the next step's sort and Gram beside the
     current pass) forms the same sketches; the gradient is summed in another
