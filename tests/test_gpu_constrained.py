@@ -129,11 +129,12 @@ def test_qp_l2_matches_oracle(gpu_lib, d, batch, frac, cond):
         assert np.linalg.norm(out[p] - ref) <= 1e-9 * cond * np.linalg.norm(ref), p
 
 
-def test_qp_l2_mixed_batch_and_identity(gpu_lib):
+@pytest.mark.parametrize("d", [40, 100])
+def test_qp_l2_mixed_batch_and_identity(gpu_lib, d):
     """H = I gives x = c min(1, r/||c||) (closed form); a batch where one
-    problem's ball is inactive and the other's active."""
+    problem's ball is inactive and the other's active. d = 100 takes the cold
+    start through the explicit inverse, d = 40 through the triangular solves."""
     P = gpu_lib
-    d = 40
     g = np.random.default_rng(11)
     c = np.stack([0.1 * g.standard_normal(d), 10.0 * g.standard_normal(d)])
     H = np.stack([np.eye(d), np.eye(d)])
