@@ -205,9 +205,10 @@ __device__ __forceinline__ void rsqrt_sqrt(double x, double& r, double& s) {
 //  3. every thread applies the rank-4 update to its entries with the
 //     published panel entries of their columns.
 // The steps run as eight groups of two with the inner two unrolled, so every
-// register index is a constant. L_jj and 1/L_jj come from rsqrt_sqrt. Writes L_kk and 1/L_jj back. The block is
-// loaded before the status is read (one memory round trip), and two waves
-// per SIMD of at most 96 registers fit beside the bucket gather.
+// register index is a constant. L_jj and 1/L_jj come from rsqrt_sqrt. Writes
+// L_kk and 1/L_jj back. The block is loaded before the status is read (one
+// memory round trip), and two waves per SIMD of at most 96 registers fit
+// beside the bucket gather.
 constexpr int kDiagThreads = 512;
 
 __global__ __launch_bounds__(kDiagThreads) void k_chol_diag(double* L, int64_t d, int64_t kb,
@@ -456,8 +457,8 @@ hipError_t launch_cholesky(const double* H, double* L, int64_t d, int32_t batch,
 // pivots from the factorisation); the remaining rows are updated by all four
 // wavefronts, four rows at a time with one transposing butterfly. The loads
 // of several passes are issued together (kSolveGroups passes forward,
-// kSolveCols columns backward), since one workgroup is bound by the latency
-// of its reads of L, not by their bandwidth.
+// kSolveCols columns backward), so fewer of one workgroup's reads of L wait
+// one after the other.
 // Also records sqrt(dx^T v) for problem 0.
 // ---------------------------------------------------------------------------
 constexpr int kSolveGroups = 4, kSolveCols = 32;
