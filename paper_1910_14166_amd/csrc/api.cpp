@@ -683,7 +683,7 @@ ihs_status solve_overlap(const ihs_matrix* A, const Layout& L, const ihs_options
       a.status = B.status;
       a.iter = t;
       a.warm = t > 0 ? 1 : 0;
-      if (opt->constraint == IHS_L1_BALL) {  // H_t's factor comes from the side stream
+      if (opt->constraint == IHS_L1_BALL) {  // H_t's factor or inverse, from the side stream
         hipLaunchKernelGGL(k_adopt_status, dim3(1), dim3(64), 0, stream, S.side_status, t,
                            B.status);
         if (use_inv) {
