@@ -680,13 +680,13 @@ __global__ __launch_bounds__(256) void k_trs_symv(const double* __restrict__ M, 
                                                   const double* __restrict__ trs,
                                                   const DeviceStatus* st) {
   const int p = blockIdx.y;
-  if (trs[4 * p + 1] >= 2.0 || status_failed_by(st, -1)) return;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t i = (int64_t)blockIdx.x * 4 + wv;
   if (i >= d) return;
   const double* mr = M + ((int64_t)p * d + i) * d;
   const double* vp = v + (int64_t)p * d;
-  const double s = row_dot<false>(mr, vp, d, lane);
+  const double s = row_dot<false>(mr, vp, d, lane);  // issued before the state is read
+  if (trs[4 * p + 1] >= 2.0 || status_failed_by(st, -1)) return;
   if (lane == 0) out[(int64_t)p * d + i] = base ? base[(int64_t)p * d + i] + s : s;
 }
 
@@ -775,13 +775,13 @@ __global__ __launch_bounds__(256) void k_trs_resid(const double* __restrict__ H,
                                                    const double* __restrict__ trs,
                                                    const DeviceStatus* st) {
   const int p = blockIdx.y;
-  if (trs[4 * p + 1] >= 2.0 || status_failed_by(st, -1)) return;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t i = (int64_t)blockIdx.x * 4 + wv;
   if (i >= d) return;
   const double* hr = H + ((int64_t)p * d + i) * d;
   const double* wp = w + (int64_t)p * d;
-  const double s = row_dot<false>(hr, wp, d, lane);
+  const double s = row_dot<false>(hr, wp, d, lane);  // issued before the state is read
+  if (trs[4 * p + 1] >= 2.0 || status_failed_by(st, -1)) return;
   if (lane == 0) {
     const int64_t e = (int64_t)p * d + i;
     out[e] = v[e] - s - trs[4 * p] * w[e];
