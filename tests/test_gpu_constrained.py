@@ -345,19 +345,20 @@ def test_overlapped_constrained_matches_sequential(gpu_lib, constraint, csr):
 
 
 @pytest.mark.gpu
-def test_overlapped_l1_ball_reports_not_pd_step(gpu_lib):
-    """The overlapped l1-ball step takes H_t's factor from the side stream; a
-    Hessian sketch that is not positive definite (an empty column of A) is
-    reported at the step the sequential schedule reports it, and x stays at
-    x^0 = 0."""
+@pytest.mark.parametrize("d", [32, 128])
+def test_overlapped_l1_ball_reports_not_pd_step(gpu_lib, d):
+    """The overlapped l1-ball step takes H_t's factor (d = 32) or inverse
+    (d = 128) from the side stream; a Hessian sketch that is not positive
+    definite (an empty column of A) is reported at the step the sequential
+    schedule reports it, and x stays at x^0 = 0."""
     P = gpu_lib
     g = np.random.default_rng(23)
-    A = g.standard_normal((4000, 32))
+    A = g.standard_normal((4000, d))
     A[:, 7] = 0.0
     b = g.standard_normal(4000)
     reps = {}
     for sched in ("sequential", "overlap"):
-        o = P.options(320, seed=5, max_iter=4, constraint="l1", radius=1.0, schedule=sched)
+        o = P.options(10 * d, seed=5, max_iter=4, constraint="l1", radius=1.0, schedule=sched)
         res = P.solve(P.Matrix(dense=dev(A)), dev(b), o, raise_on_error=False, history=True)
         reps[sched] = (res.report.status, res.report.failed_iter)
         assert bool((res.x == 0).all()), sched
