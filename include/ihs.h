@@ -45,7 +45,8 @@ typedef enum {
   IHS_ERR_WORKSPACE = 3,     /* ws_bytes below the queried size                */
   IHS_ERR_HIP = 4,           /* a HIP runtime call or kernel launch failed     */
   IHS_ERR_NOT_PD = 5,        /* non-positive Cholesky pivot: H not definite    */
-  IHS_ERR_NOT_CONVERGED = 6, /* an inner QP iteration hit its cap              */
+  IHS_ERR_NOT_CONVERGED = 6, /* an inner QP iteration hit its cap, or a solve
+                                with tol > 0 ran max_iter steps unconverged   */
   IHS_ERR_NONFINITE = 7      /* NaN or Inf in the objective or the iterate     */
 } ihs_status;
 
@@ -127,8 +128,23 @@ typedef struct {
                                   polish usually ends the iteration first);
                                   l2 ball: | ||x|| - r | <= qp_tol r, then one
                                   more Newton step (1e-10)                     */
-  double tol;                  /* reserved, must be 0: a solve always runs
-                                  max_iter steps (stopping rules read x_hist) */
+  double tol;                  /* stopping tolerance on the length of a step
+                                  in the prediction norm (Def. A.1; Thm 2.2:
+                                  the error contracts geometrically, so the
+                                  step length tracks it): after step t the
+                                  solve stops when no failure is recorded and
+                                  every problem's sqrt(dx^T H_t dx),
+                                  dx = x^{t+1} - x^t, is at most tol. The test
+                                  runs on the device; the steps already queued
+                                  behind it return at once and keep x, so the
+                                  result is bitwise that of a solve with
+                                  max_iter = rep->iters. 0: run max_iter
+                                  steps. With tol > 0, reaching max_iter first
+                                  returns IHS_ERR_NOT_CONVERGED (x holds x^N,
+                                  failed_iter = -1). Rows of x_hist after
+                                  rep->iters repeat the final iterate. Must be
+                                  finite and >= 0; not with
+                                  IHS_METHOD_FIXED_SKETCH_CG                  */
   int32_t schedule;            /* 0: overlap the next step's sort, Gram and
                                   (unconstrained and l1 ball) factorisation
                                   with the current pass over A on other
@@ -159,13 +175,20 @@ typedef struct {
 
 /* Filled by ihs_solve (host memory). */
 typedef struct {
-  int32_t iters;               /* steps actually taken                        */
+  int32_t iters;               /* steps actually taken (the tolerance stop's
+                                  step count, or the step of a failure)        */
   int32_t status;              /* ihs_status of the device work               */
   int32_t failed_iter;         /* step at which a device error occurred, or -1 */
   int32_t failed_problem;      /* problem index of that error, or -1          */
   double objective;            /* 1/2 ||A x^{N-1} - b||^2 (problem 0), from the last
                                   pass (IHS_METHOD_FIXED_SKETCH_CG: at x^0)     */
   double last_step;            /* sqrt(dx^T H dx) of the last step (problem 0) */
+  int32_t qp_unpolished;       /* l1-ball and l1-penalty QPs (over steps and
+                                  problems) that ended on a converged
+                                  first-order iterate the KKT polish did not
+                                  certify; 0 when every QP solution is an
+                                  exact KKT point                              */
+  int32_t reserved;
 } ihs_report;
 
 const char* ihs_status_string(int32_t status);
@@ -250,11 +273,13 @@ size_t ihs_qp_workspace_size(int64_t d, int32_t batch, const ihs_options* opt);
  * and qp_tol are read.
  * x_out may alias x. Synchronises; returns IHS_ERR_NOT_PD when a
  * factorisation meets a non-positive pivot and IHS_ERR_NOT_CONVERGED when a
- * ball QP ends its iteration budget unsolved (x_out then holds x^t). */
+ * ball QP ends its iteration budget unsolved (x_out then holds x^t).
+ * rep (host, nullable) receives status, failed_problem and qp_unpolished
+ * (iters = 1; the other fields are 0). */
 ihs_status ihs_qp_step(int64_t d, int32_t batch, const double* H,
                        const double* g, const double* x, double* x_out,
                        const ihs_options* opt, void* ws, size_t ws_bytes,
-                       hipStream_t stream);
+                       hipStream_t stream, ihs_report* rep);
 
 /* The IHS loop (Eq.(2), Thm 2.2): from x^0 = x (device, batch x d; zeros for
  * the usual start) run opt->max_iter steps, writing x^N back to x.

@@ -70,7 +70,8 @@ class Options_t(ctypes.Structure):
 class Report_t(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("status", ctypes.c_int32),
                 ("failed_iter", ctypes.c_int32), ("failed_problem", ctypes.c_int32),
-                ("objective", ctypes.c_double), ("last_step", ctypes.c_double)]
+                ("objective", ctypes.c_double), ("last_step", ctypes.c_double),
+                ("qp_unpolished", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 _lib = None
@@ -105,7 +106,7 @@ def load(path: Optional[str] = None):
         "ihs_gram": (i32, [vp, i32, i64, i64, i64, i32, i32, vp, vp, sz, vp]),
         "ihs_gradient": (i32, [M, vp, vp, vp, vp, vp, vp, sz, vp]),
         "ihs_qp_workspace_size": (sz, [i64, i32, O]),
-        "ihs_qp_step": (i32, [i64, i32, vp, vp, vp, vp, O, vp, sz, vp]),
+        "ihs_qp_step": (i32, [i64, i32, vp, vp, vp, vp, O, vp, sz, vp, R]),
         "ihs_solve": (i32, [M, vp, O, vp, vp, vp, R, vp, sz, vp]),
         "ihs_adjoint_solve": (i32, [M, vp, vp, i32, vp, vp, sz, vp]),
         "ihs_solution_grads": (i32, [M, vp, vp, vp, vp, vp, i64, vp]),
@@ -325,7 +326,9 @@ def gradient(A: Matrix, b, x, want_r=False):
     return g, r, f
 
 
-def qp_step(H, g, x, constraint="none", radius=0.0, qp_max_inner=0, qp_tol=0.0, out=None):
+def qp_step(H, g, x, constraint="none", radius=0.0, qp_max_inner=0, qp_tol=0.0, out=None,
+            want_report=False):
+    """x^{t+1} of Eq.(2) for each problem; with want_report, (x^{t+1}, report)."""
     torch = _torch()
     L = load()
     batch, d = g.shape
@@ -335,9 +338,10 @@ def qp_step(H, g, x, constraint="none", radius=0.0, qp_max_inner=0, qp_tol=0.0, 
                 qp_tol=qp_tol)
     need = L.ihs_qp_workspace_size(d, batch, ctypes.byref(o))
     ws = _workspace(need, g.device)
+    rep = Report_t()
     _check(L.ihs_qp_step(d, batch, _ptr(H), _ptr(g), _ptr(x), _ptr(out), ctypes.byref(o),
-                         _ptr(ws), ws.numel(), _stream()), "ihs_qp_step")
-    return out
+                         _ptr(ws), ws.numel(), _stream(), ctypes.byref(rep)), "ihs_qp_step")
+    return (out, rep) if want_report else out
 
 
 @dataclass

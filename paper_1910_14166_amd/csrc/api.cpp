@@ -159,6 +159,7 @@ struct PassBuffers {
   double* bzero = nullptr;
   double* red = nullptr;   // two-level reduction scratch
   double* rdiag = nullptr; // batch x d reciprocal pivots (adjoint path)
+  const int32_t* halt = nullptr;  // &status->done while a solve may stop early
 };
 
 void carve_pass(Carver& c, const Layout& L, const ihs_sketch* sk, PassBuffers& B) {
@@ -220,7 +221,8 @@ SketchPlan make_plan(const Layout& L, const ihs_sketch* sk, const PassBuffers& B
 // Carries a failure that another stream recorded at or before step `iter`
 // into `to`, so that the kernels reading `to` in that step see it.
 __global__ void k_adopt_status(const DeviceStatus* from, int32_t iter, DeviceStatus* to) {
-  if (threadIdx.x == 0 && status_failed_by(from, iter))
+  // after the tolerance stop the other stream works on sketches no step uses
+  if (threadIdx.x == 0 && !to->done && status_failed_by(from, iter))
     status_fail(to, from->code, from->failed_iter, from->failed_problem);
 }
 
@@ -232,6 +234,7 @@ __global__ void k_zero_status(DeviceStatus* st) {
     st->done = 0;
     st->iters = 0;
     st->claim = 0;
+    st->unpolished = 0;
     st->objective = 0.0;
     st->last_step = 0.0;
   }
@@ -323,6 +326,7 @@ ihs_status run_gather(const ihs_matrix* A, const ihs_sketch* sk, const PassBuffe
     G.gpart = B.gpart;
     G.fpart = B.fpart;
     G.r_out = r_out;
+    G.halt = B.halt;
     err = launch_sketch_gather(P, G, st);
   } else {
     CsrGatherArgs G{};
@@ -339,6 +343,7 @@ ihs_status run_gather(const ihs_matrix* A, const ihs_sketch* sk, const PassBuffe
     G.gpart = B.gpart;
     G.fpart = B.fpart;
     G.r_out = r_out;
+    G.halt = B.halt;
     err = launch_sketch_gather_csr(P, G, st);
   }
   prof_end(st, e0);
@@ -401,6 +406,9 @@ struct SolveBuffers {
   double* cg_pm = nullptr;
   double* cg_rho = nullptr;
   double* cg_zero = nullptr;
+  // the tolerance stop: x^t before each update, and per-row products
+  double* xprev = nullptr;
+  double* stepq = nullptr;
 };
 
 // Above this width the overlapped schedule forms H^{-1} on the second stream
@@ -450,6 +458,10 @@ size_t carve_solve(Carver& c, const Layout& L, const ihs_options* o, SolveBuffer
     S.cg_pm = c.take<double>(bd);
     S.cg_rho = c.take<double>((size_t)L.batch);
     S.cg_zero = c.take<double>(bd);
+  }
+  if (o->tol > 0.0) {
+    S.xprev = c.take<double>((size_t)(L.batch * L.d));
+    S.stepq = c.take<double>((size_t)(L.batch * L.d));
   }
   return c.used;
 }
@@ -510,11 +522,13 @@ ihs_status check_options(const ihs_options* o, bool need_loop) {
   if (!valid_constraint(o->constraint, o->radius)) return IHS_ERR_INVALID_ARG;
   if (need_loop && o->max_iter < 1) return IHS_ERR_INVALID_ARG;
   if (!valid_gram_types(o->gram_in, o->gram_acc)) return IHS_ERR_INVALID_ARG;
-  if (o->tol != 0.0 || o->qp_tol < 0.0 || o->qp_max_inner < 0) return IHS_ERR_INVALID_ARG;
+  if (!(o->tol >= 0.0) || !std::isfinite(o->tol) || o->qp_tol < 0.0 || o->qp_max_inner < 0)
+    return IHS_ERR_INVALID_ARG;
   if (o->schedule < 0 || o->schedule > 2) return IHS_ERR_INVALID_ARG;
   if (o->method != IHS_METHOD_IHS && o->method != IHS_METHOD_FIXED_SKETCH_CG)
     return IHS_ERR_INVALID_ARG;
-  if (o->method == IHS_METHOD_FIXED_SKETCH_CG && o->constraint != IHS_UNCONSTRAINED)
+  if (o->method == IHS_METHOD_FIXED_SKETCH_CG &&
+      (o->constraint != IHS_UNCONSTRAINED || o->tol > 0.0))
     return IHS_ERR_UNSUPPORTED;
   return IHS_OK;
 }
@@ -524,6 +538,27 @@ ihs_status read_status(DeviceStatus* dev, DeviceStatus* host, hipStream_t st) {
     return IHS_ERR_HIP;
   if (hip_failed(hipStreamSynchronize(st))) return IHS_ERR_HIP;
   return IHS_OK;
+}
+
+// The outcome of a solve from its failure record f and the main stream's
+// record m: a failure names its step and keeps the last good iterate; with
+// tol > 0 the solve either stopped at m.iters steps or ran all max_iter steps
+// without meeting tol (IHS_ERR_NOT_CONVERGED, x holds x^N).
+ihs_status finish_report(const DeviceStatus& f, const DeviceStatus& m, const ihs_options* opt,
+                         ihs_report* rep) {
+  int32_t code = f.code;
+  if (code == IHS_OK && opt->tol > 0.0 && !m.done) code = IHS_ERR_NOT_CONVERGED;
+  if (rep) {
+    *rep = ihs_report{};
+    rep->status = code;
+    rep->failed_iter = f.code ? f.failed_iter : -1;
+    rep->failed_problem = f.code ? f.failed_problem : -1;
+    rep->iters = f.code ? std::max(0, f.failed_iter) : (m.done ? m.iters : opt->max_iter);
+    rep->objective = m.objective;
+    rep->last_step = m.last_step;
+    rep->qp_unpolished = m.unpolished;
+  }
+  return (ihs_status)code;
 }
 
 // The overlapped schedule of the IHS loop (unconstrained problems). Step t
@@ -666,6 +701,9 @@ ihs_status solve_overlap(const ihs_matrix* A, const Layout& L, const ihs_options
     // main: x^{t+1} = x^t + H_t^{-1} g(x^t), or the constrained QP of Eq.(2)
     // with H_t (its l2 shift state carries over in S.work from step to step)
     if (!ck(hipStreamWaitEvent(stream, evChol.at(t), 0))) return IHS_ERR_HIP;
+    if (S.xprev && !ck(hipMemcpyAsync(S.xprev, x, bd * sizeof(double), hipMemcpyDeviceToDevice,
+                                      stream)))
+      return IHS_ERR_HIP;
     if (constrained) {
       QpArgs a{};
       a.d = d;
@@ -704,6 +742,9 @@ ihs_status solve_overlap(const ihs_matrix* A, const Layout& L, const ihs_options
                                             B.g, x, x, B.status, stream, S.side_status, t))) {
       return IHS_ERR_HIP;
     }
+    if (S.xprev && !ck(launch_step_test(constrained ? h_buf(t) : nullptr, B.g, S.xprev, x, d,
+                                        L.batch, opt->tol, S.stepq, B.status, t, stream)))
+      return IHS_ERR_HIP;
     if (x_hist && !ck(hipMemcpyAsync(x_hist + (int64_t)t * bd, x, bd * sizeof(double),
                                      hipMemcpyDeviceToDevice, stream)))
       return IHS_ERR_HIP;
@@ -714,22 +755,17 @@ ihs_status solve_overlap(const ihs_matrix* A, const Layout& L, const ihs_options
   DeviceStatus hm, hs;
   if (read_status(B.status, &hm, stream) != IHS_OK) return IHS_ERR_HIP;
   if (read_status(S.side_status, &hs, stream) != IHS_OK) return IHS_ERR_HIP;
-  // the earlier of the two failures (the side stream only fails with NOT_PD)
+  // the earlier of the two failures (the side stream only fails with NOT_PD);
+  // after a tolerance stop the side stream's later factorisations belong to
+  // sketches no step used
   DeviceStatus f = hm;
-  if (hs.code && (!hm.code || hs.failed_iter < hm.failed_iter || hm.failed_iter < 0)) {
+  const bool side_counts = hs.code && (!hm.done || hs.failed_iter < hm.iters);
+  if (side_counts && (!hm.code || hs.failed_iter < hm.failed_iter || hm.failed_iter < 0)) {
     f.code = hs.code;
     f.failed_iter = hs.failed_iter;
     f.failed_problem = hs.failed_problem;
   }
-  if (rep) {
-    rep->status = f.code;
-    rep->failed_iter = f.code ? f.failed_iter : -1;
-    rep->failed_problem = f.code ? f.failed_problem : -1;
-    rep->iters = f.code ? std::max(0, f.failed_iter) : N;
-    rep->objective = hm.objective;
-    rep->last_step = hm.last_step;
-  }
-  return (ihs_status)f.code;
+  return finish_report(f, hm, opt, rep);
 }
 
 // The reduced-access variant: one sketch S_0 (key (seed, iter)) held fixed,
@@ -794,6 +830,7 @@ ihs_status solve_fixed_sketch_cg(const ihs_matrix* A, const Layout& L, const ihs
     rep->iters = host.code ? std::max(0, host.failed_iter) : opt->max_iter;
     rep->objective = host.objective;
     rep->last_step = host.last_step;
+    rep->qp_unpolished = host.unpolished;
   }
   return (ihs_status)host.code;
 }
@@ -944,7 +981,7 @@ size_t ihs_qp_workspace_size(int64_t d, int32_t batch, const ihs_options* opt) {
 
 ihs_status ihs_qp_step(int64_t d, int32_t batch, const double* H, const double* g,
                        const double* x, double* x_out, const ihs_options* opt, void* ws,
-                       size_t ws_bytes, hipStream_t stream) {
+                       size_t ws_bytes, hipStream_t stream, ihs_report* rep) {
   if (d < 1 || batch < 1 || !H || !g || !x || !x_out || !opt || !ws) return IHS_ERR_INVALID_ARG;
   if (!valid_constraint(opt->constraint, opt->radius)) return IHS_ERR_INVALID_ARG;
   if (ws_bytes < ihs_qp_workspace_size(d, batch, opt) - 256) return IHS_ERR_WORKSPACE;
@@ -974,6 +1011,14 @@ ihs_status ihs_qp_step(int64_t d, int32_t batch, const double* H, const double* 
   if (hip_failed(e)) return IHS_ERR_HIP;
   DeviceStatus host;
   if (read_status(st, &host, stream) != IHS_OK) return IHS_ERR_HIP;
+  if (rep) {
+    *rep = ihs_report{};
+    rep->iters = 1;
+    rep->status = host.code;
+    rep->failed_iter = host.code ? 0 : -1;
+    rep->failed_problem = host.code ? host.failed_problem : -1;
+    rep->qp_unpolished = host.unpolished;
+  }
   return (ihs_status)host.code;
 }
 
@@ -1001,6 +1046,7 @@ ihs_status ihs_solve(const ihs_matrix* A, const double* b, const ihs_options* op
   SolveBuffers S;
   carve_solve(c, L, opt, S);
   PassBuffers& B = S.pass;
+  if (opt->tol > 0.0) B.halt = &B.status->done;  // a device address; read by the passes
   if ((s = upload_probs(L, B, stream)) != IHS_OK) return s;
   if (opt->method == IHS_METHOD_FIXED_SKETCH_CG)
     return solve_fixed_sketch_cg(A, L, opt, S, b, x, x_hist, rep, stream);
@@ -1034,24 +1080,24 @@ ihs_status ihs_solve(const ihs_matrix* A, const double* b, const ihs_options* op
     a.status = B.status;
     a.iter = t;
     a.warm = t > 0 ? 1 : 0;
+    if (S.xprev && hip_failed(hipMemcpyAsync(S.xprev, x, bd * sizeof(double),
+                                             hipMemcpyDeviceToDevice, stream)))
+      return IHS_ERR_HIP;
     const hipError_t e = launch_qp_step(a, stream);
     if (e == hipErrorNotSupported) return IHS_ERR_UNSUPPORTED;
     if (hip_failed(e)) return IHS_ERR_HIP;
+    if (S.xprev &&
+        hip_failed(launch_step_test(opt->constraint != IHS_UNCONSTRAINED ? S.H : nullptr, B.g,
+                                    S.xprev, x, d, L.batch, opt->tol, S.stepq, B.status, t,
+                                    stream)))
+      return IHS_ERR_HIP;
     if (x_hist && hip_failed(hipMemcpyAsync(x_hist + (int64_t)t * bd, x, bd * sizeof(double),
                                  hipMemcpyDeviceToDevice, stream)))
       return IHS_ERR_HIP;
   }
   DeviceStatus host;
   if (read_status(B.status, &host, stream) != IHS_OK) return IHS_ERR_HIP;
-  if (rep) {
-    rep->status = host.code;
-    rep->failed_iter = host.code ? host.failed_iter : -1;
-    rep->failed_problem = host.code ? host.failed_problem : -1;
-    rep->iters = host.code ? std::max(0, host.failed_iter) : opt->max_iter;
-    rep->objective = host.objective;
-    rep->last_step = host.last_step;
-  }
-  return (ihs_status)host.code;
+  return finish_report(host, host, opt, rep);
 }
 
 ihs_status ihs_adjoint_solve(const ihs_matrix* A, const double* xbar, const double* factors,

@@ -1,6 +1,8 @@
 // Device helpers shared by the libihs kernels (gfx950, wave64).
 #pragma once
 
+#include <cstddef>
+
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -103,10 +105,15 @@ struct DeviceStatus {
   int32_t done;          // early-stop flag of the outer loop
   int32_t iters;         // steps whose update was applied
   int32_t claim;         // first failure wins the claim, then publishes
-  int32_t pad[2];
+  int32_t unpolished;    // l1 QPs that ended on a converged first-order iterate
+                         // which the KKT polish did not certify
+  int32_t pad;
   double objective;      // 1/2 ||A x - b||^2 of problem 0 at the last pass
   double last_step;      // sqrt(dx^T H dx) of problem 0 at the last step
 };
+
+static_assert(sizeof(DeviceStatus) == 48 && offsetof(DeviceStatus, done) == 12,
+              "the host reads code .. done as four leading words");
 
 // The first failing thread claims the record, writes where it failed, and
 // only then publishes the code, so a reader that sees a non-zero code (from
@@ -119,6 +126,13 @@ __device__ __forceinline__ void status_fail(DeviceStatus* st, int code, int iter
     __threadfence();
     atomicExch(&st->code, code);
   }
+}
+
+// True when `st` records any failure or the tolerance stop of the outer loop
+// (`done`): the update kernels then leave x as it is.
+__device__ __forceinline__ bool status_halted(const DeviceStatus* st) {
+  return __atomic_load_n(&st->code, __ATOMIC_ACQUIRE) != 0 ||
+         __atomic_load_n(&st->done, __ATOMIC_ACQUIRE) != 0;
 }
 
 // True when `st` records a failure at or before step `iter` (iter < 0: any).

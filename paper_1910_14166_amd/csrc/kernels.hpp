@@ -73,6 +73,8 @@ struct GatherArgs {
   double* gpart;           // batch * m_blk * d
   double* fpart;           // batch * m_blk
   double* r_out;           // n, nullable
+  const int32_t* halt;     // nullable: when it reads non-zero the pass is skipped
+                           // (the outer loop's tolerance stop)
 };
 hipError_t launch_sketch_gather(const SketchPlan& p, const GatherArgs& g, hipStream_t st);
 // Sketch rows owned by one wavefront of the dense gather (1 or 2).
@@ -93,6 +95,7 @@ struct CsrGatherArgs {
   double* gpart;           // batch * m_blk * d
   double* fpart;
   double* r_out;
+  const int32_t* halt;     // as in GatherArgs
 };
 hipError_t launch_sketch_gather_csr(const SketchPlan& p, const CsrGatherArgs& g,
                                     hipStream_t st);
@@ -183,6 +186,15 @@ hipError_t launch_chol_solve_update(const double* L, const double* rdiag, int64_
                                     double* out, DeviceStatus* status, hipStream_t st,
                                     const DeviceStatus* gate = nullptr,
                                     int32_t gate_iter = -1);
+
+// The outer loop's tolerance stop after step `iter`: q_p = dx^T H dx per
+// problem (H: batch x d x d, or nullptr to use dx^T g), dx = x - xprev; sets
+// status->done and status->iters = iter + 1 when no failure is recorded and
+// every sqrt(q_p) <= tol. q: batch x d scratch. Records sqrt(q_0) as
+// status->last_step.
+hipError_t launch_step_test(const double* H, const double* g, const double* xprev,
+                            const double* x, int64_t d, int32_t batch, double tol, double* q,
+                            DeviceStatus* status, int32_t iter, hipStream_t st);
 
 // Conjugate gradients preconditioned by a fixed Hessian sketch (pm = -p):
 // begin: rho = r^T z, pm = -z; x: alpha = rho / p^T q, x += alpha p,

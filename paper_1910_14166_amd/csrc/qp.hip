@@ -117,6 +117,8 @@ __global__ __launch_bounds__(64) void k_reduce_b(const double* __restrict__ red,
                                                  int32_t iter) {
   const int p = blockIdx.y;
   const int64_t col = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  // after the tolerance stop the pass did not run: keep g, f and the objective
+  if (st != nullptr && __atomic_load_n(&st->done, __ATOMIC_ACQUIRE) != 0) return;
   if (col < d) {
     double s = 0.0;
     for (int q = 0; q < 4 * kRedSplit; ++q) s += red[((int64_t)p * 4 * kRedSplit + q) * d + col];
@@ -481,7 +483,7 @@ __global__ __launch_bounds__(256) void k_chol_solve(const double* __restrict__ L
   const double* bp = base + (int64_t)p * d;
   double* op = out + (int64_t)p * d;
   if (tid == 0) {
-    code = status_failed_by(st, -1) ? 1 : 0;
+    code = status_halted(st) ? 1 : 0;
     if (gate != nullptr && status_failed_by(gate, gate_iter)) code = 1;
   }
   __syncthreads();
@@ -611,7 +613,7 @@ hipError_t launch_chol_solve_update(const double* L, const double* rdiag, int64_
 // block needs no padding. Problems with trs[4p+1] >= 2 (nullable) are skipped.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ bool inv_skip(const DeviceStatus* st, const double* trs, int p) {
-  return status_failed_by(st, -1) || trs_skip(trs, p);
+  return status_halted(st) || trs_skip(trs, p);
 }
 
 // L_ii^{-1} by rows, right-looking: thread t keeps row t/4, columns
@@ -854,7 +856,7 @@ __global__ __launch_bounds__(256) void k_inv_apply(const double* __restrict__ Hi
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t i = (int64_t)blockIdx.x * 4 + wv;
   if (i >= d) return;
-  const bool skip = status_failed_by(st, -1) || (gate && status_failed_by(gate, gate_iter));
+  const bool skip = status_halted(st) || (gate && status_failed_by(gate, gate_iter));
   const double* hr = Hinv + ((int64_t)p * d + i) * d;
   const double* gp = g + (int64_t)p * d;
   const double s = row_dot<false>(hr, gp, d, lane);
@@ -871,6 +873,7 @@ __global__ __launch_bounds__(256) void k_inv_finish(int64_t d, int32_t batch, co
   __shared__ double red[256];
   __shared__ int bad;
   const int tid = threadIdx.x;
+  if (status_halted(st)) return;  // uniform: no update was applied
   if (tid == 0) bad = 0;
   __syncthreads();
   double part = 0.0;
@@ -945,7 +948,7 @@ __global__ __launch_bounds__(256) void k_pcg_begin(const double* __restrict__ r,
   __shared__ double red[256];
   __shared__ int skip;
   const int p = blockIdx.x, tid = threadIdx.x;
-  if (tid == 0) skip = status_failed_by(st, -1) ? 1 : 0;
+  if (tid == 0) skip = status_halted(st) ? 1 : 0;
   __syncthreads();
   if (skip) return;
   const double* rp = r + (int64_t)p * d;
@@ -971,7 +974,7 @@ __global__ __launch_bounds__(256) void k_pcg_x(const double* __restrict__ pm,
   __shared__ double red[256];
   __shared__ int skip;
   const int p = blockIdx.x, tid = threadIdx.x;
-  if (tid == 0) skip = status_failed_by(st, -1) ? 1 : 0;
+  if (tid == 0) skip = status_halted(st) ? 1 : 0;
   __syncthreads();
   if (skip) return;
   const double* pp = pm + (int64_t)p * d;
@@ -1001,7 +1004,7 @@ __global__ __launch_bounds__(256) void k_pcg_p(const double* __restrict__ r,
   __shared__ double red[256];
   __shared__ int skip;
   const int p = blockIdx.x, tid = threadIdx.x;
-  if (tid == 0) skip = status_failed_by(st, -1) ? 1 : 0;
+  if (tid == 0) skip = status_halted(st) ? 1 : 0;
   __syncthreads();
   if (skip) return;
   const double* rp = r + (int64_t)p * d;
@@ -1064,6 +1067,90 @@ hipError_t launch_qp_step(const QpArgs& a, hipStream_t st) {
   if ((e = launch_chol_inverse(a.L, rdiag, a.d, a.batch, hinv, linv, a.status, st)) != hipSuccess)
     return e;
   return launch_inv_apply(hinv, a.d, a.batch, a.g, a.x, a.x_out, dx, a.status, st, nullptr, 0);
+}
+
+
+// ---------------------------------------------------------------------------
+// The outer loop's tolerance stop (Thm 2.2: the error contracts by a constant
+// factor per step, so the prediction-norm length of a step bounds the error
+// within a constant factor). After step t, with dx = x^{t+1} - x^t per
+// problem, q_p = dx^T H_t dx, or dx^T g when the step solved H_t dx = g
+// (H == nullptr; equal to it up to rounding). When no failure is recorded and
+// every sqrt(q_p) <= tol, the step test sets `done` and `iters` = t + 1; the
+// update kernels of later steps then keep x, and the passes return at once.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_step_rows(const double* __restrict__ H, int64_t d,
+                                                   const double* __restrict__ xprev,
+                                                   const double* __restrict__ x, double* q) {
+  const int p = blockIdx.y;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * 4 + wv;
+  if (i >= d) return;
+  const double* xp = x + (int64_t)p * d;
+  const double* xo = xprev + (int64_t)p * d;
+  // (H dx)_i from the row of H and dx formed lane by lane, columns in order
+  const double* hr = H + ((int64_t)p * d + i) * d;
+  double s = 0.0;
+  for (int64_t k0 = 0; k0 < d; k0 += 64) {
+    const int64_t k = k0 + lane;
+    const double dk = k < d ? xp[k] - xo[k] : 0.0;
+    const double h = k < d ? hr[k] : 0.0;
+    s = fma(h, dk, s);
+  }
+  s = wave_sum(s);
+  if (lane == 0) q[(int64_t)p * d + i] = s * (xp[i] - xo[i]);
+}
+
+__global__ __launch_bounds__(256) void k_step_test(const double* __restrict__ q,
+                                                   const double* __restrict__ g,
+                                                   const double* __restrict__ xprev,
+                                                   const double* __restrict__ x, int64_t d,
+                                                   int32_t batch, double tol, DeviceStatus* st,
+                                                   int32_t iter) {
+  __shared__ double red[256];
+  __shared__ int over;
+  const int tid = threadIdx.x;
+  if (status_halted(st)) return;  // uniform: failures and an earlier stop keep their record
+  if (tid == 0) over = 0;
+  __syncthreads();
+  double q0 = 0.0;
+  for (int32_t p = 0; p < batch; ++p) {
+    double part = 0.0;
+    for (int64_t i = tid; i < d; i += 256) {
+      const int64_t k = (int64_t)p * d + i;
+      part += g != nullptr ? (x[k] - xprev[k]) * g[k] : q[k];
+    }
+    red[tid] = part;
+    __syncthreads();
+    for (int stride = 128; stride > 0; stride >>= 1) {
+      if (tid < stride) red[tid] += red[tid + stride];
+      __syncthreads();
+    }
+    const double qp = red[0];
+    if (tid == 0) {
+      if (p == 0) q0 = qp;
+      if (!(sqrt(fmax(qp, 0.0)) <= tol)) over = 1;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    st->last_step = sqrt(fmax(q0, 0.0));
+    if (!over) {
+      st->iters = iter + 1;
+      __atomic_store_n(&st->done, 1, __ATOMIC_RELEASE);
+    }
+  }
+}
+
+hipError_t launch_step_test(const double* H, const double* g, const double* xprev,
+                            const double* x, int64_t d, int32_t batch, double tol, double* q,
+                            DeviceStatus* status, int32_t iter, hipStream_t st) {
+  if (H != nullptr)
+    hipLaunchKernelGGL(k_step_rows, dim3((unsigned)((d + 3) / 4), batch), dim3(256), 0, st, H, d,
+                       xprev, x, q);
+  hipLaunchKernelGGL(k_step_test, dim3(1), dim3(256), 0, st, q, H != nullptr ? nullptr : g,
+                     xprev, x, d, batch, tol, status, iter);
+  return hipGetLastError();
 }
 
 }  // namespace ihs

@@ -454,12 +454,12 @@ __global__ __launch_bounds__(kQpThreads) void k_qp_l1(
   __shared__ BlockShared sh;
   const int p = blockIdx.x;
   const int tid = threadIdx.x;
-  if (tid == 0) sh.flag[0] = st->code;
+  if (tid == 0) sh.flag[0] = status_halted(st) ? 1 : 0;
   __syncthreads();
   const double* H = Hall + (int64_t)p * d * d;
   double* xout = xout_all + (int64_t)p * d;
   const double x0 = tid < d ? x0_all[(int64_t)p * d + tid] : 0.0;
-  if (sh.flag[0] != 0) {  // an earlier failure: keep x^t
+  if (sh.flag[0] != 0) {  // an earlier failure or the tolerance stop: keep x^t
     if (tid < d) xout[tid] = x0;
     return;
   }
@@ -519,6 +519,7 @@ __global__ __launch_bounds__(kQpThreads) void k_qp_l1(
   double sig_prev = -1.0;
   int stable = 0;
   bool done = false;
+  bool polished = false;
   for (int it = 0; it < max_iter && !done; ++it) {
     const double vi = tid < d ? yi - (hyi - ci) / Lip : 0.0;
     const double xn = penalty ? copysign(fmax(fabs(vi) - tau / Lip, 0.0), vi)
@@ -561,6 +562,7 @@ __global__ __launch_bounds__(kQpThreads) void k_qp_l1(
           kPolishAccepted) {
         xi = xp;
         done = true;
+        polished = true;
       } else if (conv) {
         done = true;  // converged iterate; the polish did not apply
       }
@@ -571,6 +573,9 @@ __global__ __launch_bounds__(kQpThreads) void k_qp_l1(
     if (tid == 0) status_fail(st, 6 /* IHS_ERR_NOT_CONVERGED */, iter, p);
     return;
   }
+  // counted, so that callers can tell a certified minimiser from an iterate
+  // that is only as accurate as the first-order method's stopping test
+  if (tid == 0 && !polished) atomicAdd(&st->unpolished, 1);
   if (tid < d) xout[tid] = xi;
 }
 
@@ -586,7 +591,7 @@ __global__ __launch_bounds__(256) void k_apply_inverse(const double* __restrict_
   const int64_t i = (int64_t)blockIdx.x * 4 + wv;
   if (i >= d) return;
   const int64_t e = (int64_t)p * d + i;
-  if (status_failed_by(st, -1)) {
+  if (status_halted(st)) {
     if (lane == 0) out[e] = x[e];
     return;
   }
@@ -651,7 +656,7 @@ __global__ __launch_bounds__(256) void k_trs_inside(const double* __restrict__ x
   __shared__ double red[4];
   __shared__ int skip;
   const int p = blockIdx.x, tid = threadIdx.x;
-  if (tid == 0) skip = status_failed_by(st, -1) ? 1 : 0;
+  if (tid == 0) skip = status_halted(st) ? 1 : 0;
   __syncthreads();
   if (skip) return;
   const double* xp = xunc + (int64_t)p * d;
@@ -686,7 +691,7 @@ __global__ __launch_bounds__(256) void k_trs_symv(const double* __restrict__ M, 
   const double* mr = M + ((int64_t)p * d + i) * d;
   const double* vp = v + (int64_t)p * d;
   const double s = row_dot<false>(mr, vp, d, lane);  // issued before the state is read
-  if (trs[4 * p + 1] >= 2.0 || status_failed_by(st, -1)) return;
+  if (trs[4 * p + 1] >= 2.0 || status_halted(st)) return;
   if (lane == 0) out[(int64_t)p * d + i] = base ? base[(int64_t)p * d + i] + s : s;
 }
 
@@ -705,7 +710,7 @@ __global__ __launch_bounds__(256) void k_trs_update(const double* __restrict__ x
   __shared__ double red[4];
   __shared__ int skip;
   const int p = blockIdx.x, tid = threadIdx.x;
-  if (tid == 0) skip = (status_failed_by(st, -1) || trs[4 * p + 1] >= 2.0) ? 1 : 0;
+  if (tid == 0) skip = (status_halted(st) || trs[4 * p + 1] >= 2.0) ? 1 : 0;
   __syncthreads();
   if (skip) return;
   const double* xp = xk + (int64_t)p * d;
@@ -735,7 +740,7 @@ __global__ __launch_bounds__(256) void k_trs_abs_rows(const double* __restrict__
                                                       const double* __restrict__ trs,
                                                       double* rows, const DeviceStatus* st) {
   const int p = blockIdx.y;
-  if (trs[4 * p + 1] >= 2.0 || status_failed_by(st, -1)) return;
+  if (trs[4 * p + 1] >= 2.0 || status_halted(st)) return;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t i = (int64_t)blockIdx.x * 4 + wv;
   if (i >= d) return;
@@ -751,7 +756,7 @@ __global__ __launch_bounds__(256) void k_trs_inv_norm(const double* __restrict__
                                                       double* trs, const DeviceStatus* st) {
   __shared__ double red[4];
   const int p = blockIdx.x, tid = threadIdx.x;
-  if (trs[4 * p + 1] >= 2.0 || status_failed_by(st, -1)) return;
+  if (trs[4 * p + 1] >= 2.0 || status_halted(st)) return;
   double mx = 0.0;
   for (int64_t i = tid; i < d; i += 256) mx = fmax(mx, rows[(int64_t)p * d + i]);
 #pragma unroll
@@ -781,7 +786,7 @@ __global__ __launch_bounds__(256) void k_trs_resid(const double* __restrict__ H,
   const double* hr = H + ((int64_t)p * d + i) * d;
   const double* wp = w + (int64_t)p * d;
   const double s = row_dot<false>(hr, wp, d, lane);  // issued before the state is read
-  if (trs[4 * p + 1] >= 2.0 || status_failed_by(st, -1)) return;
+  if (trs[4 * p + 1] >= 2.0 || status_halted(st)) return;
   if (lane == 0) {
     const int64_t e = (int64_t)p * d + i;
     out[e] = v[e] - s - trs[4 * p] * w[e];
@@ -802,24 +807,24 @@ __global__ void k_trs_axpy(const double* __restrict__ base, const double* __rest
 __global__ void k_trs_finish(const double* trs, int64_t d, const double* x, double* xout,
                              DeviceStatus* st, int32_t iter) {
   const int p = blockIdx.x;
-  if (status_failed_by(st, -1) || trs[4 * p + 1] >= 2.0) return;
+  if (status_halted(st) || trs[4 * p + 1] >= 2.0) return;
   for (int64_t i = threadIdx.x; i < d; i += 256) xout[(int64_t)p * d + i] = x[(int64_t)p * d + i];
   if (threadIdx.x == 0) status_fail(st, 6 /* IHS_ERR_NOT_CONVERGED */, iter, p);
 }
 
-// True when every problem has finished its Newton iteration or a failure is
-// recorded; leaves the shift state in h. Synchronises the stream.
+// True when every problem has finished its Newton iteration, a failure is
+// recorded or the outer loop has stopped; leaves the shift state in h.
+// Synchronises the stream.
 static bool trs_all_done(const double* trs, const DeviceStatus* status, int32_t batch,
                          hipStream_t st, std::vector<double>& h) {
   h.assign((size_t)4 * batch, 0.0);
-  int32_t code = 0;
+  int32_t head[4] = {0, 0, 0, 0};  // code, failed_iter, failed_problem, done
   if (hipMemcpyAsync(h.data(), trs, h.size() * sizeof(double), hipMemcpyDeviceToHost, st) !=
           hipSuccess ||
-      hipMemcpyAsync(&code, &status->code, sizeof(code), hipMemcpyDeviceToHost, st) !=
-          hipSuccess ||
+      hipMemcpyAsync(head, status, sizeof(head), hipMemcpyDeviceToHost, st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)
     return false;
-  if (code != 0) return true;
+  if (head[0] != 0 || head[3] != 0) return true;
   for (int32_t p = 0; p < batch; ++p)
     if (h[(size_t)4 * p + 1] < 2.0) return false;
   return true;

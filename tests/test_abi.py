@@ -123,6 +123,32 @@ def test_invalid_solve_options(lib):
                          ctypes.byref(rep), ws, 1 << 30, None) == P.ERR_UNSUPPORTED
 
 
+def test_tolerance_stop_validation(lib):
+    """The step tolerance must be finite and >= 0, and the fixed-sketch
+    method has no tolerance stop; all refused before any launch."""
+    A = dense_struct()
+    ws = ctypes.c_void_p(1 << 20)
+    x = ctypes.c_void_p(1 << 20)
+    rep = P.Report_t()
+    for tol in (-1e-12, float("nan"), float("inf")):
+        o = P.options(16, tol=tol)
+        assert lib.ihs_solve(ctypes.byref(A), x, ctypes.byref(o), x, None, None,
+                             ctypes.byref(rep), ws, 1 << 30, None) == P.ERR_INVALID_ARG, tol
+    o = P.options(16, tol=1e-8, method="fixed_sketch_cg")
+    assert lib.ihs_solve(ctypes.byref(A), x, ctypes.byref(o), x, None, None,
+                         ctypes.byref(rep), ws, 1 << 30, None) == P.ERR_UNSUPPORTED
+    # a positive tolerance needs two more d-vectors per problem of workspace
+    base = lib.ihs_workspace_size(ctypes.byref(A), ctypes.byref(P.options(16)))
+    with_tol = lib.ihs_workspace_size(ctypes.byref(A), ctypes.byref(P.options(16, tol=1e-8)))
+    assert with_tol > base
+
+
+def test_report_layout(lib):
+    """The report struct of the binding has the header's field order and size."""
+    assert ctypes.sizeof(P.Report_t) == 40
+    assert P.Report_t.qp_unpolished.offset == 32
+
+
 def test_gram_and_qp_validation(lib):
     p = ctypes.c_void_p(1 << 20)
     assert lib.ihs_gram(p, P.BF16, 64, 8, 8, 1, P.F64, p, p, 1 << 30, None) == P.ERR_INVALID_ARG
@@ -130,7 +156,8 @@ def test_gram_and_qp_validation(lib):
     assert lib.ihs_gram(p, P.F64, 64, 8, 8, 1, P.F64, p, p, 8, None) == P.ERR_WORKSPACE
     assert lib.ihs_gram_workspace_size(0, 8, 1, P.F64, P.F64) == 0
     o = P.options(1, constraint="l2", radius=-1.0)
-    assert lib.ihs_qp_step(8, 1, p, p, p, p, ctypes.byref(o), p, 1 << 30, None) == P.ERR_INVALID_ARG
+    assert lib.ihs_qp_step(8, 1, p, p, p, p, ctypes.byref(o), p, 1 << 30, None,
+                           None) == P.ERR_INVALID_ARG
 
 
 def test_hash_validation(lib):
