@@ -226,6 +226,27 @@ ihs_status ihs_sketch_apply(const ihs_sketch* sk, const ihs_matrix* A,
                             void* SA, int32_t sa_dtype, int64_t ld_sa,
                             void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* Bytes of the device scratch array that ihs_sketch_apply_static uses in
+ * place of a workspace (one array per GPU, held until the process ends). */
+#define IHS_STATIC_SCRATCH_BYTES (64u << 20)
+
+/* ihs_sketch_apply without a workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, hosts
+ * that forbid hipMalloc): the same SA, bit for bit, with the sort state (keys,
+ * per-tile counts, scan partials, bucket starts and the row permutation) in
+ * a file-scope device array of IHS_STATIC_SCRATCH_BYTES per GPU instead of
+ * `ws`. It calls no hipMalloc, hipFree or other allocating routine; the
+ * first call on a device looks the array's address up (hipGetSymbolAddress).
+ * The caller still provides A and SA. A problem whose sort state exceeds the
+ * array returns IHS_ERR_WORKSPACE before anything is enqueued (it fits
+ * n*s <= 2^22 rows with m = 4096, e.g. the 2^22 x 512 matrix with a
+ * CountSketch of 4096 rows). Every call on one GPU shares the array: calls
+ * that overlap in time on one GPU (different streams or threads) race, and
+ * must be ordered by the caller. Asynchronous. */
+ihs_status ihs_sketch_apply_static(const ihs_sketch* sk, const ihs_matrix* A,
+                                   void* SA, int32_t sa_dtype, int64_t ld_sa,
+                                   hipStream_t stream);
+
 /* out = S^T G (the adjoint of ihs_sketch_apply, used by its derivative).
  * G (device) is (batch*m) x d F64 with leading dimension ld_g; out (device)
  * is n x d F64 with leading dimension ld_out. Row i of problem p receives the

@@ -31,7 +31,7 @@ _DTYPES = {"float64": F64, "float32": F32, "bfloat16": BF16,
            "f64": F64, "f32": F32, "bf16": BF16}
 
 EXPORTS = ["ihs_status_string", "ihs_last_hip_error", "ihs_sketch_hash", "ihs_workspace_size",
-           "ihs_sketch_apply", "ihs_sketch_adjoint", "ihs_gram_workspace_size",
+           "ihs_sketch_apply", "ihs_sketch_apply_static", "ihs_sketch_adjoint", "ihs_gram_workspace_size",
            "ihs_gram", "ihs_gradient", "ihs_qp_workspace_size", "ihs_qp_step",
            "ihs_solve", "ihs_adjoint_solve", "ihs_solution_grads",
            "ihs_profile_enable", "ihs_profile_read"]
@@ -101,6 +101,7 @@ def load(path: Optional[str] = None):
         "ihs_sketch_hash": (i32, [S, i64, i32, vp, vp, vp]),
         "ihs_workspace_size": (sz, [M, O]),
         "ihs_sketch_apply": (i32, [S, M, vp, i32, i64, vp, sz, vp]),
+        "ihs_sketch_apply_static": (i32, [S, M, vp, i32, i64, vp]),
         "ihs_sketch_adjoint": (i32, [S, i64, i64, i32, vp, vp, i64, vp, i64, vp]),
         "ihs_gram_workspace_size": (sz, [i64, i64, i32, i32, i32]),
         "ihs_gram": (i32, [vp, i32, i64, i64, i64, i32, i32, vp, vp, sz, vp]),
@@ -277,6 +278,21 @@ def sketch_apply(A: Matrix, sketch: SketchSpec, out_dtype="float64", out=None, w
     sk = sketch.struct()
     _check(L.ihs_sketch_apply(ctypes.byref(sk), A.ref(), _ptr(out), dt, out.stride(0),
                               _ptr(ws), ws.numel(), _stream()), "ihs_sketch_apply")
+    return out
+
+
+def sketch_apply_static(A: Matrix, sketch: SketchSpec, out_dtype="float64", out=None):
+    """SA through the allocation-free entry point (its sort state lives in the
+    library's per-GPU scratch array; calls on one GPU must not overlap). The
+    library allocates nothing; pass `out` to allocate nothing here either."""
+    torch = _torch()
+    L = load()
+    dt = _dt(out_dtype)
+    if out is None:
+        out = torch.empty(A.batch * sketch.m, A.d, dtype=_torch_dtype(dt), device=A.device)
+    sk = sketch.struct()
+    _check(L.ihs_sketch_apply_static(ctypes.byref(sk), A.ref(), _ptr(out), dt, out.stride(0),
+                                     _stream()), "ihs_sketch_apply_static")
     return out
 
 

@@ -160,6 +160,7 @@ struct PassBuffers {
   double* red = nullptr;   // two-level reduction scratch
   double* rdiag = nullptr; // batch x d reciprocal pivots (adjoint path)
   const int32_t* halt = nullptr;  // &status->done while a solve may stop early
+  bool profile = true;            // false: never create timing events
 };
 
 void carve_pass(Carver& c, const Layout& L, const ihs_sketch* sk, PassBuffers& B) {
@@ -182,6 +183,44 @@ void carve_pass(Carver& c, const Layout& L, const ihs_sketch* sk, PassBuffers& B
   B.bzero = c.take<double>((size_t)std::max<int64_t>(L.n, 1));
   B.red = c.take<double>(reduce_scratch_doubles(L.batch, L.d));
   B.rdiag = c.take<double>((size_t)(L.batch * L.d));
+}
+
+// The arrays a sketch-only pass (sort + gather, no gradient) uses, for the
+// allocation-free entry point: the others of carve_pass stay null.
+void carve_sketch_only(Carver& c, const Layout& L, const ihs_sketch* sk, PassBuffers& B) {
+  const int64_t m = sk->m;
+  const int64_t entries = L.n * sk->s;
+  B.probs = c.take<ProbInfo>(L.batch);
+  B.status = c.take<DeviceStatus>(1);
+  B.keys = c.take<uint32_t>((size_t)std::max<int64_t>(entries, 1));
+  B.tile_count = c.take<int32_t>((size_t)std::max<int64_t>((int64_t)L.total_tiles * m, 1));
+  B.chunk_part = c.take<int32_t>((size_t)std::max<int64_t>((int64_t)L.total_chunks * m, 1));
+  B.bucket_start = c.take<int32_t>((size_t)(L.batch * m + 1));
+  B.perm = c.take<uint32_t>((size_t)std::max<int64_t>(entries, 1));
+}
+
+// ---- the allocation-free sketch apply ----
+// One file-scope device array serves every call of ihs_sketch_apply_static
+// on a GPU; each device holds its own copy, at its own address, found once per
+// device with hipGetSymbolAddress. In host code `scratch` names a host-side
+// stand-in, so only the looked-up addresses are ever handed to kernels.
+static __device__ __align__(256) unsigned char scratch[IHS_STATIC_SCRATCH_BYTES];
+
+// The device address of `scratch` on the current device (nullptr when the
+// lookup fails; the failure is recorded for ihs_last_hip_error).
+void* static_scratch_address() {
+  static std::mutex mu;
+  static std::vector<void*> addr;
+  int dev = 0;
+  if (hip_failed(hipGetDevice(&dev))) return nullptr;
+  std::lock_guard<std::mutex> lk(mu);
+  if (addr.size() <= (size_t)dev) addr.resize((size_t)dev + 1, nullptr);
+  if (!addr[(size_t)dev]) {
+    void* p = nullptr;
+    if (hip_failed(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)))) return nullptr;
+    addr[(size_t)dev] = p;
+  }
+  return addr[(size_t)dev];
 }
 
 // Gradient partials written by one sketch pass: one per wavefront that owns
@@ -308,8 +347,8 @@ ihs_status run_gather(const ihs_matrix* A, const ihs_sketch* sk, const PassBuffe
                       const SketchPlan& P, void* SA, int32_t sa_dtype, int64_t ld_sa,
                       const double* b, const double* x, double* r_out, hipStream_t st) {
   const double scale = sk->s > 1 ? 1.0 / std::sqrt((double)sk->s) : 1.0;
-  hipEvent_t e0;
-  prof_begin(st, &e0);
+  hipEvent_t e0 = nullptr;
+  if (B.profile) prof_begin(st, &e0);
   hipError_t err;
   if (A->format == IHS_DENSE) {
     GatherArgs G{};
@@ -901,6 +940,30 @@ ihs_status ihs_sketch_apply(const ihs_sketch* sk, const ihs_matrix* A, void* SA,
   Carver c(ws);
   PassBuffers B;
   carve_pass(c, L, sk, B);
+  if ((s = upload_probs(L, B, stream)) != IHS_OK) return s;
+  return run_pass(A, L, sk, B, sk->iter, SA, sa_dtype, ld_sa, nullptr, nullptr, nullptr, stream);
+}
+
+ihs_status ihs_sketch_apply_static(const ihs_sketch* sk, const ihs_matrix* A, void* SA,
+                                   int32_t sa_dtype, int64_t ld_sa, hipStream_t stream) {
+  ihs_status s = check_matrix(A);
+  if (s != IHS_OK) return s;
+  if ((s = check_sketch(sk)) != IHS_OK) return s;
+  if (!SA || ld_sa < A->d) return IHS_ERR_INVALID_ARG;
+  if (sa_dtype != IHS_F64 && sa_dtype != IHS_F32 && sa_dtype != IHS_BF16) return IHS_ERR_INVALID_ARG;
+  if (A->n * (int64_t)sk->s >= (int64_t(1) << 31)) return IHS_ERR_UNSUPPORTED;
+  const Layout L = make_layout(A, sk->m);
+  Carver need(nullptr);
+  PassBuffers tmp;
+  carve_sketch_only(need, L, sk, tmp);
+  if (need.used > (size_t)IHS_STATIC_SCRATCH_BYTES) return IHS_ERR_WORKSPACE;
+  clear_stale_error();
+  void* base = static_scratch_address();
+  if (!base) return IHS_ERR_HIP;
+  Carver c(base);
+  PassBuffers B;
+  carve_sketch_only(c, L, sk, B);
+  B.profile = false;
   if ((s = upload_probs(L, B, stream)) != IHS_OK) return s;
   return run_pass(A, L, sk, B, sk->iter, SA, sa_dtype, ld_sa, nullptr, nullptr, nullptr, stream);
 }

@@ -160,6 +160,18 @@ def test_gram_and_qp_validation(lib):
                            None) == P.ERR_INVALID_ARG
 
 
+def test_static_sketch_apply_refuses_oversize_before_launch(lib):
+    """The allocation-free sketch apply checks the sort state against its
+    fixed scratch array on the host: too large a problem is refused with
+    IHS_ERR_WORKSPACE before any launch (so this runs without a GPU)."""
+    sk = P.Sketch_t(P.COUNTSKETCH, 1, 4096, 0, 0)
+    A = dense_struct(n=1 << 30, d=4, ld=4)
+    assert lib.ihs_sketch_apply_static(ctypes.byref(sk), ctypes.byref(A), ctypes.c_void_p(8),
+                                       P.F64, 4, None) == P.ERR_WORKSPACE
+    assert lib.ihs_sketch_apply_static(ctypes.byref(sk), ctypes.byref(A), None, P.F64, 4,
+                                       None) == P.ERR_INVALID_ARG
+
+
 def test_hash_validation(lib):
     sk = P.Sketch_t(P.SJLT, 4, 10, 0, 0)   # 4 does not divide 10
     assert lib.ihs_sketch_hash(ctypes.byref(sk), 10, 0, ctypes.c_void_p(8), ctypes.c_void_p(8),

@@ -93,6 +93,7 @@ def test_qp_l1_matches_oracle(gpu_lib, d, batch, frac, cond):
         assert np.array_equal(np.sign(out[p]), np.sign(ref)), p   # the same face
         bound = RB.qp_budget(Hs[p], gs[p], xs[p], ref, "l1", tau, cg_tol=CG_TOL)
         assert np.linalg.norm(out[p] - ref) <= bound, (p, np.linalg.norm(out[p] - ref), bound)
+        print("share of the budget used: %.3g" % (np.linalg.norm(out[p] - ref) / bound))
         c = Hs[p] @ xs[p] + gs[p]
         assert kkt_l1_residual(Hs[p], c, out[p], tau) <= kkt_tol(Hs[p], c, out[p])
 
@@ -156,6 +157,7 @@ def test_qp_l2_matches_oracle(gpu_lib, d, batch, frac, cond):
         assert np.linalg.norm(out[p]) <= r * (1 + 1e-12)
         bound = RB.qp_budget(Hs[p], gs[p], xs[p], ref, "l2", r)
         assert np.linalg.norm(out[p] - ref) <= bound, (p, np.linalg.norm(out[p] - ref), bound)
+        print("share of the budget used: %.3g" % (np.linalg.norm(out[p] - ref) / bound))
 
 
 @pytest.mark.parametrize("d", [40, 100])
@@ -187,10 +189,13 @@ def oracle_run(A, b, m, s, seed, iters, constraint, radius, csr=None):
 
 
 def assert_within_budget(A, hist, xs, bud, what=""):
+    worst = 0.0
     for t in range(len(bud)):
         de = float(np.linalg.norm(hist[t] - xs[t + 1]))
         da = float(np.linalg.norm(A @ (hist[t] - xs[t + 1])))
         assert de <= bud[t][1] and da <= bud[t][0], (what, t, de, bud[t][1], da, bud[t][0])
+        worst = max(worst, de / bud[t][1], da / bud[t][0])
+    print("largest share of the budget used: %.3g" % worst)
 
 
 @pytest.mark.parametrize("kind,s", [("countsketch", 1), ("sjlt", 4)])
@@ -297,6 +302,7 @@ def test_qp_l1_penalty_matches_oracle(gpu_lib, d, batch, frac, cond):
         assert np.array_equal(np.sign(out[p]), np.sign(ref)), p   # the same face
         bound = RB.qp_budget(Hs[p], gs[p], xs[p], ref, "l1_penalty", lam, cg_tol=CG_TOL)
         assert np.linalg.norm(out[p] - ref) <= bound, (p, np.linalg.norm(out[p] - ref), bound)
+        print("share of the budget used: %.3g" % (np.linalg.norm(out[p] - ref) / bound))
         c = Hs[p] @ xs[p] + gs[p]
         assert kkt_l1_penalty_residual(Hs[p], c, out[p], lam) <= kkt_tol(Hs[p], c, out[p])
 

@@ -53,6 +53,7 @@ def test_qp_unconstrained_ill_conditioned(gpu_lib, d, cond):
     bound = RB.h_norm_budget(H, gv)
     step = float(np.sqrt((ref - x) @ H @ (ref - x)))
     assert hn <= bound, (hn, bound, step)
+    print("share of the budget used: %.3g (difference %.3g of the step)" % (hn / bound, hn / step))
     assert bound < 1e-3 * step   # the budget itself is far below the step
 
 
@@ -79,9 +80,12 @@ def test_headline_conditioning_iterates_match_oracle(gpu_lib, headline, schedule
     res = P.solve(P.Matrix(dense=dev(wl.A)), dev(wl.b), opts, history=True)
     assert res.report.status == 0 and res.report.iters == 30
     hist = host(res.history)[:, 0, :]
+    worst = 0.0
     for t in range(30):
         da = float(np.linalg.norm(wl.A @ (hist[t] - xs[t + 1])))
         assert da <= bud[t][0], (t, da, bud[t][0])
+        worst = max(worst, da / bud[t][0])
+    print("largest share of the budget used: %.3g" % worst)
     # Thm 2.2's geometric decay takes the prediction-norm error to 1e-10
     assert O.error_A(wl.A, hist[-1], xo) <= 1e-10
     assert O.error_A(wl.A, xs[-1], xo) <= 1e-10
@@ -117,10 +121,13 @@ def test_l2_csr_full_width_iterates_match_oracle(gpu_lib, ridge_wide):
     hist = host(res.history)[:, 0, :]
     active = np.linalg.norm(xo) > wl.radius * (1 - 1e-9)
     assert active == (wl.radius < np.linalg.norm(wl.x_star))
+    worst = 0.0
     for t in range(wl.iters):
         assert np.linalg.norm(hist[t]) <= wl.radius * (1 + 1e-12)
         da = float(np.linalg.norm(A @ (hist[t] - xs[t + 1])))
         de = float(np.linalg.norm(hist[t] - xs[t + 1]))
         assert da <= bud[t][0], (t, da, bud[t][0])
         assert de <= bud[t][1], (t, de, bud[t][1])
+        worst = max(worst, da / bud[t][0], de / bud[t][1])
+    print("largest share of the budget used: %.3g" % worst)
     assert O.error_A(A, hist[-1], xo) < 1e-3 * O.error_A(A, hist[0], xo)
