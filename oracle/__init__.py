@@ -12,6 +12,9 @@ Contents and the passages they follow:
   sketch   CountSketch / SJLT (Sec. 2), streaming application to dense and
            CSR data (Sec. 2, "Time Complexity"), the adjoint S^T G, and the
            explicit S for brute force
+  dense_sketch  the Gaussian and SRHT sketches the paper compares with
+           (Sec. 2, "Sketching Results"): Box-Muller entries from Philox, the
+           radix-2 Hadamard transform of zero-padded rows, uniform row sampling
   ihs      Gram (SA)^T SA and the gradient A^T (b - A x) (Sec. 1 after Eq.(2);
            App. A.1.1 "Iteration Time Costs"), the QP of Eq.(2) over R^d, the
            l1 ball and the l2 ball, the outer loop (Eq.(2), Thm 2.2), x_OPT of
@@ -20,7 +23,8 @@ Contents and the passages they follow:
            preconditioner of conjugate gradients)
 
 Pins (tests/test_oracle_*.py) tie each function to something other than
-itself: numpy's Philox stream, a dense S built entry by entry, integer-valued
+itself: numpy's Philox stream, a dense S built entry by entry, scipy's
+Sylvester Hadamard matrix, the normal law of the Gaussian entries, integer-valued
 data (exact in any order), Lemmas A.5-A.7, closed-form sketch variance,
 math.fsum, hand-solved projections, KKT conditions, brute-force enumeration of
 l1 faces, the exact IHS error recurrence, finite differences, finite
@@ -30,4 +34,4 @@ Parity unpinned: the inner iterates of the l1 and l2 QP solvers (only their
 solutions are pinned, through KKT and brute force), and the float rounding
 order inside the Gram and the gradient (bounded, not matched).
 """
-from . import philox, sketch, ihs  # noqa: F401
+from . import philox, sketch, dense_sketch, ihs  # noqa: F401
