@@ -51,7 +51,14 @@ typedef enum {
 } ihs_status;
 
 typedef enum { IHS_F64 = 0, IHS_F32 = 1, IHS_BF16 = 2 } ihs_dtype;
-typedef enum { IHS_COUNTSKETCH = 0, IHS_SJLT = 1 } ihs_sketch_kind;
+/* The sparse embeddings (CountSketch, SJLT) and the two dense sketches of
+ * Sec. 2 that the paper compares them with (SRHT, Gaussian). */
+typedef enum {
+  IHS_COUNTSKETCH = 0,
+  IHS_SJLT = 1,
+  IHS_SRHT = 2,
+  IHS_GAUSSIAN = 3
+} ihs_sketch_kind;
 /* The set C of Eq.(1), or (IHS_L1_PENALTY) the weight lambda ||x||_1 added to
  * the objective over R^d: the penalised LASSO of the experiments of Sec. 3. */
 typedef enum {
@@ -98,7 +105,22 @@ typedef struct {
  *                         key = (seed, iter))
  *   block k: sketch row = k*(m/s) + floor(words[2(k%2)] * (m/s) / 2^64),
  *            sign = -1 if bit 63 of words[2(k%2)+1] is set, else +1.
- * `row` counts from 0 within a problem. `m` is per problem. */
+ * `row` counts from 0 within a problem. `m` is per problem.
+ *
+ * The dense sketches (s = 1, one problem: batch = 1), with their own counter
+ * streams under the same key (counter word 3 names the stream):
+ *  SRHT (Sec. 2): S = (1/sqrt(m)) P H D. D_i = -1 if bit 63 of word 1 of
+ *   Philox(counter = (i, 0, 0, 1)) is set, else +1; H is the unnormalised
+ *   Sylvester-Hadamard transform on N = 2^ceil(log2 n) rows (A padded with
+ *   zero rows), applied as the radix-2 recursion (stages h = 1, 2, 4, ...,
+ *   (y_i, y_{i+h}) -> (y_i + y_{i+h}, y_i - y_{i+h})); row k of P samples
+ *   row floor(word 0 of Philox((k, 0, 0, 2)) * N / 2^64), independently
+ *   (with replacement). The result is bitwise that of this definition.
+ *  Gaussian (Sec. 2): S = G / sqrt(m), G[4q + j][i] (j = 0..3) from
+ *   Philox((i, q, 0, 3)) by the Box-Muller method: for word pairs (0, 1) and
+ *   (2, 3), u1 = ((w_a >> 11) + 1) 2^-53, u2 = (w_b >> 11) 2^-53,
+ *   rho = sqrt(-2 ln u1), G = rho cos(2 pi u2) (j even) and rho sin(2 pi u2)
+ *   (j odd). Summed in float64 on the matrix cores in a fixed order. */
 typedef struct {
   int32_t kind;                /* ihs_sketch_kind                             */
   int32_t s;                   /* blocks; 1 for CountSketch                   */
@@ -163,7 +185,10 @@ typedef struct {
                                   factors; the iterates agree to rounding,
                                   since the fused pass adds up A^T r in the
                                   row order of the sketch it forms (S_{t+1} or
-                                  S_{t+2} when overlapping, S_t otherwise).   */
+                                  S_{t+2} when overlapping, S_t otherwise).
+                                  The dense sketch kinds always run
+                                  sequential steps: the sketch, then a
+                                  separate gradient pass.                     */
   int32_t method;              /* ihs_method. IHS_METHOD_FIXED_SKETCH_CG:
                                   max_iter conjugate-gradient iterations after
                                   one pass that forms S_0 A (key (sketch.seed,
@@ -204,7 +229,8 @@ const char* ihs_last_hip_error(int32_t* code);
 /* Bucket and sign of every (row, block) pair of one problem's sketch, exactly
  * as defined under ihs_sketch. bucket (device, n*s int32) receives the sketch
  * row in [0, m) of pair (i, k) at index i*s + k; sign (device, n*s int8)
- * receives +1 or -1. Asynchronous. */
+ * receives +1 or -1. The dense sketch kinds have no hash
+ * (IHS_ERR_UNSUPPORTED). Asynchronous. */
 ihs_status ihs_sketch_hash(const ihs_sketch* sk, int64_t n, int32_t problem,
                            int32_t* bucket, int8_t* sign, hipStream_t stream);
 
@@ -214,7 +240,11 @@ ihs_status ihs_sketch_hash(const ihs_sketch* sk, int64_t n, int32_t problem,
  * invalid arguments. */
 size_t ihs_workspace_size(const ihs_matrix* A, const ihs_options* opt);
 
-/* SA = S A (Sec. 2, "Time Complexity": one pass over the nonzeros of A).
+/* SA = S A (Sec. 2, "Time Complexity": one pass over the nonzeros of A for
+ * the sparse embeddings; a fast Hadamard transform for the SRHT and a dense
+ * product on the matrix cores for the Gaussian sketch, both on one problem
+ * (batch = 1, else IHS_ERR_UNSUPPORTED), CSR data expanded to dense rows in
+ * the workspace first).
  * SA (device) is (batch*m) x d row-major with leading dimension ld_sa >= d;
  * problem p fills rows [p*m, (p+1)*m). Each entry is the sum, in ascending
  * row order from +0.0, of sign * A[row][col] over the rows hashed to that
@@ -253,7 +283,7 @@ ihs_status ihs_sketch_apply_static(const ihs_sketch* sk, const ihs_matrix* A,
  * sum over blocks k, ascending from +0.0, of sign(i,k) * (c_s * G[p*m +
  * bucket(i,k)][:]), c_s = 1/sqrt(s) (the factor is skipped for s = 1).
  * row_offsets: HOST, batch+1 entries (NULL when batch = 1). s > 16 returns
- * IHS_ERR_UNSUPPORTED. Asynchronous. */
+ * IHS_ERR_UNSUPPORTED, and so do the dense sketch kinds. Asynchronous. */
 ihs_status ihs_sketch_adjoint(const ihs_sketch* sk, int64_t n, int64_t d,
                               int32_t batch, const int64_t* row_offsets,
                               const double* G, int64_t ld_g,

@@ -11,6 +11,7 @@ import numpy as np
 import scipy.linalg as sla
 import scipy.sparse as sp
 
+from .dense_sketch import sketch_apply_gaussian, sketch_apply_srht
 from .sketch import sketch_apply_csr, sketch_apply_dense, round_output
 
 
@@ -257,11 +258,13 @@ def qp_step(H, g, x_t, constraint="none", radius=0.0):
 # the outer loop (Eq.(2); Thm 2.2) and the optimum (Eq.(1))
 # --------------------------------------------------------------------------
 def ihs(A, b, m, s=1, seed=0, iter0=0, iters=10, constraint="none", radius=0.0,
-        x0=None, csr=None, sketch_dtype="float64", return_hessians=False):
+        x0=None, csr=None, sketch_dtype="float64", return_hessians=False, kind="sparse"):
     """Run `iters` IHS steps from x0 (default 0). Step t draws the sketch keyed
     (seed, iter0 + t); x^{t+1} solves Eq.(2) with that sketch.
     Dense input: A (n x d). CSR input: A is ignored and csr = (indptr, indices,
-    data, n, d). Returns the iterates x^0 .. x^iters (and the Hessians)."""
+    data, n, d). kind: "sparse" (CountSketch, or SJLT with s blocks), or one of
+    the dense sketches "srht" and "gaussian" (Sec. 2) applied to A's rows.
+    Returns the iterates x^0 .. x^iters (and the Hessians)."""
     if csr is not None:
         indptr, indices, data, n, d = csr
         Aop = csr_matrix(indptr, indices, data, n, d)
@@ -271,8 +274,15 @@ def ihs(A, b, m, s=1, seed=0, iter0=0, iters=10, constraint="none", radius=0.0,
     A64 = Aop if csr is not None else Aop.astype(np.float64, copy=False)
     x = np.zeros(d) if x0 is None else np.asarray(x0, dtype=np.float64).copy()
     xs, Hs = [x.copy()], []
+    dense_rows = None
+    if kind != "sparse":
+        dense_rows = A64.toarray() if csr is not None else A64
     for t in range(iters):
-        if csr is not None:
+        if kind == "srht":
+            SA = sketch_apply_srht(dense_rows, seed, iter0 + t, m, out_dtype=sketch_dtype)
+        elif kind == "gaussian":
+            SA = sketch_apply_gaussian(dense_rows, seed, iter0 + t, m, out_dtype=sketch_dtype)
+        elif csr is not None:
             SA = sketch_apply_csr(indptr, indices, data, n, d, seed, iter0 + t,
                                   m, s, out_dtype=sketch_dtype)
         else:

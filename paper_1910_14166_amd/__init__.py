@@ -21,7 +21,8 @@ LIB_PATH = os.path.join(HERE, "libihs.so")
 OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_WORKSPACE, ERR_HIP, ERR_NOT_PD, \
     ERR_NOT_CONVERGED, ERR_NONFINITE = range(8)
 F64, F32, BF16 = 0, 1, 2
-COUNTSKETCH, SJLT = 0, 1
+COUNTSKETCH, SJLT, SRHT, GAUSSIAN = 0, 1, 2, 3
+_KINDS = {"countsketch": COUNTSKETCH, "sjlt": SJLT, "srht": SRHT, "gaussian": GAUSSIAN}
 UNCONSTRAINED, L1_BALL, L2_BALL, L1_PENALTY = 0, 1, 2, 3
 DENSE, CSR = 0, 1
 METHOD_IHS, METHOD_FIXED_SKETCH_CG = 0, 1
@@ -169,7 +170,8 @@ def _workspace(nbytes, device):
 
 @dataclass
 class SketchSpec:
-    """A CountSketch (s = 1) or SJLT (s blocks) of m rows per problem."""
+    """A sketch of m rows per problem: "countsketch" (s = 1), "sjlt" (s
+    blocks), or the dense "srht" and "gaussian" sketches (s = 1)."""
     m: int
     s: int = 1
     kind: str = "countsketch"
@@ -177,7 +179,7 @@ class SketchSpec:
     iter: int = 0
 
     def struct(self):
-        kind = SJLT if self.kind == "sjlt" else COUNTSKETCH
+        kind = _KINDS[self.kind] if isinstance(self.kind, str) else int(self.kind)
         return Sketch_t(kind, int(self.s), int(self.m), int(self.seed) & (2 ** 64 - 1),
                         int(self.iter) & (2 ** 64 - 1))
 

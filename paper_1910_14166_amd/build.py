@@ -16,7 +16,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libihs.so")
-SOURCES = ["api.cpp", "sketch.hip", "gram.hip", "qp.hip", "qp_constrained.hip"]
+SOURCES = ["api.cpp", "sketch.hip", "sketch_dense.hip", "gram.hip", "qp.hip",
+           "qp_constrained.hip"]
 ARCH = "gfx950"
 
 

@@ -57,11 +57,14 @@ struct Carver {
 
 int64_t dtype_size(int32_t dt) { return dt == IHS_F64 ? 8 : (dt == IHS_F32 ? 4 : 2); }
 
+// The Gaussian and SRHT sketches (dense S) against the sparse embeddings.
+bool dense_kind(const ihs_sketch* sk) { return sk->kind == IHS_SRHT || sk->kind == IHS_GAUSSIAN; }
+
 bool valid_sketch(const ihs_sketch* sk) {
   if (!sk) return false;
-  if (sk->kind != IHS_COUNTSKETCH && sk->kind != IHS_SJLT) return false;
+  if (sk->kind != IHS_COUNTSKETCH && sk->kind != IHS_SJLT && !dense_kind(sk)) return false;
   if (sk->m < 1 || sk->s < 1) return false;
-  if (sk->kind == IHS_COUNTSKETCH && sk->s != 1) return false;
+  if (sk->kind != IHS_SJLT && sk->s != 1) return false;
   if (sk->m % sk->s != 0) return false;
   return true;
 }
@@ -75,6 +78,7 @@ ihs_status check_sketch(const ihs_sketch* sk) {
 // Problem table of a matrix (host copy).
 struct Layout {
   std::vector<ProbInfo> probs;
+  bool csr = false;
   int32_t batch = 1;
   int64_t n = 0, d = 0;
   int32_t tile_rows = 256;
@@ -115,6 +119,7 @@ ihs_status check_matrix(const ihs_matrix* A) {
 
 Layout make_layout(const ihs_matrix* A, int64_t m_local) {
   Layout L;
+  L.csr = A->format == IHS_CSR;
   L.batch = A->batch;
   L.n = A->n;
   L.d = A->d;
@@ -389,6 +394,31 @@ ihs_status run_gather(const ihs_matrix* A, const ihs_sketch* sk, const PassBuffe
   return hip_status(err);
 }
 
+// S A for the Gaussian or SRHT sketch of key (seed, iter) (one problem).
+ihs_status run_dense_sketch(const ihs_matrix* A, const ihs_sketch* sk, uint64_t iter, void* SA,
+                            int32_t sa_dtype, int64_t ld_sa, double* work, hipStream_t st) {
+  DenseSketchArgs a{};
+  a.kind = sk->kind;
+  a.A = A->values;
+  a.a_dtype = A->dtype;
+  a.lda = A->ld;
+  a.csr = A->format == IHS_CSR;
+  a.row_ptr = A->row_ptr;
+  a.col_idx = A->col_idx;
+  a.n = A->n;
+  a.d = A->d;
+  a.m = sk->m;
+  a.scale = 1.0 / std::sqrt((double)sk->m);
+  a.SA = SA;
+  a.sa_dtype = sa_dtype;
+  a.ld_sa = ld_sa;
+  a.seed = sk->seed;
+  a.iter = iter;
+  a.problem = 0;
+  a.work = work;
+  return hip_status(launch_dense_sketch(a, st));
+}
+
 // Natural-order gradient pass + reduction into B.g / B.f.
 ihs_status run_gradient(const ihs_matrix* A, const Layout& L, const PassBuffers& B,
                         const double* b, const double* x, double* g, double* f, double* r_out,
@@ -448,6 +478,7 @@ struct SolveBuffers {
   // the tolerance stop: x^t before each update, and per-row products
   double* xprev = nullptr;
   double* stepq = nullptr;
+  double* dsk = nullptr;     // the Gaussian or SRHT sketch's own scratch
 };
 
 // Above this width the overlapped schedule forms H^{-1} on the second stream
@@ -502,6 +533,9 @@ size_t carve_solve(Carver& c, const Layout& L, const ihs_options* o, SolveBuffer
     S.xprev = c.take<double>((size_t)(L.batch * L.d));
     S.stepq = c.take<double>((size_t)(L.batch * L.d));
   }
+  if (dense_kind(&o->sketch))
+    S.dsk = c.take<double>(dense_sketch_workspace_bytes(o->sketch.kind, m, L.n, L.d, L.csr) /
+                           sizeof(double));
   return c.used;
 }
 
@@ -824,12 +858,22 @@ ihs_status solve_fixed_sketch_cg(const ihs_matrix* A, const Layout& L, const ihs
   auto ck = [](hipError_t e) { return !hip_failed(e); };
   if (!ck(fill(B.bzero, A->n, 0.0, stream)) || !ck(fill(S.cg_zero, bd, 0.0, stream)))
     return IHS_ERR_HIP;
-  ihs_status s = run_pass(A, L, &opt->sketch, B, opt->sketch.iter, S.SA, opt->gram_in, d, b, x,
-                          nullptr, stream);
-  if (s != IHS_OK) return s;
-  if (!ck(launch_reduce_partials(B.gpart, B.fpart, L.batch, pass_parts(A, &opt->sketch, L.batch),
-                                 B.probs, d, S.cg_r, B.f, B.status, 0, B.red, stream)) ||
-      !ck(launch_gram(S.SA, opt->gram_in, m, d, d, L.batch, opt->gram_acc, S.H, S.gram_part,
+  ihs_status s;
+  if (dense_kind(&opt->sketch)) {  // a dense sketch, then the gradient pass
+    if ((s = run_dense_sketch(A, &opt->sketch, opt->sketch.iter, S.SA, opt->gram_in, d, S.dsk,
+                              stream)) != IHS_OK ||
+        (s = run_gradient(A, L, B, b, x, S.cg_r, B.f, nullptr, B.status, 0, stream)) != IHS_OK)
+      return s;
+  } else {
+    s = run_pass(A, L, &opt->sketch, B, opt->sketch.iter, S.SA, opt->gram_in, d, b, x, nullptr,
+                 stream);
+    if (s != IHS_OK) return s;
+    if (!ck(launch_reduce_partials(B.gpart, B.fpart, L.batch,
+                                   pass_parts(A, &opt->sketch, L.batch), B.probs, d, S.cg_r, B.f,
+                                   B.status, 0, B.red, stream)))
+      return IHS_ERR_HIP;
+  }
+  if (!ck(launch_gram(S.SA, opt->gram_in, m, d, d, L.batch, opt->gram_acc, S.H, S.gram_part,
                       stream)) ||
       !ck(launch_cholesky(S.H, S.Lf, d, L.batch, B.status, 0, 0.0, S.work, stream)))
     return IHS_ERR_HIP;
@@ -900,6 +944,7 @@ const char* ihs_last_hip_error(int32_t* code) {
 ihs_status ihs_sketch_hash(const ihs_sketch* sk, int64_t n, int32_t problem, int32_t* bucket,
                            int8_t* sign, hipStream_t stream) {
   if (!valid_sketch(sk) || n < 0 || problem < 0) return IHS_ERR_INVALID_ARG;
+  if (dense_kind(sk)) return IHS_ERR_UNSUPPORTED;  // no hash: S is dense
   if (n > 0 && (!bucket || !sign)) return IHS_ERR_INVALID_ARG;
   if (n * (int64_t)sk->s >= (int64_t(1) << 31)) return IHS_ERR_UNSUPPORTED;
   SketchPlan P{};
@@ -931,6 +976,15 @@ ihs_status ihs_sketch_apply(const ihs_sketch* sk, const ihs_matrix* A, void* SA,
   if (sa_dtype != IHS_F64 && sa_dtype != IHS_F32 && sa_dtype != IHS_BF16) return IHS_ERR_INVALID_ARG;
   if (A->n * (int64_t)sk->s >= (int64_t(1) << 31)) return IHS_ERR_UNSUPPORTED;
   if (!ws) return IHS_ERR_INVALID_ARG;
+  if (dense_kind(sk)) {
+    if (A->batch != 1) return IHS_ERR_UNSUPPORTED;
+    if (ws_bytes < dense_sketch_workspace_bytes(sk->kind, sk->m, A->n, A->d,
+                                                A->format == IHS_CSR))
+      return IHS_ERR_WORKSPACE;
+    clear_stale_error();
+    return run_dense_sketch(A, sk, sk->iter, SA, sa_dtype, ld_sa, static_cast<double*>(ws),
+                            stream);
+  }
   const Layout L = make_layout(A, sk->m);
   Carver need(nullptr);
   PassBuffers tmp;
@@ -952,6 +1006,7 @@ ihs_status ihs_sketch_apply_static(const ihs_sketch* sk, const ihs_matrix* A, vo
   if (!SA || ld_sa < A->d) return IHS_ERR_INVALID_ARG;
   if (sa_dtype != IHS_F64 && sa_dtype != IHS_F32 && sa_dtype != IHS_BF16) return IHS_ERR_INVALID_ARG;
   if (A->n * (int64_t)sk->s >= (int64_t(1) << 31)) return IHS_ERR_UNSUPPORTED;
+  if (dense_kind(sk)) return IHS_ERR_UNSUPPORTED;
   const Layout L = make_layout(A, sk->m);
   Carver need(nullptr);
   PassBuffers tmp;
@@ -981,7 +1036,7 @@ ihs_status ihs_sketch_adjoint(const ihs_sketch* sk, int64_t n, int64_t d, int32_
       if (row_offsets[p + 1] < row_offsets[p]) return IHS_ERR_INVALID_ARG;
   }
   if (n >= (int64_t(1) << 31)) return IHS_ERR_UNSUPPORTED;
-  if (sk->s > 16) return IHS_ERR_UNSUPPORTED;
+  if (sk->s > 16 || dense_kind(sk)) return IHS_ERR_UNSUPPORTED;
   clear_stale_error();
   for (int32_t p0 = 0; p0 < batch; p0 += kAdjointBatch) {
     AdjointBatch ab{};
@@ -1095,6 +1150,7 @@ ihs_status ihs_solve(const ihs_matrix* A, const double* b, const ihs_options* op
   if (factors && (!opt->keep_factors || opt->constraint != IHS_UNCONSTRAINED))
     return IHS_ERR_INVALID_ARG;
   if (factors && opt->method != IHS_METHOD_IHS) return IHS_ERR_UNSUPPORTED;
+  if (dense_kind(&opt->sketch) && A->batch != 1) return IHS_ERR_UNSUPPORTED;
   if (A->n * (int64_t)opt->sketch.s >= (int64_t(1) << 31)) return IHS_ERR_UNSUPPORTED;
   if (A->format == IHS_CSR && opt->gram_in != IHS_F64 && opt->gram_in != IHS_F32 &&
       opt->gram_in != IHS_BF16)
@@ -1113,17 +1169,26 @@ ihs_status ihs_solve(const ihs_matrix* A, const double* b, const ihs_options* op
   if ((s = upload_probs(L, B, stream)) != IHS_OK) return s;
   if (opt->method == IHS_METHOD_FIXED_SKETCH_CG)
     return solve_fixed_sketch_cg(A, L, opt, S, b, x, x_hist, rep, stream);
-  if (opt->schedule != 1 && opt->max_iter >= 2)
+  // the overlapped schedule reads sorted rows; the dense sketches run in order
+  if (opt->schedule != 1 && opt->max_iter >= 2 && !dense_kind(&opt->sketch))
     return solve_overlap(A, L, opt, S, b, x, x_hist, factors, rep, stream);
   const int64_t d = A->d, m = opt->sketch.m;
   const int64_t bd = (int64_t)L.batch * d;
   for (int32_t t = 0; t < opt->max_iter; ++t) {
     const uint64_t iter = opt->sketch.iter + (uint64_t)t;
-    s = run_pass(A, L, &opt->sketch, B, iter, S.SA, opt->gram_in, d, b, x, nullptr, stream);
-    if (s != IHS_OK) return s;
-    if (hip_failed(launch_reduce_partials(B.gpart, B.fpart, L.batch, pass_parts(A, &opt->sketch, L.batch), B.probs,
-                               d, B.g, B.f, B.status, t, B.red, stream)))
-      return IHS_ERR_HIP;
+    if (dense_kind(&opt->sketch)) {  // a dense sketch, then the gradient pass
+      if ((s = run_dense_sketch(A, &opt->sketch, iter, S.SA, opt->gram_in, d, S.dsk, stream)) !=
+              IHS_OK ||
+          (s = run_gradient(A, L, B, b, x, B.g, B.f, nullptr, B.status, t, stream)) != IHS_OK)
+        return s;
+    } else {
+      s = run_pass(A, L, &opt->sketch, B, iter, S.SA, opt->gram_in, d, b, x, nullptr, stream);
+      if (s != IHS_OK) return s;
+      if (hip_failed(launch_reduce_partials(B.gpart, B.fpart, L.batch,
+                                            pass_parts(A, &opt->sketch, L.batch), B.probs, d, B.g,
+                                            B.f, B.status, t, B.red, stream)))
+        return IHS_ERR_HIP;
+    }
     if (hip_failed(launch_gram(S.SA, opt->gram_in, m, d, d, L.batch, opt->gram_acc, S.H, S.gram_part,
                     stream)))
       return IHS_ERR_HIP;

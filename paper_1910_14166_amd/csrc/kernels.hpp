@@ -100,6 +100,29 @@ struct CsrGatherArgs {
 hipError_t launch_sketch_gather_csr(const SketchPlan& p, const CsrGatherArgs& g,
                                     hipStream_t st);
 
+// The dense sketches of Sec. 2 (kind 2: SRHT, kind 3: Gaussian) for one
+// problem: SA (m x d, ld_sa, sa_dtype) = S A with the scale applied once.
+struct DenseSketchArgs {
+  int32_t kind;
+  const void* A;           // dense rows (a_dtype 0 f64, 1 f32, leading dim lda),
+                           // or the CSR values (f64) when csr
+  int32_t a_dtype;
+  int64_t lda;
+  bool csr;
+  const int32_t* row_ptr;
+  const int32_t* col_idx;
+  int64_t n, d, m;
+  double scale;            // 1 / sqrt(m), formed on the host
+  void* SA;
+  int32_t sa_dtype;
+  int64_t ld_sa;
+  uint64_t seed, iter;
+  int32_t problem;
+  double* work;            // dense_sketch_workspace_bytes
+};
+size_t dense_sketch_workspace_bytes(int32_t kind, int64_t m, int64_t n, int64_t d, bool csr);
+hipError_t launch_dense_sketch(const DenseSketchArgs& a, hipStream_t st);
+
 // Natural-order gradient pass over dense rows: segments of seg_rows rows.
 hipError_t launch_gradient_rows(const ProbInfo* probs, int32_t batch, int32_t total_seg,
                                 int32_t seg_rows, const void* A, int32_t a_dtype,

@@ -119,9 +119,13 @@ def _solve_var(K, z):
     return v
 
 
-def step_covariance(A, b, SA, H, x, x_next, constraint, radius):
+def step_covariance(A, b, SA, H, x, x_next, constraint, radius, sa_err=None):
     """(P, T, Xi): the step's derivative with respect to c, the error map T
-    and one run's rounding covariance Xi (before P) of one IHS step."""
+    and one run's rounding covariance Xi (before P) of one IHS step.
+    sa_err (optional, m x d): a bound on |dSA| when the two runs' sketches
+    are not bitwise equal (the Gaussian sketch, whose entries come from
+    transcendental functions); it enters H as |dSA|^T |SA| + |SA|^T |dSA|,
+    counted in full as a standard deviation."""
     n, d = A.shape
     m = SA.shape[0]
     M = _dense(A.T @ A)
@@ -133,6 +137,9 @@ def step_covariance(A, b, SA, H, x, x_next, constraint, radius):
     delta = x_next - x
     S = np.abs(SA).T @ np.abs(SA)
     v = m * U * U * ((S ** 2) @ (delta ** 2))                      # Gram
+    if sa_err is not None:
+        E = sa_err.T @ np.abs(SA)
+        v = v + ((E + E.T) ** 2) @ (delta ** 2)
     if sp.issparse(A):
         absA = abs(A)
         t2 = np.asarray(A.multiply(A).T @ (r * r)).ravel()
@@ -160,17 +167,19 @@ def step_covariance(A, b, SA, H, x, x_next, constraint, radius):
 
 
 def ihs_budget(A, b, sketches, hessians, iterates, constraint="none", radius=0.0,
-               lam=LAMBDA):
+               lam=LAMBDA, sketch_errs=None):
     """Budgets for the iterates x^1 .. x^N of one IHS run: a list of
     (bound in ||A .||, bound in ||.||_2). sketches[t] and hessians[t] are the
-    oracle's S_t A and H_t, iterates the oracle's x^0 .. x^N."""
+    oracle's S_t A and H_t, iterates the oracle's x^0 .. x^N; sketch_errs[t]
+    (optional) bounds |dSA| of step t (see step_covariance)."""
     d = len(iterates[0])
     M = _dense(A.T @ A)
     C = np.zeros((d, d))
     out = []
     for t in range(len(hessians)):
         x, xn = iterates[t], iterates[t + 1]
-        P, T, Xi = step_covariance(A, b, sketches[t], hessians[t], x, xn, constraint, radius)
+        P, T, Xi = step_covariance(A, b, sketches[t], hessians[t], x, xn, constraint, radius,
+                                   None if sketch_errs is None else sketch_errs[t])
         C = T @ C @ T.T + 2.0 * (P @ Xi @ P.T) + np.diag(2.0 * U * U * xn * xn)
         C = 0.5 * (C + C.T)
         out.append((lam * np.sqrt(max(np.trace(M @ C), 0.0)),
