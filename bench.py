@@ -190,6 +190,8 @@ def main():
     gather_avg_ms = gather_ms / max(launches, 1)
     achieved = fused_bytes / (gather_avg_ms * 1e-3) / 1e9
     traffic = recorded_traffic(fused_bytes)
+    # the rate at which this GPU reads A itself (16-byte loads over the grid)
+    ceiling = P.read_ceiling(wl.A, reps=5)
 
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "GB/s", "n_gpus": 1,
@@ -206,6 +208,8 @@ def main():
                      "traffic_vs_algorithmic": round(traffic / fused_bytes, 4)
                      if traffic else None,
                      "kernel": "k_gather (fused sketch + gradient)",
+                     "read_ceiling_GBs": round(ceiling, 1),
+                     "frac_of_read_ceiling": round(achieved / ceiling, 4),
                      "bytes_per_launch": fused_bytes, "avg_ms": round(gather_avg_ms, 4),
                      "launches": launches},
     }
@@ -374,6 +378,13 @@ def main():
         # (20000 x 50, CountSketch m = 500, 10 IHS steps): the oracle's time and
         # the library's on the same inputs
         out["cpu_baseline"]["ols_20000x50_m500_10steps"] = ols_small(P, W)
+        # the full-size constrained solves against the oracle's x_OPT
+        acc = oracle_accuracy()
+        if acc:
+            out["cpu_baseline"]["accuracy_of_full_size_solves"] = acc
+            for key, v in acc.items():
+                out.get("components", {}).get(key, {}).update(
+                    {"err_A_vs_oracle": v["err_A"], "err_2_vs_oracle": v["err_2"]})
 
     out["gen_s"] = round(t_gen, 2)
     print(json.dumps(out), flush=True)
@@ -431,6 +442,74 @@ def _apply_entry(P, M, spec, n, d, nbytes_in, reps=5):
             "frac_of_hbm_peak": round(alg / ms / 1e6 / HBM_PEAK_GBS, 4)}
 
 
+# (row key, constraint, radius or lambda, A^T A, A^T b, the library's x) of
+# the full-size constrained solves, compared with the oracle's x_OPT in the
+# CPU-baseline leg
+ACCURACY = []
+
+
+def kkt_l1_ball(A, b, x, tau):
+    """Violation of the optimality conditions of min 1/2||Ax - b||^2 over
+    ||x||_1 <= tau at x, relative to max|A^T b| (a property that holds at any
+    size): with g = A^T (b - A x) and mu = max|g|, g_j = mu sign(x_j) on the
+    support, |g_j| <= mu off it (true by the choice of mu),
+    mu (tau - ||x||_1) = 0, and ||x||_1 <= tau (relative to tau)."""
+    import torch
+    g = A.T @ (b - A @ x)
+    on = x != 0
+    mu = float(g.abs().max())
+    l1 = float(x.abs().sum())
+    scale = float((A.T @ b).abs().max())
+    stat = float((g[on] - mu * torch.sign(x[on])).abs().max()) if bool(on.any()) else mu
+    return (stat + mu * abs(tau - l1)) / scale + max(0.0, l1 - tau) / tau
+
+
+def kkt_l2_ball(AtA, Atb, x, r):
+    """Violation of the optimality conditions of min 1/2||Ax - b||^2 over
+    ||x||_2 <= r at x: g = A^T b - A^T A x equals mu x with
+    mu = g^T x / ||x||^2 >= 0, mu (r - ||x||) = 0 and ||x|| <= r; the first
+    two relative to ||A^T b||, the last to r."""
+    import numpy as np
+    g = Atb - AtA @ x
+    nx = float(np.linalg.norm(x))
+    mu = max(0.0, float(g @ x) / (nx * nx)) if nx > 0 else 0.0
+    scale = float(np.linalg.norm(Atb))
+    return float((np.linalg.norm(g - mu * x) + mu * nx * abs(r - nx) / max(r, 1e-300)) / scale
+                 + max(0.0, nx - r) / r)
+
+
+def dense_sketch_times(P, M, n, d, m, cs_ms):
+    """The SRHT and Gaussian sketches (Sec. 2) on the same matrix and m as
+    the CountSketch row: time, rate and the CountSketch speedup the paper
+    reports (about 10x on dense data)."""
+    import torch
+    out = {}
+    for kind in ("srht", "gaussian"):
+        spec = P.SketchSpec(m, kind=kind, seed=9)
+        opts = P.options(m, kind=kind, seed=9)
+        ws = torch.empty(P.workspace_size(M, opts), dtype=torch.uint8, device="cuda")
+        SA = torch.empty(m, d, dtype=torch.float64, device="cuda")
+        ms = _event_ms(lambda: P.sketch_apply(M, spec, out=SA, ws=ws), reps=3)
+        row = {"ms": round(ms, 4), "countsketch_speedup": round(ms / cs_ms, 2)}
+        if kind == "srht":
+            N = 1 << max(0, (n - 1).bit_length())
+            passes = max(1, -(-((N - 1).bit_length()) // 8))
+            moved = n * d * 8 + (2 * passes - 1) * N * d * 8 + N * d * 8 + m * d * 16
+            row.update({"padded_rows": N, "passes": passes,
+                        "hadamard_pass_bytes": moved,
+                        "GB/s_moved": round(moved / ms / 1e6, 1),
+                        "frac_of_hbm_peak": round(moved / ms / 1e6 / HBM_PEAK_GBS, 4)})
+        else:
+            fl = 2 * m * n * d
+            tf = fl / ms / 1e9
+            row.update({"flop": fl, "TFLOP/s": round(tf, 2),
+                        "mfma_frac": round(tf / PEAK_TFLOPS["float64"], 4)})
+        out[kind] = row
+        del ws, SA
+        torch.cuda.empty_cache()
+    return out
+
+
 def components(P, W, wl4):
     """Per-row timings of the hot path at the workload shapes: sketch apply
     (dense CountSketch/SJLT, CSR), gradient pass, Gram (FP64 and mixed, MFMA),
@@ -482,18 +561,29 @@ def components(P, W, wl4):
     for kind, s in (("countsketch", 1), ("sjlt", 4)):
         out[f"a3_sketch_dense_2^20x256_{kind}_s{s}_m4096"] = _apply_entry(
             P, M2, P.SketchSpec(4096, s, kind, seed=9), n2, d2, n2 * d2 * 8)
+    out["f2_dense_sketches_2^20x256_m4096"] = dense_sketch_times(
+        P, M2, n2, d2, 4096, out["a3_sketch_dense_2^20x256_countsketch_s1_m4096"]["ms"])
     SA2 = P.sketch_apply(M2, P.SketchSpec(4096, seed=3))
     H2 = P.gram(SA2, 4096)
     g2, _, _ = P.gradient(M2, wl2.b, torch.zeros(1, d2, dtype=torch.float64, device="cuda"))
     x0 = torch.zeros(1, d2, dtype=torch.float64, device="cuda")
     ms = _wall_ms(lambda: P.qp_step(H2, g2, x0, constraint="l1", radius=wl2.radius))
     out["a7_qp_l1_d256_lasso"] = {"ms_wall": round(ms, 4)}
+    # A^T A and A^T b in float64 (torch), for the accuracy of the full-size
+    # solves against the oracle's x_OPT (formed in the CPU-baseline leg)
+    AtA2 = (wl2.A.T @ wl2.A).cpu().numpy()
+    Atb2 = (wl2.A.T @ wl2.b).cpu().numpy()
     for kind, s in (("countsketch", 1), ("sjlt", 4)):
         o = P.options(4096, s=s, kind=kind, seed=wl2.sketch_seed, max_iter=wl2.iters,
                       constraint="l1", radius=wl2.radius)
-        ms = _wall_ms(lambda: P.solve(M2, wl2.b, o), reps=1)
-        out[f"a8_solve_lasso_2^20x256_l1_{kind}_s{s}_{wl2.iters}steps"] = {
-            "ms_wall": round(ms, 3), "ms_per_step": round(ms / wl2.iters, 4)}
+        res = {}
+        ms = _wall_ms(lambda: res.update(r=P.solve(M2, wl2.b, o)), reps=1)
+        xl = res["r"].x[0]
+        key = f"a8_solve_lasso_2^20x256_l1_{kind}_s{s}_{wl2.iters}steps"
+        out[key] = {"ms_wall": round(ms, 3), "ms_per_step": round(ms / wl2.iters, 4),
+                    "kkt_residual_rel": kkt_l1_ball(wl2.A, wl2.b, xl, wl2.radius),
+                    "qp_unpolished": int(res["r"].report.qp_unpolished)}
+        ACCURACY.append((key, "l1", wl2.radius, AtA2, Atb2, xl.cpu().numpy()))
     # the penalised form of the experiments, lambda = 5 (same data): time and
     # the optimality residual of the last iterate for the full problem,
     # max_j | |A^T (b - A x)|_j - lambda sign-condition | / max |A^T b|
@@ -506,10 +596,12 @@ def components(P, W, wl4):
     gl = wl2.A.T @ (wl2.b - wl2.A @ xl)
     on = xl != 0
     viol = torch.where(on, (gl - lam * torch.sign(xl)).abs(), (gl.abs() - lam).clamp(min=0))
-    out[f"a8_solve_lasso_penalised_2^20x256_lambda5_countsketch_{wl2.iters}steps"] = {
+    key = f"a8_solve_lasso_penalised_2^20x256_lambda5_countsketch_{wl2.iters}steps"
+    out[key] = {
         "ms_wall": round(ms, 3), "ms_per_step": round(ms / wl2.iters, 4),
         "support": int(on.sum()),
         "kkt_residual_rel": float(viol.max() / (wl2.A.T @ wl2.b).abs().max())}
+    ACCURACY.append((key, "l1_penalty", lam, AtA2, Atb2, xl.cpu().numpy()))
     del wl2, M2, SA2
     torch.cuda.empty_cache()
     # ---- CSR ridge (2^22 x 1024, density 1e-3): CSR apply, l2 QP, l2 solve
@@ -529,12 +621,20 @@ def components(P, W, wl4):
     x3 = torch.zeros(1, wl3.d, dtype=torch.float64, device="cuda")
     ms = _wall_ms(lambda: P.qp_step(H3, g3, x3, constraint="l2", radius=wl3.radius))
     out["a7_qp_l2_d1024_csr"] = {"ms_wall": round(ms, 4)}
+    import scipy.sparse as sps
+    A3 = sps.csr_matrix((wl3.data, wl3.indices, wl3.indptr), shape=(wl3.n, wl3.d))
+    AtA3 = (A3.T @ A3).toarray()
+    Atb3 = np.asarray(A3.T @ wl3.b).ravel()
     for gin, gacc in (("float64", "float64"), ("bfloat16", "float32")):
         o = P.options(8192, seed=wl3.sketch_seed, max_iter=wl3.iters, constraint="l2",
                       radius=wl3.radius, gram_in=gin, gram_acc=gacc)
-        ms = _wall_ms(lambda: P.solve(M3, b3, o), reps=1)
-        out[f"a8_solve_csr_2^22x1024_l2_{gin}_gram_{wl3.iters}steps"] = {
-            "ms_wall": round(ms, 3), "ms_per_step": round(ms / wl3.iters, 4)}
+        res = {}
+        ms = _wall_ms(lambda: res.update(r=P.solve(M3, b3, o)), reps=1)
+        x3 = res["r"].x[0].cpu().numpy()
+        key = f"a8_solve_csr_2^22x1024_l2_{gin}_gram_{wl3.iters}steps"
+        out[key] = {"ms_wall": round(ms, 3), "ms_per_step": round(ms / wl3.iters, 4),
+                    "kkt_residual_rel": kkt_l2_ball(AtA3, Atb3, x3, wl3.radius)}
+        ACCURACY.append((key, "l2", wl3.radius, AtA3, Atb3, x3))
     del wl3, M3, SA3, rp, ci, va, b3
     torch.cuda.empty_cache()
     # ---- ragged batch (64 problems, d = 64): adjoint, autograd
@@ -585,7 +685,8 @@ def sketch_error_sweep(P, W, trials=10, gammas=(1, 2, 5, 10, 20)):
                  col_idx=torch.from_numpy(wl.indices).cuda(),
                  values=torch.from_numpy(wl.data).cuda(), n=wl.n, d=wl.d)
     rows = []
-    for kind, s in (("countsketch", 1), ("sjlt", 4)):
+    gauss_pred = math.sqrt(rn.sum() ** 2 + (AtA ** 2).sum())
+    for kind, s in (("countsketch", 1), ("sjlt", 4), ("srht", 1), ("gaussian", 1)):
         for gm in gammas:
             m = gm * wl.d
             opts = P.options(m, s, kind)
@@ -598,13 +699,19 @@ def sketch_error_sweep(P, W, trials=10, gammas=(1, 2, 5, 10, 20)):
                                        reps=1, warm=1))
                 H = P.gram(SA, m)[0]
                 errs.append(float(torch.linalg.norm(H - AtA_dev)) / nrm)
+            pred = (math.sqrt(e2m / m) / nrm if kind in ("countsketch", "sjlt")
+                    else gauss_pred / math.sqrt(m) / nrm if kind == "gaussian" else None)
             rows.append({"sketch": kind, "s": s, "m": m, "gamma": gm,
                          "err_mean": float(np.mean(errs)), "err_std": float(np.std(errs)),
                          "err_rms": float(np.sqrt(np.mean(np.square(errs)))),
-                         "err_predicted": math.sqrt(e2m / m) / nrm,
+                         "err_predicted": pred,
                          "sketch_ms_median": round(float(np.median(times)), 4)})
+    # the sparse-data speedup the paper reports (about 100x): sketch time of
+    # each dense sketch over CountSketch's at m = 10 d
+    t10 = {r["sketch"]: r["sketch_ms_median"] for r in rows if r["gamma"] == 10}
+    speed = {k: round(t10[k] / t10["countsketch"], 2) for k in ("sjlt", "srht", "gaussian")}
     return {"data": "W8A-shaped: 49749 x 300, %d nonzeros, binary" % int(wl.indptr[-1]),
-            "trials": trials, "rows": rows}
+            "trials": trials, "rows": rows, "time_over_countsketch_at_m_10d": speed}
 
 
 def cpu_baseline(wl, m, budget_s=15.0):
@@ -642,6 +749,28 @@ def cpu_baseline(wl, m, budget_s=15.0):
             "sample": f"{steps} full IHS steps (sketch, Gram, gradient, QP) on the first "
                       f"{rows} of {wl.n} rows, m={m}; {per * 1e3:.1f} ms per step",
             "cpu_count": len(os.sched_getaffinity(0))}
+
+
+def oracle_accuracy():
+    """err_A = sqrt((x - x_OPT)^T A^T A (x - x_OPT)) / sqrt(x_OPT^T A^T A x_OPT)
+    (Def. A.1) and the Euclidean error of each full-size constrained solve,
+    x_OPT from the oracle's QP solvers on A^T A and A^T b formed in float64."""
+    import numpy as np
+    from oracle import ihs as O
+    solve = {"l1": O.qp_l1, "l2": O.qp_l2, "l1_penalty": O.qp_l1_penalty}
+    out = {}
+    cache = {}
+    for key, cons, rad, AtA, Atb, x in ACCURACY:
+        ck = (cons, rad, id(AtA))
+        if ck not in cache:
+            t0 = time.perf_counter()
+            cache[ck] = (solve[cons](AtA, Atb, rad), time.perf_counter() - t0)
+        xo, secs = cache[ck]
+        e = x - xo
+        out[key] = {"err_A": float(np.sqrt(max(e @ AtA @ e, 0.0) / (xo @ AtA @ xo))),
+                    "err_2": float(np.linalg.norm(e) / np.linalg.norm(xo)),
+                    "oracle_qp_s": round(secs, 3)}
+    return out
 
 
 def ols_small(P, W):

@@ -376,6 +376,15 @@ ihs_status ihs_solution_grads(const ihs_matrix* A, const double* b,
 void ihs_profile_enable(int32_t on);
 ihs_status ihs_profile_read(int64_t* launches, double* total_ms);
 
+/* The read ceiling a pass over A is measured against: reads the `bytes`
+ * (rounded down to a multiple of 16) of the device buffer `buf` (16-byte
+ * aligned) once per repetition, each of up to 8192 workgroups streaming one
+ * contiguous chunk with eight 16-byte loads per lane in flight, and returns the average milliseconds per read from HIP events
+ * on `stream` (after one untimed read). The buffer is not modified while it
+ * holds finite values. Synchronises; host only otherwise. */
+ihs_status ihs_profile_read_ceiling(const void* buf, int64_t bytes, int32_t reps,
+                                    double* ms_per_read, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

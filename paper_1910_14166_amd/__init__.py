@@ -35,7 +35,7 @@ EXPORTS = ["ihs_status_string", "ihs_last_hip_error", "ihs_sketch_hash", "ihs_wo
            "ihs_sketch_apply", "ihs_sketch_apply_static", "ihs_sketch_adjoint", "ihs_gram_workspace_size",
            "ihs_gram", "ihs_gradient", "ihs_qp_workspace_size", "ihs_qp_step",
            "ihs_solve", "ihs_adjoint_solve", "ihs_solution_grads",
-           "ihs_profile_enable", "ihs_profile_read"]
+           "ihs_profile_enable", "ihs_profile_read", "ihs_profile_read_ceiling"]
 
 
 class IHSError(RuntimeError):
@@ -114,6 +114,7 @@ def load(path: Optional[str] = None):
         "ihs_solution_grads": (i32, [M, vp, vp, vp, vp, vp, i64, vp]),
         "ihs_profile_enable": (None, [i32]),
         "ihs_profile_read": (i32, [ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double)]),
+        "ihs_profile_read_ceiling": (i32, [vp, i64, i32, ctypes.POINTER(ctypes.c_double), vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -426,3 +427,12 @@ def profile_read():
     ms = ctypes.c_double()
     _check(load().ihs_profile_read(ctypes.byref(n), ctypes.byref(ms)), "ihs_profile_read")
     return int(n.value), float(ms.value)
+
+
+def read_ceiling(buf, reps=5):
+    """GB/s of reading the device tensor `buf` once (the library's read probe)."""
+    ms = ctypes.c_double()
+    nbytes = buf.numel() * buf.element_size() // 16 * 16
+    _check(load().ihs_profile_read_ceiling(_ptr(buf), nbytes, int(reps), ctypes.byref(ms),
+                                           _stream()), "ihs_profile_read_ceiling")
+    return nbytes / (ms.value * 1e-3) / 1e9

@@ -1292,6 +1292,39 @@ ihs_status ihs_solution_grads(const ihs_matrix* A, const double* b, const double
   return IHS_OK;
 }
 
+ihs_status ihs_profile_read_ceiling(const void* buf, int64_t bytes, int32_t reps,
+                                    double* ms_per_read, hipStream_t stream) {
+  if (!buf || bytes < 16 || reps < 1 || !ms_per_read ||
+      reinterpret_cast<uintptr_t>(buf) % 16 != 0)
+    return IHS_ERR_INVALID_ARG;
+  clear_stale_error();
+  // the sink is never written for finite data; the buffer's first element serves
+  double* sink = const_cast<double*>(static_cast<const double*>(buf));
+  hipEvent_t a = nullptr, b = nullptr;
+  if (hip_failed(hipEventCreate(&a))) return IHS_ERR_HIP;
+  if (hip_failed(hipEventCreate(&b))) {
+    (void)hipEventDestroy(a);
+    return IHS_ERR_HIP;
+  }
+  ihs_status s = IHS_OK;
+  if (hip_failed(launch_read_probe(buf, bytes / 16 * 16, sink, stream)) ||  // warm
+      hip_failed(hipEventRecord(a, stream))) {
+    s = IHS_ERR_HIP;
+  } else {
+    for (int32_t r = 0; r < reps && s == IHS_OK; ++r)
+      if (hip_failed(launch_read_probe(buf, bytes / 16 * 16, sink, stream))) s = IHS_ERR_HIP;
+    float ms = 0.f;
+    if (s == IHS_OK && (hip_failed(hipEventRecord(b, stream)) ||
+                        hip_failed(hipEventSynchronize(b)) ||
+                        hip_failed(hipEventElapsedTime(&ms, a, b))))
+      s = IHS_ERR_HIP;
+    *ms_per_read = s == IHS_OK ? (double)ms / reps : 0.0;
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return s;
+}
+
 void ihs_profile_enable(int32_t on) {
   std::lock_guard<std::mutex> lk(g_prof.mu);
   for (auto& e : g_prof.ev) {

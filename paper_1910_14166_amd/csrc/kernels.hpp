@@ -123,6 +123,9 @@ struct DenseSketchArgs {
 size_t dense_sketch_workspace_bytes(int32_t kind, int64_t m, int64_t n, int64_t d, bool csr);
 hipError_t launch_dense_sketch(const DenseSketchArgs& a, hipStream_t st);
 
+// Reads `bytes` (a multiple of 16, 16-byte aligned) once: the read ceiling.
+hipError_t launch_read_probe(const void* buf, int64_t bytes, double* sink, hipStream_t st);
+
 // Natural-order gradient pass over dense rows: segments of seg_rows rows.
 hipError_t launch_gradient_rows(const ProbInfo* probs, int32_t batch, int32_t total_seg,
                                 int32_t seg_rows, const void* A, int32_t a_dtype,
