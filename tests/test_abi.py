@@ -172,6 +172,16 @@ def test_static_sketch_apply_refuses_oversize_before_launch(lib):
                                        None) == P.ERR_INVALID_ARG
 
 
+def test_read_ceiling_validation(lib):
+    ms = ctypes.c_double()
+    assert lib.ihs_profile_read_ceiling(None, 1 << 20, 1, ctypes.byref(ms), None) == \
+        P.ERR_INVALID_ARG
+    assert lib.ihs_profile_read_ceiling(ctypes.c_void_p(1 << 20), 8, 1, ctypes.byref(ms),
+                                        None) == P.ERR_INVALID_ARG
+    assert lib.ihs_profile_read_ceiling(ctypes.c_void_p((1 << 20) + 8), 1 << 20, 1,
+                                        ctypes.byref(ms), None) == P.ERR_INVALID_ARG
+
+
 def test_hash_validation(lib):
     sk = P.Sketch_t(P.SJLT, 4, 10, 0, 0)   # 4 does not divide 10
     assert lib.ihs_sketch_hash(ctypes.byref(sk), 10, 0, ctypes.c_void_p(8), ctypes.c_void_p(8),
