@@ -11,6 +11,7 @@
 
 #include "../../include/ihs.h"
 #include "kernels.hpp"
+#include "rowdot.hpp"
 
 using namespace ihs;
 
@@ -481,10 +482,11 @@ struct SolveBuffers {
   double* dsk = nullptr;     // the Gaussian or SRHT sketch's own scratch
 };
 
-// Above this width the overlapped schedule forms H^{-1} on the second stream
-// and the critical path only applies it; below, the triangular solves run on
-// the main stream directly.
-constexpr int64_t kInverseMinD = 89;
+// From kQpInverseMinD (rowdot.hpp) on, the overlapped schedule forms H^{-1}
+// on the second stream and the critical path only applies it; below, the
+// triangular solves run on the main stream directly. One constant serves the
+// standalone step, the ball steps and both schedules.
+constexpr int64_t kInverseMinD = kQpInverseMinD;
 
 int32_t gram_in_of(const ihs_options* o) { return o ? o->gram_in : IHS_F64; }
 int32_t gram_acc_of(const ihs_options* o) { return o ? o->gram_acc : IHS_F64; }

@@ -1,5 +1,5 @@
-// The sketched Hessian H = (SA)^T (SA) (Sec. 1, the T_QP term; App. A.1.1,
-// "O(m d^2) to compute the approximate Hessian") on gfx950 matrix cores.
+// The sketched Hessian H = (SA)^T (SA) (Sec. 1, the T_QP term; App. A.1.1:
+// forming it costs O(m d^2)) on gfx950 matrix cores.
 //
 // Two wavefronts share each 32 x 32 tile of the upper triangle of H (16 rows
 // each), for a contiguous slice of the m rows of SA (split-K). Operands come straight from

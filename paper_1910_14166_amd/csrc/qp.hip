@@ -1,6 +1,6 @@
 // The small d x d quadratic program of Eq.(2) (Sec. 1: T_solve = O(d^3);
-// App. A.1.1, "Solving the QP takes poly(d)") and the fixed-order reduction of
-// the gradient partials produced by the row passes.
+// App. A.1.1 on the cost of the QP, polynomial in d) and the fixed-order
+// reduction of the gradient partials produced by the row passes.
 //
 // Unconstrained step: x^{t+1} = x^t + H^{-1} g with H = L L^T.
 //  * Right-looking blocked Cholesky, 64-column panels: per panel one launch

@@ -579,7 +579,6 @@ __global__ __launch_bounds__(kQpThreads) void k_qp_l1(
   if (tid < d) xout[tid] = xi;
 }
 
-// c = H x + g per problem (one wavefront per row).
 // out = x + H^{-1} g per problem, one wavefront per row: the unconstrained
 // step as the wide unconstrained QP forms it. Keeps x after a failure.
 __global__ __launch_bounds__(256) void k_apply_inverse(const double* __restrict__ Hinv, int64_t d,
@@ -598,6 +597,8 @@ __global__ __launch_bounds__(256) void k_apply_inverse(const double* __restrict_
   const double s = row_dot<false>(Hinv + e * d, g + (int64_t)p * d, d, lane);
   if (lane == 0) out[e] = x[e] + s;
 }
+
+// c = H x + g per problem (one wavefront per row).
 __global__ __launch_bounds__(256) void k_form_c(const double* __restrict__ H, int64_t d,
                                                 const double* __restrict__ x,
                                                 const double* __restrict__ g, double* c) {

@@ -198,3 +198,15 @@ def test_last_hip_error_before_any_failure(lib):
     assert lib.ihs_last_hip_error(ctypes.byref(code)) == b"hipSuccess"
     assert code.value == 0
     assert lib.ihs_last_hip_error(None) == b"hipSuccess"
+
+
+def test_inverse_threshold_stated_once():
+    """The width from which the steps apply an explicit inverse is one
+    constant in the HIP sources, and the tests' copy of it matches."""
+    from conftest import INVERSE_MIN_D
+    csrc = os.path.join(ROOT, "paper_1910_14166_amd", "csrc")
+    defs = []
+    for name in os.listdir(csrc):
+        text = open(os.path.join(csrc, name)).read()
+        defs += re.findall(r"constexpr\s+int64_t\s+\w*InverseMinD\s*=\s*(\d+)\s*;", text)
+    assert defs == [str(INVERSE_MIN_D)]

@@ -18,6 +18,7 @@ import pytest
 
 import rounding_budget as RB
 import workloads as W
+from conftest import INVERSE_MIN_D
 from oracle import ihs as O
 from oracle import sketch as OS
 
@@ -111,7 +112,7 @@ def test_qp_l1_inactive_ball_is_the_unconstrained_step(gpu_lib, d):
     tau = 10 * np.abs(free).sum()
     for cons in ("l1", "l2"):
         out = host(P.qp_step(dev(H), dev(gv), dev(x), constraint=cons, radius=tau))
-        if cons == "l2" or d < 89:
+        if cons == "l2" or d < INVERSE_MIN_D:
             assert np.array_equal(out, free), cons
         else:
             assert np.linalg.norm(out - free) <= 1e-12 * 1e2 * np.linalg.norm(free - x), cons

@@ -49,8 +49,8 @@ CASES = [  # n, d, m, s
     (900, 1, 32, 2),         # single column, SJLT s=2 (scale after the sum)
     (4000, 1024, 128, 1),    # widest dense path
     (1500, 600, 96, 3),      # 600 columns (paired loads), s = 3
-    (40000, 8, 16384, 1),    # largest sketch: two 7-bit radix digits
-    (300, 5, 1, 1),          # one sketch row: no radix bits
+    (40000, 8, 16384, 1),    # largest sketch: a 64 KiB LDS histogram per sort tile
+    (300, 5, 1, 1),          # one sketch row: every row in one bucket
     (70000, 16, 4096, 4),    # many sort tiles, SJLT over 4 blocks
     (600, 20, 16, 16),       # SJLT with one bucket per block: every row in every sketch row
 ]
