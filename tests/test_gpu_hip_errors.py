@@ -15,11 +15,20 @@ pytestmark = pytest.mark.gpu
 
 
 @pytest.fixture(scope="module")
-def hip():
-    path = "/opt/rocm/lib/libamdhip64.so"
-    if not os.path.exists(path):
-        pytest.skip("HIP runtime library not found")
-    h = ctypes.CDLL(path)
+def hip(gpu_lib):
+    """The HIP runtime this process already uses (the one torch and the
+    library share), found in the process's memory map: loading another copy
+    from elsewhere would start a second runtime."""
+    import torch
+    torch.zeros(1, device="cuda")
+    path = None
+    with open("/proc/self/maps") as f:
+        for line in f:
+            if "libamdhip64.so" in line:
+                path = line.split()[-1]
+                break
+    assert path is not None, "no HIP runtime mapped"
+    h = ctypes.CDLL(path, mode=os.RTLD_NOLOAD | ctypes.RTLD_GLOBAL)
     h.hipGetLastError.restype = ctypes.c_int
     h.hipDeviceSynchronize.restype = ctypes.c_int
     return h
