@@ -1,12 +1,13 @@
 // The sketched Hessian H = (SA)^T (SA) (Sec. 1, the T_QP term; App. A.1.1:
 // forming it costs O(m d^2)) on gfx950 matrix cores.
 //
-// Two wavefronts share each 32 x 32 tile of the upper triangle of H (16 rows
-// each), for a contiguous slice of the m rows of SA (split-K). Operands come straight from
-// L2: for a 16 x 16 x 4 product a lane supplies SA[k0 + lane/16][col0 + lane%16],
-// so every operand load is four 128-byte row segments. Partial tiles are
-// summed over the slices in a fixed order and mirrored into both triangles,
-// so H is exactly symmetric and bitwise reproducible.
+// One workgroup owns a tile of the upper triangle of H (64 x 64 on the FP64
+// matrix cores, 128 x 128 when accumulating in FP32) for a contiguous slice
+// of the m rows of SA (split-K). Both operand panels of a stage are staged
+// through LDS with coalesced row loads and reused by all four wavefronts;
+// diagonal tiles stage one panel. Partial tiles are summed over the slices
+// in a fixed order and mirrored into both triangles, so H is exactly
+// symmetric and bitwise reproducible.
 #include <algorithm>
 
 #include "kernels.hpp"
@@ -17,38 +18,60 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef short bf16x8 __attribute__((ext_vector_type(8)));
 
-constexpr int kTile = 32;
+// Output tile edge: 64 for the FP64 and FP32 products (16 x 16 x 4), 128 for
+// the BF16 ones (16 x 16 x 32, eight times the work per operand load, so a
+// tile must reuse each staged operand more to keep the matrix cores fed).
+constexpr int kTileF64 = 64;
+constexpr int kTileF32 = 64;
+constexpr int kTileBf16 = 128;
 
 struct GramPlan {
   int64_t m, d, ld;
-  int32_t batch, ntile, ntri, splits;
+  int32_t batch, tile, ntile, ntri, splits;
   int64_t kchunk;
 };
 
-static GramPlan make_gram_plan(int64_t m, int64_t d, int64_t ld, int32_t batch) {
+static int tile_of(int32_t in_dtype) { return in_dtype == 2 ? kTileBf16 : kTileF64; }
+
+// Workgroups of each kernel that fit on one CU at once (LDS and registers):
+// the slices are sized so that all workgroups run in one round, since a
+// second, partly filled round would double the time.
+constexpr int kCUs = 256;
+
+static GramPlan make_gram_plan(int64_t m, int64_t d, int64_t ld, int32_t batch, int32_t acc,
+                               int32_t in) {
   GramPlan g;
   g.m = m;
   g.d = d;
   g.ld = ld;
   g.batch = batch;
-  g.ntile = (int32_t)((d + kTile - 1) / kTile);
+  g.tile = tile_of(in);
+  g.ntile = (int32_t)((d + g.tile - 1) / g.tile);
   g.ntri = g.ntile * (g.ntile + 1) / 2;
-  const int64_t waves = (int64_t)batch * g.ntri;
-  int64_t splits = (2048 + waves - 1) / waves;
-  const int64_t max_splits = std::max<int64_t>(1, (m + 63) / 64);
-  splits = std::min<int64_t>(std::max<int64_t>(splits, 1), max_splits);
-  splits = std::min<int64_t>(splits, 64);
+  const int64_t slots = (int64_t)kCUs * 4;
+  const int64_t tiles = (int64_t)batch * g.ntri;
+  int64_t splits = std::max<int64_t>(1, slots / tiles);
+  splits = std::min<int64_t>(splits, std::max<int64_t>(1, m / 128));  // >= 128 rows a slice
+  splits = std::max<int64_t>(1, std::min<int64_t>(splits, 64));
   int64_t kc = (m + splits - 1) / splits;
-  kc = (kc + 15) / 16 * 16;
-  g.splits = (int32_t)((m + kc - 1) / kc);
-  if (g.splits < 1) g.splits = 1;
-  g.kchunk = kc;
+  kc = (kc + 31) / 32 * 32;
+  g.kchunk = std::max<int64_t>(kc, 32);
+  g.splits = (int32_t)std::max<int64_t>(1, (m + g.kchunk - 1) / g.kchunk);
   return g;
 }
 
-size_t gram_partials_bytes(int64_t m, int64_t d, int32_t batch, int32_t, int32_t) {
-  const GramPlan g = make_gram_plan(m, d, d, batch);
-  return (size_t)batch * g.ntri * g.splits * kTile * kTile * sizeof(double);
+// BF16 inputs are first copied into rows of eight: element (k, c) of a
+// problem's m x d block at ((k / 8) * d + c) * 8 + k % 8, zero-padded to a
+// multiple of 8 rows, so a lane's eight consecutive k of one column (the
+// operand of a 16 x 16 x 32 product) are one 16-byte load.
+__host__ __device__ __forceinline__ int64_t bf16_rows8(int64_t m) { return (m + 7) / 8 * 8; }
+
+size_t gram_partials_bytes(int64_t m, int64_t d, int32_t batch, int32_t in, int32_t acc) {
+  const GramPlan g = make_gram_plan(m, d, d, batch, acc, in);
+  const size_t es = acc == 0 ? sizeof(double) : sizeof(float);
+  size_t bytes = (size_t)batch * g.ntri * g.splits * g.tile * g.tile * es;
+  if (in == 2) bytes = (bytes + 255) / 256 * 256 + (size_t)batch * bf16_rows8(m) * d * 2;
+  return bytes;
 }
 
 __device__ __forceinline__ void tri_index(int t, int& ti, int& tj) {
@@ -67,213 +90,403 @@ __device__ __forceinline__ double to_f64<double>(double v) { return v; }
 template <>
 __device__ __forceinline__ double to_f64<float>(float v) { return (double)v; }
 
-// Wavefront w = ((p * ntri + t) * splits + split) * 2 + half computes rows
-// [16 half, 16 half + 16) of 32 x 32 tile t over its slice of the m rows.
-// Two accumulators and a few k-steps of operands keep the register footprint
-// small enough to run beside the memory-bound pass.
-__device__ __forceinline__ void gram_wave_coords(const GramPlan& G, int64_t w, int& p, int& t,
-                                                 int& split, int& half) {
-  half = (int)(w & 1);
-  const int64_t q = w >> 1;
+// Workgroup -> (problem, upper-triangle tile, slice of the m rows).
+__device__ __forceinline__ void gram_coords(const GramPlan& G, int& p, int& ti, int& tj,
+                                            int& split) {
+  const int64_t q = blockIdx.x;
   split = (int)(q % G.splits);
-  t = (int)((q / G.splits) % G.ntri);
+  const int t = (int)((q / G.splits) % G.ntri);
   p = (int)(q / ((int64_t)G.splits * G.ntri));
+  tri_index(t, ti, tj);
 }
 
-// FP64 matrix cores; F64 inputs, or F32 inputs widened exactly to F64.
+// ---------------------------------------------------------------------------
+// FP64 matrix cores (16 x 16 x 4), F64 inputs or F32 inputs widened exactly.
+// One workgroup of four wavefronts owns a 64 x 64 tile of H for one slice of
+// rows; each wavefront a 32 x 32 quarter (2 x 2 products). The two 16 x 64
+// operand panels of a stage go through LDS (coalesced row loads), double
+// buffered: the next stage's loads are issued before the current stage's
+// products, and written to the other buffer after them.
+// ---------------------------------------------------------------------------
+constexpr int kKcF64 = 16;            // rows per stage
+constexpr int kPadF64 = kTileF64 + 1; // LDS row pitch (doubles)
+
 template <typename TI>
-__global__ __launch_bounds__(256, 8) void k_gram_f64(const TI* __restrict__ SA, GramPlan G,
-                                                     double* __restrict__ part) {
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t w = (int64_t)blockIdx.x * 4 + wv;
-  const int64_t total = (int64_t)G.batch * G.ntri * G.splits * 2;
-  if (w >= total) return;
-  int p, t, split, half;
-  gram_wave_coords(G, w, p, t, split, half);
-  int ti, tj;
-  tri_index(t, ti, tj);
-  const int64_t i0 = (int64_t)ti * kTile + 16 * half, j0 = (int64_t)tj * kTile;
+__global__ __launch_bounds__(256, 4) void k_gram_f64(const TI* __restrict__ SA, GramPlan G,
+                                                  double* __restrict__ part) {
+  __shared__ double As[2][kKcF64][kPadF64];
+  __shared__ double Bs[2][kKcF64][kPadF64];
+  int p, ti, tj, split;
+  gram_coords(G, p, ti, tj, split);
+  const bool diag = ti == tj;
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+  const int64_t i0 = (int64_t)ti * kTileF64, j0 = (int64_t)tj * kTileF64;
   const int64_t kb = (int64_t)split * G.kchunk;
   const int64_t ke = min(G.m, kb + G.kchunk);
-  const int r = lane & 15, kk = lane >> 4;
   const TI* base = SA + (int64_t)p * G.m * G.ld;
-  const bool ci = i0 + r < G.d, cj0 = j0 + r < G.d, cj1 = j0 + 16 + r < G.d;
-  f64x4 c0 = {0, 0, 0, 0}, c1 = c0;
-  for (int64_t k = kb; k < ke; k += 8) {
-    double a[2], b0[2], b1[2];
+  // thread tid stages elements e = tid + 256 u of each 16 x 64 panel
+  constexpr int kPer = kKcF64 * kTileF64 / 256;  // 4
+  double ra[kPer], rb[kPer];
+  auto load = [&](int64_t k0) {
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int64_t row = k + 4 * q + kk;
-      const bool okr = row < ke;
-      const TI* rp = base + row * G.ld;
-      a[q] = (okr && ci) ? to_f64(rp[i0 + r]) : 0.0;
-      b0[q] = (okr && cj0) ? to_f64(rp[j0 + r]) : 0.0;
-      b1[q] = (okr && cj1) ? to_f64(rp[j0 + 16 + r]) : 0.0;
+    for (int u = 0; u < kPer; ++u) {
+      const int e = tid + 256 * u;
+      const int r = e / kTileF64, c = e % kTileF64;
+      const int64_t row = k0 + r;
+      const bool ok = row < ke;
+      ra[u] = (ok && i0 + c < G.d) ? to_f64(base[row * G.ld + i0 + c]) : 0.0;
+      if (!diag) rb[u] = (ok && j0 + c < G.d) ? to_f64(base[row * G.ld + j0 + c]) : 0.0;
     }
+  };
+  auto store = [&](int buf) {
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], b0[q], c0, 0, 0, 0);
-      c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], b1[q], c1, 0, 0, 0);
+    for (int u = 0; u < kPer; ++u) {
+      const int e = tid + 256 * u;
+      const int r = e / kTileF64, c = e % kTileF64;
+      As[buf][r][c] = ra[u];
+      if (!diag) Bs[buf][r][c] = rb[u];
     }
-  }
-  // 16 x 16 f64 output: row 4*reg + lane/16, column lane%16
-  double* out = part + (w >> 1) * (kTile * kTile) + 16 * half * kTile;
-  const int col = lane & 15, rq = lane >> 4;
+  };
+  const int wr = wv >> 1, wc = wv & 1;
+  f64x4 acc[2][2];
 #pragma unroll
-  for (int reg = 0; reg < 4; ++reg) {
-    const int row = 4 * reg + rq;
-    out[row * kTile + col] = c0[reg];
-    out[row * kTile + 16 + col] = c1[reg];
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+  const int nstage = (int)((ke - kb + kKcF64 - 1) / kKcF64);
+  if (nstage > 0) {
+    load(kb);
+    store(0);
   }
+  __syncthreads();
+  for (int sidx = 0; sidx < nstage; ++sidx) {
+    const int buf = sidx & 1;
+    if (sidx + 1 < nstage) load(kb + (int64_t)(sidx + 1) * kKcF64);
+    const double(*Bp)[kPadF64] = diag ? As[buf] : Bs[buf];
+#pragma unroll
+    for (int k4 = 0; k4 < kKcF64; k4 += 4) {
+      const int kr = k4 + (lane >> 4), cl = lane & 15;
+      double a[2], b[2];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        a[q] = As[buf][kr][32 * wr + 16 * q + cl];
+        b[q] = Bp[kr][32 * wc + 16 * q + cl];
+      }
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+          acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[y], acc[x][y], 0, 0, 0);
+    }
+    if (sidx + 1 < nstage) store(buf ^ 1);
+    __syncthreads();
+  }
+  // 16 x 16 f64 output blocks: row 4*reg + lane/16, column lane%16
+  double* out = part + ((((int64_t)p * G.ntri) + (blockIdx.x / G.splits) % G.ntri) * G.splits +
+                        split) * (kTileF64 * kTileF64);
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int reg = 0; reg < 4; ++reg) {
+        const int row = 32 * wr + 16 * x + 4 * reg + (lane >> 4);
+        const int col = 32 * wc + 16 * y + (lane & 15);
+        out[row * kTileF64 + col] = acc[x][y][reg];
+      }
 }
 
-// FP32 accumulation on the matrix cores: F32 inputs (16x16x4) or BF16
-// inputs (16x16x32, eight consecutive k per lane).
-__global__ __launch_bounds__(256, 8) void k_gram_f32_f32(const float* __restrict__ SA, GramPlan G,
-                                                         double* __restrict__ part) {
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t w = (int64_t)blockIdx.x * 4 + wv;
-  const int64_t total = (int64_t)G.batch * G.ntri * G.splits * 2;
-  if (w >= total) return;
-  int p, t, split, half;
-  gram_wave_coords(G, w, p, t, split, half);
-  int ti, tj;
-  tri_index(t, ti, tj);
-  const int64_t i0 = (int64_t)ti * kTile + 16 * half, j0 = (int64_t)tj * kTile;
+// ---------------------------------------------------------------------------
+// FP32 accumulation of F32 inputs (16 x 16 x 4 products): the FP64 kernel's
+// 64 x 64 tiles and staging, in single precision.
+// ---------------------------------------------------------------------------
+constexpr int kKcF32 = 16;
+constexpr int kPadF32 = kTileF32 + 4;
+
+__global__ __launch_bounds__(256, 4) void k_gram_f32_f32(const float* __restrict__ SA, GramPlan G,
+                                                         float* __restrict__ part) {
+  __shared__ float As[2][kKcF32][kPadF32];
+  __shared__ float Bs[2][kKcF32][kPadF32];
+  int p, ti, tj, split;
+  gram_coords(G, p, ti, tj, split);
+  const bool diag = ti == tj;
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+  const int64_t i0 = (int64_t)ti * kTileF32, j0 = (int64_t)tj * kTileF32;
   const int64_t kb = (int64_t)split * G.kchunk;
   const int64_t ke = min(G.m, kb + G.kchunk);
-  const int r = lane & 15, kk = lane >> 4;
   const float* base = SA + (int64_t)p * G.m * G.ld;
-  const bool ci = i0 + r < G.d, cj0 = j0 + r < G.d, cj1 = j0 + 16 + r < G.d;
-  f32x4 c0 = {0, 0, 0, 0}, c1 = c0;
-  for (int64_t k = kb; k < ke; k += 16) {
-    float a[4], b0[4], b1[4];
+  constexpr int kPer = kKcF32 * kTileF32 / 256;  // 4
+  float ra[kPer], rb[kPer];
+  auto load = [&](int64_t k0) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int64_t row = k + 4 * q + kk;
-      const bool okr = row < ke;
-      const float* rp = base + row * G.ld;
-      a[q] = (okr && ci) ? rp[i0 + r] : 0.f;
-      b0[q] = (okr && cj0) ? rp[j0 + r] : 0.f;
-      b1[q] = (okr && cj1) ? rp[j0 + 16 + r] : 0.f;
+    for (int u = 0; u < kPer; ++u) {
+      const int e = tid + 256 * u;
+      const int r = e / kTileF32, c = e % kTileF32;
+      const int64_t row = k0 + r;
+      const bool ok = row < ke;
+      ra[u] = (ok && i0 + c < G.d) ? base[row * G.ld + i0 + c] : 0.f;
+      if (!diag) rb[u] = (ok && j0 + c < G.d) ? base[row * G.ld + j0 + c] : 0.f;
     }
+  };
+  auto store = [&](int buf) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[q], b0[q], c0, 0, 0, 0);
-      c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[q], b1[q], c1, 0, 0, 0);
+    for (int u = 0; u < kPer; ++u) {
+      const int e = tid + 256 * u;
+      const int r = e / kTileF32, c = e % kTileF32;
+      As[buf][r][c] = ra[u];
+      if (!diag) Bs[buf][r][c] = rb[u];
     }
-  }
-  // 16 x 16 f32 output: row 4*(lane/16) + reg, column lane%16
-  double* out = part + (w >> 1) * (kTile * kTile) + 16 * half * kTile;
-  const int col = lane & 15, rq = lane >> 4;
+  };
+  const int wr = wv >> 1, wc = wv & 1;
+  f32x4 acc[2][2];
 #pragma unroll
-  for (int reg = 0; reg < 4; ++reg) {
-    const int row = 4 * rq + reg;
-    out[row * kTile + col] = (double)c0[reg];
-    out[row * kTile + 16 + col] = (double)c1[reg];
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int nstage = (int)((ke - kb + kKcF32 - 1) / kKcF32);
+  if (nstage > 0) {
+    load(kb);
+    store(0);
   }
+  __syncthreads();
+  for (int sidx = 0; sidx < nstage; ++sidx) {
+    const int buf = sidx & 1;
+    if (sidx + 1 < nstage) load(kb + (int64_t)(sidx + 1) * kKcF32);
+    const float(*Bp)[kPadF32] = diag ? As[buf] : Bs[buf];
+#pragma unroll
+    for (int k4 = 0; k4 < kKcF32; k4 += 4) {
+      const int kr = k4 + (lane >> 4), cl = lane & 15;
+      float a[2], b[2];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        a[q] = As[buf][kr][32 * wr + 16 * q + cl];
+        b[q] = Bp[kr][32 * wc + 16 * q + cl];
+      }
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+          acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[x], b[y], acc[x][y], 0, 0, 0);
+    }
+    if (sidx + 1 < nstage) store(buf ^ 1);
+    __syncthreads();
+  }
+  // 16 x 16 f32 output blocks: row 4*(lane/16) + reg, column lane%16
+  float* out = part + ((((int64_t)p * G.ntri) + (blockIdx.x / G.splits) % G.ntri) * G.splits +
+                       split) * (kTileF32 * kTileF32);
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int reg = 0; reg < 4; ++reg) {
+        const int row = 32 * wr + 16 * x + 4 * (lane >> 4) + reg;
+        const int col = 32 * wc + 16 * y + (lane & 15);
+        out[row * kTileF32 + col] = acc[x][y][reg];
+      }
 }
 
-__global__ __launch_bounds__(256, 6) void k_gram_bf16_f32(const uint16_t* __restrict__ SA,
-                                                          GramPlan G, double* __restrict__ part) {
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t w = (int64_t)blockIdx.x * 4 + wv;
-  const int64_t total = (int64_t)G.batch * G.ntri * G.splits * 2;
-  if (w >= total) return;
-  int p, t, split, half;
-  gram_wave_coords(G, w, p, t, split, half);
-  int ti, tj;
-  tri_index(t, ti, tj);
-  const int64_t i0 = (int64_t)ti * kTile + 16 * half, j0 = (int64_t)tj * kTile;
-  const int64_t kb = (int64_t)split * G.kchunk;
-  const int64_t ke = min(G.m, kb + G.kchunk);
-  const int r = lane & 15, kk = lane >> 4;
-  const uint16_t* base = SA + (int64_t)p * G.m * G.ld;
-  const bool ci = i0 + r < G.d, cj0 = j0 + r < G.d, cj1 = j0 + 16 + r < G.d;
-  f32x4 c0 = {0, 0, 0, 0}, c1 = c0;
-  // lane supplies A[i = lane%16][k = 8*(lane/16) + e]; A and B use the same k map
-  for (int64_t k = kb; k < ke; k += 32) {
-    bf16x8 a, b0, b1;
+// ---------------------------------------------------------------------------
+// FP32 accumulation of BF16 inputs (16 x 16 x 32 products). The inputs are
+// first regrouped into rows of eight (k_bf16_rows8), so every staging load
+// and every operand read is 16 bytes. One workgroup of four wavefronts owns
+// a 128 x 128 tile; each wavefront a 64 x 64 quarter (4 x 4 products); a
+// stage is 32 rows (four groups of eight).
+// ---------------------------------------------------------------------------
+constexpr int kKcBf16 = 32;
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// One thread per 16-byte cell (eight rows of one column): the eight reads of
+// a wavefront's threads cover eight rows of 64 consecutive columns.
+__global__ __launch_bounds__(256) void k_bf16_rows8(const uint16_t* __restrict__ SA, int64_t m,
+                                                    int64_t d, int64_t ld, int32_t batch,
+                                                    u32x4* __restrict__ out) {
+  const int64_t groups = bf16_rows8(m) / 8;
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;  // output cell
+  if (idx >= (int64_t)batch * groups * d) return;
+  const int64_t p = idx / (groups * d);
+  const int64_t rem = idx - p * groups * d;
+  const int64_t g = rem / d, c = rem - (rem / d) * d;
+  uint32_t w[4];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int64_t row = k + 8 * kk + e;
-      const bool okr = row < ke;
-      const uint16_t* rp = base + row * G.ld;
-      a[e] = (short)((okr && ci) ? rp[i0 + r] : 0);
-      b0[e] = (short)((okr && cj0) ? rp[j0 + r] : 0);
-      b1[e] = (short)((okr && cj1) ? rp[j0 + 16 + r] : 0);
+  for (int h = 0; h < 4; ++h) {
+    const int64_t k0 = 8 * g + 2 * h;
+    const uint32_t lo = k0 < m ? SA[(p * m + k0) * ld + c] : 0u;
+    const uint32_t hi = k0 + 1 < m ? SA[(p * m + k0 + 1) * ld + c] : 0u;
+    w[h] = lo | (hi << 16);
+  }
+  out[idx] = u32x4{w[0], w[1], w[2], w[3]};
+}
+
+__global__ __launch_bounds__(256, 4) void k_gram_bf16_f32(const uint16_t* __restrict__ S8,
+                                                          GramPlan G, float* __restrict__ part) {
+  // [buffer][group of 8 rows][column] of 16-byte cells
+  __shared__ u32x4 At[2][kKcBf16 / 8][kTileBf16];
+  __shared__ u32x4 Bt[2][kKcBf16 / 8][kTileBf16];
+  int p, ti, tj, split;
+  gram_coords(G, p, ti, tj, split);
+  const bool diag = ti == tj;
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+  const int64_t i0 = (int64_t)ti * kTileBf16, j0 = (int64_t)tj * kTileBf16;
+  const int64_t kb = (int64_t)split * G.kchunk;  // a multiple of 32
+  const int64_t ke = min(bf16_rows8(G.m), kb + G.kchunk);
+  const u32x4* base = reinterpret_cast<const u32x4*>(S8) + (int64_t)p * (bf16_rows8(G.m) / 8) * G.d;
+  constexpr int kPer = (kKcBf16 / 8) * kTileBf16 / 256;  // 2 cells per thread and panel
+  u32x4 ra[kPer], rb[kPer];
+  const u32x4 zero = {0u, 0u, 0u, 0u};
+  auto load = [&](int64_t k0) {
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int e = tid + 256 * u;
+      const int g = e / kTileBf16, c = e % kTileBf16;
+      const int64_t row = k0 + 8 * g;
+      const bool ok = row < ke;
+      ra[u] = (ok && i0 + c < G.d) ? base[(row / 8) * G.d + i0 + c] : zero;
+      if (!diag) rb[u] = (ok && j0 + c < G.d) ? base[(row / 8) * G.d + j0 + c] : zero;
     }
-    c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b0, c0, 0, 0, 0);
-    c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b1, c1, 0, 0, 0);
-  }
-  double* out = part + (w >> 1) * (kTile * kTile) + 16 * half * kTile;
-  const int col = lane & 15, rq = lane >> 4;
+  };
+  auto store = [&](int buf) {
 #pragma unroll
-  for (int reg = 0; reg < 4; ++reg) {
-    const int row = 4 * rq + reg;
-    out[row * kTile + col] = (double)c0[reg];
-    out[row * kTile + 16 + col] = (double)c1[reg];
+    for (int u = 0; u < kPer; ++u) {
+      const int e = tid + 256 * u;
+      const int g = e / kTileBf16, c = e % kTileBf16;
+      At[buf][g][c] = ra[u];
+      if (!diag) Bt[buf][g][c] = rb[u];
+    }
+  };
+  const int wr = wv >> 1, wc = wv & 1;
+  f32x4 acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int nstage = (int)((ke - kb + kKcBf16 - 1) / kKcBf16);
+  if (nstage > 0) {
+    load(kb);
+    store(0);
   }
+  __syncthreads();
+  for (int sidx = 0; sidx < nstage; ++sidx) {
+    const int buf = sidx & 1;
+    if (sidx + 1 < nstage) load(kb + (int64_t)(sidx + 1) * kKcBf16);
+    const u32x4(*Bp)[kTileBf16] = diag ? At[buf] : Bt[buf];
+    // lane supplies operand row lane%16 at rows 8*(lane/16) .. +7 of the stage
+    const int g = lane >> 4, cl = lane & 15;
+    bf16x8 a[4], b[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const u32x4 av = At[buf][g][64 * wr + 16 * q + cl];
+      const u32x4 bv = Bp[g][64 * wc + 16 * q + cl];
+      a[q] = __builtin_bit_cast(bf16x8, av);
+      b[q] = __builtin_bit_cast(bf16x8, bv);
+    }
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int y = 0; y < 4; ++y)
+        acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[x], b[y], acc[x][y], 0, 0, 0);
+    if (sidx + 1 < nstage) store(buf ^ 1);
+    __syncthreads();
+  }
+  float* out = part + ((((int64_t)p * G.ntri) + (blockIdx.x / G.splits) % G.ntri) * G.splits +
+                       split) * (kTileBf16 * kTileBf16);
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y)
+#pragma unroll
+      for (int reg = 0; reg < 4; ++reg) {
+        const int row = 64 * wr + 16 * x + 4 * (lane >> 4) + reg;
+        const int col = 64 * wc + 16 * y + (lane & 15);
+        out[row * kTileBf16 + col] = acc[x][y][reg];
+      }
 }
 
 // Sum the split-K partials in ascending split order and write both halves.
-// acc32: add the partials in float (the F32-accumulation variants).
-__global__ __launch_bounds__(256) void k_gram_reduce(GramPlan G, const double* __restrict__ part,
-                                                     double* __restrict__ H, int32_t acc32) {
-  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int64_t dd = G.d * G.d;
-  if (idx >= (int64_t)G.batch * dd) return;
-  const int p = (int)(idx / dd);
-  const int64_t e = idx - (int64_t)p * dd;
-  const int64_t i = e / G.d, j = e - (e / G.d) * G.d;
-  int64_t a = i, b = j;
-  if (a / kTile > b / kTile) {
-    a = j;
-    b = i;
+// One workgroup per 64 x 16 strip of a 64 x 64 block of a tile, four
+// elements per thread with all their loads in flight together: the partials
+// are read along rows, the strip is written in place and, through LDS,
+// transposed into the lower triangle, so every global access is coalesced.
+// Diagonal tiles keep their upper half and mirror it. TP: the partials' type
+// (double for FP64 accumulation; float otherwise, added in float).
+constexpr int kRedStrip = 16;
+
+template <typename TP>
+__global__ __launch_bounds__(256) void k_gram_reduce(GramPlan G, const TP* __restrict__ part,
+                                                     double* __restrict__ H) {
+  __shared__ double S[64][kRedStrip + 1];
+  const int T = G.tile, per = T / 64, nstrip = 64 / kRedStrip;
+  int64_t q = blockIdx.x;
+  const int strip = (int)(q % nstrip);
+  q /= nstrip;
+  const int sb = (int)(q % (per * per));
+  q /= per * per;
+  const int t = (int)(q % G.ntri);
+  const int p = (int)(q / G.ntri);
+  int ti, tj;
+  tri_index(t, ti, tj);
+  const bool diag = ti == tj;
+  const int sr = sb / per, sc = sb % per;
+  if (diag && sr > sc) return;  // below the diagonal of a diagonal tile: mirrored
+  const int64_t i0 = (int64_t)ti * T + 64 * sr, j0 = (int64_t)tj * T + 64 * sc + kRedStrip * strip;
+  const TP* src = part + (((int64_t)p * G.ntri + t) * G.splits) * ((int64_t)T * T);
+  const int64_t stride = (int64_t)T * T;
+  double* Hp = H + (int64_t)p * G.d * G.d;
+  constexpr int kE = 64 * kRedStrip / 256;  // 4 elements per thread
+  int64_t off[kE];
+  TP s[kE];
+#pragma unroll
+  for (int u = 0; u < kE; ++u) {
+    const int e = threadIdx.x + 256 * u;
+    const int r = e / kRedStrip, c = e % kRedStrip;
+    off[u] = (int64_t)(64 * sr + r) * T + 64 * sc + kRedStrip * strip + c;
+    s[u] = (TP)0;
   }
-  const int ti = (int)(a / kTile), tj = (int)(b / kTile);
-  const int t = tj * (tj + 1) / 2 + ti;
-  const int li = (int)(a - (int64_t)ti * kTile), lj = (int)(b - (int64_t)tj * kTile);
-  const double* src = part + (((int64_t)p * G.ntri + t) * G.splits) * (kTile * kTile);
-  // inside a diagonal tile the lower half mirrors the upper half
-  int64_t off = (ti == tj && li > lj) ? (lj * kTile + li) : (li * kTile + lj);
-  // loads of eight slices are issued together, then added in ascending order
-  const int64_t stride = (int64_t)kTile * kTile;
-  if (acc32) {
-    float s = 0.f;
-    int q = 0;
-    for (; q + 8 <= G.splits; q += 8) {
-      double v[8];
+  // loads of two slices of every element are issued together, then added in
+  // ascending slice order
+  int k = 0;
+  for (; k + 2 <= G.splits; k += 2) {
+    TP v[2][kE];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = src[(int64_t)(q + u) * stride + off];
+    for (int h = 0; h < 2; ++h)
 #pragma unroll
-      for (int u = 0; u < 8; ++u) s += (float)v[u];
-    }
-    for (; q < G.splits; ++q) s += (float)src[(int64_t)q * stride + off];
-    H[idx] = (double)s;
-  } else {
-    double s = 0.0;
-    int q = 0;
-    for (; q + 8 <= G.splits; q += 8) {
-      double v[8];
+      for (int u = 0; u < kE; ++u) v[h][u] = src[(int64_t)(k + h) * stride + off[u]];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = src[(int64_t)(q + u) * stride + off];
+    for (int h = 0; h < 2; ++h)
 #pragma unroll
-      for (int u = 0; u < 8; ++u) s += v[u];
-    }
-    for (; q < G.splits; ++q) s += src[(int64_t)q * stride + off];
-    H[idx] = s;
+      for (int u = 0; u < kE; ++u) s[u] += v[h][u];
+  }
+  for (; k < G.splits; ++k)
+#pragma unroll
+    for (int u = 0; u < kE; ++u) s[u] += src[(int64_t)k * stride + off[u]];
+  const int cdiag = kRedStrip * strip;  // this strip's first column within the block
+#pragma unroll
+  for (int u = 0; u < kE; ++u) {
+    const int e = threadIdx.x + 256 * u;
+    const int r = e / kRedStrip, c = e % kRedStrip;
+    const double v = (double)s[u];
+    S[r][c] = v;
+    const int64_t gi = i0 + r, gj = j0 + c;
+    if (gi < G.d && gj < G.d && (!diag || sr < sc || r <= cdiag + c)) Hp[gi * G.d + gj] = v;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 64 * kRedStrip; e += 256) {
+    const int c = e / 64, r = e % 64;  // write row j0 + c, column i0 + r
+    const int64_t gi = i0 + r, gj = j0 + c;
+    if (gi < G.d && gj < G.d && (!diag || sr < sc || r < cdiag + c)) Hp[gj * G.d + gi] = S[r][c];
   }
 }
 
 hipError_t launch_gram(const void* SA, int32_t in_dtype, int64_t m, int64_t d, int64_t ld,
                        int32_t batch, int32_t acc_dtype, double* H, void* partials,
                        hipStream_t st) {
-  const GramPlan G = make_gram_plan(m, d, ld, batch);
-  const int64_t waves = (int64_t)batch * G.ntri * G.splits * 2;
-  const unsigned blocks = (unsigned)((waves + 3) / 4);
-  double* part = static_cast<double*>(partials);
+  const GramPlan G = make_gram_plan(m, d, ld, batch, acc_dtype, in_dtype);
+  const unsigned blocks = (unsigned)((int64_t)batch * G.ntri * G.splits);
+  const dim3 rgrid((unsigned)((int64_t)batch * G.ntri * (G.tile / 64) * (G.tile / 64) *
+                              (64 / kRedStrip)));
   if (acc_dtype == 0) {
+    double* part = static_cast<double*>(partials);
     if (in_dtype == 0)
       hipLaunchKernelGGL(k_gram_f64<double>, dim3(blocks), dim3(256), 0, st,
                          static_cast<const double*>(SA), G, part);
@@ -282,19 +495,26 @@ hipError_t launch_gram(const void* SA, int32_t in_dtype, int64_t m, int64_t d, i
                          static_cast<const float*>(SA), G, part);
     else
       return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_gram_reduce<double>, rgrid, dim3(256), 0, st, G, part, H);
   } else {
-    if (in_dtype == 1)
+    float* part = static_cast<float*>(partials);
+    if (in_dtype == 1) {
       hipLaunchKernelGGL(k_gram_f32_f32, dim3(blocks), dim3(256), 0, st,
                          static_cast<const float*>(SA), G, part);
-    else if (in_dtype == 2)
-      hipLaunchKernelGGL(k_gram_bf16_f32, dim3(blocks), dim3(256), 0, st,
-                         static_cast<const uint16_t*>(SA), G, part);
-    else
+    } else if (in_dtype == 2) {
+      const size_t pbytes = (size_t)batch * G.ntri * G.splits * G.tile * G.tile * sizeof(float);
+      uint16_t* s8 = reinterpret_cast<uint16_t*>(static_cast<char*>(partials) +
+                                                 (pbytes + 255) / 256 * 256);
+      const int64_t cells = (int64_t)batch * (bf16_rows8(m) / 8) * d;
+      hipLaunchKernelGGL(k_bf16_rows8, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, st,
+                         static_cast<const uint16_t*>(SA), m, d, ld, batch,
+                         reinterpret_cast<u32x4*>(s8));
+      hipLaunchKernelGGL(k_gram_bf16_f32, dim3(blocks), dim3(256), 0, st, s8, G, part);
+    } else {
       return hipErrorInvalidValue;
+    }
+    hipLaunchKernelGGL(k_gram_reduce<float>, rgrid, dim3(256), 0, st, G, part, H);
   }
-  const int64_t n_out = (int64_t)batch * d * d;
-  hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((n_out + 255) / 256)), dim3(256), 0, st, G,
-                     part, H, acc_dtype == 0 ? 0 : 1);
   return hipGetLastError();
 }
 
