@@ -128,19 +128,28 @@ __device__ __forceinline__ void status_fail(DeviceStatus* st, int code, int iter
   }
 }
 
+// Status words are read at device (agent) scope: every writer is a kernel on
+// this GPU. A system-scope acquire would invalidate the L2 for every reading
+// wavefront, which in the d x d row kernels (one wavefront per row) cost more
+// than the products themselves.
+__device__ __forceinline__ int status_word(const int32_t* w) {
+  return __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // True when `st` records any failure or the tolerance stop of the outer loop
-// (`done`): the update kernels then leave x as it is.
+// (`done`): the update kernels then leave x as it is. Only the words
+// themselves are read, so no ordering is needed.
 __device__ __forceinline__ bool status_halted(const DeviceStatus* st) {
-  return __atomic_load_n(&st->code, __ATOMIC_ACQUIRE) != 0 ||
-         __atomic_load_n(&st->done, __ATOMIC_ACQUIRE) != 0;
+  return status_word(&st->code) != 0 || status_word(&st->done) != 0;
 }
 
 // True when `st` records a failure at or before step `iter` (iter < 0: any).
 __device__ __forceinline__ bool status_failed_by(const DeviceStatus* st, int iter) {
-  const int code = __atomic_load_n(&st->code, __ATOMIC_ACQUIRE);
+  // acquire: the step recorded before the code was published is visible
+  const int code = __hip_atomic_load(&st->code, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
   if (code == 0) return false;
   if (iter < 0) return true;
-  const int fi = __atomic_load_n(&st->failed_iter, __ATOMIC_RELAXED);
+  const int fi = status_word(&st->failed_iter);
   return fi <= iter;
 }
 

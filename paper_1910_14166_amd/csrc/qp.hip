@@ -118,7 +118,7 @@ __global__ __launch_bounds__(64) void k_reduce_b(const double* __restrict__ red,
   const int p = blockIdx.y;
   const int64_t col = (int64_t)blockIdx.x * 64 + threadIdx.x;
   // after the tolerance stop the pass did not run: keep g, f and the objective
-  if (st != nullptr && __atomic_load_n(&st->done, __ATOMIC_ACQUIRE) != 0) return;
+  if (st != nullptr && status_word(&st->done) != 0) return;
   if (col < d) {
     double s = 0.0;
     for (int q = 0; q < 4 * kRedSplit; ++q) s += red[((int64_t)p * 4 * kRedSplit + q) * d + col];
@@ -1137,7 +1137,7 @@ __global__ __launch_bounds__(256) void k_step_test(const double* __restrict__ q,
     st->last_step = sqrt(fmax(q0, 0.0));
     if (!over) {
       st->iters = iter + 1;
-      __atomic_store_n(&st->done, 1, __ATOMIC_RELEASE);
+      __hip_atomic_store(&st->done, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
 }

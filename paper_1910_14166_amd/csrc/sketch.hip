@@ -436,7 +436,7 @@ template <typename TA, int VEC, int NCH, int U, int BPW, bool GRAD, bool IDENT>
 __global__ __launch_bounds__(256, (BPW > 1 ? 3 : (NCH <= 4 ? 4 : 2))) void k_gather(
     SketchPlan P, GatherArgs G, int32_t total_seg, int32_t seg_rows) {
   // waves are independent (no workgroup barriers), so each may leave here
-  if (G.halt != nullptr && __atomic_load_n(G.halt, __ATOMIC_RELAXED) != 0) return;
+  if (G.halt != nullptr && status_word(G.halt) != 0) return;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t d = G.d;
   constexpr int SPAN = 64 * VEC;
@@ -740,7 +740,7 @@ __global__ __launch_bounds__(256) void k_gather_csr(SketchPlan P, CsrGatherArgs 
   const int64_t nbk = IDENT ? (int64_t)total_seg : (int64_t)P.batch * P.m;
   const int64_t bg = (int64_t)blockIdx.x * 4 + wv;
   if (bg >= nbk) return;  // no workgroup barriers below: waves are independent
-  if (G.halt != nullptr && __atomic_load_n(G.halt, __ATOMIC_RELAXED) != 0) return;
+  if (G.halt != nullptr && status_word(G.halt) != 0) return;
   int p;
   int64_t bl, beg, end, gslot;
   if (IDENT) {
