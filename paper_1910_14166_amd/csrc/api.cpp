@@ -480,6 +480,13 @@ struct SolveBuffers {
   double* xprev = nullptr;
   double* stepq = nullptr;
   double* dsk = nullptr;     // the Gaussian or SRHT sketch's own scratch
+  // the l2 step's inverse formed ahead on the side stream (overlapped schedule):
+  // per parity factor, shift snapshot; shared scratch; its own status record
+  double* Lpre[2] = {nullptr, nullptr};
+  double* snap[2] = {nullptr, nullptr};
+  double* pre_scratch = nullptr;
+  double* pre_rows = nullptr;
+  DeviceStatus* pre_status = nullptr;
 };
 
 // From kQpInverseMinD (rowdot.hpp) on, the overlapped schedule forms H^{-1}
@@ -515,8 +522,19 @@ size_t carve_solve(Carver& c, const Layout& L, const ihs_options* o, SolveBuffer
     S.Lf2 = c.take<double>((size_t)(L.batch * L.d * L.d));
     S.work2 = c.take<double>((size_t)L.batch * qp_work_doubles(L.d, o->constraint));
   }
-  if (L.d >= kInverseMinD &&
-      (o->constraint == IHS_UNCONSTRAINED || o->constraint == IHS_L1_BALL)) {
+  const bool l2pre = o->constraint == IHS_L2_BALL && o->schedule != 1;
+  if (l2pre) {
+    const size_t bdd = (size_t)(L.batch * L.d * L.d);
+    S.Lpre[0] = c.take<double>(bdd);
+    S.Lpre[1] = c.take<double>(bdd);
+    S.snap[0] = c.take<double>((size_t)(4 * L.batch));
+    S.snap[1] = c.take<double>((size_t)(4 * L.batch));
+    S.pre_scratch = c.take<double>((size_t)L.batch * (64 * 64 + L.d));
+    S.pre_rows = c.take<double>((size_t)(L.batch * L.d));
+    S.pre_status = c.take<DeviceStatus>(1);
+  }
+  if ((L.d >= kInverseMinD &&
+       (o->constraint == IHS_UNCONSTRAINED || o->constraint == IHS_L1_BALL)) || l2pre) {
     S.Hinv0 = c.take<double>((size_t)(L.batch * L.d * L.d));
     S.Hinv1 = c.take<double>((size_t)(L.batch * L.d * L.d));
     if (ahead2) S.Hinv2 = c.take<double>((size_t)(L.batch * L.d * L.d));
@@ -668,6 +686,7 @@ ihs_status solve_overlap(const ihs_matrix* A, const Layout& L, const ihs_options
       !ck(hipStreamWaitEvent(sorter, evMisc.at(0), 0)))
     return IHS_ERR_HIP;
   hipLaunchKernelGGL(k_zero_status, dim3(1), dim3(64), 0, side, S.side_status);
+  if (S.pre_status) hipLaunchKernelGGL(k_zero_status, dim3(1), dim3(64), 0, side, S.pre_status);
 
   auto plan_for = [&](int64_t k) {  // sketch S_k, sorted into buffer set k % 2
     SketchPlan P = make_plan(L, &opt->sketch, B, opt->sketch.iter + (uint64_t)k);
@@ -708,6 +727,14 @@ ihs_status solve_overlap(const ihs_matrix* A, const Layout& L, const ihs_options
     // unconstrained minimiser, so H_k is factored (and, from kInverseMinD
     // on, inverted) here, beside the pass.
     if (constrained) {
+      if (opt->constraint == IHS_L2_BALL) {
+        // step k's QP (k >= 1, warm) sweeps from (H_k + mu I)^{-1}, mu from
+        // the snapshot taken before pass k - 1
+        if (k < 1 || !S.pre_status) return true;
+        return ck(launch_l2_prefactor(h_buf(k), d, L.batch, S.snap[k % 2], S.Lpre[k % 2],
+                                      hinv_buf(k), S.Linv, S.pre_scratch, S.pre_rows,
+                                      S.pre_status, (int32_t)k, side));
+      }
       if (opt->constraint != IHS_L1_BALL) return true;
       if (!ck(launch_cholesky(h_buf(k), l_buf(k), d, L.batch, S.side_status, (int32_t)k, 0.0,
                               w_buf(k), side)))
@@ -750,6 +777,11 @@ ihs_status solve_overlap(const ihs_matrix* A, const Layout& L, const ihs_options
   }
 
   for (int32_t t = 0; t < N; ++t) {
+    // main (l2 ball): the shift state after QP_{t-1}, for the side stream's
+    // factorisation of H_{t+1} beside pass t and QP_t
+    if (S.pre_status && t + LA < N &&
+        !ck(launch_l2_snapshot(S.work, d, L.batch, S.snap[(t + LA) % 2], t == 0 ? 1 : 0, stream)))
+      return IHS_ERR_HIP;
     // main: pass P_t forms g(x^t) and S_{t+LA} A
     if (!ck(hipStreamWaitEvent(stream, evSort.at(t + LA), 0))) return IHS_ERR_HIP;
     s = run_gather(A, &opt->sketch, B, plan_for(t + LA), sa_buf(t + LA), opt->gram_in, d, b, x,
@@ -796,6 +828,11 @@ ihs_status solve_overlap(const ihs_matrix* A, const Layout& L, const ihs_options
       a.status = B.status;
       a.iter = t;
       a.warm = t > 0 ? 1 : 0;
+      if (opt->constraint == IHS_L2_BALL && S.pre_status && t >= 1) {
+        a.hinv_pre = hinv_buf(t);   // (H_t + mu I)^{-1} from the side stream
+        a.trs_pre = S.snap[t % 2];
+        a.pre_status = S.pre_status;
+      }
       if (opt->constraint == IHS_L1_BALL) {  // H_t's factor or inverse, from the side stream
         hipLaunchKernelGGL(k_adopt_status, dim3(1), dim3(64), 0, stream, S.side_status, t,
                            B.status);

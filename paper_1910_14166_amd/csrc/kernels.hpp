@@ -178,8 +178,21 @@ struct QpArgs {
   const double* rdiag_pre; // l1 ball (nullable): L already holds the factor of H and
                            // this its reciprocal pivots, so the step does not factor H
   const double* hinv_pre;  // l1 ball (nullable): H^{-1} formed elsewhere; the step
-                           // then uses neither L nor rdiag_pre
+                           // then uses neither L nor rdiag_pre. l2 ball (with
+                           // trs_pre, warm steps): (H + mu0 I)^{-1} formed ahead
+  const double* trs_pre;   // l2 ball (nullable): the snapshot state of hinv_pre
+                           // (mu0 and a norm bound at [4p + 2], [4p + 3])
+  const DeviceStatus* pre_status;  // l2 ball: failures while forming hinv_pre
 };
+// The l2 step's inverse ahead of time: snapshot the shift state of the QP
+// workspace `work` (cold: mu = 0), and factor and invert H + mu I at that
+// snapshot into L / hinv (linv: d x d scratch; scratch: batch * (64*64 + d);
+// rows: batch * d), its shift and norm bound into snap[4p + 2], snap[4p + 3].
+hipError_t launch_l2_snapshot(double* work, int64_t d, int32_t batch, double* snap, int32_t cold,
+                              hipStream_t st);
+hipError_t launch_l2_prefactor(const double* H, int64_t d, int32_t batch, double* snap, double* L,
+                               double* hinv, double* linv, double* scratch, double* rows,
+                               DeviceStatus* status, int32_t iter, hipStream_t st);
 size_t qp_work_doubles(int64_t d, int32_t constraint);
 hipError_t launch_qp_step(const QpArgs& a, hipStream_t st);
 // The l1-ball, l2-ball and l1-penalty steps (constraint 1, 2, 3); a.work holds

@@ -639,6 +639,31 @@ __device__ __forceinline__ double block256_sum(double v, double* red) {
   return red[0] + red[1] + red[2] + red[3];
 }
 
+// The inverse of H + mu0 I formed ahead of the step (on another stream, at
+// the shift mu0 of a snapshot): its shift and norm bound become the held
+// state, so the first Newton step can sweep from it instead of factoring.
+// A failure recorded while forming it (pre_st) leaves an infinite bound, so
+// the step factors H + mu I itself as it would without the inverse.
+__global__ void k_trs_adopt(double* trs, const double* pre, int32_t batch,
+                            const DeviceStatus* pre_st) {
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p >= batch) return;
+  const bool bad = pre_st != nullptr && status_failed_by(pre_st, -1);
+  trs[4 * p + 2] = pre[4 * p + 2];
+  trs[4 * p + 3] = bad ? INFINITY : pre[4 * p + 3];
+}
+
+// The shift state as the next step's side work will see it: mu of each
+// problem, phase 0 (so the factorisation and inverse kernels run for it).
+__global__ void k_trs_snapshot(const double* trs, double* snap, int32_t batch, int32_t cold) {
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p >= batch) return;
+  snap[4 * p] = cold ? 0.0 : fmax(trs[4 * p], 0.0);
+  snap[4 * p + 1] = 0.0;
+  snap[4 * p + 2] = 0.0;
+  snap[4 * p + 3] = INFINITY;
+}
+
 // Start of a step: phase 0; the shift starts from the previous step's root
 // when `warm` (the same problems, with nearby H and c), else from 0.
 __global__ void k_trs_init(double* trs, int32_t batch, int32_t warm) {
@@ -813,19 +838,25 @@ __global__ void k_trs_finish(const double* trs, int64_t d, const double* x, doub
   if (threadIdx.x == 0) status_fail(st, 6 /* IHS_ERR_NOT_CONVERGED */, iter, p);
 }
 
+// Copies the status words that end the Newton loop (a failure, the outer
+// loop's stop) behind the shift state, so one read brings both to the host.
+__global__ void k_trs_status(const DeviceStatus* st, double* dst) {
+  if (threadIdx.x == 0) dst[0] = (double)(status_word(&st->code) | status_word(&st->done));
+}
+
 // True when every problem has finished its Newton iteration, a failure is
 // recorded or the outer loop has stopped; leaves the shift state in h.
 // Synchronises the stream.
-static bool trs_all_done(const double* trs, const DeviceStatus* status, int32_t batch,
+static bool trs_all_done(double* trs, const DeviceStatus* status, int32_t batch,
                          hipStream_t st, std::vector<double>& h) {
-  h.assign((size_t)4 * batch, 0.0);
-  int32_t head[4] = {0, 0, 0, 0};  // code, failed_iter, failed_problem, done
-  if (hipMemcpyAsync(h.data(), trs, h.size() * sizeof(double), hipMemcpyDeviceToHost, st) !=
+  h.assign((size_t)4 * batch + 1, 0.0);
+  hipLaunchKernelGGL(k_trs_status, dim3(1), dim3(64), 0, st, status, trs + 4 * batch);
+  if (hipGetLastError() != hipSuccess ||
+      hipMemcpyAsync(h.data(), trs, h.size() * sizeof(double), hipMemcpyDeviceToHost, st) !=
           hipSuccess ||
-      hipMemcpyAsync(head, status, sizeof(head), hipMemcpyDeviceToHost, st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)
     return false;
-  if (head[0] != 0 || head[3] != 0) return true;
+  if (h[(size_t)4 * batch] != 0.0) return true;
   for (int32_t p = 0; p < batch; ++p)
     if (h[(size_t)4 * p + 1] < 2.0) return false;
   return true;
@@ -924,16 +955,28 @@ hipError_t launch_qp_constrained(const QpArgs& a, hipStream_t st) {
   double* rbuf = zero;
   std::vector<double> h;
   bool held = false;
+  const double* hinv_use = hinv;
+  if (a.warm && a.hinv_pre && a.trs_pre) {  // an inverse formed ahead at a nearby shift
+    hipLaunchKernelGGL(k_trs_adopt, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, st, trs,
+                       a.trs_pre, B, a.pre_status);
+    if (trs_all_done(trs, a.status, B, st, h)) {
+      hipLaunchKernelGGL(k_trs_finish, dim3(B), dim3(256), 0, st, trs, d, a.x, a.x_out, a.status,
+                         a.iter);
+      return hipGetLastError();
+    }
+    held = true;
+    hinv_use = a.hinv_pre;
+  }
   // out = base + (H + mu I)^{-1} v by S sweeps from (H + mu0 I)^{-1} v (base
   // nullable; out must differ from v)
   auto richardson = [&](const double* v, const double* base, double* out, int32_t S) {
     double* w = base ? wbuf : out;
-    hipLaunchKernelGGL(k_trs_symv, rows_grid, dim3(256), 0, st, hinv, d, v, nullptr, w, trs,
+    hipLaunchKernelGGL(k_trs_symv, rows_grid, dim3(256), 0, st, hinv_use, d, v, nullptr, w, trs,
                        a.status);
     for (int32_t j = 0; j < S; ++j) {
       hipLaunchKernelGGL(k_trs_resid, rows_grid, dim3(256), 0, st, a.H, d, w, v, rbuf, trs,
                          a.status);
-      hipLaunchKernelGGL(k_trs_symv, rows_grid, dim3(256), 0, st, hinv, d, rbuf, w, w, trs,
+      hipLaunchKernelGGL(k_trs_symv, rows_grid, dim3(256), 0, st, hinv_use, d, rbuf, w, w, trs,
                          a.status);
     }
     if (base)
@@ -961,6 +1004,7 @@ hipError_t launch_qp_constrained(const QpArgs& a, hipStream_t st) {
                          a.status);
       hipLaunchKernelGGL(k_trs_inv_norm, dim3(B), dim3(256), 0, st, rbuf, d, trs, a.status);
       held = true;
+      hinv_use = hinv;
     } else {
       // error after j sweeps <= rho^(j+1) relative to the solution
       sweeps = 1;
@@ -984,6 +1028,44 @@ hipError_t launch_qp_constrained(const QpArgs& a, hipStream_t st) {
   }
   hipLaunchKernelGGL(k_trs_finish, dim3(B), dim3(256), 0, st, trs, d, a.x, a.x_out, a.status,
                      a.iter);
+  return hipGetLastError();
+}
+
+
+// ---------------------------------------------------------------------------
+// The l2 step's factorisation ahead of time (overlapped schedule): while the
+// caller's stream runs step t's QP and step t+1's pass, another stream
+// factors H_{t+1} + mu I and inverts it, mu from a snapshot of the shift
+// state taken before pass t (the root of step t-1). Step t+1's first Newton
+// step then sweeps from that inverse when |mu_t - mu| ||(H + mu I)^{-1}|| is
+// small enough, as later Newton steps sweep from the inverse held inside a
+// step.
+// ---------------------------------------------------------------------------
+static double* l2_trs(double* work, int64_t d, int32_t B) {
+  // past the unconstrained step's scratch: c, x_unc, x(mu), z, a spare, then
+  // the shift state (as laid out in launch_qp_constrained)
+  return work + (int64_t)B * (64 * 64 + 9 * d + 64) + (int64_t)B * 5 * d;
+}
+
+hipError_t launch_l2_snapshot(double* work, int64_t d, int32_t batch, double* snap, int32_t cold,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(k_trs_snapshot, dim3((unsigned)((batch + 255) / 256)), dim3(256), 0, st,
+                     l2_trs(work, d, batch), snap, batch, cold);
+  return hipGetLastError();
+}
+
+hipError_t launch_l2_prefactor(const double* H, int64_t d, int32_t batch, double* snap, double* L,
+                               double* hinv, double* linv, double* scratch, double* rows,
+                               DeviceStatus* status, int32_t iter, hipStream_t st) {
+  hipError_t e;
+  if ((e = launch_cholesky(H, L, d, batch, status, iter, 0.0, scratch, st, snap)) != hipSuccess)
+    return e;
+  if ((e = launch_chol_inverse(L, chol_rdiag(scratch, batch), d, batch, hinv, linv, status, st,
+                               snap)) != hipSuccess)
+    return e;
+  const dim3 rows_grid((unsigned)((d + 3) / 4), batch);
+  hipLaunchKernelGGL(k_trs_abs_rows, rows_grid, dim3(256), 0, st, hinv, d, snap, rows, status);
+  hipLaunchKernelGGL(k_trs_inv_norm, dim3(batch), dim3(256), 0, st, rows, d, snap, status);
   return hipGetLastError();
 }
 
