@@ -4,8 +4,12 @@
 
 #include <algorithm>
 #include <cmath>
+#include <condition_variable>
 #include <cstring>
+#include <deque>
+#include <functional>
 #include <mutex>
+#include <thread>
 #include <utility>
 #include <vector>
 
@@ -450,7 +454,8 @@ struct SolveBuffers {
   void* SA = nullptr;
   double* H = nullptr;
   void* gram_part = nullptr;
-  double* H1 = nullptr;      // second sketched Hessian of the overlapped constrained schedule
+  double* H1 = nullptr;      // second (and third) sketched Hessian of the overlapped
+  double* H2 = nullptr;      // constrained schedule
   double* Lf = nullptr;
   double* work = nullptr;
   // second set of the double-buffered arrays of the overlapped schedule
@@ -480,12 +485,16 @@ struct SolveBuffers {
   double* xprev = nullptr;
   double* stepq = nullptr;
   double* dsk = nullptr;     // the Gaussian or SRHT sketch's own scratch
-  // the l2 step's inverse formed ahead on the side stream (overlapped schedule):
-  // per parity factor, shift snapshot; shared scratch; its own status record
+  // the l2 step's inverse formed ahead (overlapped schedule), two steps ahead
+  // on two side streams: per stream a Gram partial buffer, the factor and the
+  // factorisation's scratch; per step (three in flight) the shift snapshot;
+  // one status record for failures while forming them
+  void* gram_part1 = nullptr;
+  double* Linv1 = nullptr;
   double* Lpre[2] = {nullptr, nullptr};
-  double* snap[2] = {nullptr, nullptr};
-  double* pre_scratch = nullptr;
-  double* pre_rows = nullptr;
+  double* pre_scratch[2] = {nullptr, nullptr};
+  double* pre_rows[2] = {nullptr, nullptr};
+  double* snap[3] = {nullptr, nullptr, nullptr};
   DeviceStatus* pre_status = nullptr;
 };
 
@@ -516,21 +525,27 @@ size_t carve_solve(Carver& c, const Layout& L, const ihs_options* o, SolveBuffer
   S.side_status = c.take<DeviceStatus>(1);
   if (o->constraint != IHS_UNCONSTRAINED && o->schedule != 1)
     S.H1 = c.take<double>((size_t)(L.batch * L.d * L.d));
-  const bool ahead2 = o->schedule == 2 && o->constraint == IHS_UNCONSTRAINED;
+  const bool l2pre = o->constraint == IHS_L2_BALL && o->schedule != 1;
+  const bool ahead2 = (o->schedule == 2 && o->constraint == IHS_UNCONSTRAINED) || l2pre;
   if (ahead2) {
     S.SA2 = c.take<char>((size_t)(L.batch * m * L.d * dtype_size(gram_in_of(o))));
-    S.Lf2 = c.take<double>((size_t)(L.batch * L.d * L.d));
-    S.work2 = c.take<double>((size_t)L.batch * qp_work_doubles(L.d, o->constraint));
+    if (!l2pre) {  // the l2 step's side work keeps its factors apart (Lpre)
+      S.Lf2 = c.take<double>((size_t)(L.batch * L.d * L.d));
+      S.work2 = c.take<double>((size_t)L.batch * qp_work_doubles(L.d, o->constraint));
+    }
   }
-  const bool l2pre = o->constraint == IHS_L2_BALL && o->schedule != 1;
   if (l2pre) {
     const size_t bdd = (size_t)(L.batch * L.d * L.d);
-    S.Lpre[0] = c.take<double>(bdd);
-    S.Lpre[1] = c.take<double>(bdd);
-    S.snap[0] = c.take<double>((size_t)(4 * L.batch));
-    S.snap[1] = c.take<double>((size_t)(4 * L.batch));
-    S.pre_scratch = c.take<double>((size_t)L.batch * (64 * 64 + L.d));
-    S.pre_rows = c.take<double>((size_t)(L.batch * L.d));
+    S.H2 = c.take<double>(bdd);
+    S.gram_part1 = c.take<char>(
+        gram_partials_bytes(m, L.d, L.batch, gram_in_of(o), gram_acc_of(o)));
+    S.Linv1 = c.take<double>(bdd);
+    for (int q = 0; q < 2; ++q) {
+      S.Lpre[q] = c.take<double>(bdd);
+      S.pre_scratch[q] = c.take<double>((size_t)L.batch * (64 * 64 + L.d));
+      S.pre_rows[q] = c.take<double>((size_t)(L.batch * L.d));
+    }
+    for (int q = 0; q < 3; ++q) S.snap[q] = c.take<double>((size_t)(4 * L.batch));
     S.pre_status = c.take<DeviceStatus>(1);
   }
   if ((L.d >= kInverseMinD &&
@@ -560,14 +575,15 @@ size_t carve_solve(Carver& c, const Layout& L, const ihs_options* o, SolveBuffer
 }
 
 // ---- the extra streams of the overlapped schedule (kept per device) ----
-// which = 0: Gram / factorisation / inverse; which = 1: bucket sorts.
+// which = 0: Gram / factorisation / inverse; which = 1: bucket sorts;
+// which = 2: the second Gram / factorisation / inverse stream (l2 ball).
 hipStream_t side_stream(int which) {
   static std::mutex mu;
   static std::vector<hipStream_t> streams;
   int dev = 0;
   if (hip_failed(hipGetDevice(&dev))) return nullptr;
   std::lock_guard<std::mutex> lk(mu);
-  const size_t slot = (size_t)dev * 2 + (size_t)which;
+  const size_t slot = (size_t)dev * 3 + (size_t)which;
   if (streams.size() <= slot) streams.resize(slot + 1, nullptr);
   if (!streams[slot]) {
     hipStream_t s = nullptr;
@@ -668,12 +684,87 @@ ihs_status finish_report(const DeviceStatus& f, const DeviceStatus& m, const ihs
 // summed in the row order of S_{t+LA} instead of S_t, and H_t^{-1} g is a
 // product with the explicit inverse, so iterates agree with the sequential
 // loop to rounding.
+// A host thread that queues the side stream's work (a Gram, a factorisation
+// and an inverse: some sixty launches per step) in order, so that the thread
+// that runs the step never waits for those launches before its own. Jobs
+// return false when a launch fails; every later job is then skipped. The
+// destructor drops jobs not yet started and joins the thread.
+class SideQueue {
+ public:
+  explicit SideQueue(int device) : dev_(device), th_([this] { loop(); }) {}
+  ~SideQueue() {
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      stop_ = true;
+    }
+    cv_.notify_all();
+    th_.join();
+  }
+  // returns the job's number (1, 2, ...)
+  int64_t post(std::function<bool()> f) {
+    std::lock_guard<std::mutex> lk(mu_);
+    q_.push_back(std::move(f));
+    cv_.notify_all();
+    return ++posted_;
+  }
+  // waits until job n (and every earlier one) has run; false if any failed
+  bool wait(int64_t n) {
+    std::unique_lock<std::mutex> lk(mu_);
+    cv_.wait(lk, [&] { return done_ >= n; });
+    return ok_;
+  }
+  bool drain() {
+    int64_t n;
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      n = posted_;
+    }
+    return wait(n);
+  }
+
+ private:
+  void loop() {
+    const bool dev_ok = !hip_failed(hipSetDevice(dev_));
+    for (;;) {
+      std::function<bool()> f;
+      bool run;
+      {
+        std::unique_lock<std::mutex> lk(mu_);
+        cv_.wait(lk, [&] { return stop_ || !q_.empty(); });
+        if (stop_) return;
+        f = std::move(q_.front());
+        q_.pop_front();
+        run = ok_ && dev_ok;
+      }
+      const bool r = run && f();
+      {
+        std::lock_guard<std::mutex> lk(mu_);
+        if (!r) ok_ = false;
+        ++done_;
+      }
+      cv_.notify_all();
+    }
+  }
+  int dev_;
+  std::mutex mu_;
+  std::condition_variable cv_;
+  std::deque<std::function<bool()>> q_;
+  int64_t posted_ = 0, done_ = 0;
+  bool ok_ = true, stop_ = false;
+  std::thread th_;  // last: starts once the members above exist
+};
+
 ihs_status solve_overlap(const ihs_matrix* A, const Layout& L, const ihs_options* opt,
                          SolveBuffers& S, const double* b, double* x, double* x_hist,
                          double* factors, ihs_report* rep, hipStream_t stream) {
+  // l2 ball: the factorisations run two steps ahead, alternating between two
+  // side streams, so that two of these latency-bound chains run at once
+  const bool l2pre = S.pre_status != nullptr;
   hipStream_t side = side_stream(0);
+  hipStream_t side2 = l2pre ? side_stream(2) : side;
   hipStream_t sorter = side_stream(1);
-  if (!side || !sorter) return IHS_ERR_HIP;
+  if (!side || !side2 || !sorter) return IHS_ERR_HIP;
+  auto side_of = [&](int64_t k) { return (k % 2) ? side2 : side; };
   PassBuffers& B = S.pass;
   const int32_t N = opt->max_iter;
   const int64_t d = A->d, m = opt->sketch.m;
@@ -681,12 +772,14 @@ ihs_status solve_overlap(const ihs_matrix* A, const Layout& L, const ihs_options
   EventRing evSort(4), evPass(4), evChol(4), evMisc(3);
   if (!evSort.ok || !evPass.ok || !evChol.ok || !evMisc.ok) return IHS_ERR_HIP;
   auto ck = [](hipError_t e) { return !hip_failed(e); };
-  // the extra streams start after everything already queued on the caller's stream
+  // the extra streams start after everything already queued on the caller's
+  // stream, the cleared side status records included
+  hipLaunchKernelGGL(k_zero_status, dim3(1), dim3(64), 0, stream, S.side_status);
+  if (l2pre) hipLaunchKernelGGL(k_zero_status, dim3(1), dim3(64), 0, stream, S.pre_status);
   if (!ck(hipEventRecord(evMisc.at(0), stream)) || !ck(hipStreamWaitEvent(side, evMisc.at(0), 0)) ||
+      !ck(hipStreamWaitEvent(side2, evMisc.at(0), 0)) ||
       !ck(hipStreamWaitEvent(sorter, evMisc.at(0), 0)))
     return IHS_ERR_HIP;
-  hipLaunchKernelGGL(k_zero_status, dim3(1), dim3(64), 0, side, S.side_status);
-  if (S.pre_status) hipLaunchKernelGGL(k_zero_status, dim3(1), dim3(64), 0, side, S.pre_status);
 
   auto plan_for = [&](int64_t k) {  // sketch S_k, sorted into buffer set k % 2
     SketchPlan P = make_plan(L, &opt->sketch, B, opt->sketch.iter + (uint64_t)k);
@@ -697,9 +790,10 @@ ihs_status solve_overlap(const ihs_matrix* A, const Layout& L, const ihs_options
     return P;
   };
   // LA: how many steps ahead the passes form sketches; slots k % (LA + 1).
-  // Constrained steps look one step ahead: their side work is the Gram only.
+  // l1 steps look one step ahead (their side work is the Gram and a factor),
+  // l2 steps two (each factorisation has two steps' time on its stream).
   const bool constrained = opt->constraint != IHS_UNCONSTRAINED;
-  const int LA = (opt->schedule == 2 && !constrained) ? 2 : 1;
+  const int LA = ((opt->schedule == 2 && !constrained) || l2pre) ? 2 : 1;
   const int NS = LA + 1;
   auto sa_buf = [&](int64_t k) {
     const int64_t q = k % NS;
@@ -718,37 +812,43 @@ ihs_status solve_overlap(const ihs_matrix* A, const Layout& L, const ihs_options
     const int64_t q = k % NS;
     return q == 0 ? S.Hinv0 : (q == 1 ? S.Hinv1 : S.Hinv2);
   };
-  auto h_buf = [&](int64_t k) { return (constrained && k % 2) ? S.H1 : S.H; };
+  auto h_buf = [&](int64_t k) {
+    if (!constrained) return S.H;
+    if (l2pre) return k % 3 == 0 ? S.H : (k % 3 == 1 ? S.H1 : S.H2);
+    return k % 2 ? S.H1 : S.H;
+  };
   auto factor = [&](int64_t k) -> bool {  // side stream: H_k, its factor (and inverse)
+    const hipStream_t sk = side_of(k);
     if (!ck(launch_gram(sa_buf(k), opt->gram_in, m, d, d, L.batch, opt->gram_acc, h_buf(k),
-                        S.gram_part, side)))
+                        (k % 2 && l2pre) ? S.gram_part1 : S.gram_part, sk)))
       return false;
     // The constrained QPs work from H_k itself; the l1 ball's also needs the
     // unconstrained minimiser, so H_k is factored (and, from kInverseMinD
     // on, inverted) here, beside the pass.
     if (constrained) {
       if (opt->constraint == IHS_L2_BALL) {
-        // step k's QP (k >= 1, warm) sweeps from (H_k + mu I)^{-1}, mu from
-        // the snapshot taken before pass k - 1
-        if (k < 1 || !S.pre_status) return true;
-        return ck(launch_l2_prefactor(h_buf(k), d, L.batch, S.snap[k % 2], S.Lpre[k % 2],
-                                      hinv_buf(k), S.Linv, S.pre_scratch, S.pre_rows,
-                                      S.pre_status, (int32_t)k, side));
+        // step k's QP (k >= 1, warm) iterates on (H_k + mu I)^{-1}, mu from
+        // the snapshot taken before pass k - LA
+        if (k < 1 || !l2pre) return true;
+        const int q = (int)(k % 2);
+        return ck(launch_l2_prefactor(h_buf(k), d, L.batch, S.snap[k % 3], S.Lpre[q],
+                                      hinv_buf(k), q ? S.Linv1 : S.Linv, S.pre_scratch[q],
+                                      S.pre_rows[q], S.pre_status, (int32_t)k, sk));
       }
       if (opt->constraint != IHS_L1_BALL) return true;
       if (!ck(launch_cholesky(h_buf(k), l_buf(k), d, L.batch, S.side_status, (int32_t)k, 0.0,
-                              w_buf(k), side)))
+                              w_buf(k), sk)))
         return false;
       return !use_inv ||
              ck(launch_chol_inverse(l_buf(k), chol_rdiag(w_buf(k), L.batch), d, L.batch,
-                                    hinv_buf(k), S.Linv, S.side_status, side));
+                                    hinv_buf(k), S.Linv, S.side_status, sk));
     }
     if (!ck(launch_cholesky(S.H, l_buf(k), d, L.batch, S.side_status, (int32_t)k, 0.0,
-                            w_buf(k), side)))
+                            w_buf(k), sk)))
       return false;
     if (!use_inv) return true;
     return ck(launch_chol_inverse(l_buf(k), chol_rdiag(w_buf(k), L.batch), d, L.batch,
-                                  hinv_buf(k), S.Linv, S.side_status, side));
+                                  hinv_buf(k), S.Linv, S.side_status, sk));
   };
 
   // prologue: sketch-only passes for S_0 A .. S_{LA-1} A with the factors of
@@ -760,14 +860,16 @@ ihs_status solve_overlap(const ihs_matrix* A, const Layout& L, const ihs_options
       return IHS_ERR_HIP;
   ihs_status s = IHS_OK;
   for (int k = 0; k < LA; ++k) {
+    if (l2pre && !ck(launch_l2_snapshot(S.work, d, L.batch, S.snap[k % 3], 1, stream)))
+      return IHS_ERR_HIP;
     if (!ck(hipStreamWaitEvent(stream, evSort.at(k), 0))) return IHS_ERR_HIP;
     s = run_gather(A, &opt->sketch, B, plan_for(k), sa_buf(k), opt->gram_in, d, nullptr,
                    nullptr, nullptr, stream);
     if (s != IHS_OK) return s;
     if (!ck(hipEventRecord(evPass.at(k - LA), stream)) ||
-        !ck(hipStreamWaitEvent(side, evPass.at(k - LA), 0)))
+        !ck(hipStreamWaitEvent(side_of(k), evPass.at(k - LA), 0)))
       return IHS_ERR_HIP;
-    if (k < N && (!factor(k) || !ck(hipEventRecord(evChol.at(k), side)))) return IHS_ERR_HIP;
+    if (k < N && (!factor(k) || !ck(hipEventRecord(evChol.at(k), side_of(k))))) return IHS_ERR_HIP;
     if (k + 2 <= LA) {
       if (!ck(hipStreamWaitEvent(sorter, evPass.at(k - LA), 0)) ||
           !ck(launch_sort(plan_for(k + 2), sorter)) ||
@@ -776,11 +878,16 @@ ihs_status solve_overlap(const ihs_matrix* A, const Layout& L, const ihs_options
     }
   }
 
+  int dev = 0;
+  if (!ck(hipGetDevice(&dev))) return IHS_ERR_HIP;
+  // chol_job[k % 4]: the side job that records evChol(k) (0: recorded above)
+  std::vector<int64_t> chol_job(4, 0);
+  SideQueue sq(dev);  // after everything its jobs refer to, so it is joined first
   for (int32_t t = 0; t < N; ++t) {
-    // main (l2 ball): the shift state after QP_{t-1}, for the side stream's
-    // factorisation of H_{t+1} beside pass t and QP_t
-    if (S.pre_status && t + LA < N &&
-        !ck(launch_l2_snapshot(S.work, d, L.batch, S.snap[(t + LA) % 2], t == 0 ? 1 : 0, stream)))
+    // main (l2 ball): the shift state after QP_{t-1}, for the factorisation
+    // of H_{t+LA} + mu I that a side stream starts once pass t is done
+    if (l2pre && t + LA < N &&
+        !ck(launch_l2_snapshot(S.work, d, L.batch, S.snap[(t + LA) % 3], t == 0 ? 1 : 0, stream)))
       return IHS_ERR_HIP;
     // main: pass P_t forms g(x^t) and S_{t+LA} A
     if (!ck(hipStreamWaitEvent(stream, evSort.at(t + LA), 0))) return IHS_ERR_HIP;
@@ -800,14 +907,19 @@ ihs_status solve_overlap(const ihs_matrix* A, const Layout& L, const ihs_options
           !ck(hipEventRecord(evSort.at(t + LA + 1), sorter)))
         return IHS_ERR_HIP;
     }
-    // side: H_{t+LA} and its factor, during the next LA passes
-    if (!ck(hipStreamWaitEvent(side, evPass.at(t), 0))) return IHS_ERR_HIP;
-    if (t + LA < N) {
-      if (!factor(t + LA) || !ck(hipEventRecord(evChol.at(t + LA), side))) return IHS_ERR_HIP;
-    }
+    // side: H_{t+LA} and its factor, during the next LA passes (queued by
+    // the side thread)
+    const int64_t job = sq.post([&, t]() {
+      const hipStream_t sk = side_of(t + LA);
+      if (!ck(hipStreamWaitEvent(sk, evPass.at(t), 0))) return false;
+      return t + LA >= N || (factor(t + LA) && ck(hipEventRecord(evChol.at(t + LA), sk)));
+    });
+    chol_job.at((size_t)((t + LA) % chol_job.size())) = job;
     // main: x^{t+1} = x^t + H_t^{-1} g(x^t), or the constrained QP of Eq.(2)
     // with H_t (its l2 shift state carries over in S.work from step to step)
-    if (!ck(hipStreamWaitEvent(stream, evChol.at(t), 0))) return IHS_ERR_HIP;
+    if (!sq.wait(chol_job.at((size_t)(t % chol_job.size()))) ||
+        !ck(hipStreamWaitEvent(stream, evChol.at(t), 0)))
+      return IHS_ERR_HIP;
     if (S.xprev && !ck(hipMemcpyAsync(S.xprev, x, bd * sizeof(double), hipMemcpyDeviceToDevice,
                                       stream)))
       return IHS_ERR_HIP;
@@ -828,9 +940,9 @@ ihs_status solve_overlap(const ihs_matrix* A, const Layout& L, const ihs_options
       a.status = B.status;
       a.iter = t;
       a.warm = t > 0 ? 1 : 0;
-      if (opt->constraint == IHS_L2_BALL && S.pre_status && t >= 1) {
-        a.hinv_pre = hinv_buf(t);   // (H_t + mu I)^{-1} from the side stream
-        a.trs_pre = S.snap[t % 2];
+      if (l2pre && t >= 1) {
+        a.hinv_pre = hinv_buf(t);   // (H_t + mu I)^{-1} from a side stream
+        a.trs_pre = S.snap[t % 3];
         a.pre_status = S.pre_status;
       }
       if (opt->constraint == IHS_L1_BALL) {  // H_t's factor or inverse, from the side stream
@@ -861,7 +973,9 @@ ihs_status solve_overlap(const ihs_matrix* A, const Layout& L, const ihs_options
                                      hipMemcpyDeviceToDevice, stream)))
       return IHS_ERR_HIP;
   }
-  if (!ck(hipEventRecord(evMisc.at(1), side)) || !ck(hipStreamWaitEvent(stream, evMisc.at(1), 0)) ||
+  if (!sq.drain() || !ck(hipEventRecord(evMisc.at(1), side)) ||
+      !ck(hipStreamWaitEvent(stream, evMisc.at(1), 0)) ||
+      !ck(hipEventRecord(evMisc.at(0), side2)) || !ck(hipStreamWaitEvent(stream, evMisc.at(0), 0)) ||
       !ck(hipEventRecord(evMisc.at(2), sorter)) || !ck(hipStreamWaitEvent(stream, evMisc.at(2), 0)))
     return IHS_ERR_HIP;
   DeviceStatus hm, hs;

@@ -193,6 +193,8 @@ hipError_t launch_l2_snapshot(double* work, int64_t d, int32_t batch, double* sn
 hipError_t launch_l2_prefactor(const double* H, int64_t d, int32_t batch, double* snap, double* L,
                                double* hinv, double* linv, double* scratch, double* rows,
                                DeviceStatus* status, int32_t iter, hipStream_t st);
+// Terms of the shifted-inverse series the l2 step iterates on.
+constexpr int32_t kL2SeriesTerms = 24;
 size_t qp_work_doubles(int64_t d, int32_t constraint);
 hipError_t launch_qp_step(const QpArgs& a, hipStream_t st);
 // The l1-ball, l2-ball and l1-penalty steps (constraint 1, 2, 3); a.work holds

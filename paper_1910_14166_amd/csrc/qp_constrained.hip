@@ -618,12 +618,13 @@ __global__ void k_fill_zero(double* v, int64_t n) {
 }
 
 // ---------------------------------------------------------------------------
-// Largest contraction rho for which a Newton step reuses the held inverse,
-// and the most Richardson sweeps it takes (0.04^13 < 1e-18 at the limit).
-// Twelve sweeps (two mat-vecs each, for x and for z) cost under half of a
-// factorisation and inverse at d = 1024.
-constexpr double kReuseRho = 0.04;
-constexpr int32_t kMaxSweeps = 12;
+// The shifted-inverse series of the l2 step. With R = (H + mu0 I)^{-1} held
+// and beta >= ||R||, every shift mu with |t| < 1, t = -(mu - mu0) beta, has
+// (H + mu I)^{-1} = R sum_j (t R / beta)^j. The series is cut after
+// kSeriesTerms + 1 terms where its tail is provably below kSeriesTail of the
+// first term (see series_reaches).
+constexpr int32_t kSeriesTerms = kL2SeriesTerms;
+constexpr double kSeriesTail = 1e-17;
 
 // l2 ball. State per problem: trs[4p] = mu, trs[4p+1] = phase
 // (0 iterating, 1 one last Newton step, 2 done), trs[4p+2] = the shift mu0
@@ -693,14 +694,15 @@ __global__ __launch_bounds__(256) void k_trs_inside(const double* __restrict__ x
   if (tid == 0) trs[4 * p + 1] = 2.0;
 }
 
-// v = g - mu x^t per problem: with it x(mu) = x^t + (H + mu I)^{-1} v, the
-// same point as (H + mu I)^{-1} (H x^t + g) without forming H x^t.
+// v = g - mu0 x^t per problem (mu0 the shift of the held inverse): with it
+// x(mu0) = x^t + (H + mu0 I)^{-1} v, the same point as (H + mu0 I)^{-1}
+// (H x^t + g) without forming H x^t.
 __global__ void k_trs_rhs(const double* __restrict__ g, const double* __restrict__ x,
                           const double* __restrict__ trs, int64_t d, int32_t batch, double* v) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= (int64_t)batch * d) return;
   const int p = (int)(e / d);
-  v[e] = fma(-trs[4 * p], x[e], g[e]);
+  v[e] = fma(-trs[4 * p + 2], x[e], g[e]);
 }
 
 // out = base + M v per problem (M symmetric, one wavefront per row; base
@@ -719,6 +721,116 @@ __global__ __launch_bounds__(256) void k_trs_symv(const double* __restrict__ M, 
   const double s = row_dot<false>(mr, vp, d, lane);  // issued before the state is read
   if (trs[4 * p + 1] >= 2.0 || status_halted(st)) return;
   if (lane == 0) out[(int64_t)p * d + i] = base ? base[(int64_t)p * d + i] + s : s;
+}
+
+// y_next = (R / beta) v per problem (one wavefront per row; beta = the norm
+// bound trs[4p + 3], base nullable: out = base + R v unscaled), for problems
+// still iterating. The scaling keeps the series vectors y_j = (R / beta)^j y_0
+// at or below the size of y_0 however small or large ||R|| is.
+__global__ __launch_bounds__(256) void k_trs_krylov(const double* __restrict__ R, int64_t d,
+                                                    const double* __restrict__ v,
+                                                    const double* __restrict__ base,
+                                                    double* out, const double* __restrict__ trs,
+                                                    const DeviceStatus* st) {
+  const int p = blockIdx.y;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * 4 + wv;
+  if (i >= d) return;
+  const double s = row_dot<false>(R + ((int64_t)p * d + i) * d, v + (int64_t)p * d, d, lane);
+  if (trs[4 * p + 1] >= 2.0 || status_halted(st)) return;
+  if (lane == 0) {
+    const int64_t e = (int64_t)p * d + i;
+    out[e] = base ? base[e] + s : s / trs[4 * p + 3];
+  }
+}
+
+// The moments M_s = y_0^T (R / beta)^s y_0, s = 0 .. 2J, from the series
+// vectors: M_2j = y_j^T y_j and M_2j+1 = y_j^T y_j+1 (R is symmetric). One
+// workgroup per moment and problem, a fixed summation order.
+__global__ __launch_bounds__(256) void k_trs_moments(const double* __restrict__ Y, int64_t d,
+                                                     int32_t batch, const double* __restrict__ trs,
+                                                     double* mom, const DeviceStatus* st) {
+  __shared__ double red[4];
+  const int sidx = blockIdx.x, p = blockIdx.y, tid = threadIdx.x;
+  if (trs[4 * p + 1] >= 2.0 || status_halted(st)) return;
+  const int j = sidx >> 1, k = j + (sidx & 1);
+  const double* a = Y + ((int64_t)j * batch + p) * d;
+  const double* b = Y + ((int64_t)k * batch + p) * d;
+  double acc = 0.0;
+  for (int64_t i = tid; i < d; i += 256) acc = fma(a[i], b[i], acc);
+  const double m = block256_sum(acc, red);
+  if (tid == 0) mom[(int64_t)p * (2 * kSeriesTerms + 1) + sidx] = m;
+}
+
+// Whether the series cut after y_J (J = kSeriesTerms) reaches the shift with
+// coefficient t: the tail sum_{k > J} t^k y_k has norm at most
+// |t|^(J+1) ||y_J|| / (1 - |t|), since ||R / beta|| <= 1 makes every later
+// vector no longer than y_J; it must stay below kSeriesTail ||y_0||. The
+// measured ||y_J|| = sqrt(M_2J) is far below ||y_0|| when beta overstates
+// ||R||, which widens the reach to what the spectrum allows. Infinite or NaN
+// t (no inverse held) is never reached.
+__device__ __forceinline__ bool series_reaches(double t, double m0, double m2j) {
+  const double a = fabs(t);
+  if (!(a < 1.0)) return false;
+  double pw = a;
+  for (int j = 0; j < kSeriesTerms; ++j) pw *= a;
+  return pw * sqrt(m2j) <= kSeriesTail * (1.0 - a) * sqrt(m0);
+}
+
+// The Newton iteration of k_trs_update on the series: with t = -(mu - mu0)
+// beta, x(mu) = sum_j t^j y_j, so ||x(mu)||^2 = sum_s (s + 1) M_s t^s and
+// x^T (H + mu I)^{-1} x = -(1/2) d||x||^2/dmu = (beta / 2) sum_s s (s + 1)
+// M_s t^(s-1), all from the moments. A shift the series does not reach is
+// left in trs[4p] for a new factorisation; an accepted one is marked phase 3
+// for k_trs_series_x. One thread per problem.
+__global__ void k_trs_series_newton(const double* __restrict__ mom, int32_t batch, double r,
+                                    double tol, int32_t max_steps, double* trs,
+                                    const DeviceStatus* st) {
+  const int p = blockIdx.x * 64 + threadIdx.x;
+  if (p >= batch || status_halted(st) || trs[4 * p + 1] >= 2.0) return;
+  const double* M = mom + (int64_t)p * (2 * kSeriesTerms + 1);
+  const double mu0 = trs[4 * p + 2], beta = trs[4 * p + 3];
+  double mu = trs[4 * p], phase = trs[4 * p + 1];
+  for (int32_t k = 0; k < max_steps; ++k) {
+    const double t = -(mu - mu0) * beta;
+    if (!series_reaches(t, M[0], M[2 * kSeriesTerms])) break;
+    double phi = 0.0, dq = 0.0;  // Horner, highest power first
+    for (int sidx = 2 * kSeriesTerms; sidx >= 0; --sidx) {
+      phi = fma(phi, t, (sidx + 1) * M[sidx]);
+      if (sidx >= 1) dq = fma(dq, t, 0.5 * sidx * (sidx + 1) * M[sidx]);
+    }
+    const double nx2 = phi, q = beta * dq, nx = sqrt(nx2);
+    if (phase == 1.0 || (mu == 0.0 && nx <= r)) {
+      trs[4 * p] = mu;
+      trs[4 * p + 1] = 3.0;
+      return;
+    }
+    const double next = fmax(mu + (nx2 / q) * ((nx - r) / r), 0.0);
+    if (fabs(nx - r) <= tol * r) phase = 1.0;
+    mu = next;
+  }
+  trs[4 * p] = mu;
+  trs[4 * p + 1] = phase;
+}
+
+// x_out = sum_j t^j y_j for the problems the series accepted (phase 3), which
+// then finish (phase 2).
+__global__ __launch_bounds__(256) void k_trs_series_x(const double* __restrict__ Y, int64_t d,
+                                                      int32_t batch, double* trs, double* xout,
+                                                      const DeviceStatus* st) {
+  __shared__ int take;
+  const int p = blockIdx.x, tid = threadIdx.x;
+  if (tid == 0) take = (!status_halted(st) && trs[4 * p + 1] == 3.0) ? 1 : 0;
+  __syncthreads();
+  if (!take) return;
+  const double t = -(trs[4 * p] - trs[4 * p + 2]) * trs[4 * p + 3];
+  for (int64_t i = tid; i < d; i += 256) {
+    double acc = Y[((int64_t)kSeriesTerms * batch + p) * d + i];
+    for (int j = kSeriesTerms - 1; j >= 0; --j) acc = fma(acc, t, Y[((int64_t)j * batch + p) * d + i]);
+    xout[(int64_t)p * d + i] = acc;
+  }
+  __syncthreads();
+  if (tid == 0) trs[4 * p + 1] = 2.0;
 }
 
 // Given x = x(mu) and z = (H + mu I)^{-1} x, applies the Newton step
@@ -796,37 +908,6 @@ __global__ __launch_bounds__(256) void k_trs_inv_norm(const double* __restrict__
     trs[4 * p + 2] = mu0;
     trs[4 * p + 3] = nrm;
   }
-}
-
-// out = v - (H + mu I) w per problem (one wavefront per row), for problems
-// still iterating: the residual of a Richardson sweep.
-__global__ __launch_bounds__(256) void k_trs_resid(const double* __restrict__ H, int64_t d,
-                                                   const double* __restrict__ w,
-                                                   const double* __restrict__ v, double* out,
-                                                   const double* __restrict__ trs,
-                                                   const DeviceStatus* st) {
-  const int p = blockIdx.y;
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t i = (int64_t)blockIdx.x * 4 + wv;
-  if (i >= d) return;
-  const double* hr = H + ((int64_t)p * d + i) * d;
-  const double* wp = w + (int64_t)p * d;
-  const double s = row_dot<false>(hr, wp, d, lane);  // issued before the state is read
-  if (trs[4 * p + 1] >= 2.0 || status_halted(st)) return;
-  if (lane == 0) {
-    const int64_t e = (int64_t)p * d + i;
-    out[e] = v[e] - s - trs[4 * p] * w[e];
-  }
-}
-
-// x = base + w per problem, for problems still iterating.
-__global__ void k_trs_axpy(const double* __restrict__ base, const double* __restrict__ w,
-                           const double* __restrict__ trs, int64_t d, int32_t batch, double* x) {
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= (int64_t)batch * d) return;
-  const int p = (int)(e / d);
-  if (trs[4 * p + 1] >= 2.0) return;
-  x[e] = base[e] + w[e];
 }
 
 // Problems still iterating after the last Newton step keep x^t and report.
@@ -944,85 +1025,51 @@ hipError_t launch_qp_constrained(const QpArgs& a, hipStream_t st) {
     hipLaunchKernelGGL(k_trs_update, dim3(B), dim3(256), 0, st, xunc, zk, d, a.radius, tol, trs,
                        a.x_out, a.status);
   }
-  // Each Newton step needs x(mu) = x^t + (H + mu I)^{-1} (g - mu x^t) and
-  // z = (H + mu I)^{-1} x(mu). It factors H + mu I and forms the inverse,
-  // unless the inverse held from an earlier shift mu0 is close enough: with
-  // rho = |mu - mu0| ||(H + mu0 I)^{-1}|| the preconditioned Richardson
-  // sweep w <- w + (H + mu0 I)^{-1} (v - (H + mu I) w) contracts the error by
-  // rho, and a few sweeps reach rounding level (the last Newton step, whose
-  // shift moves at rounding level, always qualifies).
-  double* wbuf = xunc;  // free once the cold start is done
-  double* rbuf = zero;
+  // The Newton iteration runs on the series of a held inverse R = (H + mu0
+  // I)^{-1}: y_0 = x(mu0), y_j = (R / beta) y_j-1 and their moments give
+  // ||x(mu)|| and its derivative at every shift the series reaches, so the
+  // iteration itself needs no solve and no read-back. A round factors H + mu I
+  // at the current shift (unless an inverse formed ahead is held), forms the
+  // series and iterates; a shift beyond its reach starts the next round there.
+  // The accepted x(mu) is formed from the series vectors.
+  double* Y = linv + (int64_t)B * d * d;
+  double* mom = Y + (int64_t)(kSeriesTerms + 1) * B * d;
   std::vector<double> h;
   bool held = false;
-  const double* hinv_use = hinv;
+  const double* R = hinv;
   if (a.warm && a.hinv_pre && a.trs_pre) {  // an inverse formed ahead at a nearby shift
     hipLaunchKernelGGL(k_trs_adopt, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, st, trs,
                        a.trs_pre, B, a.pre_status);
-    if (trs_all_done(trs, a.status, B, st, h)) {
-      hipLaunchKernelGGL(k_trs_finish, dim3(B), dim3(256), 0, st, trs, d, a.x, a.x_out, a.status,
-                         a.iter);
-      return hipGetLastError();
-    }
     held = true;
-    hinv_use = a.hinv_pre;
+    R = a.hinv_pre;
   }
-  // out = base + (H + mu I)^{-1} v by S sweeps from (H + mu0 I)^{-1} v (base
-  // nullable; out must differ from v)
-  auto richardson = [&](const double* v, const double* base, double* out, int32_t S) {
-    double* w = base ? wbuf : out;
-    hipLaunchKernelGGL(k_trs_symv, rows_grid, dim3(256), 0, st, hinv_use, d, v, nullptr, w, trs,
-                       a.status);
-    for (int32_t j = 0; j < S; ++j) {
-      hipLaunchKernelGGL(k_trs_resid, rows_grid, dim3(256), 0, st, a.H, d, w, v, rbuf, trs,
-                         a.status);
-      hipLaunchKernelGGL(k_trs_symv, rows_grid, dim3(256), 0, st, hinv_use, d, rbuf, w, w, trs,
-                         a.status);
-    }
-    if (base)
-      hipLaunchKernelGGL(k_trs_axpy, dim3((unsigned)((bd + 255) / 256)), dim3(256), 0, st, base, w,
-                         trs, d, B, out);
-  };
-  for (int32_t k = 0; k < newton; ++k) {
-    double rho = INFINITY;
-    if (held) {
-      rho = 0.0;
-      for (int32_t p = 0; p < B; ++p)
-        if (h[(size_t)4 * p + 1] < 2.0)
-          rho = std::max(rho, std::fabs(h[(size_t)4 * p] - h[(size_t)4 * p + 2]) *
-                                  h[(size_t)4 * p + 3]);
-    }
-    int32_t sweeps = 0;
-    if (!(rho <= kReuseRho)) {
+  for (int32_t round = 0; round < newton; ++round) {
+    if (!held) {
       if ((e = launch_cholesky(a.H, a.L, d, B, a.status, a.iter, 0.0, scratch, st, trs)) !=
           hipSuccess)
         return e;
       if ((e = launch_chol_inverse(a.L, rdiag, d, B, hinv, linv, a.status, st, trs)) !=
           hipSuccess)
         return e;
-      hipLaunchKernelGGL(k_trs_abs_rows, rows_grid, dim3(256), 0, st, hinv, d, trs, rbuf,
+      hipLaunchKernelGGL(k_trs_abs_rows, rows_grid, dim3(256), 0, st, hinv, d, trs, zero,
                          a.status);
-      hipLaunchKernelGGL(k_trs_inv_norm, dim3(B), dim3(256), 0, st, rbuf, d, trs, a.status);
-      held = true;
-      hinv_use = hinv;
-    } else {
-      // error after j sweeps <= rho^(j+1) relative to the solution
-      sweeps = 1;
-      while (sweeps < kMaxSweeps && std::pow(rho, sweeps + 1) > 1e-17) ++sweeps;
+      hipLaunchKernelGGL(k_trs_inv_norm, dim3(B), dim3(256), 0, st, zero, d, trs, a.status);
+      R = hinv;
     }
+    held = false;
     hipLaunchKernelGGL(k_trs_rhs, dim3((unsigned)((bd + 255) / 256)), dim3(256), 0, st, a.g, a.x,
                        trs, d, B, cbuf);
-    if (sweeps == 0) {
-      hipLaunchKernelGGL(k_trs_symv, rows_grid, dim3(256), 0, st, hinv, d, cbuf, a.x, xk, trs,
-                         a.status);
-      hipLaunchKernelGGL(k_trs_symv, rows_grid, dim3(256), 0, st, hinv, d, xk, nullptr, zk, trs,
-                         a.status);
-    } else {
-      richardson(cbuf, a.x, xk, sweeps);
-      richardson(xk, nullptr, zk, sweeps);
-    }
-    hipLaunchKernelGGL(k_trs_update, dim3(B), dim3(256), 0, st, xk, zk, d, a.radius, tol, trs,
-                       a.x_out, a.status);
+    hipLaunchKernelGGL(k_trs_krylov, rows_grid, dim3(256), 0, st, R, d, cbuf, a.x, Y, trs,
+                       a.status);
+    for (int32_t j = 1; j <= kSeriesTerms; ++j)
+      hipLaunchKernelGGL(k_trs_krylov, rows_grid, dim3(256), 0, st, R, d, Y + (j - 1) * bd,
+                         nullptr, Y + j * bd, trs, a.status);
+    hipLaunchKernelGGL(k_trs_moments, dim3(2 * kSeriesTerms + 1, B), dim3(256), 0, st, Y, d, B,
+                       trs, mom, a.status);
+    hipLaunchKernelGGL(k_trs_series_newton, dim3((unsigned)((B + 63) / 64)), dim3(64), 0, st, mom,
+                       B, a.radius, tol, newton, trs, a.status);
+    hipLaunchKernelGGL(k_trs_series_x, dim3(B), dim3(256), 0, st, Y, d, B, trs, a.x_out,
+                       a.status);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (trs_all_done(trs, a.status, B, st, h)) break;
   }
