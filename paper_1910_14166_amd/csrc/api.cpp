@@ -883,6 +883,16 @@ ihs_status solve_overlap(const ihs_matrix* A, const Layout& L, const ihs_options
   // chol_job[k % 4]: the side job that records evChol(k) (0: recorded above)
   std::vector<int64_t> chol_job(4, 0);
   SideQueue sq(dev);  // after everything its jobs refer to, so it is joined first
+  // side: H_{t+LA} and its factor, queued by the side thread once `after`
+  // has been reached on the caller's stream
+  auto post_side = [&](int32_t t, hipEvent_t after) {
+    const int64_t job = sq.post([&, t, after]() {
+      const hipStream_t sk = side_of(t + LA);
+      if (!ck(hipStreamWaitEvent(sk, after, 0))) return false;
+      return t + LA >= N || (factor(t + LA) && ck(hipEventRecord(evChol.at(t + LA), sk)));
+    });
+    chol_job.at((size_t)((t + LA) % chol_job.size())) = job;
+  };
   for (int32_t t = 0; t < N; ++t) {
     // main (l2 ball): the shift state after QP_{t-1}, for the factorisation
     // of H_{t+LA} + mu I that a side stream starts once pass t is done
@@ -907,14 +917,8 @@ ihs_status solve_overlap(const ihs_matrix* A, const Layout& L, const ihs_options
           !ck(hipEventRecord(evSort.at(t + LA + 1), sorter)))
         return IHS_ERR_HIP;
     }
-    // side: H_{t+LA} and its factor, during the next LA passes (queued by
-    // the side thread)
-    const int64_t job = sq.post([&, t]() {
-      const hipStream_t sk = side_of(t + LA);
-      if (!ck(hipStreamWaitEvent(sk, evPass.at(t), 0))) return false;
-      return t + LA >= N || (factor(t + LA) && ck(hipEventRecord(evChol.at(t + LA), sk)));
-    });
-    chol_job.at((size_t)((t + LA) % chol_job.size())) = job;
+    // side: H_{t+LA} and its factor, from the end of pass t on
+    post_side(t, evPass.at(t));
     // main: x^{t+1} = x^t + H_t^{-1} g(x^t), or the constrained QP of Eq.(2)
     // with H_t (its l2 shift state carries over in S.work from step to step)
     if (!sq.wait(chol_job.at((size_t)(t % chol_job.size()))) ||

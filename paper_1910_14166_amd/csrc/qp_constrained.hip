@@ -791,6 +791,11 @@ __global__ void k_trs_series_newton(const double* __restrict__ mom, int32_t batc
   const double* M = mom + (int64_t)p * (2 * kSeriesTerms + 1);
   const double mu0 = trs[4 * p + 2], beta = trs[4 * p + 3];
   double mu = trs[4 * p], phase = trs[4 * p + 1];
+  // a warm start beyond the series' reach starts at mu0 instead (t = 0, where
+  // the series is exact): the root may still lie within reach
+  if (phase == 0.0 && !series_reaches(-(mu - mu0) * beta, M[0], M[2 * kSeriesTerms]) &&
+      series_reaches(0.0, M[0], M[2 * kSeriesTerms]))
+    mu = mu0;
   for (int32_t k = 0; k < max_steps; ++k) {
     const double t = -(mu - mu0) * beta;
     if (!series_reaches(t, M[0], M[2 * kSeriesTerms])) break;

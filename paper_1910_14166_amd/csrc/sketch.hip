@@ -719,16 +719,105 @@ hipError_t launch_gradient_rows(const ProbInfo* probs, int32_t batch, int32_t to
 }
 
 // ---------------------------------------------------------------------------
-// CSR bucket gather. One wavefront per sketch row keeps a dense row of S A
-// (and of the gradient partial) in LDS. Nonzeros are staged 64 at a time in
+// CSR gradient rows in natural order (the gradient pass without a sketch;
+// k_gather_csr_bucket below is the sketch's gather). One wavefront per
+// segment of rows keeps a dense gradient row in LDS. Nonzeros are staged 64 at a time in
 // (row, column) order; lanes holding the same column are ranked with ballots
-// and applied round by round, so each (sketch row, column) still sums in
-// ascending row order.
+// and applied round by round, so each column still sums in ascending row
+// order.
 // ---------------------------------------------------------------------------
-template <bool GRAD, bool IDENT>
-__global__ __launch_bounds__(256) void k_gather_csr(SketchPlan P, CsrGatherArgs G,
-                                                    int32_t col_bits, int32_t total_seg,
-                                                    int32_t seg_rows) {
+__global__ __launch_bounds__(256) void k_gradient_rows_csr(SketchPlan P, CsrGatherArgs G,
+                                                           int32_t col_bits, int32_t total_seg,
+                                                           int32_t seg_rows) {
+  extern __shared__ double smem[];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t d = G.d;
+  double* gac = smem + (int64_t)wv * d;
+  __shared__ int32_t st_col[4][64];
+  __shared__ double st_rv[4][64];
+  const int64_t bg = (int64_t)blockIdx.x * 4 + wv;
+  if (bg >= (int64_t)total_seg) return;  // no workgroup barriers below
+  if (G.halt != nullptr && status_word(G.halt) != 0) return;
+  const int p = find_by_seg(P.probs, P.batch, (int)bg);
+  const ProbInfo pi = P.probs[p];
+  const int64_t beg = pi.row0 + (bg - pi.seg0) * (int64_t)seg_rows;
+  const int64_t end = min(beg + seg_rows, pi.row0 + pi.rows);
+  for (int64_t c = lane; c < d; c += 64) gac[c] = 0.0;
+  const uint64_t lt = lanemask_lt();
+  double fa = 0.0;
+  for (int64_t base = beg; base < end; base += 64) {
+    const bool rv_ok = base + lane < end;
+    const int64_t row = base + lane;
+    int32_t rs = 0, re = 0;
+    if (rv_ok) {
+      rs = G.row_ptr[row];
+      re = G.row_ptr[row + 1];
+    }
+    double ri = 0.0;
+    if (rv_ok) {
+      double dot = 0.0;
+      for (int32_t q = rs; q < re; ++q) dot = fma(G.values[q], G.x[(int64_t)p * d + G.col_idx[q]], dot);
+      ri = G.b[row] - dot;
+      fa = fma(ri, ri, fa);
+      if (G.r_out != nullptr) G.r_out[row] = ri;
+    }
+    // flattened positions of this batch's nonzeros
+    const int len = re - rs;
+    int incl = len;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int y = __shfl_up(incl, off, 64);
+      if (lane >= off) incl += y;
+    }
+    const int excl = incl - len;
+    const int total = __shfl(incl, 63, 64);
+    for (int w0 = 0; w0 < total; w0 += 64) {
+      // stage the nonzeros whose flattened index falls in [w0, w0 + 64)
+      for (int q = max(excl, w0); q < min(excl + len, w0 + 64); ++q) {
+        const int32_t src = rs + (q - excl);
+        st_col[wv][q - w0] = G.col_idx[src];
+        st_rv[wv][q - w0] = ri * G.values[src];
+      }
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      const bool ok = (w0 + lane) < total;
+      const int32_t col = ok ? st_col[wv][lane] : 0;
+      const double rvv = ok ? st_rv[wv][lane] : 0.0;
+      uint64_t peers = __ballot(ok);
+      for (int bit = 0; bit < col_bits; ++bit) {
+        const bool on = (col >> bit) & 1;
+        const uint64_t bb = __ballot(on);
+        peers &= on ? bb : ~bb;
+      }
+      const int rank = __popcll(peers & lt);
+      for (int r = 0; __ballot(ok && rank >= r) != 0ull; ++r) {
+        if (ok && rank == r) gac[col] = gac[col] + rvv;
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      }
+    }
+  }
+  double* gp = G.gpart + bg * d;
+  for (int64_t c = lane; c < d; c += 64) gp[c] = gac[c];
+  const double fs = wave_sum(fa);
+  if (lane == 0) G.fpart[bg] = fs;
+}
+
+// ---------------------------------------------------------------------------
+// CSR bucket gather. One wavefront per sketch row keeps a dense row of S A
+// (and of the gradient partial) in LDS and walks the sketch row's sorted rows
+// 64 at a time. The walk is software-pipelined: the sorted-row entries are
+// requested two batches ahead and the rows' extents (and b) one batch ahead,
+// so a batch waits only for its own nonzeros. Nonzeros are staged 64 at a
+// time in (row, column) order; lanes holding the same column are ranked with
+// ballots and applied round by round, so each (sketch row, column) still sums
+// in ascending row order.
+// ---------------------------------------------------------------------------
+template <bool GRAD>
+__global__ __launch_bounds__(256) void k_gather_csr_bucket(SketchPlan P, CsrGatherArgs G,
+                                                           int32_t col_bits) {
   extern __shared__ double smem[];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t d = G.d;
@@ -737,50 +826,54 @@ __global__ __launch_bounds__(256) void k_gather_csr(SketchPlan P, CsrGatherArgs 
   __shared__ int32_t st_col[4][64];
   __shared__ double st_val[4][64];
   __shared__ double st_rv[4][64];
-  const int64_t nbk = IDENT ? (int64_t)total_seg : (int64_t)P.batch * P.m;
+  const int64_t nbk = (int64_t)P.batch * P.m;
   const int64_t bg = (int64_t)blockIdx.x * 4 + wv;
   if (bg >= nbk) return;  // no workgroup barriers below: waves are independent
   if (G.halt != nullptr && status_word(G.halt) != 0) return;
-  int p;
-  int64_t bl, beg, end, gslot;
-  if (IDENT) {
-    p = find_by_seg(P.probs, P.batch, (int)bg);
-    const ProbInfo pi = P.probs[p];
-    beg = pi.row0 + (bg - pi.seg0) * (int64_t)seg_rows;
-    end = min(beg + seg_rows, pi.row0 + pi.rows);
-    bl = 0;
-    gslot = bg;
-  } else {
-    p = (int)(bg / P.m);
-    bl = bg - (int64_t)p * P.m;
-    beg = P.bucket_start[bg];
-    end = P.bucket_start[bg + 1];
-    gslot = (int64_t)p * P.m_blk + bl;
-  }
+  const int p = (int)(bg / P.m);
+  const int64_t bl = bg - (int64_t)p * P.m;
+  const int64_t beg = P.bucket_start[bg], end = P.bucket_start[bg + 1];
+  const int64_t gslot = (int64_t)p * P.m_blk + bl;
   const bool grad = GRAD && (bl < P.m_blk);
   for (int64_t c = lane; c < d; c += 64) {
-    if (!IDENT) acc[c] = 0.0;
+    acc[c] = 0.0;
     if (GRAD) gac[c] = 0.0;
   }
   const uint64_t lt = lanemask_lt();
+  const double* xp = G.x + (int64_t)p * d;
+  auto perm_at = [&](int64_t base) -> uint32_t {
+    return base + lane < end ? P.perm[base + lane] : 0u;
+  };
+  // the current batch's entry and extent, the next batch's entry
+  uint32_t pe = perm_at(beg), pe_n = perm_at(beg + 64);
+  int32_t rs = 0, re = 0;
+  double bi = 0.0;
+  if (beg + lane < end) {
+    const uint32_t row = pe & 0x7FFFFFFFu;
+    rs = G.row_ptr[row];
+    re = G.row_ptr[row + 1];
+    if (grad) bi = G.b[row];
+  }
   double fa = 0.0;
   for (int64_t base = beg; base < end; base += 64) {
-    const int cnt = (int)min((int64_t)64, end - base);
-    const bool rv_ok = lane < cnt;
-    uint32_t pe = 0u;
-    if (rv_ok) pe = IDENT ? (uint32_t)(base + lane) : P.perm[base + lane];
+    const bool rv_ok = base + lane < end;
+    // requests for the next two batches
+    const uint32_t pe_nn = perm_at(base + 128);
+    int32_t rs_n = 0, re_n = 0;
+    double bi_n = 0.0;
+    if (base + 64 + lane < end) {
+      const uint32_t row_n = pe_n & 0x7FFFFFFFu;
+      rs_n = G.row_ptr[row_n];
+      re_n = G.row_ptr[row_n + 1];
+      if (grad) bi_n = G.b[row_n];
+    }
     const uint32_t row = pe & 0x7FFFFFFFu;
     const double sg = (pe >> 31) ? -1.0 : 1.0;
-    int32_t rs = 0, re = 0;
-    if (rv_ok) {
-      rs = G.row_ptr[row];
-      re = G.row_ptr[row + 1];
-    }
     double ri = 0.0;
     if (grad && rv_ok) {
       double dot = 0.0;
-      for (int32_t q = rs; q < re; ++q) dot = fma(G.values[q], G.x[(int64_t)p * d + G.col_idx[q]], dot);
-      ri = G.b[row] - dot;
+      for (int32_t q = rs; q < re; ++q) dot = fma(G.values[q], xp[G.col_idx[q]], dot);
+      ri = bi - dot;
       fa = fma(ri, ri, fa);
       if (G.r_out != nullptr) G.r_out[row] = ri;
     }
@@ -819,7 +912,7 @@ __global__ __launch_bounds__(256) void k_gather_csr(SketchPlan P, CsrGatherArgs 
       const int rank = __popcll(peers & lt);
       for (int r = 0; __ballot(ok && rank >= r) != 0ull; ++r) {
         if (ok && rank == r) {
-          if (!IDENT) acc[col] = acc[col] + v;
+          acc[col] = acc[col] + v;
           if (grad) gac[col] = gac[col] + rvv;
         }
         __builtin_amdgcn_wave_barrier();
@@ -827,11 +920,14 @@ __global__ __launch_bounds__(256) void k_gather_csr(SketchPlan P, CsrGatherArgs 
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       }
     }
+    pe = pe_n;
+    pe_n = pe_nn;
+    rs = rs_n;
+    re = re_n;
+    bi = bi_n;
   }
-  if (!IDENT) {
-    const int64_t orow = bg * G.ld_sa;
-    for (int64_t c = lane; c < d; c += 64) store_sa(G.SA, G.sa_dtype, orow + c, acc[c] * G.scale);
-  }
+  const int64_t orow = bg * G.ld_sa;
+  for (int64_t c = lane; c < d; c += 64) store_sa(G.SA, G.sa_dtype, orow + c, acc[c] * G.scale);
   if (grad) {
     double* gp = G.gpart + gslot * d;
     for (int64_t c = lane; c < d; c += 64) gp[c] = gac[c];
@@ -853,11 +949,11 @@ hipError_t launch_sketch_gather_csr(const SketchPlan& P, const CsrGatherArgs& G,
   const bool grad = G.b != nullptr;
   const size_t lds = (size_t)4 * (grad ? 2 : 1) * G.d * sizeof(double);
   if (grad)
-    hipLaunchKernelGGL((k_gather_csr<true, false>), dim3(blocks), dim3(256), lds, st, P, G,
-                       bits_for(G.d), 0, 0);
+    hipLaunchKernelGGL(k_gather_csr_bucket<true>, dim3(blocks), dim3(256), lds, st, P, G,
+                       bits_for(G.d));
   else
-    hipLaunchKernelGGL((k_gather_csr<false, false>), dim3(blocks), dim3(256), lds, st, P, G,
-                       bits_for(G.d), 0, 0);
+    hipLaunchKernelGGL(k_gather_csr_bucket<false>, dim3(blocks), dim3(256), lds, st, P, G,
+                       bits_for(G.d));
   return hipGetLastError();
 }
 
@@ -884,10 +980,9 @@ hipError_t launch_gradient_rows_csr(const ProbInfo* probs, int32_t batch, int32_
   G.gpart = gpart;
   G.fpart = fpart;
   G.r_out = r_out;
-  // the IDENT variant keeps only the gradient row in LDS; acc aliases it
-  const size_t lds = (size_t)4 * 2 * d * sizeof(double);
-  hipLaunchKernelGGL((k_gather_csr<true, true>), dim3((unsigned)((total_seg + 3) / 4)),
-                     dim3(256), lds, st, P, G, bits_for(d), total_seg, seg_rows);
+  const size_t lds = (size_t)4 * d * sizeof(double);
+  hipLaunchKernelGGL(k_gradient_rows_csr, dim3((unsigned)((total_seg + 3) / 4)), dim3(256), lds,
+                     st, P, G, bits_for(d), total_seg, seg_rows);
   return hipGetLastError();
 }
 

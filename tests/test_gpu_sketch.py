@@ -125,8 +125,12 @@ def test_empty_matrix_gives_zero_sketch(gpu_lib):
 
 @pytest.mark.parametrize("n,d,density,m,s", [(3000, 40, 0.05, 64, 1), (20000, 300, 0.01, 512, 4),
                                              (500, 1024, 0.002, 16, 1), (100, 5, 0.0, 8, 1),
-                                             (800, 30, 0.2, 8, 8)])
+                                             (800, 30, 0.2, 8, 8), (300, 1024, 0.2, 32, 2),
+                                             (40000, 64, 0.05, 16384, 1)])
 def test_csr_sketch_bit_exact(gpu_lib, n, d, density, m, s):
+    """Bit-exact against the oracle's sequential definition, with rows of
+    ~200 nonzeros (several 64-entry batches per row) and the largest number
+    of sketch rows (the sort's two LDS histograms at their largest)."""
     P = gpu_lib
     import torch
     wl = W.ridge_csr(rows=n, d=d, density=density, m=m)
