@@ -819,8 +819,10 @@ ihs_status solve_overlap(const ihs_matrix* A, const Layout& L, const ihs_options
   };
   auto factor = [&](int64_t k) -> bool {  // side stream: H_k, its factor (and inverse)
     const hipStream_t sk = side_of(k);
+    // the l2 step's Gram runs beside the step's latency-bound series products:
+    // three workgroups per CU leave each SIMD registers for them
     if (!ck(launch_gram(sa_buf(k), opt->gram_in, m, d, d, L.batch, opt->gram_acc, h_buf(k),
-                        (k % 2 && l2pre) ? S.gram_part1 : S.gram_part, sk)))
+                        (k % 2 && l2pre) ? S.gram_part1 : S.gram_part, sk, l2pre ? 3 : 4)))
       return false;
     // The constrained QPs work from H_k itself; the l1 ball's also needs the
     // unconstrained minimiser, so H_k is factored (and, from kInverseMinD

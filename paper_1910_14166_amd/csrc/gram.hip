@@ -35,11 +35,13 @@ static int tile_of(int32_t in_dtype) { return in_dtype == 2 ? kTileBf16 : kTileF
 
 // Workgroups of each kernel that fit on one CU at once (LDS and registers):
 // the slices are sized so that all workgroups run in one round, since a
-// second, partly filled round would double the time.
+// second, partly filled round would double the time. `per_cu` caps the
+// workgroups per CU below that (a Gram that runs beside latency-bound work
+// leaves registers free for it).
 constexpr int kCUs = 256;
 
 static GramPlan make_gram_plan(int64_t m, int64_t d, int64_t ld, int32_t batch, int32_t acc,
-                               int32_t in) {
+                               int32_t in, int32_t per_cu = 4) {
   GramPlan g;
   g.m = m;
   g.d = d;
@@ -48,7 +50,7 @@ static GramPlan make_gram_plan(int64_t m, int64_t d, int64_t ld, int32_t batch, 
   g.tile = tile_of(in);
   g.ntile = (int32_t)((d + g.tile - 1) / g.tile);
   g.ntri = g.ntile * (g.ntile + 1) / 2;
-  const int64_t slots = (int64_t)kCUs * 4;
+  const int64_t slots = (int64_t)kCUs * std::max(1, std::min(per_cu, 4));
   const int64_t tiles = (int64_t)batch * g.ntri;
   int64_t splits = std::max<int64_t>(1, slots / tiles);
   splits = std::min<int64_t>(splits, std::max<int64_t>(1, m / 128));  // >= 128 rows a slice
@@ -480,8 +482,8 @@ __global__ __launch_bounds__(256) void k_gram_reduce(GramPlan G, const TP* __res
 
 hipError_t launch_gram(const void* SA, int32_t in_dtype, int64_t m, int64_t d, int64_t ld,
                        int32_t batch, int32_t acc_dtype, double* H, void* partials,
-                       hipStream_t st) {
-  const GramPlan G = make_gram_plan(m, d, ld, batch, acc_dtype, in_dtype);
+                       hipStream_t st, int32_t per_cu) {
+  const GramPlan G = make_gram_plan(m, d, ld, batch, acc_dtype, in_dtype, per_cu);
   const unsigned blocks = (unsigned)((int64_t)batch * G.ntri * G.splits);
   const dim3 rgrid((unsigned)((int64_t)batch * G.ntri * (G.tile / 64) * (G.tile / 64) *
                               (64 / kRedStrip)));

@@ -154,9 +154,12 @@ hipError_t launch_recip_diag(const double* L, int64_t d, int32_t batch, double* 
 // Gram H = SA^T SA.
 size_t gram_partials_bytes(int64_t m, int64_t d, int32_t batch, int32_t in_dtype,
                            int32_t acc_dtype);
+// per_cu (1 .. 4): workgroups per CU the launch may fill; below 4 the Gram
+// takes longer but leaves registers for kernels running beside it. The
+// partials buffer sized by gram_partials_bytes serves every per_cu.
 hipError_t launch_gram(const void* SA, int32_t in_dtype, int64_t m, int64_t d,
                        int64_t ld, int32_t batch, int32_t acc_dtype, double* H,
-                       void* partials, hipStream_t st);
+                       void* partials, hipStream_t st, int32_t per_cu = 4);
 
 // QP step kernels.
 struct QpArgs {

@@ -1044,14 +1044,14 @@ hipError_t launch_pcg_p(const double* r, const double* z, double* pm, double* rh
 // buffer of the blocked Cholesky plus vectors.
 size_t qp_work_doubles(int64_t d, int32_t constraint) {
   // ball steps add c, the unconstrained minimiser, two Newton vectors, a
-  // spare vector and the shift state; the l2 step also H^{-1}, L^{-1}, the
-  // series vectors and their moments;
+  // spare vector and the shift state; the l2 step also H^{-1}, L^{-1} and the
+  // series vectors;
   // the wide unconstrained step H^{-1}, L^{-1} and its dx
   size_t n = (size_t)(kNb * kNb + 9 * d + 64);
   if (constraint == 0 && d >= kQpInverseMinD) n += (size_t)(2 * d * d + d);
   if (constraint != 0) n += (size_t)(5 * d + 8);
   if (constraint == 2)
-    n += (size_t)(2 * d * d + (kL2SeriesTerms + 1) * d + 2 * kL2SeriesTerms + 1);
+    n += (size_t)(2 * d * d + (kL2SeriesTerms + 1) * d);
   return n;
 }
 

@@ -620,10 +620,13 @@ __global__ void k_fill_zero(double* v, int64_t n) {
 // ---------------------------------------------------------------------------
 // The shifted-inverse series of the l2 step. With R = (H + mu0 I)^{-1} held
 // and beta >= ||R||, every shift mu with |t| < 1, t = -(mu - mu0) beta, has
-// (H + mu I)^{-1} = R sum_j (t R / beta)^j. The series is cut after
-// kSeriesTerms + 1 terms where its tail is provably below kSeriesTail of the
-// first term (see series_reaches).
+// (H + mu I)^{-1} = R sum_j (t R / beta)^j. The series is cut after J + 1
+// terms where its tail is provably below kSeriesTail of the first term (see
+// series_reaches): first at J = kSeriesFirst, which covers the small shift
+// changes of later steps, then, for the problems that need it, at
+// J = kSeriesTerms.
 constexpr int32_t kSeriesTerms = kL2SeriesTerms;
+constexpr int32_t kSeriesFirst = 8;
 constexpr double kSeriesTail = 1e-17;
 
 // l2 ball. State per problem: trs[4p] = mu, trs[4p+1] = phase
@@ -640,18 +643,28 @@ __device__ __forceinline__ double block256_sum(double v, double* red) {
   return red[0] + red[1] + red[2] + red[3];
 }
 
-// The inverse of H + mu0 I formed ahead of the step (on another stream, at
-// the shift mu0 of a snapshot): its shift and norm bound become the held
-// state, so the first Newton step can sweep from it instead of factoring.
-// A failure recorded while forming it (pre_st) leaves an infinite bound, so
-// the step factors H + mu I itself as it would without the inverse.
-__global__ void k_trs_adopt(double* trs, const double* pre, int32_t batch,
-                            const DeviceStatus* pre_st) {
-  const int p = blockIdx.x * 256 + threadIdx.x;
-  if (p >= batch) return;
-  const bool bad = pre_st != nullptr && status_failed_by(pre_st, -1);
-  trs[4 * p + 2] = pre[4 * p + 2];
-  trs[4 * p + 3] = bad ? INFINITY : pre[4 * p + 3];
+// Start of a warm step that holds the inverse of H + mu0 I formed ahead (on
+// another stream, at the shift mu0 of a snapshot `pre`): the shift starts
+// from the previous step's root, the inverse's shift and norm bound become
+// the held state, and v = g - mu0 x^t (as k_trs_rhs). A failure recorded
+// while forming the inverse (pre_st) leaves an infinite bound, so the step
+// factors H + mu I itself as it would without it. One thread per entry of v.
+__global__ void k_trs_begin_held(double* trs, const double* __restrict__ pre,
+                                 const DeviceStatus* pre_st, const double* __restrict__ g,
+                                 const double* __restrict__ x, int64_t d, int32_t batch,
+                                 double* v) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)batch * d) return;
+  const int p = (int)(e / d);
+  const double mu0 = pre[4 * p + 2];
+  v[e] = fma(-mu0, x[e], g[e]);
+  if (e - (int64_t)p * d == 0) {
+    const bool bad = pre_st != nullptr && status_failed_by(pre_st, -1);
+    trs[4 * p] = fmax(trs[4 * p], 0.0);
+    trs[4 * p + 1] = 0.0;
+    trs[4 * p + 2] = mu0;
+    trs[4 * p + 3] = bad ? INFINITY : pre[4 * p + 3];
+  }
 }
 
 // The shift state as the next step's side work will see it: mu of each
@@ -726,7 +739,10 @@ __global__ __launch_bounds__(256) void k_trs_symv(const double* __restrict__ M, 
 // y_next = (R / beta) v per problem (one wavefront per row; beta = the norm
 // bound trs[4p + 3], base nullable: out = base + R v unscaled), for problems
 // still iterating. The scaling keeps the series vectors y_j = (R / beta)^j y_0
-// at or below the size of y_0 however small or large ||R|| is.
+// at or below the size of y_0 however small or large ||R|| is. LATE: the
+// problem has usually finished already, so its state is read first and the
+// row only when needed; otherwise the row's loads go out first.
+template <bool LATE>
 __global__ __launch_bounds__(256) void k_trs_krylov(const double* __restrict__ R, int64_t d,
                                                     const double* __restrict__ v,
                                                     const double* __restrict__ base,
@@ -736,106 +752,117 @@ __global__ __launch_bounds__(256) void k_trs_krylov(const double* __restrict__ R
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t i = (int64_t)blockIdx.x * 4 + wv;
   if (i >= d) return;
+  if (LATE && (trs[4 * p + 1] >= 2.0 || status_halted(st))) return;
   const double s = row_dot<false>(R + ((int64_t)p * d + i) * d, v + (int64_t)p * d, d, lane);
-  if (trs[4 * p + 1] >= 2.0 || status_halted(st)) return;
+  if (!LATE && (trs[4 * p + 1] >= 2.0 || status_halted(st))) return;
   if (lane == 0) {
     const int64_t e = (int64_t)p * d + i;
     out[e] = base ? base[e] + s : s / trs[4 * p + 3];
   }
 }
 
-// The moments M_s = y_0^T (R / beta)^s y_0, s = 0 .. 2J, from the series
-// vectors: M_2j = y_j^T y_j and M_2j+1 = y_j^T y_j+1 (R is symmetric). One
-// workgroup per moment and problem, a fixed summation order.
-__global__ __launch_bounds__(256) void k_trs_moments(const double* __restrict__ Y, int64_t d,
-                                                     int32_t batch, const double* __restrict__ trs,
-                                                     double* mom, const DeviceStatus* st) {
-  __shared__ double red[4];
-  const int sidx = blockIdx.x, p = blockIdx.y, tid = threadIdx.x;
-  if (trs[4 * p + 1] >= 2.0 || status_halted(st)) return;
-  const int j = sidx >> 1, k = j + (sidx & 1);
-  const double* a = Y + ((int64_t)j * batch + p) * d;
-  const double* b = Y + ((int64_t)k * batch + p) * d;
-  double acc = 0.0;
-  for (int64_t i = tid; i < d; i += 256) acc = fma(a[i], b[i], acc);
-  const double m = block256_sum(acc, red);
-  if (tid == 0) mom[(int64_t)p * (2 * kSeriesTerms + 1) + sidx] = m;
-}
-
-// Whether the series cut after y_J (J = kSeriesTerms) reaches the shift with
-// coefficient t: the tail sum_{k > J} t^k y_k has norm at most
+// Whether the series cut after y_J reaches the shift with coefficient t: the
+// tail sum_{k > J} t^k y_k has norm at most
 // |t|^(J+1) ||y_J|| / (1 - |t|), since ||R / beta|| <= 1 makes every later
 // vector no longer than y_J; it must stay below kSeriesTail ||y_0||. The
 // measured ||y_J|| = sqrt(M_2J) is far below ||y_0|| when beta overstates
 // ||R||, which widens the reach to what the spectrum allows. Infinite or NaN
 // t (no inverse held) is never reached.
-__device__ __forceinline__ bool series_reaches(double t, double m0, double m2j) {
+__device__ __forceinline__ bool series_reaches(double t, double m0, double m2j, int32_t J) {
   const double a = fabs(t);
   if (!(a < 1.0)) return false;
   double pw = a;
-  for (int j = 0; j < kSeriesTerms; ++j) pw *= a;
+  for (int j = 0; j < J; ++j) pw *= a;
   return pw * sqrt(m2j) <= kSeriesTail * (1.0 - a) * sqrt(m0);
 }
 
-// The Newton iteration of k_trs_update on the series: with t = -(mu - mu0)
-// beta, x(mu) = sum_j t^j y_j, so ||x(mu)||^2 = sum_s (s + 1) M_s t^s and
-// x^T (H + mu I)^{-1} x = -(1/2) d||x||^2/dmu = (beta / 2) sum_s s (s + 1)
-// M_s t^(s-1), all from the moments. A shift the series does not reach is
-// left in trs[4p] for a new factorisation; an accepted one is marked phase 3
-// for k_trs_series_x. One thread per problem.
-__global__ void k_trs_series_newton(const double* __restrict__ mom, int32_t batch, double r,
-                                    double tol, int32_t max_steps, double* trs,
-                                    const DeviceStatus* st) {
-  const int p = blockIdx.x * 64 + threadIdx.x;
-  if (p >= batch || status_halted(st) || trs[4 * p + 1] >= 2.0) return;
-  const double* M = mom + (int64_t)p * (2 * kSeriesTerms + 1);
-  const double mu0 = trs[4 * p + 2], beta = trs[4 * p + 3];
-  double mu = trs[4 * p], phase = trs[4 * p + 1];
-  // a warm start beyond the series' reach starts at mu0 instead (t = 0, where
-  // the series is exact): the root may still lie within reach
-  if (phase == 0.0 && !series_reaches(-(mu - mu0) * beta, M[0], M[2 * kSeriesTerms]) &&
-      series_reaches(0.0, M[0], M[2 * kSeriesTerms]))
-    mu = mu0;
-  for (int32_t k = 0; k < max_steps; ++k) {
-    const double t = -(mu - mu0) * beta;
-    if (!series_reaches(t, M[0], M[2 * kSeriesTerms])) break;
-    double phi = 0.0, dq = 0.0;  // Horner, highest power first
-    for (int sidx = 2 * kSeriesTerms; sidx >= 0; --sidx) {
-      phi = fma(phi, t, (sidx + 1) * M[sidx]);
-      if (sidx >= 1) dq = fma(dq, t, 0.5 * sidx * (sidx + 1) * M[sidx]);
-    }
-    const double nx2 = phi, q = beta * dq, nx = sqrt(nx2);
-    if (phase == 1.0 || (mu == 0.0 && nx <= r)) {
-      trs[4 * p] = mu;
-      trs[4 * p + 1] = 3.0;
-      return;
-    }
-    const double next = fmax(mu + (nx2 / q) * ((nx - r) / r), 0.0);
-    if (fabs(nx - r) <= tol * r) phase = 1.0;
-    mu = next;
-  }
-  trs[4 * p] = mu;
-  trs[4 * p + 1] = phase;
-}
-
-// x_out = sum_j t^j y_j for the problems the series accepted (phase 3), which
-// then finish (phase 2).
-__global__ __launch_bounds__(256) void k_trs_series_x(const double* __restrict__ Y, int64_t d,
-                                                      int32_t batch, double* trs, double* xout,
-                                                      const DeviceStatus* st) {
-  __shared__ int take;
-  const int p = blockIdx.x, tid = threadIdx.x;
-  if (tid == 0) take = (!status_halted(st) && trs[4 * p + 1] == 3.0) ? 1 : 0;
+// One round's series step for one problem (one workgroup of 256 per
+// problem), for the problems still iterating:
+//  1. the moments M_s = y_0^T (R / beta)^s y_0, s = 0 .. 2J, from the series
+//     vectors: M_2j = y_j^T y_j and M_2j+1 = y_j^T y_j+1 (R is symmetric),
+//     each summed strided over the threads, then over the wavefronts in a
+//     fixed order;
+//  2. the Newton iteration of k_trs_update on the series, in one thread:
+//     with t = -(mu - mu0) beta, x(mu) = sum_j t^j y_j, so ||x(mu)||^2 =
+//     sum_s (s + 1) M_s t^s and x^T (H + mu I)^{-1} x = -(1/2) d||x||^2/dmu
+//     = (beta / 2) sum_s s (s + 1) M_s t^(s-1). A shift the series does not
+//     reach is left in trs[4p] for a new factorisation (or a longer series);
+//  3. for an accepted shift, x_out = sum_j t^j y_j; the problem finishes
+//     (phase 2).
+template <int J>
+__global__ __launch_bounds__(256) void k_trs_series_solve(const double* __restrict__ Y, int64_t d,
+                                                          int32_t batch, double r, double tol,
+                                                          int32_t max_steps, double* trs,
+                                                          double* xout, const DeviceStatus* st) {
+  constexpr int NM = 2 * J + 1;
+  __shared__ double part[4][NM];
+  __shared__ double M[NM];
+  __shared__ int skip;
+  __shared__ double t_acc;
+  const int p = blockIdx.x, tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+  if (tid == 0) skip = (status_halted(st) || trs[4 * p + 1] >= 2.0) ? 1 : 0;
   __syncthreads();
-  if (!take) return;
-  const double t = -(trs[4 * p] - trs[4 * p + 2]) * trs[4 * p + 3];
+  if (skip) return;
+  double acc[NM];
+#pragma unroll
+  for (int q = 0; q < NM; ++q) acc[q] = 0.0;
   for (int64_t i = tid; i < d; i += 256) {
-    double acc = Y[((int64_t)kSeriesTerms * batch + p) * d + i];
-    for (int j = kSeriesTerms - 1; j >= 0; --j) acc = fma(acc, t, Y[((int64_t)j * batch + p) * d + i]);
-    xout[(int64_t)p * d + i] = acc;
+    double y[J + 1];
+#pragma unroll
+    for (int j = 0; j <= J; ++j) y[j] = Y[((int64_t)j * batch + p) * d + i];
+#pragma unroll
+    for (int j = 0; j <= J; ++j) {
+      acc[2 * j] = fma(y[j], y[j], acc[2 * j]);
+      if (j < J) acc[2 * j + 1] = fma(y[j], y[j + 1], acc[2 * j + 1]);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < NM; ++q) {
+    const double w = wave_sum(acc[q]);
+    if (lane == 0) part[wv][q] = w;
   }
   __syncthreads();
-  if (tid == 0) trs[4 * p + 1] = 2.0;
+  if (tid < NM) M[tid] = part[0][tid] + part[1][tid] + part[2][tid] + part[3][tid];
+  __syncthreads();
+  if (tid == 0) {
+    const double mu0 = trs[4 * p + 2], beta = trs[4 * p + 3];
+    double mu = trs[4 * p], phase = trs[4 * p + 1];
+    bool accepted = false;
+    // a warm start beyond the series' reach starts at mu0 instead (t = 0,
+    // where the series is exact): the root may still lie within reach
+    if (phase == 0.0 && !series_reaches(-(mu - mu0) * beta, M[0], M[2 * J], J) &&
+        series_reaches(0.0, M[0], M[2 * J], J))
+      mu = mu0;
+    for (int32_t k = 0; k < max_steps; ++k) {
+      const double t = -(mu - mu0) * beta;
+      if (!series_reaches(t, M[0], M[2 * J], J)) break;
+      double phi = 0.0, dq = 0.0;  // Horner, highest power first
+      for (int sidx = 2 * J; sidx >= 0; --sidx) {
+        phi = fma(phi, t, (sidx + 1) * M[sidx]);
+        if (sidx >= 1) dq = fma(dq, t, 0.5 * sidx * (sidx + 1) * M[sidx]);
+      }
+      const double nx2 = phi, q = beta * dq, nx = sqrt(nx2);
+      if (phase == 1.0 || (mu == 0.0 && nx <= r)) {
+        accepted = true;
+        break;
+      }
+      const double next = fmax(mu + (nx2 / q) * ((nx - r) / r), 0.0);
+      if (fabs(nx - r) <= tol * r) phase = 1.0;
+      mu = next;
+    }
+    trs[4 * p] = mu;
+    trs[4 * p + 1] = accepted ? 2.0 : phase;
+    skip = accepted ? 0 : 1;
+    t_acc = -(mu - mu0) * beta;
+  }
+  __syncthreads();
+  if (skip) return;
+  const double t = t_acc;
+  for (int64_t i = tid; i < d; i += 256) {
+    double x = Y[((int64_t)J * batch + p) * d + i];
+    for (int j = J - 1; j >= 0; --j) x = fma(x, t, Y[((int64_t)j * batch + p) * d + i]);
+    xout[(int64_t)p * d + i] = x;
+  }
 }
 
 // Given x = x(mu) and z = (H + mu I)^{-1} x, applies the Newton step
@@ -999,8 +1026,13 @@ hipError_t launch_qp_constrained(const QpArgs& a, hipStream_t st) {
   const double tol = a.tol > 0 ? a.tol : 1e-10;
   const int64_t bd = (int64_t)B * d;
   const dim3 rows_grid((unsigned)((d + 3) / 4), B);
-  hipLaunchKernelGGL(k_trs_init, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, st, trs, B,
-                     a.warm);
+  const bool pre_held = a.warm && a.hinv_pre && a.trs_pre;  // an inverse formed ahead
+  if (pre_held)
+    hipLaunchKernelGGL(k_trs_begin_held, dim3((unsigned)((bd + 255) / 256)), dim3(256), 0, st,
+                       trs, a.trs_pre, a.pre_status, a.g, a.x, d, B, cbuf);
+  else
+    hipLaunchKernelGGL(k_trs_init, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, st, trs, B,
+                       a.warm);
   if (!a.warm) {
     if ((e = launch_cholesky(a.H, a.L, d, B, a.status, a.iter, 0.0, scratch, st)) != hipSuccess)
       return e;
@@ -1038,16 +1070,9 @@ hipError_t launch_qp_constrained(const QpArgs& a, hipStream_t st) {
   // series and iterates; a shift beyond its reach starts the next round there.
   // The accepted x(mu) is formed from the series vectors.
   double* Y = linv + (int64_t)B * d * d;
-  double* mom = Y + (int64_t)(kSeriesTerms + 1) * B * d;
   std::vector<double> h;
-  bool held = false;
-  const double* R = hinv;
-  if (a.warm && a.hinv_pre && a.trs_pre) {  // an inverse formed ahead at a nearby shift
-    hipLaunchKernelGGL(k_trs_adopt, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, st, trs,
-                       a.trs_pre, B, a.pre_status);
-    held = true;
-    R = a.hinv_pre;
-  }
+  bool held = pre_held;  // v = g - mu0 x^t is then formed already
+  const double* R = pre_held ? a.hinv_pre : hinv;
   for (int32_t round = 0; round < newton; ++round) {
     if (!held) {
       if ((e = launch_cholesky(a.H, a.L, d, B, a.status, a.iter, 0.0, scratch, st, trs)) !=
@@ -1060,21 +1085,27 @@ hipError_t launch_qp_constrained(const QpArgs& a, hipStream_t st) {
                          a.status);
       hipLaunchKernelGGL(k_trs_inv_norm, dim3(B), dim3(256), 0, st, zero, d, trs, a.status);
       R = hinv;
+      hipLaunchKernelGGL(k_trs_rhs, dim3((unsigned)((bd + 255) / 256)), dim3(256), 0, st, a.g,
+                         a.x, trs, d, B, cbuf);
     }
     held = false;
-    hipLaunchKernelGGL(k_trs_rhs, dim3((unsigned)((bd + 255) / 256)), dim3(256), 0, st, a.g, a.x,
-                       trs, d, B, cbuf);
-    hipLaunchKernelGGL(k_trs_krylov, rows_grid, dim3(256), 0, st, R, d, cbuf, a.x, Y, trs,
-                       a.status);
-    for (int32_t j = 1; j <= kSeriesTerms; ++j)
-      hipLaunchKernelGGL(k_trs_krylov, rows_grid, dim3(256), 0, st, R, d, Y + (j - 1) * bd,
-                         nullptr, Y + j * bd, trs, a.status);
-    hipLaunchKernelGGL(k_trs_moments, dim3(2 * kSeriesTerms + 1, B), dim3(256), 0, st, Y, d, B,
-                       trs, mom, a.status);
-    hipLaunchKernelGGL(k_trs_series_newton, dim3((unsigned)((B + 63) / 64)), dim3(64), 0, st, mom,
-                       B, a.radius, tol, newton, trs, a.status);
-    hipLaunchKernelGGL(k_trs_series_x, dim3(B), dim3(256), 0, st, Y, d, B, trs, a.x_out,
-                       a.status);
+    hipLaunchKernelGGL(k_trs_krylov<false>, rows_grid, dim3(256), 0, st, R, d, cbuf, a.x, Y,
+                       trs, a.status);
+    // the series to kSeriesFirst; then, only if some problem needs it, on to
+    // kSeriesTerms (one read-back between: launches that would find every
+    // problem finished still cost their dispatch)
+    for (int32_t j = 1; j <= kSeriesFirst; ++j)
+      hipLaunchKernelGGL(k_trs_krylov<false>, rows_grid, dim3(256), 0, st, R, d,
+                         Y + (j - 1) * bd, nullptr, Y + j * bd, trs, a.status);
+    hipLaunchKernelGGL(k_trs_series_solve<kSeriesFirst>, dim3(B), dim3(256), 0, st, Y, d, B,
+                       a.radius, tol, newton, trs, a.x_out, a.status);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (trs_all_done(trs, a.status, B, st, h)) break;
+    for (int32_t j = kSeriesFirst + 1; j <= kSeriesTerms; ++j)
+      hipLaunchKernelGGL(k_trs_krylov<true>, rows_grid, dim3(256), 0, st, R, d,
+                         Y + (j - 1) * bd, nullptr, Y + j * bd, trs, a.status);
+    hipLaunchKernelGGL(k_trs_series_solve<kSeriesTerms>, dim3(B), dim3(256), 0, st, Y, d, B,
+                       a.radius, tol, newton, trs, a.x_out, a.status);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (trs_all_done(trs, a.status, B, st, h)) break;
   }
