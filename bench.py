@@ -48,6 +48,10 @@ def parse():
                     help="steps on the float32 copy of A before switching to A")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 2 GiB device copy (counter calibration)")
+    ap.add_argument("--rows-only", choices=["apply", "gram", "l2"], default=None,
+                    help="time only these rows (for counter runs under a profiler): the "
+                         "lasso-matrix CountSketch/SJLT and CSR sketch applies, the Gram "
+                         "shapes, or the CSR l2-ball solve; prints them and exits")
     return ap.parse_args()
 
 
@@ -149,6 +153,10 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.rows_only:
+        print(json.dumps({"rows_only": args.rows_only,
+                          "rows": rows_only(P, W, args.rows_only)}), flush=True)
+        return
     t_gen = time.time()
     if args.workload == "precision":
         wl = W.precision(rows=args.rows, backend="torch", device=dev, keep_factors=True)
@@ -510,6 +518,66 @@ def dense_sketch_times(P, M, n, d, m, cs_ms):
     return out
 
 
+def gram_rows(P, out):
+    """a6: the Gram at the 4096 x 512 and 8192 x 1024 shapes, every input /
+    accumulation pair."""
+    import torch
+    for (m, d) in ((4096, 512), (8192, 1024)):
+        SA = torch.randn(m, d, dtype=torch.float64, device="cuda")
+        for gin, gacc in (("float64", "float64"), ("float32", "float32"),
+                          ("bfloat16", "float32")):
+            src = SA if gin == "float64" else SA.to(getattr(torch, gin))
+            H = torch.empty(1, d, d, dtype=torch.float64, device="cuda")
+            ms = _event_ms(lambda: P.gram(src, m, in_dtype=gin, acc_dtype=gacc, out=H), reps=10)
+            fl = m * d * (d + 1)
+            tf = fl / ms / 1e9
+            out[f"a6_gram_{m}x{d}_{gin}_in_{gacc}_acc"] = {
+                "ms": round(ms, 4), "flop": fl, "TFLOP/s": round(tf, 2),
+                "peak_TFLOP/s": PEAK_TFLOPS[gin], "mfma_frac": round(tf / PEAK_TFLOPS[gin], 4)}
+        del SA
+
+
+def csr_ridge(P, W):
+    """The CSR ridge problem (2^22 x 1024, density 1e-3) on the device."""
+    import torch
+    wl3 = W.ridge_csr()
+    M3 = P.Matrix(row_ptr=torch.from_numpy(wl3.indptr).cuda(),
+                  col_idx=torch.from_numpy(wl3.indices).cuda(),
+                  values=torch.from_numpy(wl3.data).cuda(), n=wl3.n, d=wl3.d)
+    return wl3, M3, torch.from_numpy(wl3.b).cuda()
+
+
+def rows_only(P, W, which):
+    """The rows that the counter profiles cover, alone."""
+    import torch
+    out = {}
+    if which == "gram":
+        gram_rows(P, out)
+    elif which == "apply":
+        wl2 = W.lasso_dense(backend="torch", device="cuda")
+        M2 = P.Matrix(dense=wl2.A)
+        for kind, s in (("countsketch", 1), ("sjlt", 4)):
+            out[f"a3_sketch_dense_2^20x256_{kind}_s{s}_m4096"] = _apply_entry(
+                P, M2, P.SketchSpec(4096, s, kind, seed=9), wl2.n, wl2.d, wl2.n * wl2.d * 8)
+        del wl2, M2
+        torch.cuda.empty_cache()
+        wl3, M3, _ = csr_ridge(P, W)
+        nnz = int(wl3.indptr[-1])
+        out["a4_sketch_csr_2^22x1024_m8192"] = dict(
+            _apply_entry(P, M3, P.SketchSpec(8192, seed=4), wl3.n, wl3.d,
+                         nnz * 12 + (wl3.n + 1) * 4), nnz=nnz)
+    else:
+        wl3, M3, b3 = csr_ridge(P, W)
+        for sched in ("overlap", "sequential"):
+            o = P.options(8192, seed=wl3.sketch_seed, max_iter=wl3.iters, constraint="l2",
+                          radius=wl3.radius, schedule=sched)
+            P.solve(M3, b3, o)
+            ms = _wall_ms(lambda: P.solve(M3, b3, o), reps=2)
+            out[f"a8_solve_csr_2^22x1024_l2_float64_gram_{wl3.iters}steps_{sched}"] = {
+                "ms_wall": round(ms, 3), "ms_per_step": round(ms / wl3.iters, 4)}
+    return out
+
+
 def components(P, W, wl4):
     """Per-row timings of the hot path at the workload shapes: sketch apply
     (dense CountSketch/SJLT, CSR), gradient pass, Gram (FP64 and mixed, MFMA),
@@ -531,19 +599,7 @@ def components(P, W, wl4):
                                    "GB/s": round(gbytes / gms / 1e6, 1),
                                    "frac_of_hbm_peak": round(gbytes / gms / 1e6 / HBM_PEAK_GBS, 4)}
     # ---- a6 Gram at the 4096 x 512 and 8192 x 1024 shapes
-    for (m, d) in ((4096, 512), (8192, 1024)):
-        SA = torch.randn(m, d, dtype=torch.float64, device="cuda")
-        for gin, gacc in (("float64", "float64"), ("float32", "float32"),
-                          ("bfloat16", "float32")):
-            src = SA if gin == "float64" else SA.to(getattr(torch, gin))
-            H = torch.empty(1, d, d, dtype=torch.float64, device="cuda")
-            ms = _event_ms(lambda: P.gram(src, m, in_dtype=gin, acc_dtype=gacc, out=H), reps=10)
-            fl = m * d * (d + 1)
-            tf = fl / ms / 1e9
-            out[f"a6_gram_{m}x{d}_{gin}_in_{gacc}_acc"] = {
-                "ms": round(ms, 4), "flop": fl, "TFLOP/s": round(tf, 2),
-                "peak_TFLOP/s": PEAK_TFLOPS[gin], "mfma_frac": round(tf / PEAK_TFLOPS[gin], 4)}
-        del SA
+    gram_rows(P, out)
     # ---- a7 unconstrained QP at d = 512 and 1024
     for d in (512, 1024):
         g = torch.Generator(device="cuda").manual_seed(d)
@@ -605,12 +661,7 @@ def components(P, W, wl4):
     del wl2, M2, SA2
     torch.cuda.empty_cache()
     # ---- CSR ridge (2^22 x 1024, density 1e-3): CSR apply, l2 QP, l2 solve
-    wl3 = W.ridge_csr()
-    rp = torch.from_numpy(wl3.indptr).cuda()
-    ci = torch.from_numpy(wl3.indices).cuda()
-    va = torch.from_numpy(wl3.data).cuda()
-    b3 = torch.from_numpy(wl3.b).cuda()
-    M3 = P.Matrix(row_ptr=rp, col_idx=ci, values=va, n=wl3.n, d=wl3.d)
+    wl3, M3, b3 = csr_ridge(P, W)
     nnz = int(wl3.indptr[-1])
     csr_bytes = nnz * 12 + (wl3.n + 1) * 4
     out["a4_sketch_csr_2^22x1024_m8192"] = dict(
@@ -635,7 +686,7 @@ def components(P, W, wl4):
         out[key] = {"ms_wall": round(ms, 3), "ms_per_step": round(ms / wl3.iters, 4),
                     "kkt_residual_rel": kkt_l2_ball(AtA3, Atb3, x3, wl3.radius)}
         ACCURACY.append((key, "l2", wl3.radius, AtA3, Atb3, x3))
-    del wl3, M3, SA3, rp, ci, va, b3
+    del wl3, M3, SA3, b3
     torch.cuda.empty_cache()
     # ---- ragged batch (64 problems, d = 64): adjoint, autograd
     from paper_1910_14166_amd import autograd as AG
