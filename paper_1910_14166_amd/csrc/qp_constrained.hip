@@ -1117,12 +1117,11 @@ hipError_t launch_qp_constrained(const QpArgs& a, hipStream_t st) {
 
 // ---------------------------------------------------------------------------
 // The l2 step's factorisation ahead of time (overlapped schedule): while the
-// caller's stream runs step t's QP and step t+1's pass, another stream
-// factors H_{t+1} + mu I and inverts it, mu from a snapshot of the shift
-// state taken before pass t (the root of step t-1). Step t+1's first Newton
-// step then sweeps from that inverse when |mu_t - mu| ||(H + mu I)^{-1}|| is
-// small enough, as later Newton steps sweep from the inverse held inside a
-// step.
+// caller's stream runs the steps before it, another stream factors H_k + mu I
+// and inverts it, mu from a snapshot of the shift state taken on the caller's
+// stream (the root of an earlier step). Step k then runs its Newton iteration
+// on the series of that inverse for every shift the series reaches, and
+// factors afresh only beyond.
 // ---------------------------------------------------------------------------
 static double* l2_trs(double* work, int64_t d, int32_t B) {
   // past the unconstrained step's scratch: c, x_unc, x(mu), z, a spare, then
