@@ -15,8 +15,11 @@ u^2 times the sum over its k roundings of the squared partial sum each
 rounds. Per step t, with x = x^t, delta = x^{t+1} - x^t, M = A^T A:
 
   Gram     H_ij = sum of m products; partial sums are at most
-           S_ij = sum_k |SA_ki| |SA_kj|, so var(dH_ij) <= m u^2 S_ij^2. The
-           step's response to dH is dx = -P dH delta (P below).
+           S_ij = sum_k |SA_ki| |SA_kj|, so var(dH_ij) <= m u_g^2 S_ij^2, with
+           u_g the unit roundoff of the Gram's accumulation (u, or 2^-24 for
+           a float32 accumulation of inputs rounded identically on both
+           sides, whose products are exact). The step's response to dH is
+           dx = -P dH delta (P below).
   gradient g_i = sum over the n rows of A_ri r_r. The rows are i.i.d. draws
            and every summation order here is independent of their values,
            so the terms are exchangeable and a partial sum over k of them has
@@ -119,13 +122,14 @@ def _solve_var(K, z):
     return v
 
 
-def step_covariance(A, b, SA, H, x, x_next, constraint, radius, sa_err=None):
+def step_covariance(A, b, SA, H, x, x_next, constraint, radius, sa_err=None, gram_u=U):
     """(P, T, Xi): the step's derivative with respect to c, the error map T
     and one run's rounding covariance Xi (before P) of one IHS step.
     sa_err (optional, m x d): a bound on |dSA| when the two runs' sketches
     are not bitwise equal (the Gaussian sketch, whose entries come from
     transcendental functions); it enters H as |dSA|^T |SA| + |SA|^T |dSA|,
-    counted in full as a standard deviation."""
+    counted in full as a standard deviation. gram_u: the unit roundoff of the
+    Gram's accumulation in the run compared (u_g above)."""
     n, d = A.shape
     m = SA.shape[0]
     M = _dense(A.T @ A)
@@ -136,7 +140,7 @@ def step_covariance(A, b, SA, H, x, x_next, constraint, radius, sa_err=None):
     T = P @ (H - M)
     delta = x_next - x
     S = np.abs(SA).T @ np.abs(SA)
-    v = m * U * U * ((S ** 2) @ (delta ** 2))                      # Gram
+    v = m * gram_u * gram_u * ((S ** 2) @ (delta ** 2))            # Gram
     if sa_err is not None:
         E = sa_err.T @ np.abs(SA)
         v = v + ((E + E.T) ** 2) @ (delta ** 2)
@@ -167,11 +171,13 @@ def step_covariance(A, b, SA, H, x, x_next, constraint, radius, sa_err=None):
 
 
 def ihs_budget(A, b, sketches, hessians, iterates, constraint="none", radius=0.0,
-               lam=LAMBDA, sketch_errs=None):
+               lam=LAMBDA, sketch_errs=None, gram_u=U):
     """Budgets for the iterates x^1 .. x^N of one IHS run: a list of
     (bound in ||A .||, bound in ||.||_2). sketches[t] and hessians[t] are the
     oracle's S_t A and H_t, iterates the oracle's x^0 .. x^N; sketch_errs[t]
-    (optional) bounds |dSA| of step t (see step_covariance)."""
+    (optional) bounds |dSA| of step t (see step_covariance); gram_u the unit
+    roundoff of the compared run's Gram accumulation (one of the two runs:
+    the oracle's Gram is float64)."""
     d = len(iterates[0])
     M = _dense(A.T @ A)
     C = np.zeros((d, d))
@@ -179,8 +185,13 @@ def ihs_budget(A, b, sketches, hessians, iterates, constraint="none", radius=0.0
     for t in range(len(hessians)):
         x, xn = iterates[t], iterates[t + 1]
         P, T, Xi = step_covariance(A, b, sketches[t], hessians[t], x, xn, constraint, radius,
-                                   None if sketch_errs is None else sketch_errs[t])
-        C = T @ C @ T.T + 2.0 * (P @ Xi @ P.T) + np.diag(2.0 * U * U * xn * xn)
+                                   None if sketch_errs is None else sketch_errs[t], gram_u)
+        if gram_u != U:  # the oracle's own float64 Gram rounds at u
+            _, _, Xi64 = step_covariance(A, b, sketches[t], hessians[t], x, xn, constraint,
+                                         radius, None, U)
+            C = T @ C @ T.T + P @ (Xi + Xi64) @ P.T + np.diag(2.0 * U * U * xn * xn)
+        else:
+            C = T @ C @ T.T + 2.0 * (P @ Xi @ P.T) + np.diag(2.0 * U * U * xn * xn)
         C = 0.5 * (C + C.T)
         out.append((lam * np.sqrt(max(np.trace(M @ C), 0.0)),
                     lam * np.sqrt(max(np.trace(C), 0.0))))

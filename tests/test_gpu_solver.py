@@ -167,20 +167,36 @@ def test_ihs_unconstrained_iterates_match_oracle(gpu_lib):
     assert abs(res.report.objective - f_ref) <= 1e-11 * f_ref
 
 
-def test_ihs_f32_data_and_mixed_gram(gpu_lib):
+@pytest.mark.parametrize("gin,gacc", [("float64", "float64"), ("float32", "float64"),
+                                      ("float32", "float32"), ("bfloat16", "float32")])
+def test_ihs_f32_data_and_mixed_gram(gpu_lib, gin, gacc):
+    """float32 data with each Gram route, every iterate against the oracle's
+    run with S A rounded the same way (the Gram of the rounded inputs formed
+    in float64) within the rounding budget: the GPU's Gram rounds at u for
+    a float64 accumulation (the products of rounded inputs are exact), at
+    2^-24 for a float32 one."""
     P = gpu_lib
+    import rounding_budget as RB
     wl = W.ols_dense(rows=8000, d=40, m=400, iters=8)
     A32 = wl.A.astype(np.float32)
-    for gin, gacc in (("float64", "float64"), ("float32", "float64"), ("float32", "float32"),
-                      ("bfloat16", "float32")):
-        opts = P.options(wl.m, seed=wl.sketch_seed, max_iter=wl.iters, gram_in=gin, gram_acc=gacc)
-        res = P.solve(P.Matrix(dense=dev(A32)), dev(wl.b), opts)
-        xs = O.ihs(A32, wl.b, wl.m, seed=wl.sketch_seed, iters=wl.iters, sketch_dtype=gin)
-        xo = O.x_opt(A32.astype(np.float64), wl.b)
-        e_gpu = O.error_A(A32.astype(np.float64), host(res.x)[0], xo)
-        e_ref = O.error_A(A32.astype(np.float64), xs[-1], xo)
-        # about 0.37 per step at m = 10 d: 8 steps reach a few 1e-4
-        assert e_gpu < 3e-3 and abs(np.log10(e_gpu) - np.log10(e_ref)) < 0.3, (gin, gacc)
+    A64 = A32.astype(np.float64)
+    opts = P.options(wl.m, seed=wl.sketch_seed, max_iter=wl.iters, gram_in=gin, gram_acc=gacc)
+    res = P.solve(P.Matrix(dense=dev(A32)), dev(wl.b), opts, history=True)
+    hist = host(res.history)[:, 0, :]
+    xs, Hs = O.ihs(A64, wl.b, wl.m, seed=wl.sketch_seed, iters=wl.iters, sketch_dtype=gin,
+                   return_hessians=True)
+    sas = [OS.sketch_apply_dense(A64, wl.sketch_seed, t, wl.m, out_dtype=gin)
+           for t in range(wl.iters)]
+    gram_u = 2.0 ** -24 if gacc == "float32" else 2.0 ** -53
+    bud = RB.ihs_budget(A64, wl.b, sas, Hs, xs, gram_u=gram_u)
+    for t in range(wl.iters):
+        dx = hist[t] - xs[t + 1]
+        assert np.linalg.norm(A64 @ dx) <= bud[t][0], (gin, gacc, t, np.linalg.norm(A64 @ dx),
+                                                      bud[t][0])
+        assert np.linalg.norm(dx) <= bud[t][1], (gin, gacc, t)
+    # and the method converges at its rate (about 0.37 per step at m = 10 d)
+    xo = O.x_opt(A64, wl.b)
+    assert O.error_A(A64, hist[-1], xo) < 3e-3
 
 
 def test_ihs_ragged_batch(gpu_lib):

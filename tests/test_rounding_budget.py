@@ -95,3 +95,41 @@ def test_budget_shrinks_with_the_error_at_high_conditioning():
     for t in range(N):
         assert bud[t][0] < 1e-3 * np.linalg.norm(A @ (xs[t + 1] - xo)), t
     assert bud[-1][0] < 1e-3 * bud[0][0]
+
+
+def test_float32_accumulated_gram_budget():
+    """A Gram accumulated in float32 from S A rounded to float32 (the mixed
+    route: both sides round the same float64 S A, so the products agree and
+    only the float32 sums differ) stays within the budget with u_g = 2^-24 at
+    every iterate; a Gram accumulated at u_g = 2^-16 (planted: every partial
+    sum of float32 data rounded to 8 fewer bits) leaves it."""
+    wl = W.ols_dense(rows=8000, d=40, m=400, iters=8)
+    A, b, N = wl.A, wl.b, 8
+    sas = [OS.sketch_apply_dense(A, wl.sketch_seed, t, wl.m, out_dtype="float32")
+           for t in range(N)]
+    xs, Hs = O.ihs(A, b, wl.m, seed=wl.sketch_seed, iters=N, sketch_dtype="float32",
+                   return_hessians=True)
+    bud = RB.ihs_budget(A, b, sas, Hs, xs, gram_u=2.0 ** -24)
+
+    def run(round_bits):
+        x, out = xs[0].copy(), []
+        for SA in sas:
+            S32 = SA.astype(np.float32)
+            H = np.zeros((A.shape[1],) * 2, dtype=np.float32)
+            for k in range(S32.shape[0]):   # sequential float32 accumulation
+                H = H + np.outer(S32[k], S32[k])
+                if round_bits:
+                    m, e = np.frexp(H.astype(np.float64))
+                    H = np.ldexp(np.round(m * 2.0 ** round_bits) / 2.0 ** round_bits,
+                                 e).astype(np.float32)
+            _, g, _ = O.gradient(A, b, x)
+            x = O.qp_step(H.astype(np.float64), g, x)
+            out.append(x)
+        return out
+
+    good = run(0)
+    for t in range(N):
+        assert np.linalg.norm(A @ (good[t] - xs[t + 1])) <= bud[t][0], t
+    bad = run(16)
+    assert any(np.linalg.norm(A @ (bad[t] - xs[t + 1])) > bud[t][0] for t in range(N))
+
