@@ -1,8 +1,9 @@
 // The sketched Hessian H = (SA)^T (SA) (Sec. 1, the T_QP term; App. A.1.1:
 // forming it costs O(m d^2)) on gfx950 matrix cores.
 //
-// One workgroup owns a tile of the upper triangle of H (64 x 64 on the FP64
-// matrix cores, 128 x 128 when accumulating in FP32) for a contiguous slice
+// One workgroup owns a tile of the upper triangle of H (64 x 64, or 128 x 128
+// from d = 1024 on, for FP64 accumulation; 64 x 64 for FP32 products; 128 x
+// 128 for BF16 products) for a contiguous slice
 // of the m rows of SA (split-K). Both operand panels of a stage are staged
 // through LDS with coalesced row loads and reused by all four wavefronts;
 // diagonal tiles stage one panel. Partial tiles are summed over the slices
@@ -21,7 +22,12 @@ typedef short bf16x8 __attribute__((ext_vector_type(8)));
 // Output tile edge: 64 for the FP64 and FP32 products (16 x 16 x 4), 128 for
 // the BF16 ones (16 x 16 x 32, eight times the work per operand load, so a
 // tile must reuse each staged operand more to keep the matrix cores fed).
+// From d = 1024 on the FP64 products also take 128 x 128 tiles: every tile
+// re-reads its two panels of SA, so the panels' traffic from L2 halves (at
+// d = 512 the wide tiles leave too few workgroups to fill the chip).
 constexpr int kTileF64 = 64;
+constexpr int kTileF64Wide = 128;
+constexpr int kF64WideMinD = 1024;
 constexpr int kTileF32 = 64;
 constexpr int kTileBf16 = 128;
 
@@ -31,7 +37,11 @@ struct GramPlan {
   int64_t kchunk;
 };
 
-static int tile_of(int32_t in_dtype) { return in_dtype == 2 ? kTileBf16 : kTileF64; }
+static int tile_of(int32_t in_dtype, int32_t acc, int64_t d) {
+  if (in_dtype == 2) return kTileBf16;
+  if (acc == 1) return kTileF32;
+  return d >= kF64WideMinD ? kTileF64Wide : kTileF64;
+}
 
 // Workgroups of each kernel that fit on one CU at once (LDS and registers):
 // the slices are sized so that all workgroups run in one round, since a
@@ -47,10 +57,12 @@ static GramPlan make_gram_plan(int64_t m, int64_t d, int64_t ld, int32_t batch, 
   g.d = d;
   g.ld = ld;
   g.batch = batch;
-  g.tile = tile_of(in);
+  g.tile = tile_of(in, acc, d);
   g.ntile = (int32_t)((d + g.tile - 1) / g.tile);
   g.ntri = g.ntile * (g.ntile + 1) / 2;
-  const int64_t slots = (int64_t)kCUs * std::max(1, std::min(per_cu, 4));
+  // the wide FP64 tiles: two workgroups per CU (LDS and registers)
+  const int32_t cap = g.tile == kTileF64Wide && in != 2 ? 2 : 4;
+  const int64_t slots = (int64_t)kCUs * std::max(1, std::min(per_cu, cap));
   const int64_t tiles = (int64_t)batch * g.ntri;
   int64_t splits = std::max<int64_t>(1, slots / tiles);
   splits = std::min<int64_t>(splits, std::max<int64_t>(1, m / 128));  // >= 128 rows a slice
@@ -111,29 +123,30 @@ __device__ __forceinline__ void gram_coords(const GramPlan& G, int& p, int& ti, 
 // products, and written to the other buffer after them.
 // ---------------------------------------------------------------------------
 constexpr int kKcF64 = 16;            // rows per stage
-constexpr int kPadF64 = kTileF64 + 1; // LDS row pitch (doubles)
 
-template <typename TI>
-__global__ __launch_bounds__(256, 4) void k_gram_f64(const TI* __restrict__ SA, GramPlan G,
-                                                  double* __restrict__ part) {
-  __shared__ double As[2][kKcF64][kPadF64];
-  __shared__ double Bs[2][kKcF64][kPadF64];
+template <typename TI, int TILE>
+__global__ __launch_bounds__(256, TILE == 128 ? 2 : 4) void k_gram_f64(
+    const TI* __restrict__ SA, GramPlan G, double* __restrict__ part) {
+  constexpr int kPad = TILE + 1;  // LDS row pitch (doubles)
+  constexpr int MT = TILE / 32;   // 16 x 16 output blocks per wavefront edge
+  __shared__ double As[2][kKcF64][kPad];
+  __shared__ double Bs[2][kKcF64][kPad];
   int p, ti, tj, split;
   gram_coords(G, p, ti, tj, split);
   const bool diag = ti == tj;
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
-  const int64_t i0 = (int64_t)ti * kTileF64, j0 = (int64_t)tj * kTileF64;
+  const int64_t i0 = (int64_t)ti * TILE, j0 = (int64_t)tj * TILE;
   const int64_t kb = (int64_t)split * G.kchunk;
   const int64_t ke = min(G.m, kb + G.kchunk);
   const TI* base = SA + (int64_t)p * G.m * G.ld;
-  // thread tid stages elements e = tid + 256 u of each 16 x 64 panel
-  constexpr int kPer = kKcF64 * kTileF64 / 256;  // 4
+  // thread tid stages elements e = tid + 256 u of each kKcF64 x TILE panel
+  constexpr int kPer = kKcF64 * TILE / 256;
   double ra[kPer], rb[kPer];
   auto load = [&](int64_t k0) {
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
       const int e = tid + 256 * u;
-      const int r = e / kTileF64, c = e % kTileF64;
+      const int r = e / TILE, c = e % TILE;
       const int64_t row = k0 + r;
       const bool ok = row < ke;
       ra[u] = (ok && i0 + c < G.d) ? to_f64(base[row * G.ld + i0 + c]) : 0.0;
@@ -144,17 +157,19 @@ __global__ __launch_bounds__(256, 4) void k_gram_f64(const TI* __restrict__ SA, 
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
       const int e = tid + 256 * u;
-      const int r = e / kTileF64, c = e % kTileF64;
+      const int r = e / TILE, c = e % TILE;
       As[buf][r][c] = ra[u];
       if (!diag) Bs[buf][r][c] = rb[u];
     }
   };
+  // wavefront (wr, wc) of the 2 x 2 grid owns a (TILE/2) x (TILE/2) block
   const int wr = wv >> 1, wc = wv & 1;
-  f64x4 acc[2][2];
+  constexpr int HALF = TILE / 2;
+  f64x4 acc[MT][MT];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < MT; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+    for (int b = 0; b < MT; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
   const int nstage = (int)((ke - kb + kKcF64 - 1) / kKcF64);
   if (nstage > 0) {
     load(kb);
@@ -164,20 +179,20 @@ __global__ __launch_bounds__(256, 4) void k_gram_f64(const TI* __restrict__ SA, 
   for (int sidx = 0; sidx < nstage; ++sidx) {
     const int buf = sidx & 1;
     if (sidx + 1 < nstage) load(kb + (int64_t)(sidx + 1) * kKcF64);
-    const double(*Bp)[kPadF64] = diag ? As[buf] : Bs[buf];
+    const double(*Bp)[kPad] = diag ? As[buf] : Bs[buf];
 #pragma unroll
     for (int k4 = 0; k4 < kKcF64; k4 += 4) {
       const int kr = k4 + (lane >> 4), cl = lane & 15;
-      double a[2], b[2];
+      double a[MT], b[MT];
 #pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        a[q] = As[buf][kr][32 * wr + 16 * q + cl];
-        b[q] = Bp[kr][32 * wc + 16 * q + cl];
+      for (int q = 0; q < MT; ++q) {
+        a[q] = As[buf][kr][HALF * wr + 16 * q + cl];
+        b[q] = Bp[kr][HALF * wc + 16 * q + cl];
       }
 #pragma unroll
-      for (int x = 0; x < 2; ++x)
+      for (int x = 0; x < MT; ++x)
 #pragma unroll
-        for (int y = 0; y < 2; ++y)
+        for (int y = 0; y < MT; ++y)
           acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[y], acc[x][y], 0, 0, 0);
     }
     if (sidx + 1 < nstage) store(buf ^ 1);
@@ -185,16 +200,16 @@ __global__ __launch_bounds__(256, 4) void k_gram_f64(const TI* __restrict__ SA, 
   }
   // 16 x 16 f64 output blocks: row 4*reg + lane/16, column lane%16
   double* out = part + ((((int64_t)p * G.ntri) + (blockIdx.x / G.splits) % G.ntri) * G.splits +
-                        split) * (kTileF64 * kTileF64);
+                        split) * (TILE * TILE);
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
+  for (int x = 0; x < MT; ++x)
 #pragma unroll
-    for (int y = 0; y < 2; ++y)
+    for (int y = 0; y < MT; ++y)
 #pragma unroll
       for (int reg = 0; reg < 4; ++reg) {
-        const int row = 32 * wr + 16 * x + 4 * reg + (lane >> 4);
-        const int col = 32 * wc + 16 * y + (lane & 15);
-        out[row * kTileF64 + col] = acc[x][y][reg];
+        const int row = HALF * wr + 16 * x + 4 * reg + (lane >> 4);
+        const int col = HALF * wc + 16 * y + (lane & 15);
+        out[row * TILE + col] = acc[x][y][reg];
       }
 }
 
@@ -489,11 +504,18 @@ hipError_t launch_gram(const void* SA, int32_t in_dtype, int64_t m, int64_t d, i
                               (64 / kRedStrip)));
   if (acc_dtype == 0) {
     double* part = static_cast<double*>(partials);
-    if (in_dtype == 0)
-      hipLaunchKernelGGL(k_gram_f64<double>, dim3(blocks), dim3(256), 0, st,
+    const bool wide = G.tile == kTileF64Wide;
+    if (in_dtype == 0 && wide)
+      hipLaunchKernelGGL((k_gram_f64<double, kTileF64Wide>), dim3(blocks), dim3(256), 0, st,
                          static_cast<const double*>(SA), G, part);
+    else if (in_dtype == 0)
+      hipLaunchKernelGGL((k_gram_f64<double, kTileF64>), dim3(blocks), dim3(256), 0, st,
+                         static_cast<const double*>(SA), G, part);
+    else if (in_dtype == 1 && wide)
+      hipLaunchKernelGGL((k_gram_f64<float, kTileF64Wide>), dim3(blocks), dim3(256), 0, st,
+                         static_cast<const float*>(SA), G, part);
     else if (in_dtype == 1)
-      hipLaunchKernelGGL(k_gram_f64<float>, dim3(blocks), dim3(256), 0, st,
+      hipLaunchKernelGGL((k_gram_f64<float, kTileF64>), dim3(blocks), dim3(256), 0, st,
                          static_cast<const float*>(SA), G, part);
     else
       return hipErrorInvalidValue;
