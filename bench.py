@@ -49,10 +49,11 @@ def parse():
                     help="steps on the float32 copy of A before switching to A")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 2 GiB device copy (counter calibration)")
-    ap.add_argument("--rows-only", choices=["apply", "gram", "l2"], default=None,
+    ap.add_argument("--rows-only", choices=["apply", "gram", "l2", "ceiling"], default=None,
                     help="time only these rows (for counter runs under a profiler): the "
                          "lasso-matrix CountSketch/SJLT and CSR sketch applies, the Gram "
-                         "shapes, or the CSR l2-ball solve; prints them and exits")
+                         "shapes, the CSR l2-ball solve, or the read rate of buffers from "
+                         "16 MiB to 2 GiB (which cache level serves them); prints and exits")
     return ap.parse_args()
 
 
@@ -554,6 +555,13 @@ def rows_only(P, W, which):
     out = {}
     if which == "gram":
         gram_rows(P, out)
+    elif which == "ceiling":
+        # one streaming read of the buffer per launch, 20 launches: small buffers
+        # stay in the L2 caches, mid-sized ones in the last-level cache
+        for mib in (16, 32, 64, 128, 192, 256, 384, 512, 1024, 2048):
+            buf = torch.ones(mib * (1 << 20) // 8, dtype=torch.float64, device="cuda")
+            out[f"read_{mib}MiB_GBs"] = round(P.read_ceiling(buf, reps=20), 1)
+            del buf
     elif which == "apply":
         wl2 = W.lasso_dense(backend="torch", device="cuda")
         M2 = P.Matrix(dense=wl2.A)
