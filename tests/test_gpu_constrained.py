@@ -424,3 +424,46 @@ def test_overlapped_l1_ball_reports_not_pd_step(gpu_lib, d):
         reps[sched] = (res.report.status, res.report.failed_iter)
         assert bool((res.x == 0).all()), sched
     assert reps["overlap"] == reps["sequential"] == (P.ERR_NOT_PD, 0)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("schedule", ["overlap", "sequential"])
+def test_ihs_l2_ragged_batch_matches_oracle(gpu_lib, schedule):
+    """A ragged batch through the l2-ball solve: one radius for all
+    problems, between the smallest and the largest ||x_OPT||, so some balls
+    are active and some inactive, and the problems' shifts (and whether the
+    held inverse's series reaches them) differ within each step. Every
+    problem's iterates against the oracle's within the rounding budget; each
+    problem draws its own sketch stream."""
+    P = gpu_lib
+    wl = W.batch_ragged(num=4, n_lo=3000, n_hi=8000, d=128, m=1280, iters=8)
+    offs = wl.row_offsets
+    norms = [np.linalg.norm(O.x_opt(wl.A[offs[p]:offs[p + 1]], wl.b[offs[p]:offs[p + 1]]))
+             for p in range(wl.batch)]
+    radius = 0.5 * (min(norms) + max(norms))
+    o = P.options(wl.m, seed=wl.sketch_seed, max_iter=wl.iters, constraint="l2", radius=radius,
+                  schedule=schedule)
+    res = P.solve(P.Matrix(dense=dev(wl.A), row_offsets=offs), dev(wl.b), o, history=True)
+    assert res.report.status == 0
+    hist = host(res.history)
+    active = 0
+    for p in range(wl.batch):
+        Ap, bp = wl.A[offs[p]:offs[p + 1]], wl.b[offs[p]:offs[p + 1]]
+        x = np.zeros(wl.d)
+        xs, sas, Hs = [x.copy()], [], []
+        for t in range(wl.iters):
+            SA = OS.sketch_apply_dense(Ap, wl.sketch_seed, t, wl.m, 1, problem=p)
+            H = SA.T @ SA
+            _, gr, _ = O.gradient(Ap, bp, x)
+            x = O.qp_step(H, gr, x, "l2", radius)
+            xs.append(x.copy())
+            sas.append(SA)
+            Hs.append(H)
+        active += np.linalg.norm(xs[-1]) > radius * (1 - 1e-9)
+        bud = RB.ihs_budget(Ap, bp, sas, Hs, xs, "l2", radius)
+        for t in range(wl.iters):
+            dx = hist[t, p] - xs[t + 1]
+            assert np.linalg.norm(Ap @ dx) <= bud[t][0], (p, t, np.linalg.norm(Ap @ dx),
+                                                         bud[t][0])
+            assert np.linalg.norm(dx) <= bud[t][1], (p, t)
+    assert 0 < active < wl.batch, active
