@@ -72,6 +72,7 @@ __device__ __forceinline__ void wave_sync_lds() {
 // (second kernel). The objective f[p] follows the same pattern.
 // ---------------------------------------------------------------------------
 constexpr int kRedSplit = 16;
+constexpr int kRedBatch = 16;
 
 __global__ __launch_bounds__(256) void k_reduce_a(const double* __restrict__ gpart,
                                                   const double* __restrict__ fpart,
@@ -89,24 +90,29 @@ __global__ __launch_bounds__(256) void k_reduce_a(const double* __restrict__ gpa
     const int64_t col = (int64_t)blockIdx.x * 64 + lane;
     double s = 0.0;
     if (col < d) {
-      int64_t w = w0;
-      for (; w + 4 <= w1; w += 4) {
-        const double a0 = gpart[(pbase + w) * d + col];
-        const double a1 = gpart[(pbase + w + 1) * d + col];
-        const double a2 = gpart[(pbase + w + 2) * d + col];
-        const double a3 = gpart[(pbase + w + 3) * d + col];
-        s += a0;
-        s += a1;
-        s += a2;
-        s += a3;
+      for (int64_t w = w0; w < w1; w += kRedBatch) {
+        double v[kRedBatch];
+#pragma unroll
+        for (int u = 0; u < kRedBatch; ++u)
+          v[u] = w + u < w1 ? gpart[(pbase + w + u) * d + col] : 0.0;
+#pragma unroll
+        for (int u = 0; u < kRedBatch; ++u)
+          if (w + u < w1) s += v[u];
       }
-      for (; w < w1; ++w) s += gpart[(pbase + w) * d + col];
       red[((int64_t)p * 4 * kRedSplit + grp) * d + col] = s;
     }
   }
   if (blockIdx.x == 0 && lane == 0) {
+    // loads requested kRedBatch at a time, summed in ascending order
     double fs = 0.0;
-    for (int64_t w = w0; w < w1; ++w) fs += fpart[pbase + w];
+    for (int64_t w = w0; w < w1; w += kRedBatch) {
+      double v[kRedBatch];
+#pragma unroll
+      for (int u = 0; u < kRedBatch; ++u) v[u] = w + u < w1 ? fpart[pbase + w + u] : 0.0;
+#pragma unroll
+      for (int u = 0; u < kRedBatch; ++u)
+        if (w + u < w1) fs += v[u];
+    }
     fred[(int64_t)p * 4 * kRedSplit + grp] = fs;
   }
 }
@@ -119,14 +125,24 @@ __global__ __launch_bounds__(64) void k_reduce_b(const double* __restrict__ red,
   const int64_t col = (int64_t)blockIdx.x * 64 + threadIdx.x;
   // after the tolerance stop the pass did not run: keep g, f and the objective
   if (st != nullptr && status_word(&st->done) != 0) return;
+  // every group sum is requested before the first addition (one round trip
+  // instead of one per group); the additions keep the ascending order
   if (col < d) {
+    double v[4 * kRedSplit];
+#pragma unroll
+    for (int q = 0; q < 4 * kRedSplit; ++q) v[q] = red[((int64_t)p * 4 * kRedSplit + q) * d + col];
     double s = 0.0;
-    for (int q = 0; q < 4 * kRedSplit; ++q) s += red[((int64_t)p * 4 * kRedSplit + q) * d + col];
+#pragma unroll
+    for (int q = 0; q < 4 * kRedSplit; ++q) s += v[q];
     g[(int64_t)p * d + col] = s;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
+    double v[4 * kRedSplit];
+#pragma unroll
+    for (int q = 0; q < 4 * kRedSplit; ++q) v[q] = fred[(int64_t)p * 4 * kRedSplit + q];
     double fs = 0.0;
-    for (int q = 0; q < 4 * kRedSplit; ++q) fs += fred[(int64_t)p * 4 * kRedSplit + q];
+#pragma unroll
+    for (int q = 0; q < 4 * kRedSplit; ++q) fs += v[q];
     const double fv = 0.5 * fs;
     if (f != nullptr) f[p] = fv;
     if (st != nullptr) {
