@@ -162,6 +162,7 @@ struct PassBuffers {
   int32_t* chunk_part = nullptr;
   int32_t* bucket_start = nullptr;
   uint32_t* perm = nullptr;
+  int32_t* border = nullptr;  // pairing of long with short sketch rows (dense gather)
   double* gpart = nullptr;
   double* fpart = nullptr;
   double* g = nullptr;
@@ -185,6 +186,7 @@ void carve_pass(Carver& c, const Layout& L, const ihs_sketch* sk, PassBuffers& B
   B.chunk_part = c.take<int32_t>((size_t)std::max<int64_t>((int64_t)L.total_chunks * m, 1));
   B.bucket_start = c.take<int32_t>((size_t)(L.batch * m + 1));
   B.perm = c.take<uint32_t>((size_t)std::max<int64_t>(entries, 1));
+  B.border = c.take<int32_t>((size_t)(L.batch * m));
   const int64_t parts = std::max<int64_t>((int64_t)L.batch * m_blk, L.total_seg);
   B.gpart = c.take<double>((size_t)std::max<int64_t>(parts * L.d, 1));
   B.fpart = c.take<double>((size_t)std::max<int64_t>(parts, 1));
@@ -207,6 +209,7 @@ void carve_sketch_only(Carver& c, const Layout& L, const ihs_sketch* sk, PassBuf
   B.chunk_part = c.take<int32_t>((size_t)std::max<int64_t>((int64_t)L.total_chunks * m, 1));
   B.bucket_start = c.take<int32_t>((size_t)(L.batch * m + 1));
   B.perm = c.take<uint32_t>((size_t)std::max<int64_t>(entries, 1));
+  B.border = c.take<int32_t>((size_t)(L.batch * m));
 }
 
 // ---- the allocation-free sketch apply ----
@@ -264,6 +267,9 @@ SketchPlan make_plan(const Layout& L, const ihs_sketch* sk, const PassBuffers& B
   P.chunk_part = B.chunk_part;
   P.bucket_start = B.bucket_start;
   P.perm = B.perm;
+  const bool paired = !L.csr && gather_rows_per_wave(sk->m, L.batch, L.d) == 2 &&
+                      P.m_blk <= kPairMaxBlock;
+  P.border = paired ? B.border : nullptr;
   return P;
 }
 
@@ -461,6 +467,7 @@ struct SolveBuffers {
   // second set of the double-buffered arrays of the overlapped schedule
   uint32_t* perm1 = nullptr;
   int32_t* bstart1 = nullptr;
+  int32_t* border1 = nullptr;
   void* SA1 = nullptr;
   double* Lf1 = nullptr;
   double* work1 = nullptr;
@@ -519,6 +526,7 @@ size_t carve_solve(Carver& c, const Layout& L, const ihs_options* o, SolveBuffer
   const int64_t entries = L.n * o->sketch.s;
   S.perm1 = c.take<uint32_t>((size_t)std::max<int64_t>(entries, 1));
   S.bstart1 = c.take<int32_t>((size_t)(L.batch * m + 1));
+  S.border1 = c.take<int32_t>((size_t)(L.batch * m));
   S.SA1 = c.take<char>((size_t)(L.batch * m * L.d * dtype_size(gram_in_of(o))));
   S.Lf1 = c.take<double>((size_t)(L.batch * L.d * L.d));
   S.work1 = c.take<double>((size_t)L.batch * qp_work_doubles(L.d, o->constraint));
@@ -786,6 +794,7 @@ ihs_status solve_overlap(const ihs_matrix* A, const Layout& L, const ihs_options
     if (k % 2) {
       P.perm = S.perm1;
       P.bucket_start = S.bstart1;
+      if (P.border != nullptr) P.border = S.border1;
     }
     return P;
   };

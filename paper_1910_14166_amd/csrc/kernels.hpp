@@ -52,7 +52,16 @@ struct SketchPlan {
   int32_t* chunk_part;     // total_chunks * m
   int32_t* bucket_start;   // batch*m + 1
   uint32_t* perm;          // entries: global row | sign << 31, bucket-sorted
+  // nullable, batch*m: border[p*m + j] is the sketch row that position j of
+  // problem p stands for in the dense gather with two sketch rows per
+  // wavefront (positions 2w, 2w+1 belong to wavefront w); null: position j is
+  // sketch row j
+  int32_t* border;
 };
+
+// Largest block length (m / s) for which the sort pairs long with short
+// sketch rows (the ranking costs m_blk^2 comparisons per block).
+constexpr int64_t kPairMaxBlock = 8192;
 
 hipError_t launch_sketch_hash(const SketchPlan& p, int64_t n, int32_t problem,
                               int32_t* bucket, int8_t* sign, hipStream_t st);

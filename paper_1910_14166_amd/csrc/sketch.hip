@@ -312,6 +312,39 @@ __global__ __launch_bounds__(256) void k_scatter(SketchPlan P) {
   }
 }
 
+// Sort step 4 (dense gather with two sketch rows per wavefront): the list
+// lengths vary from sketch row to sketch row, and a wavefront that streams two
+// long lists finishes well after the others. Within every block the rows are
+// ranked by (length descending, index ascending), and rank r goes to position
+// 2r for r < ceil(m_blk/2), else to 2(m_blk-1-r)+1: each wavefront then takes
+// one long and one short list. Each sketch row keeps its own list and order,
+// so S A is unchanged; the order is a function of the lengths alone.
+// One wavefront ranks one sketch row against its block, staged through LDS.
+__global__ __launch_bounds__(256) void k_pair_order(SketchPlan P) {
+  extern __shared__ int32_t len[];
+  const int p = blockIdx.z, blk = blockIdx.y;
+  const int64_t mb = P.m_blk;
+  const int32_t* bs = P.bucket_start + (int64_t)p * P.m + (int64_t)blk * mb;
+  for (int64_t j = threadIdx.x; j < mb; j += blockDim.x) len[j] = bs[j + 1] - bs[j];
+  __syncthreads();
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t r0 = (int64_t)blockIdx.x * 4 + wv;
+  if (r0 >= mb) return;  // no barriers below
+  const int32_t mine = len[r0];
+  int32_t cnt = 0;
+  for (int64_t j = lane; j < mb; j += 64) {
+    const int32_t v = len[j];
+    cnt += (v > mine || (v == mine && j < r0)) ? 1 : 0;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
+  if (lane == 0) {
+    const int64_t half = (mb + 1) / 2;
+    const int64_t pos = cnt < half ? 2 * (int64_t)cnt : 2 * (mb - 1 - cnt) + 1;
+    P.border[(int64_t)p * P.m + (int64_t)blk * mb + pos] = (int32_t)((int64_t)blk * mb + r0);
+  }
+}
+
 constexpr int32_t kSortGrid = 2048;  // workgroup cap of the tile-parallel sort kernels
 
 __global__ void k_zero_i32(int32_t* p, int64_t n) {
@@ -326,16 +359,19 @@ hipError_t launch_sort(const SketchPlan& P, hipStream_t st) {
     const int64_t nb = (int64_t)P.batch * P.m + 1;
     hipLaunchKernelGGL(k_zero_i32, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, st,
                        P.bucket_start, nb);
-    return hipGetLastError();
+  } else {
+    const size_t lds_m = (size_t)P.m * sizeof(int32_t);
+    const unsigned tiles_grid = (unsigned)std::min<int32_t>(P.total_tiles, kSortGrid);
+    hipLaunchKernelGGL(k_hash_count, dim3(tiles_grid), dim3(256), lds_m, st, P);
+    hipLaunchKernelGGL(k_scan_chunks, dim3(P.total_chunks, gy), dim3(256), 0, st, P);
+    hipLaunchKernelGGL(k_scan_rows, dim3(gy, P.batch), dim3(256), 0, st, P);
+    hipLaunchKernelGGL(k_scan_totals, dim3(P.batch), dim3(1024), 0, st, P);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(P.total_chunks, gy), dim3(256), 0, st, P);
+    hipLaunchKernelGGL(k_scatter, dim3(tiles_grid), dim3(256), lds_m, st, P);
   }
-  const size_t lds_m = (size_t)P.m * sizeof(int32_t);
-  const unsigned tiles_grid = (unsigned)std::min<int32_t>(P.total_tiles, kSortGrid);
-  hipLaunchKernelGGL(k_hash_count, dim3(tiles_grid), dim3(256), lds_m, st, P);
-  hipLaunchKernelGGL(k_scan_chunks, dim3(P.total_chunks, gy), dim3(256), 0, st, P);
-  hipLaunchKernelGGL(k_scan_rows, dim3(gy, P.batch), dim3(256), 0, st, P);
-  hipLaunchKernelGGL(k_scan_totals, dim3(P.batch), dim3(1024), 0, st, P);
-  hipLaunchKernelGGL(k_scan_tiles, dim3(P.total_chunks, gy), dim3(256), 0, st, P);
-  hipLaunchKernelGGL(k_scatter, dim3(tiles_grid), dim3(256), lds_m, st, P);
+  if (P.border != nullptr)
+    hipLaunchKernelGGL(k_pair_order, dim3((unsigned)((P.m_blk + 3) / 4), P.s, P.batch), dim3(256),
+                       (size_t)P.m_blk * sizeof(int32_t), st, P);
   return hipGetLastError();
 }
 
@@ -490,6 +526,7 @@ __global__ __launch_bounds__(256, (BPW > 1 ? 3 : (NCH <= 4 ? 4 : 2))) void k_gat
       end = min(beg + seg_rows, pi.row0 + pi.rows);
     } else {
       bl = wid * BPW + own;
+      if (BPW > 1 && P.border != nullptr) bl = P.border[(int64_t)p * P.m + bl];
       bg = (int64_t)p * P.m + bl;
       beg = P.bucket_start[bg];
       end = P.bucket_start[bg + 1];

@@ -53,6 +53,10 @@ CASES = [  # n, d, m, s
     (300, 5, 1, 1),          # one sketch row: every row in one bucket
     (70000, 16, 4096, 4),    # many sort tiles, SJLT over 4 blocks
     (600, 20, 16, 16),       # SJLT with one bucket per block: every row in every sketch row
+    # two sketch rows per wavefront, long lists paired with short ones:
+    (6000, 96, 4098, 2),     # odd block length (2049): one wavefront spans both blocks
+    (3000, 200, 2048, 1),    # about one row per sketch row: many equal list lengths
+    (20000, 72, 16384, 1),   # block longer than the pairing takes: natural order
 ]
 
 
@@ -170,6 +174,23 @@ def test_ragged_batch_sketch(gpu_lib):
     out = host(P.sketch_apply(P.Matrix(dense=dev(A), row_offsets=offs), P.SketchSpec(m, seed=8)))
     for p in range(len(sizes)):
         ref = OS.sketch_apply_dense(A[offs[p]:offs[p + 1]], 8, 0, m, 1, problem=p)
+        assert np.array_equal(out[p * m:(p + 1) * m], ref), p
+
+
+@pytest.mark.parametrize("sizes", [[3000, 0, 1, 2500], [0, 0, 0]])
+def test_ragged_batch_two_rows_per_wave(gpu_lib, sizes):
+    """Batches wide enough (batch * m >= 2048, 64 < d <= 768) for the paired
+    two-rows-per-wavefront gather, with empty problems, and a batch of empty
+    problems only (every list empty)."""
+    P = gpu_lib
+    g = np.random.default_rng(len(sizes))
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    d, m = 80, 1024
+    A = g.standard_normal((offs[-1], d))
+    M = P.Matrix(dense=dev(A.reshape(-1, d)), row_offsets=offs)
+    out = host(P.sketch_apply(M, P.SketchSpec(m, seed=12, iter=2)))
+    for p in range(len(sizes)):
+        ref = OS.sketch_apply_dense(A[offs[p]:offs[p + 1]], 12, 2, m, 1, problem=p)
         assert np.array_equal(out[p * m:(p + 1) * m], ref), p
 
 
