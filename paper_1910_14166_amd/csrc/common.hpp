@@ -18,20 +18,6 @@ struct U64x4 {
   uint64_t w[4];
 };
 
-// The full 128-bit product a*b from its four 32 x 32 -> 64 partial products
-// (one multiply-add instruction each); the low half reuses them instead of
-// separate low multiplies.
-__device__ __forceinline__ void mul_64x64_128(uint64_t a, uint64_t b, uint64_t& lo,
-                                              uint64_t& hi) {
-  const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32);
-  const uint32_t b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
-  const uint64_t p00 = (uint64_t)a0 * b0, p01 = (uint64_t)a0 * b1;
-  const uint64_t p10 = (uint64_t)a1 * b0, p11 = (uint64_t)a1 * b1;
-  const uint64_t mid = (p00 >> 32) + (uint32_t)p01 + (uint32_t)p10;  // < 3 * 2^32
-  lo = (mid << 32) | (uint32_t)p00;
-  hi = p11 + (p01 >> 32) + (p10 >> 32) + (mid >> 32);
-}
-
 __device__ __forceinline__ U64x4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2,
                                                uint64_t c3, uint64_t k0, uint64_t k1) {
   const uint64_t kMul0 = 0xD2E7470EE14C6C93ull;
@@ -44,9 +30,8 @@ __device__ __forceinline__ U64x4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_
       k0 += kInc0;
       k1 += kInc1;
     }
-    uint64_t lo_a, hi_a, lo_b, hi_b;
-    mul_64x64_128(kMul0, c0, lo_a, hi_a);
-    mul_64x64_128(kMul1, c2, lo_b, hi_b);
+    const uint64_t lo_a = kMul0 * c0, hi_a = __umul64hi(kMul0, c0);
+    const uint64_t lo_b = kMul1 * c2, hi_b = __umul64hi(kMul1, c2);
     const uint64_t n0 = hi_b ^ c1 ^ k0;
     const uint64_t n2 = hi_a ^ c3 ^ k1;
     c0 = n0;

@@ -319,19 +319,38 @@ __global__ __launch_bounds__(256) void k_scatter(SketchPlan P) {
 // 2r for r < ceil(m_blk/2), else to 2(m_blk-1-r)+1: each wavefront then takes
 // one long and one short list. Each sketch row keeps its own list and order,
 // so S A is unchanged; the order is a function of the lengths alone.
-// One wavefront ranks one sketch row against its block, staged through LDS.
-__global__ __launch_bounds__(256) void k_pair_order(SketchPlan P) {
+// A 1024-thread workgroup stages its block's lengths in LDS once; each of its
+// sixteen wavefronts then ranks one sketch row against them.
+constexpr int kPairThreads = 1024;
+constexpr int kPairPerGroup = kPairThreads / 64;
+
+__global__ __launch_bounds__(kPairThreads) void k_pair_order(SketchPlan P) {
   extern __shared__ int32_t len[];
   const int p = blockIdx.z, blk = blockIdx.y;
   const int64_t mb = P.m_blk;
   const int32_t* bs = P.bucket_start + (int64_t)p * P.m + (int64_t)blk * mb;
-  for (int64_t j = threadIdx.x; j < mb; j += blockDim.x) len[j] = bs[j + 1] - bs[j];
+  // every thread requests 8 list extents before it stores their lengths
+  for (int64_t j0 = 0; j0 < mb; j0 += 8 * kPairThreads) {
+    int32_t lo[8], hi[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t j = j0 + u * kPairThreads + threadIdx.x;
+      lo[u] = j < mb ? bs[j] : 0;
+      hi[u] = j < mb ? bs[j + 1] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t j = j0 + u * kPairThreads + threadIdx.x;
+      if (j < mb) len[j] = hi[u] - lo[u];
+    }
+  }
   __syncthreads();
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t r0 = (int64_t)blockIdx.x * 4 + wv;
+  const int64_t r0 = (int64_t)blockIdx.x * kPairPerGroup + wv;
   if (r0 >= mb) return;  // no barriers below
   const int32_t mine = len[r0];
   int32_t cnt = 0;
+#pragma unroll 8
   for (int64_t j = lane; j < mb; j += 64) {
     const int32_t v = len[j];
     cnt += (v > mine || (v == mine && j < r0)) ? 1 : 0;
@@ -370,8 +389,9 @@ hipError_t launch_sort(const SketchPlan& P, hipStream_t st) {
     hipLaunchKernelGGL(k_scatter, dim3(tiles_grid), dim3(256), lds_m, st, P);
   }
   if (P.border != nullptr)
-    hipLaunchKernelGGL(k_pair_order, dim3((unsigned)((P.m_blk + 3) / 4), P.s, P.batch), dim3(256),
-                       (size_t)P.m_blk * sizeof(int32_t), st, P);
+    hipLaunchKernelGGL(k_pair_order,
+                       dim3((unsigned)((P.m_blk + kPairPerGroup - 1) / kPairPerGroup), P.s, P.batch),
+                       dim3(kPairThreads), (size_t)P.m_blk * sizeof(int32_t), st, P);
   return hipGetLastError();
 }
 
