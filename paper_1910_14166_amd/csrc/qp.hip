@@ -229,15 +229,22 @@ __device__ __forceinline__ void rsqrt_sqrt(double x, double& r, double& s) {
 // beside the bucket gather.
 constexpr int kDiagThreads = 512;
 
-__global__ __launch_bounds__(kDiagThreads) void k_chol_diag(double* L, int64_t d, int64_t kb,
-                                                            double* rdiag, DeviceStatus* st,
-                                                            int32_t iter,
-                                                            const double* __restrict__ trs) {
+// The factor of problem p's diagonal block at kb, by one kDiagThreads workgroup.
+// UPDATE: the block first takes its share of the trailing update of the
+// panel before it, B -= P P^T with P = W[kb:kb+64, kb-64:kb]: P is staged in
+// LDS with the block's own loads (one memory round trip), each wavefront forms
+// one or two of the block's ten lower 16 x 16 tiles on MFMA from LDS, in the
+// operand and accumulation order of chol_update_tile (so the factor is
+// bitwise that of a separate update), and the tiles return through LDS to the
+// threads that hold the block's rows.
+template <bool UPDATE>
+__device__ __forceinline__ void chol_diag_block(double* L, int64_t d, int64_t kb, double* rdiag,
+                                                DeviceStatus* st, int32_t iter,
+                                                const double* __restrict__ trs, int p) {
   __shared__ double Pb[kNb][4];  // the step's four columns of every row
   __shared__ double Zb[kNb][4];  // the step's panel entries of every row
   __shared__ double rd[kNb];
   __shared__ int flag;
-  const int p = blockIdx.x;
   const int tid = threadIdx.x;
   double* W = L + (int64_t)p * d * d;
   const int nb = (int)min((int64_t)kNb, d - kb);
@@ -246,9 +253,61 @@ __global__ __launch_bounds__(kDiagThreads) void k_chol_diag(double* L, int64_t d
 #pragma unroll
   for (int q = 0; q < 8; ++q)
     a[q] = (i < nb && k0 + q <= i) ? W[(kb + i) * d + kb + k0 + q] : 0.0;
-  if (tid == 0) flag = (st->code != 0 || trs_skip(trs, p)) ? 1 : 0;
-  __syncthreads();
-  if (flag != 0) return;
+  if constexpr (UPDATE) {
+    __shared__ double Ps[kNb][kNb + 1];  // P, then the update's tiles
+    constexpr int kPer = kNb * kNb / kDiagThreads;
+    double pv[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int e = u * kDiagThreads + tid, r = e / kNb, c = e % kNb;
+      pv[u] = r < nb ? W[(kb + r) * d + kb - kNb + c] : 0.0;
+    }
+    if (tid == 0) flag = (st->code != 0 || trs_skip(trs, p)) ? 1 : 0;
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int e = u * kDiagThreads + tid;
+      Ps[e / kNb][e % kNb] = pv[u];
+    }
+    __syncthreads();
+    if (flag != 0) return;
+    const int wv = tid >> 6, lane = tid & 63;
+    const int r = lane & 15, kk = lane >> 4, rq = lane >> 4, col = lane & 15;
+    constexpr int kTiles = (kNb / 16) * (kNb / 16 + 1) / 2;
+    constexpr int kWaves = kDiagThreads / 64;
+    f64x4 acc[2] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int t = wv + h * kWaves;
+      if (t < kTiles) {
+        const int ti = t >= 6 ? 3 : (t >= 3 ? 2 : (t >= 1 ? 1 : 0));
+        const int tj = t - ti * (ti + 1) / 2;
+#pragma unroll
+        for (int k = 0; k < kNb / 4; ++k)
+          acc[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(Ps[ti * 16 + r][4 * k + kk],
+                                                        Ps[tj * 16 + r][4 * k + kk], acc[h], 0, 0,
+                                                        0);
+      }
+    }
+    __syncthreads();  // every read of P is done
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int t = wv + h * kWaves;
+      if (t < kTiles) {
+        const int ti = t >= 6 ? 3 : (t >= 3 ? 2 : (t >= 1 ? 1 : 0));
+        const int tj = t - ti * (ti + 1) / 2;
+#pragma unroll
+        for (int reg = 0; reg < 4; ++reg) Ps[ti * 16 + 4 * reg + rq][tj * 16 + col] = acc[h][reg];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      if (i < nb && k0 + q <= i) a[q] = a[q] - Ps[i][k0 + q];
+  } else {
+    if (tid == 0) flag = (st->code != 0 || trs_skip(trs, p)) ? 1 : 0;
+    __syncthreads();
+    if (flag != 0) return;
+  }
   int bad = 0;
   for (int S = 0; S < 8 && !bad; ++S) {
 #pragma unroll
@@ -351,6 +410,13 @@ __global__ __launch_bounds__(kDiagThreads) void k_chol_diag(double* L, int64_t d
   if (tid < nb) rdiag[(int64_t)p * d + kb + tid] = rd[tid];
 }
 
+__global__ __launch_bounds__(kDiagThreads) void k_chol_diag(double* L, int64_t d, int64_t kb,
+                                                            double* rdiag, DeviceStatus* st,
+                                                            int32_t iter,
+                                                            const double* __restrict__ trs) {
+  chol_diag_block<false>(L, d, kb, rdiag, st, iter, trs, blockIdx.x);
+}
+
 // Panel rows below the diagonal block: x L_kk^T = a for each row, one row per
 // wavefront pass with lanes over the 64 columns; the factored block is staged
 // in LDS and x_c is read from lane c (column-oriented substitution).
@@ -399,33 +465,21 @@ __global__ __launch_bounds__(256) void k_chol_trsm(double* L, int64_t d, int64_t
 // P = W[:, kb:kb+64]. One wavefront per 16 x 16 lower tile (small register
 // footprint, so these tiles also run beside a memory-bound pass). All operand
 // loads, the tile's own entries and the status are requested up front: one
-// memory round trip before the MFMA chain.
-__global__ __launch_bounds__(256) void k_chol_update(double* L, int64_t d, int64_t kb,
-                                                     int32_t batch, DeviceStatus* st,
-                                                     const double* __restrict__ trs) {
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+// memory round trip before the MFMA chain. Tile t of the lower triangle of
+// T x T tiles is (ti, tj), t = ti (ti + 1) / 2 + tj.
+__device__ __forceinline__ void chol_update_tile(double* W, int64_t d, int64_t kb, int64_t t,
+                                                 int lane, const DeviceStatus* st,
+                                                 const double* __restrict__ trs, int p) {
   const int64_t t0 = kb + kNb;
-  const int64_t T = (d - t0 + 15) / 16;
-  const int64_t ntri = T * (T + 1) / 2;
-  const int64_t w = (int64_t)blockIdx.x * 4 + wv;
-  if (w >= ntri * batch) return;
-  const int p = (int)(w / ntri);
-  const int64_t t = w - (int64_t)p * ntri;
   int64_t ti = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
   while (ti * (ti + 1) / 2 > t) --ti;
   while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
   const int64_t tj = t - ti * (ti + 1) / 2;
-  double* W = L + (int64_t)p * d * d;
   const int64_t r0 = t0 + ti * 16, c0 = t0 + tj * 16;
   const int r = lane & 15, kk = lane >> 4;
   const bool ra = r0 + r < d, rb = c0 + r < d;
-  double av[kNb / 4], bv[kNb / 4];
-#pragma unroll
-  for (int k = 0; k < kNb / 4; ++k) {
-    const int64_t col = kb + 4 * k + kk;
-    av[k] = ra ? W[(r0 + r) * d + col] : 0.0;
-    bv[k] = rb ? W[(c0 + r) * d + col] : 0.0;
-  }
+  const double* pa = W + (r0 + r) * d + kb + kk;
+  const double* pb = W + (c0 + r) * d + kb + kk;
   const int col = lane & 15, rq = lane >> 4;
   double cur[4];
 #pragma unroll
@@ -433,16 +487,68 @@ __global__ __launch_bounds__(256) void k_chol_update(double* L, int64_t d, int64
     const int64_t ii = r0 + 4 * reg + rq, jj = c0 + col;
     cur[reg] = (ii < d && jj < d && jj <= ii) ? W[ii * d + jj] : 0.0;
   }
+  // the panel's 64 columns in four chunks of 16, each chunk's operands
+  // requested before the previous chunk's products (few registers, so a
+  // workgroup of the diagonal factor's size fits beside a memory-bound pass)
+  constexpr int KC = kNb / 16;  // MFMA steps per chunk
+  double av[KC], bv[KC];
+#pragma unroll
+  for (int k = 0; k < KC; ++k) {
+    av[k] = ra ? pa[4 * k] : 0.0;
+    bv[k] = rb ? pb[4 * k] : 0.0;
+  }
   if (st->code != 0 || trs_skip(trs, p)) return;
   f64x4 acc = {0, 0, 0, 0};
 #pragma unroll
-  for (int k = 0; k < kNb / 4; ++k)
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[k], bv[k], acc, 0, 0, 0);
+  for (int c = 0; c < 4; ++c) {
+    double an[KC], bn[KC];
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+      an[k] = (c + 1 < 4 && ra) ? pa[4 * (KC * (c + 1) + k)] : 0.0;
+      bn[k] = (c + 1 < 4 && rb) ? pb[4 * (KC * (c + 1) + k)] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < KC; ++k) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[k], bv[k], acc, 0, 0, 0);
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+      av[k] = an[k];
+      bv[k] = bn[k];
+    }
+  }
 #pragma unroll
   for (int reg = 0; reg < 4; ++reg) {
     const int64_t ii = r0 + 4 * reg + rq, jj = c0 + col;
     if (ii < d && jj < d && jj <= ii) W[ii * d + jj] = cur[reg] - acc[reg];
   }
+}
+
+// The trailing update after panel kb fused with the factor of the next
+// diagonal block (kb + 64): workgroup p < batch updates that block (the first
+// tiles of the triangle) and factors it, while the other workgroups update the
+// rest of the trailing matrix, which that block does not read. One launch per
+// block step instead of two, and the block's factor runs beside the update
+// instead of after it. At most 96 registers, so that two of these 512-thread
+// workgroups' waves per SIMD fit beside the bucket gather.
+__global__ __launch_bounds__(kDiagThreads) __attribute__((amdgpu_waves_per_eu(5))) void k_chol_update_diag(
+    double* L, int64_t d, int64_t kb, int32_t batch, double* rdiag, DeviceStatus* st,
+    int32_t iter, const double* __restrict__ trs) {
+  constexpr int kWaves = kDiagThreads / 64;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t t0 = kb + kNb;
+  const int64_t T = (d - t0 + 15) / 16;
+  const int64_t Tn = min(T, (int64_t)(kNb / 16));
+  const int64_t ndiag = Tn * (Tn + 1) / 2;  // tiles of the next diagonal block
+  const int64_t ntri = T * (T + 1) / 2;
+  if ((int)blockIdx.x < batch) {
+    chol_diag_block<true>(L, d, t0, rdiag, st, iter, trs, blockIdx.x);
+    return;
+  }
+  const int64_t per = ntri - ndiag;
+  const int64_t w = (int64_t)(blockIdx.x - batch) * kWaves + wv;
+  if (w >= per * batch) return;
+  const int p = (int)(w / per);
+  chol_update_tile(L + (int64_t)p * d * d, d, kb, ndiag + (w - (int64_t)p * per), lane, st, trs,
+                   p);
 }
 
 hipError_t launch_cholesky(const double* H, double* L, int64_t d, int32_t batch,
@@ -452,18 +558,20 @@ hipError_t launch_cholesky(const double* H, double* L, int64_t d, int32_t batch,
   const int64_t tot = (int64_t)batch * d * d;
   hipLaunchKernelGGL(k_chol_init, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, H, L, d,
                      batch, shift, trs);
-  for (int64_t kb = 0; kb < d; kb += kNb) {
-    hipLaunchKernelGGL(k_chol_diag, dim3(batch), dim3(kDiagThreads), 0, st, L, d, kb, rdiag, status,
-                       iter, trs);
-    const int64_t below = std::max<int64_t>(0, d - kb - kNb);
-    if (below == 0) break;
+  hipLaunchKernelGGL(k_chol_diag, dim3(batch), dim3(kDiagThreads), 0, st, L, d, (int64_t)0, rdiag,
+                     status, iter, trs);
+  for (int64_t kb = 0; kb + kNb < d; kb += kNb) {
+    const int64_t below = d - kb - kNb;
     const unsigned gx = (unsigned)((below + 15) / 16);  // 16 rows per workgroup
     hipLaunchKernelGGL(k_chol_trsm, dim3(gx, batch), dim3(256), 0, st, L, d, kb, rdiag, status,
                        trs);
+    // the update after panel kb and the factor of the diagonal block at kb + 64
     const int64_t T = (below + 15) / 16;
-    const int64_t waves = T * (T + 1) / 2 * batch;
-    hipLaunchKernelGGL(k_chol_update, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st, L, d,
-                       kb, batch, status, trs);
+    const int64_t Tn = std::min<int64_t>(T, kNb / 16);
+    const int64_t rest = (T * (T + 1) / 2 - Tn * (Tn + 1) / 2) * batch;
+    constexpr int64_t kWaves = kDiagThreads / 64;
+    hipLaunchKernelGGL(k_chol_update_diag, dim3((unsigned)(batch + (rest + kWaves - 1) / kWaves)),
+                       dim3(kDiagThreads), 0, st, L, d, kb, batch, rdiag, status, iter, trs);
   }
   return hipGetLastError();
 }
