@@ -777,8 +777,8 @@ ihs_status solve_overlap(const ihs_matrix* A, const Layout& L, const ihs_options
   const int32_t N = opt->max_iter;
   const int64_t d = A->d, m = opt->sketch.m;
   const int64_t bd = (int64_t)L.batch * d;
-  EventRing evSort(4), evPass(4), evChol(4), evMisc(3);
-  if (!evSort.ok || !evPass.ok || !evChol.ok || !evMisc.ok) return IHS_ERR_HIP;
+  EventRing evSort(4), evPass(4), evChol(4), evMisc(3), evHash(4);
+  if (!evSort.ok || !evPass.ok || !evChol.ok || !evMisc.ok || !evHash.ok) return IHS_ERR_HIP;
   auto ck = [](hipError_t e) { return !hip_failed(e); };
   // the extra streams start after everything already queued on the caller's
   // stream, the cleared side status records included
@@ -896,10 +896,11 @@ ihs_status solve_overlap(const ihs_matrix* A, const Layout& L, const ihs_options
   SideQueue sq(dev);  // after everything its jobs refer to, so it is joined first
   // side: H_{t+LA} and its factor, queued by the side thread once `after`
   // has been reached on the caller's stream
-  auto post_side = [&](int32_t t, hipEvent_t after) {
-    const int64_t job = sq.post([&, t, after]() {
+  auto post_side = [&](int32_t t, hipEvent_t after, hipEvent_t after2) {
+    const int64_t job = sq.post([&, t, after, after2]() {
       const hipStream_t sk = side_of(t + LA);
       if (!ck(hipStreamWaitEvent(sk, after, 0))) return false;
+      if (after2 != nullptr && !ck(hipStreamWaitEvent(sk, after2, 0))) return false;
       return t + LA >= N || (factor(t + LA) && ck(hipEventRecord(evChol.at(t + LA), sk)));
     });
     chol_job.at((size_t)((t + LA) % chol_job.size())) = job;
@@ -921,15 +922,19 @@ ihs_status solve_overlap(const ihs_matrix* A, const Layout& L, const ihs_options
       return IHS_ERR_HIP;
     // sorter: rows for S_{t+LA+1}, once P_t is done (its scattered writes
     // would slow the pass if they ran beside it); it shares the gap between
-    // passes with the tail of the side stream and the update of x
+    // passes with the tail of the side stream and the update of x. The sort
+    // is what the next pass waits for; its hash is arithmetic-bound, so an
+    // unconstrained step's Gram (whose factorisation has time to spare) starts
+    // only once the hash is done.
+    const bool hash_first = !constrained && t + 2 <= N;
     if (t + 2 <= N) {
       if (!ck(hipStreamWaitEvent(sorter, evPass.at(t), 0)) ||
-          !ck(launch_sort(plan_for(t + LA + 1), sorter)) ||
+          !ck(launch_sort(plan_for(t + LA + 1), sorter, hash_first ? evHash.at(t) : nullptr)) ||
           !ck(hipEventRecord(evSort.at(t + LA + 1), sorter)))
         return IHS_ERR_HIP;
     }
     // side: H_{t+LA} and its factor, from the end of pass t on
-    post_side(t, evPass.at(t));
+    post_side(t, evPass.at(t), hash_first ? evHash.at(t) : nullptr);
     // main: x^{t+1} = x^t + H_t^{-1} g(x^t), or the constrained QP of Eq.(2)
     // with H_t (its l2 shift state carries over in S.work from step to step)
     if (!sq.wait(chol_job.at((size_t)(t % chol_job.size()))) ||

@@ -65,7 +65,8 @@ constexpr int64_t kPairMaxBlock = 8192;
 
 hipError_t launch_sketch_hash(const SketchPlan& p, int64_t n, int32_t problem,
                               int32_t* bucket, int8_t* sign, hipStream_t st);
-hipError_t launch_sort(const SketchPlan& p, hipStream_t st);
+// after_hash (nullable) is recorded on st once every key is hashed and counted.
+hipError_t launch_sort(const SketchPlan& p, hipStream_t st, hipEvent_t after_hash = nullptr);
 
 struct GatherArgs {
   const void* A;           // dense rows

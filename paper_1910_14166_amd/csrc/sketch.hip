@@ -371,17 +371,25 @@ __global__ void k_zero_i32(int32_t* p, int64_t n) {
   if (i < n) p[i] = 0;
 }
 
-hipError_t launch_sort(const SketchPlan& P, hipStream_t st) {
+hipError_t launch_sort(const SketchPlan& P, hipStream_t st, hipEvent_t after_hash) {
   const unsigned gy = (unsigned)((P.m + 255) / 256);
   if (P.total_tiles == 0) {
     // every problem is empty: all segments start (and end) at 0
     const int64_t nb = (int64_t)P.batch * P.m + 1;
     hipLaunchKernelGGL(k_zero_i32, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, st,
                        P.bucket_start, nb);
+    if (after_hash != nullptr) {
+      const hipError_t e = hipEventRecord(after_hash, st);
+      if (e != hipSuccess) return e;
+    }
   } else {
     const size_t lds_m = (size_t)P.m * sizeof(int32_t);
     const unsigned tiles_grid = (unsigned)std::min<int32_t>(P.total_tiles, kSortGrid);
     hipLaunchKernelGGL(k_hash_count, dim3(tiles_grid), dim3(256), lds_m, st, P);
+    if (after_hash != nullptr) {
+      const hipError_t e = hipEventRecord(after_hash, st);
+      if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(k_scan_chunks, dim3(P.total_chunks, gy), dim3(256), 0, st, P);
     hipLaunchKernelGGL(k_scan_rows, dim3(gy, P.batch), dim3(256), 0, st, P);
     hipLaunchKernelGGL(k_scan_totals, dim3(P.batch), dim3(1024), 0, st, P);
