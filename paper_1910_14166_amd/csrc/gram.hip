@@ -60,8 +60,10 @@ static GramPlan make_gram_plan(int64_t m, int64_t d, int64_t ld, int32_t batch, 
   g.tile = tile_of(in, acc, d);
   g.ntile = (int32_t)((d + g.tile - 1) / g.tile);
   g.ntri = g.ntile * (g.ntile + 1) / 2;
-  // the wide FP64 tiles: two workgroups per CU (LDS and registers)
-  const int32_t cap = g.tile == kTileF64Wide && in != 2 ? 2 : 4;
+  // the wide FP64 tiles: two workgroups per CU (LDS and registers); BF16
+  // products: two per CU as well, since each extra slice adds a tile of FP32
+  // partials to write and reduce (8192 x 1024: 51 us at four, 42 at two)
+  const int32_t cap = (g.tile == kTileF64Wide || in == 2) ? 2 : 4;
   const int64_t slots = (int64_t)kCUs * std::max(1, std::min(per_cu, cap));
   const int64_t tiles = (int64_t)batch * g.ntri;
   int64_t splits = std::max<int64_t>(1, slots / tiles);
