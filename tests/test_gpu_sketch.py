@@ -177,20 +177,24 @@ def test_ragged_batch_sketch(gpu_lib):
         assert np.array_equal(out[p * m:(p + 1) * m], ref), p
 
 
-@pytest.mark.parametrize("sizes", [[3000, 0, 1, 2500], [0, 0, 0]])
-def test_ragged_batch_two_rows_per_wave(gpu_lib, sizes):
+@pytest.mark.parametrize("sizes,s", [([3000, 0, 1, 2500], 1), ([0, 0, 0], 1),
+                                     ([3000, 0, 1, 2500], 4), ([2500, 700], 2)])
+def test_ragged_batch_two_rows_per_wave(gpu_lib, sizes, s):
     """Batches wide enough (batch * m >= 2048, 64 < d <= 768) for the paired
-    two-rows-per-wavefront gather, with empty problems, and a batch of empty
-    problems only (every list empty)."""
+    two-rows-per-wavefront gather, with empty problems, a batch of empty
+    problems only (every list empty), and SJLT blocks (pairs formed within
+    each block; m = 1026 at s = 2 gives blocks of odd length)."""
     P = gpu_lib
-    g = np.random.default_rng(len(sizes))
+    g = np.random.default_rng(len(sizes) + s)
     offs = np.concatenate([[0], np.cumsum(sizes)])
-    d, m = 80, 1024
+    d = 80
+    m = 1026 if s == 2 else 1024
+    kind = "sjlt" if s > 1 else "countsketch"
     A = g.standard_normal((offs[-1], d))
     M = P.Matrix(dense=dev(A.reshape(-1, d)), row_offsets=offs)
-    out = host(P.sketch_apply(M, P.SketchSpec(m, seed=12, iter=2)))
+    out = host(P.sketch_apply(M, P.SketchSpec(m, s, kind, seed=12, iter=2)))
     for p in range(len(sizes)):
-        ref = OS.sketch_apply_dense(A[offs[p]:offs[p + 1]], 12, 2, m, 1, problem=p)
+        ref = OS.sketch_apply_dense(A[offs[p]:offs[p + 1]], 12, 2, m, s, problem=p)
         assert np.array_equal(out[p * m:(p + 1) * m], ref), p
 
 
