@@ -79,10 +79,11 @@ typedef enum { IHS_METHOD_IHS = 0, IHS_METHOD_FIXED_SKETCH_CG = 1 } ihs_method;
 /* The data matrix A (n x d). Dense: `values` (device) holds n rows of `ld`
  * elements, dtype F64 or F32. CSR: `row_ptr` (device, n+1), `col_idx`
  * (device, nnz, sorted and unique within each row, in [0, d)) and `values`
- * (device, nnz, F64). A ragged batch (`batch` > 1, dense only) stacks the rows
- * of `batch` independent problems of the same width d; `row_offsets` is a HOST
- * array of batch+1 increasing entries with row_offsets[0] = 0 and
- * row_offsets[batch] = n. batch = 1 ignores row_offsets. */
+ * (device, nnz, F64). A ragged batch (`batch` > 1, dense or CSR) stacks the
+ * rows of `batch` independent problems of the same width d (for CSR, row_ptr
+ * and col_idx span all n rows); `row_offsets` is a HOST array of batch+1
+ * increasing entries with row_offsets[0] = 0 and row_offsets[batch] = n.
+ * batch = 1 ignores row_offsets. */
 typedef struct {
   int32_t format;              /* ihs_format                                  */
   int32_t dtype;               /* ihs_dtype of values: IHS_F64 or IHS_F32     */

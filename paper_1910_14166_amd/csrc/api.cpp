@@ -105,7 +105,6 @@ ihs_status check_matrix(const ihs_matrix* A) {
       return IHS_ERR_UNSUPPORTED;
   } else if (A->format == IHS_CSR) {
     if (A->dtype != IHS_F64) return IHS_ERR_INVALID_ARG;
-    if (A->batch != 1) return IHS_ERR_UNSUPPORTED;
     if (A->nnz < 0 || !A->row_ptr) return IHS_ERR_INVALID_ARG;
     if (A->nnz > 0 && (!A->col_idx || !A->values)) return IHS_ERR_INVALID_ARG;
     if (A->nnz >= (int64_t(1) << 31)) return IHS_ERR_UNSUPPORTED;

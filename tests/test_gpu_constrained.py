@@ -467,3 +467,51 @@ def test_ihs_l2_ragged_batch_matches_oracle(gpu_lib, schedule):
                                                          bud[t][0])
             assert np.linalg.norm(dx) <= bud[t][1], (p, t)
     assert 0 < active < wl.batch, active
+
+
+@pytest.mark.gpu
+def test_ihs_l2_csr_ragged_batch_matches_oracle(gpu_lib):
+    """The l2-ball solve on a ragged batch of CSR problems (rows of one CSR
+    matrix split by row_offsets), in the overlapped schedule: one radius for
+    all, between the smallest and largest ||x_OPT||; every problem's iterates
+    against the oracle's loop on its own rows within the rounding budget."""
+    P = gpu_lib
+    wl = W.ridge_csr(rows=24000, d=128, density=0.01, m=1024, iters=6)
+    offs = np.array([0, 7000, 15000, 24000])
+    nb = len(offs) - 1
+
+    def rows(p):
+        r0, r1 = int(offs[p]), int(offs[p + 1])
+        lo, hi = int(wl.indptr[r0]), int(wl.indptr[r1])
+        return (wl.indptr[r0:r1 + 1] - lo, wl.indices[lo:hi], wl.data[lo:hi], r1 - r0, wl.d)
+
+    csrs = [rows(p) for p in range(nb)]
+    As = [O.csr_matrix(*c) for c in csrs]
+    bs = [wl.b[offs[p]:offs[p + 1]] for p in range(nb)]
+    norms = [np.linalg.norm(O.x_opt(As[p], bs[p])) for p in range(nb)]
+    radius = 0.5 * (min(norms) + max(norms))
+    M = P.Matrix(row_ptr=dev(wl.indptr), col_idx=dev(wl.indices), values=dev(wl.data),
+                 n=wl.n, d=wl.d, row_offsets=offs)
+    o = P.options(wl.m, seed=wl.sketch_seed, max_iter=wl.iters, constraint="l2", radius=radius)
+    res = P.solve(M, dev(wl.b), o, history=True)
+    assert res.report.status == 0
+    hist = host(res.history)
+    active = 0
+    for p in range(nb):
+        x = np.zeros(wl.d)
+        xs, sas, Hs = [x.copy()], [], []
+        for t in range(wl.iters):
+            SA = OS.sketch_apply_csr(*csrs[p], wl.sketch_seed, t, wl.m, 1, problem=p)
+            H = SA.T @ SA
+            _, gr, _ = O.gradient(As[p], bs[p], x)
+            x = O.qp_step(H, gr, x, "l2", radius)
+            xs.append(x.copy())
+            sas.append(SA)
+            Hs.append(H)
+        active += np.linalg.norm(xs[-1]) > radius * (1 - 1e-9)
+        bud = RB.ihs_budget(As[p], bs[p], sas, Hs, xs, "l2", radius)
+        for t in range(wl.iters):
+            dx = hist[t, p] - xs[t + 1]
+            assert np.linalg.norm(As[p] @ dx) <= bud[t][0], (p, t)
+            assert np.linalg.norm(dx) <= bud[t][1], (p, t)
+    assert 0 < active < nb, active

@@ -146,6 +146,32 @@ def test_csr_sketch_bit_exact(gpu_lib, n, d, density, m, s):
     assert np.array_equal(out, ref)
 
 
+def csr_rows(wl, r0, r1):
+    """Rows r0 .. r1 of a CSR workload as a CSR matrix of their own."""
+    lo, hi = int(wl.indptr[r0]), int(wl.indptr[r1])
+    return wl.indptr[r0:r1 + 1] - lo, wl.indices[lo:hi], wl.data[lo:hi], r1 - r0
+
+
+@pytest.mark.parametrize("s", [1, 4])
+def test_csr_ragged_batch_sketch(gpu_lib, s):
+    """A ragged batch of CSR problems (rows of one CSR matrix split by
+    row_offsets, an empty problem among them): each problem's sketch
+    bit-exact against the oracle's on its own rows, with its own hash
+    stream."""
+    P = gpu_lib
+    wl = W.ridge_csr(rows=9000, d=200, density=0.02, m=512)
+    offs = np.array([0, 3000, 3000, 3001, 9000])
+    M = P.Matrix(row_ptr=dev(wl.indptr), col_idx=dev(wl.indices), values=dev(wl.data),
+                 n=wl.n, d=wl.d, row_offsets=offs)
+    kind = "sjlt" if s > 1 else "countsketch"
+    m = 512
+    out = host(P.sketch_apply(M, P.SketchSpec(m, s, kind, seed=6, iter=2)))
+    for p in range(len(offs) - 1):
+        ip, ix, dv, n_p = csr_rows(wl, offs[p], offs[p + 1])
+        ref = OS.sketch_apply_csr(ip, ix, dv, n_p, wl.d, 6, 2, m, s, problem=p)
+        assert np.array_equal(out[p * m:(p + 1) * m], ref), p
+
+
 def test_csr_hot_column_ordering(gpu_lib):
     """Every row hits column 0: each wavefront batch holds 64 equal columns."""
     P = gpu_lib

@@ -61,6 +61,60 @@ def test_gradient_csr(gpu_lib):
     assert abs(host(f)[0] - f_ref) <= 1e-12 * f_ref
 
 
+def csr_rows(wl, r0, r1):
+    """Rows r0 .. r1 of a CSR workload as a CSR matrix of their own."""
+    lo, hi = int(wl.indptr[r0]), int(wl.indptr[r1])
+    return wl.indptr[r0:r1 + 1] - lo, wl.indices[lo:hi], wl.data[lo:hi], r1 - r0
+
+
+def test_gradient_csr_ragged_batch(gpu_lib):
+    """CSR rows split into a ragged batch (an empty problem and a one-row
+    problem among them): each problem's gradient and objective against the
+    oracle's on its own rows."""
+    P = gpu_lib
+    wl = W.ridge_csr(rows=12000, d=300, density=0.01)
+    offs = np.array([0, 5000, 5000, 5001, 12000])
+    X = np.random.default_rng(3).standard_normal((len(offs) - 1, wl.d))
+    M = P.Matrix(row_ptr=dev(wl.indptr), col_idx=dev(wl.indices), values=dev(wl.data),
+                 n=wl.n, d=wl.d, row_offsets=offs)
+    gg, _, f = P.gradient(M, dev(wl.b), dev(X))
+    for p in range(len(offs) - 1):
+        ip, ix, dv, n_p = csr_rows(wl, offs[p], offs[p + 1])
+        Ap = O.csr_matrix(ip, ix, dv, n_p, wl.d)
+        bp = wl.b[offs[p]:offs[p + 1]]
+        _, g_ref, f_ref = O.gradient(Ap, bp, X[p])
+        absA = abs(Ap)
+        scale = absA.T @ (np.abs(bp) + absA @ np.abs(X[p]))
+        assert np.all(np.abs(host(gg)[p] - g_ref) <= 4 * (n_p + wl.d) * U * scale + 1e-300), p
+        assert abs(host(f)[p] - f_ref) <= 1e-12 * max(f_ref, 1e-300), p
+
+
+@pytest.mark.parametrize("schedule", ["overlap", "sequential"])
+def test_ihs_csr_ragged_batch(gpu_lib, schedule):
+    """IHS on a ragged batch of CSR problems: every problem's iterate after
+    each step against the oracle's loop on its own rows, with its own
+    sketch stream (problem index p)."""
+    P = gpu_lib
+    wl = W.ridge_csr(rows=30000, d=80, density=0.02, m=640, iters=6)
+    offs = np.array([0, 9000, 21000, 30000])
+    M = P.Matrix(row_ptr=dev(wl.indptr), col_idx=dev(wl.indices), values=dev(wl.data),
+                 n=wl.n, d=wl.d, row_offsets=offs)
+    opts = P.options(wl.m, seed=wl.sketch_seed, max_iter=wl.iters, schedule=schedule)
+    res = P.solve(M, dev(wl.b), opts, history=True)
+    assert res.report.status == 0
+    hist = host(res.history)
+    for p in range(len(offs) - 1):
+        ip, ix, dv, n_p = csr_rows(wl, offs[p], offs[p + 1])
+        Ap = O.csr_matrix(ip, ix, dv, n_p, wl.d)
+        bp = wl.b[offs[p]:offs[p + 1]]
+        x = np.zeros(wl.d)
+        for t in range(wl.iters):
+            SA = OS.sketch_apply_csr(ip, ix, dv, n_p, wl.d, wl.sketch_seed, t, wl.m, 1, problem=p)
+            _, gr, _ = O.gradient(Ap, bp, x)
+            x = O.qp_step(SA.T @ SA, gr, x)
+            assert np.linalg.norm(hist[t, p] - x) <= 1e-11 * np.linalg.norm(x), (p, t)
+
+
 def test_gradient_ragged_batch(gpu_lib):
     P = gpu_lib
     g = np.random.default_rng(2)
