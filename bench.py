@@ -689,7 +689,8 @@ def components(P, W, wl4):
         o = P.options(8192, seed=wl3.sketch_seed, max_iter=wl3.iters, constraint="l2",
                       radius=wl3.radius, gram_in=gin, gram_acc=gacc)
         res = {}
-        ms = _wall_ms(lambda: res.update(r=P.solve(M3, b3, o)), reps=1)
+        # the average of three solves: one alone varies by up to a tenth
+        ms = _wall_ms(lambda: res.update(r=P.solve(M3, b3, o)), reps=3)
         x3 = res["r"].x[0].cpu().numpy()
         key = f"a8_solve_csr_2^22x1024_l2_{gin}_gram_{wl3.iters}steps"
         out[key] = {"ms_wall": round(ms, 3), "ms_per_step": round(ms / wl3.iters, 4),
