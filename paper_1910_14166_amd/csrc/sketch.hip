@@ -692,11 +692,12 @@ static hipError_t gather_inst(const SketchPlan& P, const GatherArgs& G, int32_t 
     hipLaunchKernelGGL((k_gather<TA, VEC, NCH, U, 1, GRAD, IDENT>), dim3(blocks), dim3(256), 0,
                        st, P, G, total_seg, seg_rows);
   } else if (gather_rows_per_wave(P.m, P.batch, G.d) == 2) {
-    // half the wavefronts; about eight 16-byte chunks per lane in flight
-    // (measured in one process on the same sorted rows at 2^22 x 512: two rows
-    // of four chunks 2.86 ms against four rows 2.91; at 2^20 x 256 four rows of
-    // two chunks and two rows of two chunks are equal)
-    constexpr int U = std::min(8, UF * (NE == 1 ? 8 : (NE == 2 ? 4 : 2)));
+    // half the wavefronts; about eight 16-byte loads per lane in flight, U rows
+    // of NCH (measured in one process on the same sorted rows at 2^22 x 512
+    // float64: two rows of four loads 2.86 ms against four rows 2.91; at
+    // 2^20 x 256 four rows of two loads and two rows are equal; float32 rows
+    // of two loads keep four rows in flight)
+    constexpr int U = std::min(8, UF * (NE == 1 ? 8 : (NCH <= 2 ? 4 : 2)));
     const int64_t waves = (P.m + 1) / 2;
     hipLaunchKernelGGL((k_gather<TA, VEC, NCH, U, 2, GRAD, IDENT>),
                        dim3((unsigned)((waves + 3) / 4), P.batch), dim3(256), 0, st, P, G,
