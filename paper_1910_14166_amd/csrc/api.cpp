@@ -24,7 +24,7 @@ namespace {
 constexpr int64_t kMaxSketchRows = 16384;  // per problem: 64 KiB LDS histogram
 constexpr int64_t kMaxDenseD = 1024;       // register-resident row slices
 constexpr int64_t kMaxCsrD = 1024;         // LDS-resident bucket rows (64 KiB)
-constexpr int32_t kSegRows = 256;          // rows per wavefront, natural-order passes
+constexpr int32_t kSegRows = 512;          // rows per wavefront, natural-order passes
 constexpr int32_t kTilesPerChunk = 32;
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
