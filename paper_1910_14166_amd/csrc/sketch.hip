@@ -491,11 +491,13 @@ __device__ __forceinline__ double readlane_f64(double v, int l) {
 // IDENT: natural row order (no sketch): wavefront w takes rows
 // [row0 + seg*seg_rows, ...) of its problem, and only the gradient is formed.
 // Otherwise the grid is (ceil(ceil(m/BPW)/4), batch): wavefront w of problem
-// blockIdx.y owns sketch rows [w*BPW, w*BPW + BPW) and streams them one after
-// the other, so each sketch row is still summed in ascending input-row order
-// by one lane per column. Owning two sketch rows halves the number of
-// resident wavefronts, which leaves room on every CU for the overlapped work
-// of the next step. Each wavefront of block 0 writes one gradient partial.
+// blockIdx.y owns positions [w*BPW, w*BPW + BPW) (the sketch rows that
+// P.border names for them when it is set, else the same rows) and streams
+// them one after the other, so each sketch row is still summed in ascending
+// input-row order by one lane per column. Owning two sketch rows halves the
+// number of resident wavefronts, which leaves room on every CU for the
+// overlapped work of the next step. Each wavefront of block 0 writes one
+// gradient partial.
 template <typename TA, int VEC, int NCH, int U, int BPW, bool GRAD, bool IDENT>
 __global__ __launch_bounds__(256, (BPW > 1 ? 3 : (NCH <= 4 ? 4 : 2))) void k_gather(
     SketchPlan P, GatherArgs G, int32_t total_seg, int32_t seg_rows) {
