@@ -175,7 +175,10 @@ typedef struct {
                                   solve); the constrained QP of the step then
                                   runs on the caller's stream from the Gram
                                   (and factor) formed beside the previous
-                                  pass;
+                                  pass. From d = 89 on the factor is also
+                                  inverted there, and the l1 penalty's step
+                                  (whose H is otherwise not factored) gets
+                                  the inverse too, for its KKT polish;
                                   1: strictly sequential steps;
                                   2: as 0 but two steps ahead, so the
                                   factorisation has two passes of time (for

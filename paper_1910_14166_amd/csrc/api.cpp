@@ -479,6 +479,10 @@ struct SolveBuffers {
   double* Hinv1 = nullptr;
   double* Hinv2 = nullptr;
   double* Linv = nullptr;    // triangular-inverse scratch of the second stream
+  // the l1 penalty's inverses (overlapped schedule, from kInverseMinD on) serve
+  // only its KKT polish; failures while forming them are kept here, apart
+  // from the solve's status, and make the step polish without them
+  DeviceStatus* inv_status = nullptr;
   double* dx = nullptr;
   // conjugate gradients with a fixed sketch: residual A^T (b - A x), its
   // preconditioned copy, -p, r^T z per problem, and a zero vector
@@ -555,13 +559,17 @@ size_t carve_solve(Carver& c, const Layout& L, const ihs_options* o, SolveBuffer
     for (int q = 0; q < 3; ++q) S.snap[q] = c.take<double>((size_t)(4 * L.batch));
     S.pre_status = c.take<DeviceStatus>(1);
   }
+  const bool pen_inv =
+      L.d >= kInverseMinD && o->constraint == IHS_L1_PENALTY && o->schedule != 1;
   if ((L.d >= kInverseMinD &&
-       (o->constraint == IHS_UNCONSTRAINED || o->constraint == IHS_L1_BALL)) || l2pre) {
+       (o->constraint == IHS_UNCONSTRAINED || o->constraint == IHS_L1_BALL)) || l2pre ||
+      pen_inv) {
     S.Hinv0 = c.take<double>((size_t)(L.batch * L.d * L.d));
     S.Hinv1 = c.take<double>((size_t)(L.batch * L.d * L.d));
     if (ahead2) S.Hinv2 = c.take<double>((size_t)(L.batch * L.d * L.d));
     S.Linv = c.take<double>((size_t)(L.batch * L.d * L.d));
   }
+  if (pen_inv) S.inv_status = c.take<DeviceStatus>(1);
   S.dx = c.take<double>((size_t)(L.batch * L.d));
   if (o->method == IHS_METHOD_FIXED_SKETCH_CG) {
     const size_t bd = (size_t)(L.batch * L.d);
@@ -783,6 +791,8 @@ ihs_status solve_overlap(const ihs_matrix* A, const Layout& L, const ihs_options
   // stream, the cleared side status records included
   hipLaunchKernelGGL(k_zero_status, dim3(1), dim3(64), 0, stream, S.side_status);
   if (l2pre) hipLaunchKernelGGL(k_zero_status, dim3(1), dim3(64), 0, stream, S.pre_status);
+  if (S.inv_status)
+    hipLaunchKernelGGL(k_zero_status, dim3(1), dim3(64), 0, stream, S.inv_status);
   if (!ck(hipEventRecord(evMisc.at(0), stream)) || !ck(hipStreamWaitEvent(side, evMisc.at(0), 0)) ||
       !ck(hipStreamWaitEvent(side2, evMisc.at(0), 0)) ||
       !ck(hipStreamWaitEvent(sorter, evMisc.at(0), 0)))
@@ -834,7 +844,8 @@ ihs_status solve_overlap(const ihs_matrix* A, const Layout& L, const ihs_options
       return false;
     // The constrained QPs work from H_k itself; the l1 ball's also needs the
     // unconstrained minimiser, so H_k is factored (and, from kInverseMinD
-    // on, inverted) here, beside the pass.
+    // on, inverted) here, beside the pass. From kInverseMinD on the l1
+    // penalty's polish uses H_k^{-1} too.
     if (constrained) {
       if (opt->constraint == IHS_L2_BALL) {
         // step k's QP (k >= 1, warm) iterates on (H_k + mu I)^{-1}, mu from
@@ -845,6 +856,11 @@ ihs_status solve_overlap(const ihs_matrix* A, const Layout& L, const ihs_options
                                       hinv_buf(k), q ? S.Linv1 : S.Linv, S.pre_scratch[q],
                                       S.pre_rows[q], S.pre_status, (int32_t)k, sk));
       }
+      if (opt->constraint == IHS_L1_PENALTY && S.inv_status)
+        return ck(launch_cholesky(h_buf(k), l_buf(k), d, L.batch, S.inv_status, (int32_t)k, 0.0,
+                                  w_buf(k), sk)) &&
+               ck(launch_chol_inverse(l_buf(k), chol_rdiag(w_buf(k), L.batch), d, L.batch,
+                                      hinv_buf(k), S.Linv, S.inv_status, sk));
       if (opt->constraint != IHS_L1_BALL) return true;
       if (!ck(launch_cholesky(h_buf(k), l_buf(k), d, L.batch, S.side_status, (int32_t)k, 0.0,
                               w_buf(k), sk)))
@@ -973,6 +989,10 @@ ihs_status solve_overlap(const ihs_matrix* A, const Layout& L, const ihs_options
           a.L = l_buf(t);
           a.rdiag_pre = chol_rdiag(w_buf(t), L.batch);
         }
+      }
+      if (opt->constraint == IHS_L1_PENALTY && S.inv_status) {  // for the polish
+        a.hinv_pre = hinv_buf(t);
+        a.pre_status = S.inv_status;
       }
       const hipError_t e = launch_qp_step(a, stream);
       if (e == hipErrorNotSupported) return IHS_ERR_UNSUPPORTED;

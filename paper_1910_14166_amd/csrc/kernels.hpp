@@ -191,11 +191,14 @@ struct QpArgs {
   const double* rdiag_pre; // l1 ball (nullable): L already holds the factor of H and
                            // this its reciprocal pivots, so the step does not factor H
   const double* hinv_pre;  // l1 ball (nullable): H^{-1} formed elsewhere; the step
-                           // then uses neither L nor rdiag_pre. l2 ball (with
-                           // trs_pre, warm steps): (H + mu0 I)^{-1} formed ahead
+                           // then uses neither L nor rdiag_pre, and its polish
+                           // uses it too. l1 penalty (nullable): H^{-1} for the
+                           // polish only. l2 ball (with trs_pre, warm steps):
+                           // (H + mu0 I)^{-1} formed ahead
   const double* trs_pre;   // l2 ball (nullable): the snapshot state of hinv_pre
                            // (mu0 and a norm bound at [4p + 2], [4p + 3])
-  const DeviceStatus* pre_status;  // l2 ball: failures while forming hinv_pre
+  const DeviceStatus* pre_status;  // l2 ball, l1 penalty: failures while forming
+                                   // hinv_pre (the penalty step then ignores it)
 };
 // The l2 step's inverse ahead of time: snapshot the shift state of the QP
 // workspace `work` (cold: mu = 0), and factor and invert H + mu I at that

@@ -231,6 +231,56 @@ __device__ int polish_finish(const double* __restrict__ H, int64_t d, double ci,
   return (r[0] == 0.0 && r[1] <= 1e-9 * cscale) ? kPolishAccepted : kPolishRejected;
 }
 
+// Cholesky factor of the n x n symmetric positive definite matrix M (row
+// major, LDS or global; lower triangle, in place, one column per round).
+// False, in every thread, when a pivot is not positive. Ends with a barrier.
+__device__ bool lds_cholesky(double* M, int n, BlockShared& sh) {
+  const int tid = threadIdx.x;
+  if (tid == 0) sh.flag[2] = 1;
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    const double piv = M[j * n + j];
+    if (!(piv > 0.0) || !isfinite(piv)) {  // the same value in every thread
+      if (tid == 0) sh.flag[2] = 0;
+      break;
+    }
+    const double ljj = sqrt(piv);
+    for (int i = j + 1 + tid; i < n; i += kQpThreads) M[i * n + j] /= ljj;
+    __syncthreads();
+    if (tid == 0) M[j * n + j] = ljj;
+    const int rem = n - j - 1;
+    for (int e = tid; e < rem * rem; e += kQpThreads) {
+      const int i = j + 1 + e / rem, k = j + 1 + (e - (e / rem) * rem);
+      if (k <= i) M[i * n + k] = fma(-M[i * n + j], M[k * n + j], M[i * n + k]);
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+  const bool ok = sh.flag[2] != 0;
+  __syncthreads();
+  return ok;
+}
+
+// z = (L L^T)^{-1} z for the factor L left in M by lds_cholesky (z: n
+// doubles of LDS): a forward then a backward sweep. Ends with a barrier.
+__device__ void lds_chol_solve(const double* M, int n, double* z) {
+  const int tid = threadIdx.x;
+  for (int j = 0; j < n; ++j) {
+    const double zj = z[j] / M[j * n + j];
+    for (int i = j + 1 + tid; i < n; i += kQpThreads) z[i] = fma(-M[i * n + j], zj, z[i]);
+    __syncthreads();
+    if (tid == 0) z[j] = zj;
+  }
+  __syncthreads();
+  for (int j = n - 1; j >= 0; --j) {
+    const double zj = z[j] / M[j * n + j];
+    for (int i = tid; i < j; i += kQpThreads) z[i] = fma(-M[j * n + i], zj, z[i]);
+    __syncthreads();
+    if (tid == 0) z[j] = zj;
+  }
+  __syncthreads();
+}
+
 // KKT polish on the support of x (thread i holds x_i in *xi). M: ns*ns
 // doubles (LDS or global), u, w: kPolishMax doubles, idx: kPolishMax ints,
 // cand, hc: d doubles of LDS. Ball (penalty false): mu from sigma^T x_S = tau;
@@ -264,28 +314,7 @@ __device__ __attribute__((noinline)) int l1_polish(const double* __restrict__ H,
     const int a = e / ns, b = e - (e / ns) * ns;
     M[e] = H[(int64_t)idx[a] * d + idx[b]];
   }
-  if (tid == 0) sh.flag[2] = 1;
-  __syncthreads();
-  // Cholesky of H_SS (lower, in place, one column per round)
-  for (int j = 0; j < ns; ++j) {
-    const double piv = M[j * ns + j];
-    if (!(piv > 0.0) || !isfinite(piv)) {  // the same value in every thread
-      if (tid == 0) sh.flag[2] = 0;
-      break;
-    }
-    const double ljj = sqrt(piv);
-    for (int i = j + 1 + tid; i < ns; i += kQpThreads) M[i * ns + j] /= ljj;
-    __syncthreads();
-    if (tid == 0) M[j * ns + j] = ljj;
-    const int rem = ns - j - 1;
-    for (int e = tid; e < rem * rem; e += kQpThreads) {
-      const int i = j + 1 + e / rem, k = j + 1 + (e - (e / rem) * rem);
-      if (k <= i) M[i * ns + k] = fma(-M[i * ns + j], M[k * ns + j], M[i * ns + k]);
-    }
-    __syncthreads();
-  }
-  __syncthreads();
-  if (!sh.flag[2]) return kPolishNone;
+  if (!lds_cholesky(M, ns, sh)) return kPolishNone;
   // u = H_SS^{-1} c_S and w = H_SS^{-1} sigma: forward then backward sweep
   for (int a = tid; a < ns; a += kQpThreads) u[a] = w[a] = 0.0;
   __syncthreads();
@@ -404,8 +433,94 @@ __device__ int l1_polish_cg(const double* __restrict__ H, int64_t d, double ci, 
   return polish_finish(H, d, ci, on, sg, xs, mu, pa, qa, cscale, xi, gi, mu_out, sh);
 }
 
-// The polish on the face of *xi (its support and signs): factored in LDS
-// when the support is small enough, by conjugate gradients otherwise.
+// y_S = (H_SS)^{-1} f_S through G = H^{-1}, thread i holding f_i (zero off
+// the support S): with N the complement of S, the inverse of the block H_SS
+// is the Schur complement G_SS - G_SN G_NN^{-1} G_NS of G_NN in G, so
+// y_S = (G f)_S - (G z)_S with z = G_NN^{-1} (G f)_N. M holds the factor of
+// G_NN (lds_cholesky), slot the thread's position in N (-1 on S), z nn
+// doubles of LDS, vec and hv d doubles of LDS. Zero off S.
+__device__ double inv_face_solve(const double* __restrict__ G, int64_t d, double f, bool on,
+                                 int slot, int nn, const double* M, double* z, double* vec,
+                                 double* hv, BlockShared& sh) {
+  const int tid = threadIdx.x;
+  if (tid < d) vec[tid] = f;
+  __syncthreads();
+  block_rows(G, d, vec, hv, sh);
+  const double y = tid < d ? hv[tid] : 0.0;
+  if (nn == 0) return on ? y : 0.0;
+  if (slot >= 0) z[slot] = y;
+  __syncthreads();
+  lds_chol_solve(M, nn, z);
+  if (tid < d) vec[tid] = slot >= 0 ? z[slot] : 0.0;
+  __syncthreads();
+  block_rows(G, d, vec, hv, sh);
+  return on ? y - hv[tid] : 0.0;
+}
+
+// KKT polish through the explicit inverse G = H^{-1}, for a support whose
+// complement N is the smaller set: each face solve is two products with G
+// and a solve with the |N| x |N| block G_NN (inv_face_solve), followed by one
+// step of iterative refinement whose residual is formed with H itself. Ball:
+// u = H_SS^{-1} c_S and w = H_SS^{-1} sigma_S, mu = (sigma^T u - tau) /
+// sigma^T w, x_S = u - mu w; penalty: x_S = H_SS^{-1} (c_S - lambda sigma_S).
+// Acceptance as in l1_polish. M: nn*nn doubles, z: kPolishMax doubles, idx:
+// kPolishMax ints, vec, hv, cand: d doubles, all LDS.
+__device__ __attribute__((noinline)) int l1_polish_inverse(
+    const double* __restrict__ H, const double* __restrict__ G, int64_t d, double ci, double tau,
+    bool penalty, double* xi, double* gi, double* mu_out, double* M, double* z, int* idx,
+    double* vec, double* hv, double* cand, double cscale, BlockShared& sh) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const bool on = tid < d && *xi != 0.0;
+  const bool off = tid < d && !on;
+  // ascending complement indices by wave ballots
+  const uint64_t bal = __ballot(off);
+  if (lane == 0) sh.wave_count[wv] = __popcll(bal);
+  __syncthreads();
+  int base = 0, nn = 0;
+  for (int k = 0; k < kQpWaves; ++k) {
+    if (k < wv) base += sh.wave_count[k];
+    nn += sh.wave_count[k];
+  }
+  __syncthreads();
+  if (nn > kPolishMax) return kPolishNone;
+  const int slot = off ? base + __popcll(bal & lanemask_lt()) : -1;
+  if (off) idx[slot] = tid;
+  __syncthreads();
+  for (int e = tid; e < nn * nn; e += kQpThreads) {
+    const int a = e / nn, b = e - (e / nn) * nn;
+    M[e] = G[(int64_t)idx[a] * d + idx[b]];
+  }
+  __syncthreads();
+  if (!lds_cholesky(M, nn, sh)) return kPolishNone;
+  const double sg = on ? copysign(1.0, *xi) : 0.0;
+  // one face solve and one refinement step: y += H_SS^{-1} (f - H_SS y)_S
+  auto solve = [&](double f) {
+    double y = inv_face_solve(G, d, f, on, slot, nn, M, z, vec, hv, sh);
+    if (tid < d) vec[tid] = y;
+    __syncthreads();
+    block_rows(H, d, vec, hv, sh);
+    const double r = on ? f - hv[tid] : 0.0;
+    return y + inv_face_solve(G, d, r, on, slot, nn, M, z, vec, hv, sh);
+  };
+  double xs, mu;
+  if (penalty) {
+    mu = tau;
+    xs = solve(on ? ci - tau * sg : 0.0);
+  } else {
+    const double u = solve(on ? ci : 0.0);
+    const double w = solve(sg);
+    double sw[2] = {sg * u, sg * w};
+    block_reduce<2, 0>(sw, sh);
+    mu = (sw[0] - tau) / sw[1];
+    xs = on ? u - mu * w : 0.0;
+  }
+  return polish_finish(H, d, ci, on, sg, xs, mu, cand, hv, cscale, xi, gi, mu_out, sh);
+}
+
+// The polish on the face of *xi (its support and signs): through G = H^{-1}
+// (nullable) when the complement of the support is the smaller set and its
+// block of G fits in LDS; otherwise factored in LDS when the support is small
+// enough, by conjugate gradients beyond.
 struct PolishLds {
   double* vec;
   double* cand;
@@ -417,12 +532,15 @@ struct PolishLds {
   int32_t mcap;  // doubles of M
 };
 
-__device__ int polish_face(const double* __restrict__ H, int64_t d, double ci, double tau,
-                           bool penalty, double* xi, double* gi, double* mu_out,
-                           const PolishLds& L, double cscale, BlockShared& sh) {
+__device__ int polish_face(const double* __restrict__ H, const double* __restrict__ G, int64_t d,
+                           double ci, double tau, bool penalty, double* xi, double* gi,
+                           double* mu_out, const PolishLds& L, double cscale, BlockShared& sh) {
   double nz[1] = {*xi != 0.0 ? 1.0 : 0.0};
   block_reduce<1, 0>(nz, sh);
-  const int64_t nsz = (int64_t)nz[0];
+  const int64_t nsz = (int64_t)nz[0], ncz = d - nsz;
+  if (G != nullptr && ncz < nsz && ncz <= kPolishMax && ncz * ncz <= L.mcap)
+    return l1_polish_inverse(H, G, d, ci, tau, penalty, xi, gi, mu_out, L.M, L.u, L.idx, L.vec,
+                             L.hv, L.cand, cscale, sh);
   if (nsz * nsz <= L.mcap)
     return l1_polish(H, d, ci, tau, penalty, xi, gi, mu_out, L.M, L.u, L.w, L.idx, L.cand, L.hv,
                      cscale, sh);
@@ -430,8 +548,10 @@ __device__ int polish_face(const double* __restrict__ H, int64_t d, double ci, d
                       (int)(2 * nsz + 40), sh);
 }
 
-// One workgroup per problem. xunc: the unconstrained minimiser. The polish
-// factors H_SS in LDS when it fits and runs conjugate gradients otherwise.
+// One workgroup per problem. xunc: the unconstrained minimiser. Ginv_all
+// (nullable): H^{-1} per problem for the polish, unused when gst records a
+// failure at or before this step (gst nullable). The polish factors H_SS in
+// LDS when it fits and runs conjugate gradients otherwise.
 //
 // The Lipschitz constant L of the gradient starts at 1.05 x the Rayleigh
 // quotient of kPowerSteps power steps and is raised by backtracking (Beck and
@@ -441,8 +561,9 @@ __device__ int polish_face(const double* __restrict__ H, int64_t d, double ci, d
 __global__ __launch_bounds__(kQpThreads) void k_qp_l1(
     const double* __restrict__ Hall, const double* __restrict__ call,
     const double* __restrict__ xunc_all, const double* x0_all, double* xout_all,
-    int64_t d, double tau, int32_t penalty, int32_t max_iter, double tol,
-    int32_t lds_mcap, DeviceStatus* st, int32_t iter) {
+    const double* __restrict__ Ginv_all, const DeviceStatus* gst, int64_t d, double tau,
+    int32_t penalty, int32_t max_iter, double tol, int32_t lds_mcap, DeviceStatus* st,
+    int32_t iter) {
   extern __shared__ double lds[];
   double* vec = lds;            // d: the vector being multiplied
   double* cand = vec + d;       // d: polish candidate
@@ -454,9 +575,13 @@ __global__ __launch_bounds__(kQpThreads) void k_qp_l1(
   __shared__ BlockShared sh;
   const int p = blockIdx.x;
   const int tid = threadIdx.x;
-  if (tid == 0) sh.flag[0] = status_halted(st) ? 1 : 0;
+  if (tid == 0) {
+    sh.flag[0] = status_halted(st) ? 1 : 0;
+    sh.flag[1] = (Ginv_all != nullptr && (gst == nullptr || !status_failed_by(gst, iter))) ? 1 : 0;
+  }
   __syncthreads();
   const double* H = Hall + (int64_t)p * d * d;
+  const double* G = sh.flag[1] != 0 ? Ginv_all + (int64_t)p * d * d : nullptr;
   double* xout = xout_all + (int64_t)p * d;
   const double x0 = tid < d ? x0_all[(int64_t)p * d + tid] : 0.0;
   if (sh.flag[0] != 0) {  // an earlier failure or the tolerance stop: keep x^t
@@ -488,7 +613,7 @@ __global__ __launch_bounds__(kQpThreads) void k_qp_l1(
   const double xw = penalty ? x0 : project_l1(x0, d, tau, sh);
   {
     double xp = xw, gp = 0.0, mup = 0.0;
-    if (polish_face(H, d, ci, tau, penalty != 0, &xp, &gp, &mup, pl, cscale, sh) ==
+    if (polish_face(H, G, d, ci, tau, penalty != 0, &xp, &gp, &mup, pl, cscale, sh) ==
         kPolishAccepted) {
       if (tid < d) xout[tid] = xp;
       return;
@@ -558,7 +683,7 @@ __global__ __launch_bounds__(kQpThreads) void k_qp_l1(
     if (conv || stable == kPolishEvery) {
       stable = 0;
       double xp = xi, gp = 0.0, mup = 0.0;
-      if (polish_face(H, d, ci, tau, penalty != 0, &xp, &gp, &mup, pl, cscale, sh) ==
+      if (polish_face(H, G, d, ci, tau, penalty != 0, &xp, &gp, &mup, pl, cscale, sh) ==
           kPolishAccepted) {
         xi = xp;
         done = true;
@@ -1015,8 +1140,8 @@ hipError_t launch_qp_constrained(const QpArgs& a, hipStream_t st) {
     const size_t fixed = (size_t)(3 * d + 2 * kPolishMax) * sizeof(double);
     const int32_t lds_mcap = (int32_t)((kQpLdsBytes - fixed) / sizeof(double));
     hipLaunchKernelGGL(k_qp_l1, dim3(B), dim3(kQpThreads), kQpLdsBytes, st, a.H, cbuf, xunc,
-                       a.x, a.x_out, d, a.radius, penalty ? 1 : 0, max_iter, tol, lds_mcap,
-                       a.status, a.iter);
+                       a.x, a.x_out, a.hinv_pre, penalty ? a.pre_status : nullptr, d, a.radius,
+                       penalty ? 1 : 0, max_iter, tol, lds_mcap, a.status, a.iter);
     return hipGetLastError();
   }
   // l2 ball. A cold start (mu = 0) first takes the unconstrained step

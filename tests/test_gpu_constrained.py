@@ -344,6 +344,28 @@ def test_ihs_l1_penalty_iterates_match_oracle(gpu_lib):
         assert O.error_A(wl.A, hist[-1], xo) < 1e-7, kind
 
 
+@pytest.mark.parametrize("lam", [2.0, 10.0])
+def test_ihs_l1_penalty_inverse_polish_matches_oracle(gpu_lib, lam):
+    """From the width at which the overlapped schedule forms H_t^{-1} beside
+    the pass, the penalised step polishes a face whose complement N is the
+    smaller set through that inverse: (H_SS)^{-1} is the Schur complement of
+    G_NN in G = H^{-1}. At lambda 2 and 10 the minimiser keeps 113 and 67 of
+    128 coordinates. Both schedules' iterates (the sequential one polishes by
+    conjugate gradients on H_SS) stay within the oracle's rounding budget."""
+    P = gpu_lib
+    wl = W.lasso_dense(rows=20000, d=128, m=1024, iters=6, penalty=lam)
+    assert wl.d >= INVERSE_MIN_D
+    xs, bud, _ = oracle_run(wl.A, wl.b, wl.m, 1, wl.sketch_seed, 6, "l1_penalty", wl.radius)
+    M = P.Matrix(dense=dev(wl.A))
+    for sched in ("overlap", "sequential"):
+        o = P.options(wl.m, seed=wl.sketch_seed, max_iter=6, constraint="l1_penalty",
+                      radius=wl.radius, schedule=sched)
+        r = P.solve(M, dev(wl.b), o, history=True)
+        assert r.report.status == 0 and r.report.qp_unpolished == 0, sched
+        assert_within_budget(wl.A, host(r.history)[:, 0], xs, bud, sched)
+    assert int((xs[-1] != 0).sum()) > wl.d // 2
+
+
 def test_ihs_l1_penalty_full_size_kkt(gpu_lib):
     """The penalised LASSO of the experiments (lambda = 5) at the full lasso
     shape (2^20 x 256, CountSketch m = 4096): after 20 steps the iterate meets
