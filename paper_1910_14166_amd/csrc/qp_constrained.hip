@@ -21,8 +21,10 @@
 // l1 penalty lambda ||x||_1 added to the objective (the penalised LASSO of
 // the experiments of Sec. 3): the same kernel with the soft threshold by
 // lambda / L as the proximal map in place of the projection, and the polish
-// with mu fixed at lambda (H_SS x_S = c_S - lambda sigma). An empty support
-// is the answer when every |c_j| <= lambda. No unconstrained solve first.
+// with mu fixed at lambda (H_SS x_S = c_S - lambda sigma); a rejected
+// polish of the warm start's face is followed by a few primal-dual
+// active-set corrections before FISTA. An empty support is the answer when
+// every |c_j| <= lambda. No unconstrained solve first.
 // l2 ball ||x||_2 <= r:
 //   Newton's method on phi(mu) = 1/||x(mu)|| - 1/r, x(mu) = (H + mu I)^{-1} c
 //   (More and Sorensen, 1983). 1/||x(mu)|| is concave and increasing, so from
@@ -41,7 +43,8 @@ namespace ihs {
 constexpr int kQpThreads = 1024;
 constexpr int kQpWaves = kQpThreads / 64;
 constexpr int kPolishMax = 256;   // largest support the KKT polish takes on
-constexpr int kPolishEvery = 16;  // unchanged iterations before a polish attempt
+constexpr int kPolishEvery = 4;   // unchanged iterations before a polish attempt
+constexpr int kActiveSetSteps = 4;  // penalty: active-set corrections of a rejected face
 constexpr int kPowerSteps = 8;    // power steps for the first Lipschitz estimate
 constexpr size_t kQpLdsBytes = 61440;
 
@@ -606,15 +609,33 @@ __global__ __launch_bounds__(kQpThreads) void k_qp_l1(
   // IHS steps the support and signs of the solution rarely change once the
   // iterates settle, so the KKT polish is tried on the warm start's face
   // first; an accepted polish is the minimiser and needs no Lipschitz
-  // estimate and no iteration. Otherwise FISTA runs from the warm start.
-  // (Primal-dual active-set corrections of a rejected face were measured
-  // here: the faces of the early steps differ too much for them to settle.)
+  // estimate and no iteration. For the penalty a rejected face is followed by
+  // up to kActiveSetSteps primal-dual active-set corrections (the semismooth
+  // Newton method for this problem): with g = c - H x of the last candidate,
+  // the next face keeps j where the coordinate-wise minimiser of the
+  // objective, soft(x_j + g_j / H_jj, lambda / H_jj), is non-zero, with its
+  // sign, i.e. |H_jj x_j + g_j| > lambda. They stop when the face repeats.
+  // (For the ball the same corrections were measured: the faces of its early
+  // steps differ too much for them to settle.) Otherwise FISTA runs from the
+  // warm start.
   const PolishLds pl{vec, cand, hv, u, w, Mlds, idx, lds_mcap};
   const double xw = penalty ? x0 : project_l1(x0, d, tau, sh);
   {
     double xp = xw, gp = 0.0, mup = 0.0;
-    if (polish_face(H, G, d, ci, tau, penalty != 0, &xp, &gp, &mup, pl, cscale, sh) ==
-        kPolishAccepted) {
+    double face = (tid < d && xw != 0.0) ? copysign(1.0, xw) : 0.0;
+    int res = polish_face(H, G, d, ci, tau, penalty != 0, &xp, &gp, &mup, pl, cscale, sh);
+    const double hjj = tid < d ? H[(int64_t)tid * d + tid] : 0.0;
+    for (int k = 0; penalty && res == kPolishRejected && k < kActiveSetSteps; ++k) {
+      const double v = fma(hjj, xp, gp);
+      const double next = (tid < d && fabs(v) > tau) ? copysign(1.0, v) : 0.0;
+      double moved[1] = {next != face ? 1.0 : 0.0};
+      block_reduce<0, 1>(moved, sh);
+      if (moved[0] == 0.0) break;  // uniform: a block-wide value
+      face = next;
+      xp = next;  // polish_face reads the face from the signs of xp
+      res = polish_face(H, G, d, ci, tau, true, &xp, &gp, &mup, pl, cscale, sh);
+    }
+    if (res == kPolishAccepted) {
       if (tid < d) xout[tid] = xp;
       return;
     }
