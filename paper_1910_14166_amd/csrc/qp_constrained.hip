@@ -633,28 +633,37 @@ __global__ __launch_bounds__(kQpThreads) void k_qp_l1(
   // objective, soft(x_j + g_j / H_jj, lambda / H_jj), is non-zero, with its
   // sign, i.e. |H_jj x_j + g_j| > lambda. They stop when the face repeats.
   // (For the ball the same corrections were measured: the faces of its early
-  // steps differ too much for them to settle.) Otherwise FISTA runs from the
-  // warm start.
+  // steps differ too much for them to settle.) For the ball the one other
+  // face tried is that of the projected unconstrained minimiser, which is
+  // then also FISTA's starting point; the penalty's FISTA starts at x^t.
+  // One call site of the polish keeps the kernel's registers for FISTA.
   const PolishLds pl{vec, cand, hv, u, w, Mlds, idx, lds_mcap};
   const double xw = penalty ? x0 : project_l1(x0, d, tau, sh);
+  double xstart = xw;
   {
+    const double hjj = (penalty && tid < d) ? H[(int64_t)tid * d + tid] : 0.0;
     double xp = xw, gp = 0.0, mup = 0.0;
     double face = (tid < d && xw != 0.0) ? copysign(1.0, xw) : 0.0;
-    int res = polish_face(H, G, d, ci, tau, penalty != 0, &xp, &gp, &mup, pl, cscale, sh);
-    const double hjj = tid < d ? H[(int64_t)tid * d + tid] : 0.0;
-    for (int k = 0; penalty && res == kPolishRejected && k < kActiveSetSteps; ++k) {
+    for (int k = 0;; ++k) {  // every exit below follows block-wide values
+      const int res = polish_face(H, G, d, ci, tau, penalty != 0, &xp, &gp, &mup, pl, cscale, sh);
+      if (res == kPolishAccepted) {
+        if (tid < d) xout[tid] = xp;
+        return;
+      }
+      if (!penalty) {
+        if (k > 0) break;
+        xstart = project_l1(xu, d, tau, sh);
+        xp = xstart;
+        continue;
+      }
+      if (res != kPolishRejected || k == kActiveSetSteps) break;
       const double v = fma(hjj, xp, gp);
       const double next = (tid < d && fabs(v) > tau) ? copysign(1.0, v) : 0.0;
       double moved[1] = {next != face ? 1.0 : 0.0};
       block_reduce<0, 1>(moved, sh);
-      if (moved[0] == 0.0) break;  // uniform: a block-wide value
+      if (moved[0] == 0.0) break;
       face = next;
       xp = next;  // polish_face reads the face from the signs of xp
-      res = polish_face(H, G, d, ci, tau, true, &xp, &gp, &mup, pl, cscale, sh);
-    }
-    if (res == kPolishAccepted) {
-      if (tid < d) xout[tid] = xp;
-      return;
     }
   }
   // power steps for the initial Lipschitz estimate
@@ -671,8 +680,8 @@ __global__ __launch_bounds__(kQpThreads) void k_qp_l1(
     pv = hp / sqrt(fmax(q[1], 1e-300));
   }
   double Lip = 1.05 * rq;
-  // FISTA from the warm start; thread i keeps x_i, (Hx)_i, y_i, (Hy)_i
-  double xi = xw;
+  // FISTA from xstart; thread i keeps x_i, (Hx)_i, y_i, (Hy)_i
+  double xi = xstart;
   if (tid < d) vec[tid] = xi;
   __syncthreads();
   block_rows(H, d, vec, hv, sh);
