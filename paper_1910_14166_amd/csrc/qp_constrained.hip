@@ -51,7 +51,7 @@ constexpr size_t kQpLdsBytes = 61440;
 constexpr int kRed = 8;  // values one fused block reduction carries
 
 constexpr int kColChunk = 256;  // columns per pass of the symmetric product
-constexpr int kRowsPer = 4;     // rows whose loads a wavefront issues together
+constexpr int kRowsPer = 2;     // rows whose loads a wavefront issues together
 
 struct ColPartials {
   double v[kQpWaves][kColChunk];
@@ -119,9 +119,12 @@ __device__ __forceinline__ void block_reduce(double (&v)[NS + NM], BlockShared& 
 
 // out = H v for the symmetric H, v and out in LDS, formed by columns:
 // (H v)_j = sum_i v_i H[i][j]. Each lane of wavefront w accumulates four
-// columns of a 256-column chunk over rows w, w + 16, ..., four
-// rows' loads at a time (rows read coalesced, no cross-lane reduction); the
-// 16 wavefronts' partial sums are then added through LDS in a fixed order.
+// columns of a 256-column chunk over the row pairs 2w, 2w + 1, 2w + 32,
+// 2w + 33, ..., kRowsPer rows' loads at a time (rows read coalesced, no
+// cross-lane reduction); the 16 wavefronts' partial sums are then added
+// through LDS in a fixed order. (Two rows at a time measured 6% faster than
+// four at d = 256, one row the same as two, eight rows 60% slower: the
+// kernel's registers are full.)
 // Ends with a barrier.
 template <int NV>
 __device__ __forceinline__ void sym_products(const double* __restrict__ H, int64_t d,
@@ -540,7 +543,7 @@ __device__ __attribute__((noinline)) int l1_polish_inverse(
 // The polish on the face of *xi (its support and signs): through G = H^{-1}
 // (nullable) when the complement of the support is the smaller set and its
 // block of G fits in LDS; otherwise factored in LDS when the support is small
-// enough, by conjugate gradients beyond.
+// enough, by conjugate gradients beyond (kPolishNone instead unless allow_cg).
 struct PolishLds {
   double* vec;
   double* cand;
@@ -554,7 +557,8 @@ struct PolishLds {
 
 __device__ int polish_face(const double* __restrict__ H, const double* __restrict__ G, int64_t d,
                            double ci, double tau, bool penalty, double* xi, double* gi,
-                           double* mu_out, const PolishLds& L, double cscale, BlockShared& sh) {
+                           double* mu_out, const PolishLds& L, double cscale, bool allow_cg,
+                           BlockShared& sh) {
   double nz[1] = {*xi != 0.0 ? 1.0 : 0.0};
   block_reduce<1, 0>(nz, sh);
   const int64_t nsz = (int64_t)nz[0], ncz = d - nsz;
@@ -564,6 +568,7 @@ __device__ int polish_face(const double* __restrict__ H, const double* __restric
   if (nsz * nsz <= L.mcap)
     return l1_polish(H, d, ci, tau, penalty, xi, gi, mu_out, L.M, L.u, L.w, L.idx, L.cand, L.hv,
                      cscale, sh);
+  if (!allow_cg) return kPolishNone;
   return l1_polish_cg(H, d, ci, tau, penalty, xi, gi, mu_out, L.vec, L.cand, L.hv, L.M, cscale,
                       (int)(2 * nsz + 40), sh);
 }
@@ -634,26 +639,26 @@ __global__ __launch_bounds__(kQpThreads) void k_qp_l1(
   // sign, i.e. |H_jj x_j + g_j| > lambda. They stop when the face repeats.
   // (For the ball the same corrections were measured: the faces of its early
   // steps differ too much for them to settle.) For the ball the one other
-  // face tried is that of the projected unconstrained minimiser, which is
-  // then also FISTA's starting point; the penalty's FISTA starts at x^t.
-  // One call site of the polish keeps the kernel's registers for FISTA.
+  // face tried is that of the projected unconstrained minimiser. FISTA then
+  // starts from the warm start. One call site of the polish keeps the
+  // kernel's registers for FISTA.
   const PolishLds pl{vec, cand, hv, u, w, Mlds, idx, lds_mcap};
   const double xw = penalty ? x0 : project_l1(x0, d, tau, sh);
-  double xstart = xw;
   {
     const double hjj = (penalty && tid < d) ? H[(int64_t)tid * d + tid] : 0.0;
     double xp = xw, gp = 0.0, mup = 0.0;
     double face = (tid < d && xw != 0.0) ? copysign(1.0, xw) : 0.0;
     for (int k = 0;; ++k) {  // every exit below follows block-wide values
-      const int res = polish_face(H, G, d, ci, tau, penalty != 0, &xp, &gp, &mup, pl, cscale, sh);
+      // the ball's second face is a guess: not worth conjugate gradients
+      const int res = polish_face(H, G, d, ci, tau, penalty != 0, &xp, &gp, &mup, pl, cscale,
+                                  penalty != 0 || k == 0, sh);
       if (res == kPolishAccepted) {
         if (tid < d) xout[tid] = xp;
         return;
       }
       if (!penalty) {
         if (k > 0) break;
-        xstart = project_l1(xu, d, tau, sh);
-        xp = xstart;
+        xp = project_l1(xu, d, tau, sh);
         continue;
       }
       if (res != kPolishRejected || k == kActiveSetSteps) break;
@@ -680,8 +685,8 @@ __global__ __launch_bounds__(kQpThreads) void k_qp_l1(
     pv = hp / sqrt(fmax(q[1], 1e-300));
   }
   double Lip = 1.05 * rq;
-  // FISTA from xstart; thread i keeps x_i, (Hx)_i, y_i, (Hy)_i
-  double xi = xstart;
+  // FISTA from the warm start; thread i keeps x_i, (Hx)_i, y_i, (Hy)_i
+  double xi = xw;
   if (tid < d) vec[tid] = xi;
   __syncthreads();
   block_rows(H, d, vec, hv, sh);
@@ -730,7 +735,7 @@ __global__ __launch_bounds__(kQpThreads) void k_qp_l1(
     if (conv || stable == kPolishEvery) {
       stable = 0;
       double xp = xi, gp = 0.0, mup = 0.0;
-      if (polish_face(H, G, d, ci, tau, penalty != 0, &xp, &gp, &mup, pl, cscale, sh) ==
+      if (polish_face(H, G, d, ci, tau, penalty != 0, &xp, &gp, &mup, pl, cscale, true, sh) ==
           kPolishAccepted) {
         xi = xp;
         done = true;
