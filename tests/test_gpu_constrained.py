@@ -366,6 +366,43 @@ def test_ihs_l1_penalty_inverse_polish_matches_oracle(gpu_lib, lam):
     assert int((xs[-1] != 0).sum()) > wl.d // 2
 
 
+@pytest.mark.parametrize("lam", [20.0, 500.0])
+def test_ihs_l1_penalty_inverse_polish_ragged_batch(gpu_lib, lam):
+    """The same polish through each problem's own H_t^{-1} in a ragged batch
+    (three problems of 7471, 6726 and 5733 rows, d = 128). At lambda 20 the
+    minimisers keep 128, 128 and 126 coordinates (an empty complement: the
+    face solve is two products with H^{-1}); at 500, 119, 117 and 121. Every
+    problem's iterates against the oracle's within the rounding budget."""
+    P = gpu_lib
+    wl = W.batch_ragged(num=3, n_lo=3000, n_hi=8000, d=128, m=1280, iters=6)
+    assert wl.d >= INVERSE_MIN_D
+    offs = wl.row_offsets
+    o = P.options(wl.m, seed=wl.sketch_seed, max_iter=wl.iters, constraint="l1_penalty",
+                  radius=lam)
+    res = P.solve(P.Matrix(dense=dev(wl.A), row_offsets=offs), dev(wl.b), o, history=True)
+    assert res.report.status == 0 and res.report.qp_unpolished == 0
+    hist = host(res.history)
+    for p in range(wl.batch):
+        Ap, bp = wl.A[offs[p]:offs[p + 1]], wl.b[offs[p]:offs[p + 1]]
+        x = np.zeros(wl.d)
+        xs, sas, Hs = [x.copy()], [], []
+        for t in range(wl.iters):
+            SA = OS.sketch_apply_dense(Ap, wl.sketch_seed, t, wl.m, 1, problem=p)
+            H = SA.T @ SA
+            _, gr, _ = O.gradient(Ap, bp, x)
+            x = O.qp_step(H, gr, x, "l1_penalty", lam)
+            xs.append(x.copy())
+            sas.append(SA)
+            Hs.append(H)
+        assert int((xs[-1] != 0).sum()) > wl.d // 2
+        bud = RB.ihs_budget(Ap, bp, sas, Hs, xs, "l1_penalty", lam)
+        for t in range(wl.iters):
+            dx = hist[t, p] - xs[t + 1]
+            assert np.linalg.norm(Ap @ dx) <= bud[t][0], (p, t, np.linalg.norm(Ap @ dx),
+                                                         bud[t][0])
+            assert np.linalg.norm(dx) <= bud[t][1], (p, t)
+
+
 def test_ihs_l1_penalty_full_size_kkt(gpu_lib):
     """The penalised LASSO of the experiments (lambda = 5) at the full lasso
     shape (2^20 x 256, CountSketch m = 4096): after 20 steps the iterate meets
